@@ -1,0 +1,342 @@
+"""CPU oracle of the TPC sector tracker -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this package; the product library never does.  It wraps ``liboracle.so``
+(built from ``tpc_oracle.c`` twice: binary32 without FP contraction for the
+bit-exact comparison, binary64 for accuracy references) with numpy arrays.
+
+Stages follow the readings documented with the C source: grid (a1),
+neighbours (a2), cleaner (a3), start hits (a4), tracklets (a5), selection
+(a6), refit and adjoint (a8/a9).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.environ.get("TPC_ORACLE_LIB", os.path.join(HERE, "liboracle.so"))
+N_ROWS_MAX = 152
+
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",
+          "-Wno-unused-function"]
+
+
+def build(force: bool = True, src: str | None = None, out: str | None = None) -> str:
+    """Compile liboracle.so with gcc (binary32 and binary64 objects)."""
+    out = out or LIB
+    if not force and os.path.exists(out):
+        return out
+    src = src or os.path.join(HERE, "tpc_oracle.c")
+    objs = []
+    for tag, defs in (("f32", []), ("f64", ["-DORC_F64"])):
+        obj = out + f".{tag}.o"
+        subprocess.run(["gcc", *CFLAGS, *defs, "-I", HERE, "-c", src, "-o", obj], check=True)
+        objs.append(obj)
+    tmp = out + ".tmp"
+    subprocess.run(["gcc", "-shared", "-o", tmp, *objs, "-lm"], check=True)
+    os.replace(tmp, out)
+    for o in objs:
+        os.remove(o)
+    return out
+
+
+class Geom(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("row_x", C.c_float * N_ROWS_MAX), ("bz", C.c_float),
+                ("tan_half", C.c_float), ("sigma_y2", C.c_float), ("sigma_z2", C.c_float)]
+
+
+class Params(C.Structure):
+    _fields_ = [("nf_win_y", C.c_float), ("nf_win_z", C.c_float), ("nf_chi2_max", C.c_float),
+                ("tc_chi2_pick", C.c_float), ("snp_max", C.c_float),
+                ("grid_occupancy", C.c_float), ("edge_margin", C.c_float),
+                ("search_margin", C.c_float), ("y_valid_margin", C.c_float),
+                ("min_chain", C.c_int32), ("tc_max_miss", C.c_int32),
+                ("min_tracklet_hits", C.c_int32), ("min_track_hits", C.c_int32)]
+
+
+DEFAULT_PARAMS = dict(nf_win_y=3.0, nf_win_z=3.5, nf_chi2_max=13.8, tc_chi2_pick=13.8,
+                      snp_max=0.99, grid_occupancy=2.0, edge_margin=1.0, search_margin=0.01,
+                      y_valid_margin=2.0, min_chain=3, tc_max_miss=10, min_tracklet_hits=10,
+                      min_track_hits=10)
+
+
+def make_geom(geom: dict) -> Geom:
+    g = Geom()
+    g.n_rows = int(geom["n_rows"])
+    rx = np.asarray(geom["row_x"], np.float32)
+    for r in range(g.n_rows):
+        g.row_x[r] = float(rx[r])
+    g.bz = float(geom["bz"])
+    g.tan_half = float(geom["tan_half"])
+    g.sigma_y2 = float(geom["sigma_y2"])
+    g.sigma_z2 = float(geom["sigma_z2"])
+    return g
+
+
+def make_params(**over) -> Params:
+    p = Params()
+    d = dict(DEFAULT_PARAMS)
+    d.update(over)
+    for k, v in d.items():
+        setattr(p, k, v)
+    return p
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        _lib = C.CDLL(LIB)
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dt(prec):
+    return np.float32 if prec == 32 else np.float64
+
+
+def _fn(name, prec):
+    return getattr(lib(), f"{name}_f{prec}")
+
+
+@dataclass
+class Grid:
+    sseg: np.ndarray
+    row_off: np.ndarray
+    meta_i: np.ndarray
+    meta_f: np.ndarray
+    bin_off: np.ndarray
+    perm: np.ndarray
+    ys: np.ndarray
+    zs: np.ndarray
+    n_bad: int
+    n_bins: int
+
+
+def grid_build(geom, params, inst_off, y, z, row, prec=32) -> Grid:
+    g, P = make_geom(geom), params if isinstance(params, Params) else make_params(**params)
+    n_inst = len(inst_off) - 1
+    n = int(inst_off[-1])
+    nr = g.n_rows
+    inst_off = np.ascontiguousarray(inst_off, np.int64)
+    y = np.ascontiguousarray(y, np.float32)
+    z = np.ascontiguousarray(z, np.float32)
+    row = np.ascontiguousarray(row, np.uint16)
+    dt = _dt(prec)
+    sseg = np.empty(n, np.int32)
+    perm = np.empty(n, np.int32)
+    ys = np.empty(n, dt)
+    zs = np.empty(n, dt)
+    row_off = np.empty(n_inst * (nr + 1), np.int32)
+    meta_i = np.empty((n_inst * nr, 4), np.int32)
+    meta_f = np.empty((n_inst * nr, 4), dt)
+    cap = 2 * n + 16 * nr * n_inst + 16
+    bin_off = np.empty(cap, np.int32)
+    nbad = C.c_int64(0)
+    f = _fn("orc_grid_build", prec)
+    f.restype = C.c_int64
+    used = f(C.byref(g), C.byref(P), C.c_int32(n_inst), _p(inst_off), _p(y), _p(z), _p(row),
+             _p(sseg), _p(row_off), _p(meta_i), _p(meta_f), _p(bin_off), C.c_int64(cap),
+             _p(perm), _p(ys), _p(zs), C.byref(nbad))
+    if used < 0:
+        raise RuntimeError("oracle grid: bin capacity exceeded")
+    return Grid(sseg, row_off, meta_i, meta_f, bin_off[:used].copy(), perm, ys, zs,
+                int(nbad.value), int(used))
+
+
+def neighbours(geom, params, grid: Grid, prec=32, brute=False):
+    g, P = make_geom(geom), params if isinstance(params, Params) else make_params(**params)
+    n = len(grid.sseg)
+    up = np.empty(n, np.int32)
+    dn = np.empty(n, np.int32)
+    f = _fn("orc_neighbours", prec)
+    f.restype = None
+    f(C.byref(g), C.byref(P), C.c_int64(n), _p(grid.sseg), _p(grid.row_off), _p(grid.meta_i),
+      _p(grid.meta_f), _p(grid.bin_off), _p(grid.perm), _p(grid.ys), _p(grid.zs), _p(up), _p(dn),
+      C.c_int(1 if brute else 0))
+    return up, dn
+
+
+def clean(up, dn, prec=32):
+    n = len(up)
+    up2 = np.empty(n, np.int32)
+    dn2 = np.empty(n, np.int32)
+    f = _fn("orc_clean", prec)
+    f.restype = None
+    f(C.c_int64(n), _p(np.ascontiguousarray(up, np.int32)), _p(np.ascontiguousarray(dn, np.int32)),
+      _p(up2), _p(dn2))
+    return up2, dn2
+
+
+def start_hits(params, up2, dn2, prec=32):
+    P = params if isinstance(params, Params) else make_params(**params)
+    n = len(up2)
+    st = np.empty(max(1, n), np.int32)
+    f = _fn("orc_start_hits", prec)
+    f.restype = C.c_int64
+    S = f(C.byref(P), C.c_int64(n), _p(up2), _p(dn2), _p(st))
+    return st[:S].copy()
+
+
+@dataclass
+class Tracklets:
+    par: np.ndarray     # [S,5]
+    cov: np.ndarray     # [S,15]
+    chi2: np.ndarray
+    nhit: np.ndarray
+    rmin: np.ndarray
+    rmax: np.ndarray
+    hit: np.ndarray     # [S, n_rows]
+    status: np.ndarray
+
+
+def tracklets(geom, params, grid: Grid, start, up2, prec=32) -> Tracklets:
+    g, P = make_geom(geom), params if isinstance(params, Params) else make_params(**params)
+    S = len(start)
+    dt = _dt(prec)
+    nr = g.n_rows
+    Sa = max(S, 1)
+    out = Tracklets(np.zeros((Sa, 5), dt), np.zeros((Sa, 15), dt), np.zeros(Sa, dt),
+                    np.zeros(Sa, np.int32), np.zeros(Sa, np.int32), np.zeros(Sa, np.int32),
+                    np.full((Sa, nr), -1, np.int32), np.zeros(Sa, np.int32))
+    f = _fn("orc_tracklets", prec)
+    f.restype = None
+    f(C.byref(g), C.byref(P), C.c_int64(S), _p(np.ascontiguousarray(start, np.int32)),
+      _p(up2), _p(grid.sseg), _p(grid.row_off), _p(grid.meta_i), _p(grid.meta_f),
+      _p(grid.bin_off), _p(grid.perm), _p(grid.ys), _p(grid.zs), _p(out.par), _p(out.cov),
+      _p(out.chi2), _p(out.nhit), _p(out.rmin), _p(out.rmax), _p(out.hit), _p(out.status))
+    if S == 0:
+        out = Tracklets(*(a[:0] for a in (out.par, out.cov, out.chi2, out.nhit, out.rmin,
+                                          out.rmax, out.hit, out.status)))
+    return out
+
+
+@dataclass
+class Tracks:
+    par: np.ndarray
+    cov: np.ndarray
+    chi2: np.ndarray
+    ndf: np.ndarray
+    x_ref: np.ndarray
+    hit_off: np.ndarray
+    hit_clu: np.ndarray
+    clu2trk: np.ndarray
+    owner: np.ndarray
+    need_tracks: int
+    need_hits: int
+
+
+def select(geom, params, inst_off, grid: Grid, start, tl: Tracklets, prec=32,
+           cap_tracks=None, cap_hits=None) -> Tracks:
+    g, P = make_geom(geom), params if isinstance(params, Params) else make_params(**params)
+    n = len(grid.sseg)
+    S = len(start)
+    dt = _dt(prec)
+    ct = S if cap_tracks is None else cap_tracks
+    ch = n if cap_hits is None else cap_hits
+    owner = np.zeros(max(n, 1), np.uint64)
+    tpar = np.zeros((max(ct, 1), 5), dt)
+    tcov = np.zeros((max(ct, 1), 15), dt)
+    tchi2 = np.zeros(max(ct, 1), dt)
+    tndf = np.zeros(max(ct, 1), np.int32)
+    txref = np.zeros(max(ct, 1), np.float32)
+    thoff = np.zeros(ct + 1, np.int32)
+    thclu = np.zeros(max(ch, 1), np.int32)
+    clu2trk = np.full(max(n, 1), -1, np.int32)
+    nh = C.c_int64(0)
+    need_t = C.c_int64(0)
+    need_h = C.c_int64(0)
+    Sa = max(S, 1)
+
+    def arr(a, dtp, shape):
+        return np.ascontiguousarray(a, dtp) if S else np.zeros(shape, dtp)
+
+    f = _fn("orc_select", prec)
+    f.restype = C.c_int64
+    nt = f(C.byref(g), C.byref(P), C.c_int64(n), C.c_int64(S),
+           _p(np.ascontiguousarray(inst_off, np.int64)), _p(arr(start, np.int32, Sa)),
+           _p(grid.sseg), _p(grid.perm), _p(arr(tl.par, dt, (Sa, 5))),
+           _p(arr(tl.cov, dt, (Sa, 15))), _p(arr(tl.chi2, dt, Sa)), _p(arr(tl.nhit, np.int32, Sa)),
+           _p(arr(tl.rmin, np.int32, Sa)), _p(arr(tl.rmax, np.int32, Sa)),
+           _p(arr(tl.hit, np.int32, (Sa, g.n_rows))), _p(arr(tl.status, np.int32, Sa)),
+           _p(owner), C.c_int64(ct), C.c_int64(ch), _p(tpar), _p(tcov), _p(tchi2), _p(tndf),
+           _p(txref), _p(thoff), _p(thclu), _p(clu2trk), C.byref(nh), C.byref(need_t),
+           C.byref(need_h))
+    return Tracks(tpar[:nt], tcov[:nt], tchi2[:nt], tndf[:nt], txref[:nt], thoff[:nt + 1],
+                  thclu[:nh.value], clu2trk[:n], owner[:n], int(need_t.value), int(need_h.value))
+
+
+@dataclass
+class ChainResult:
+    grid: Grid
+    up: np.ndarray
+    dn: np.ndarray
+    up2: np.ndarray
+    dn2: np.ndarray
+    start: np.ndarray
+    tracklets: Tracklets
+    tracks: Tracks
+
+
+def track(geom, params, inst_off, y, z, row, prec=32) -> ChainResult:
+    """The whole sector-tracking chain a1..a6, one stage after the other."""
+    gr = grid_build(geom, params, inst_off, y, z, row, prec)
+    up, dn = neighbours(geom, params, gr, prec)
+    up2, dn2 = clean(up, dn, prec)
+    st = start_hits(params, up2, dn2, prec)
+    tl = tracklets(geom, params, gr, st, up2, prec)
+    tr = select(geom, params, inst_off, gr, st, tl, prec)
+    return ChainResult(gr, up, dn, up2, dn2, st, tl, tr)
+
+
+def replay(geom, params, r0, rmin, rmax, hy, hz, has, prec=64):
+    """Re-run a tracklet's filter sequence on a fixed per-row hit list."""
+    g, P = make_geom(geom), params if isinstance(params, Params) else make_params(**params)
+    dt = _dt(prec)
+    par = np.zeros(5, dt)
+    cov = np.zeros(15, dt)
+    chi2 = (C.c_double if prec == 64 else C.c_float)(0)
+    f = _fn("orc_replay", prec)
+    f.restype = C.c_int
+    ok = f(C.byref(g), C.byref(P), C.c_int(int(r0)), C.c_int(int(rmin)), C.c_int(int(rmax)),
+           _p(np.ascontiguousarray(hy, np.float32)), _p(np.ascontiguousarray(hz, np.float32)),
+           _p(np.ascontiguousarray(has, np.uint8)), _p(par), _p(cov), C.byref(chi2))
+    return bool(ok), par, cov, float(chi2.value)
+
+
+def propagate(geom, params, p, c, x1, x2, prec=64):
+    """One R7/R8 step of state p[5] and lower-triangular covariance c[15]."""
+    g, P = make_geom(geom), params if isinstance(params, Params) else make_params(**params)
+    dt = _dt(prec)
+    p = np.array(p, dt)
+    c = np.array(c, dt)
+    f = _fn("orc_propagate", prec)
+    f.restype = C.c_int
+    sc = C.c_double if prec == 64 else C.c_float
+    ok = f(C.byref(g), C.byref(P), _p(p), _p(c), sc(x1), sc(x2))
+    return bool(ok), p, c
+
+
+def update(geom, p, c, my, mz, prec=64):
+    """One R9 measurement update; returns (chi2, p, c)."""
+    g = make_geom(geom)
+    dt = _dt(prec)
+    p = np.array(p, dt)
+    c = np.array(c, dt)
+    f = _fn("orc_update", prec)
+    sc = C.c_double if prec == 64 else C.c_float
+    f.restype = sc
+    ch = f(C.byref(g), _p(p), _p(c), sc(my), sc(mz))
+    return float(ch), p, c
