@@ -1,0 +1,209 @@
+/*
+ * tpcca.h -- C ABI of the MI355X TPC sector tracker (libtpcca.so).
+ *
+ * Problem (Rohr, "Improvements of the GPU Processing Framework for ALICE"):
+ * online TPC processing finds tracks in the clusters of each TPC sector and
+ * assigns clusters to tracks (Sec. 1; the cluster-to-track association is the
+ * quantity compared in Sec. 2).  The library runs the hot path of that step on
+ * one gfx950 GPU: cluster grid (a1), neighbour finding (a2) and cleaning (a3),
+ * start hits (a4), tracklet construction with a Kalman helix fit in the
+ * solenoid field (a5) and tracklet selection (a6), in a deterministic mode
+ * whose output is bit-identical to the CPU reference and a production mode
+ * (Sec. 2: deterministic processing mode).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named *_dev and every array inside the tpc_clusters, tpc_grid,
+ *     tpc_tracks and tpc_result structs are DEVICE pointers owned by the
+ *     caller; pointers named *_host and the tpc_geometry / tpc_params structs
+ *     are host memory, read during the call only.
+ *   - Calls enqueue work on `stream` (a hipStream_t, NULL = default stream)
+ *     and return before it completes; nothing is allocated or freed.
+ *   - Argument errors are returned synchronously (nothing is enqueued then);
+ *     data-dependent conditions (invalid clusters, output capacity) are
+ *     reported in the device-resident tpc_result, readable after the stream
+ *     has completed.
+ *   - One workspace may serve one call at a time; calls with distinct
+ *     workspaces and outputs may run concurrently.  No C++ exception crosses
+ *     the ABI.
+ *
+ * Data layout:
+ *   clusters   SoA over all instances; instance i owns input indices
+ *              [inst_off[i], inst_off[i+1]); inst_off[0] = 0 and each
+ *              instance holds fewer than 2^24 clusters.
+ *   positions  the grid orders the valid clusters of instance i by
+ *              (row, bin, input index) into positions
+ *              [inst_off[i], inst_off[i] + n_valid_i); the remaining positions
+ *              of the instance are padding (sseg = perm = -1, ys = zs = 0).
+ *              Links and tracklet hits are positions; track hit lists and
+ *              clu2trk use input indices.
+ */
+#ifndef TPCCA_H
+#define TPCCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPC_N_ROWS 152
+
+typedef enum {
+  TPC_OK = 0,
+  TPC_ERR_INVALID = -1,     /* bad argument (null pointer, size, layout)  */
+  TPC_ERR_UNSUPPORTED = -2, /* mode not built into this library           */
+  TPC_ERR_HIP = -3,         /* a HIP runtime call failed                  */
+  TPC_ERR_WORKSPACE = -4    /* workspace smaller than the size query said */
+} tpc_status;
+
+enum {
+  TPC_FLAG_DETERMINISTIC = 1u, /* contraction-free code object + ordering kernels (Sec. 2) */
+  TPC_FLAG_PERSISTENT = 2u,    /* reserved for work-queue kernels                         */
+  TPC_FLAG_GRAPH = 4u          /* reserved for graph-captured chains                      */
+};
+
+/* Detector description (host, by pointer).  n_rows must be 152; row_x are
+ * the pad-row plane positions [cm] along the sector axis, ascending;
+ * bz_tesla the solenoid field; tan_half_sector = tan(10 deg); sigma_y2,
+ * sigma_z2 the cluster position variances [cm^2]. */
+typedef struct {
+  int32_t n_rows;
+  float row_x[TPC_N_ROWS];
+  float bz_tesla;
+  float tan_half_sector;
+  float sigma_y2, sigma_z2;
+} tpc_geometry;
+
+/* Algorithm parameters (host); tpc_default_params() fills the defaults:
+ * neighbour windows 3.0 / 3.5 cm and score cut 13.8, tracklet chi2 cut 13.8,
+ * |snp| < 0.99, grid occupancy 2, sector-edge margin 1 cm, window margin
+ * 0.01 cm, cluster validity margin 2 cm, chains >= 3 hits, 10 consecutive
+ * misses, >= 10 hits per tracklet and per track, flags 0. */
+typedef struct {
+  float nf_win_y, nf_win_z, nf_chi2_max;
+  float tc_chi2_pick, snp_max;
+  float grid_occupancy;
+  float edge_margin, search_margin;
+  float y_valid_margin;
+  int32_t min_chain, tc_max_miss, min_tracklet_hits, min_track_hits;
+  uint32_t flags;
+} tpc_params;
+
+/* Clusters: device SoA, n_clusters entries each (charge is carried, unused). */
+typedef struct {
+  const float *x, *y, *z;
+  const uint16_t *row, *charge;
+} tpc_clusters;
+
+/* Geometry of one (instance,row) grid: ny x nz bins, bin = iz*ny + iy,
+ * bin_off entries [bin_base, bin_base + ny*nz] (last = row end);
+ * count = valid clusters; iy = trunc((y - y0) * iwy) clamped to [0, ny-1]. */
+typedef struct {
+  int32_t ny, nz, bin_base, count;
+  float y0, z0, iwy, iwz;
+} tpc_row_meta;
+
+/* Grid output of tpc_grid_build (device arrays, caller-allocated):
+ *   sseg    [n_clusters]            instance*152 + row of each position, -1 = padding
+ *   row_off [n_inst*153]            first position of each (instance,row); entry 152 = end
+ *   meta    [n_inst*152]
+ *   bin_off [bin_cap]               bin_cap >= tpc_grid_bin_capacity()
+ *   perm    [n_clusters]            input index of each position, -1 = padding
+ *   ys, zs  [n_clusters]            cluster y, z in position order                   */
+typedef struct {
+  int32_t* sseg;
+  int32_t* row_off;
+  tpc_row_meta* meta;
+  int32_t* bin_off;
+  int32_t* perm;
+  float* ys;
+  float* zs;
+  int64_t bin_cap;
+} tpc_grid;
+
+/* Tracks (device arrays, caller-allocated): parameters (y, z, snp, tgl, qpt)
+ * and lower-triangular covariance at plane x_ref (innermost hit of the fit);
+ * chi2 and ndf of the fit; hit lists in CSR form (hit_off[cap_tracks+1],
+ * hit_clu[cap_hits], input indices, ascending row); clu2trk[n_clusters]
+ * = track index or -1.  Deterministic mode emits tracks in tracklet order;
+ * production mode in any order.  If capacity is short the longest prefix
+ * that fits is written and tpc_result says what was needed. */
+typedef struct {
+  float* param;    /* [cap_tracks][5]  */
+  float* cov;      /* [cap_tracks][15] */
+  float* chi2;     /* [cap_tracks]     */
+  int32_t* ndf;    /* [cap_tracks]     */
+  float* x_ref;    /* [cap_tracks]     */
+  int32_t* hit_off;
+  int32_t* hit_clu;
+  int32_t* clu2trk;
+  int64_t cap_tracks, cap_hits;
+} tpc_tracks;
+
+/* Device-resident status word, written by the calls.  overflow bits:
+ * 1 bin table, 2 tracklets, 4 tracks, 8 track hits. */
+typedef struct {
+  int64_t n_valid, n_bad, n_bins;
+  int64_t n_start, n_tracklets_kept;
+  int64_t n_tracks, n_hits;
+  int64_t need_tracklets, need_tracks, need_hits;
+  int32_t overflow, reserved;
+} tpc_result;
+
+/* Byte offsets of the intermediate arrays inside the tracking workspace
+ * (for inspection and testing; the tracker owns them during a call):
+ *   up, dn, up2, dn2   i32[n_clusters]  raw and cleaned links (positions, -1 none)
+ *   start              i32[cap_tracklets] start hits in list order
+ *   tl_par             f32[5][cap_tracklets]   tl_cov f32[15][cap_tracklets]
+ *   tl_chi2            f32[cap_tracklets]      tl_nhit, tl_rmin, tl_rmax, tl_status i32
+ *   tl_hit             i32[152][cap_tracklets] (valid for rmin <= row <= rmax)
+ *   owner              u64[n_clusters]  selection keys per position          */
+typedef struct {
+  int64_t up, dn, up2, dn2, start;
+  int64_t tl_par, tl_cov, tl_chi2, tl_nhit, tl_rmin, tl_rmax, tl_status, tl_hit;
+  int64_t owner;
+  int64_t scratch;
+  int64_t total;
+  int64_t cap_tracklets;
+} tpc_track_ws_layout;
+
+void tpc_default_params(tpc_params* p);
+const char* tpc_status_string(tpc_status s);
+
+/* Size queries (no device work).  cap_tracklets <= 0 selects the proven
+ * bound n_clusters/3 + n_inst (every start hit heads a disjoint chain of at
+ * least three clusters). */
+int64_t tpc_grid_bin_capacity(int32_t n_inst, int64_t n_clusters);
+size_t tpc_grid_workspace_bytes(int32_t n_inst, int64_t n_clusters);
+size_t tpc_track_workspace_bytes(int32_t n_inst, int64_t n_clusters, int64_t cap_tracklets);
+tpc_status tpc_track_workspace_layout(int32_t n_inst, int64_t n_clusters, int64_t cap_tracklets,
+                                      tpc_track_ws_layout* out);
+
+/* a1: build the per (instance,row) grid of the valid clusters (R10 of the
+ * design notes; total-order sort of Sec. 2).  Invalid clusters (row >= 152,
+ * |y| beyond the sector plus margin, |z| > 1e5, NaN) are counted in
+ * result->n_bad and left out.  Writes result fields n_valid, n_bad, n_bins
+ * (overflow bit 1 if bin_cap is too small; the grid is then unusable).
+ * inst_off_host and inst_off_dev hold the same n_inst+1 offsets.
+ * Errors: TPC_ERR_INVALID (null pointer, n_rows != 152, bad offsets,
+ * instance >= 2^24 clusters), TPC_ERR_WORKSPACE, TPC_ERR_HIP. */
+tpc_status tpc_grid_build(const tpc_geometry* geom, const tpc_params* params, int32_t n_inst,
+                          const int64_t* inst_off_host, const int64_t* inst_off_dev,
+                          tpc_clusters in, const tpc_grid* grid, tpc_result* result_dev,
+                          void* ws_dev, size_t ws_bytes, void* stream);
+
+/* a2..a6: neighbours, cleaner, start hits, tracklets, selection on a grid
+ * built by tpc_grid_build with the same arguments.  Writes the tracks and the
+ * remaining result fields.  TPC_FLAG_DETERMINISTIC in params->flags selects
+ * the deterministic code object and ordering kernels. */
+tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, int32_t n_inst,
+                            const int64_t* inst_off_host, const int64_t* inst_off_dev,
+                            tpc_clusters in, const tpc_grid* grid, const tpc_tracks* out,
+                            tpc_result* result_dev, void* ws_dev, size_t ws_bytes,
+                            int64_t cap_tracklets, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -124,7 +124,10 @@ int64_t SFX(orc_grid_build)(const orc_geom* g, const orc_params* P, int32_t n_in
       int ny = 1, nz = 1;
       real y0 = 0, z0 = 0, iwy = 0, iwz = 0;
       if (cnt[r] > 0) {
-        real dy = ymax[r] - ymin[r], dz = zmax[r] - zmin[r];
+        /* one canonical zero: a -0 extreme of the data box becomes +0 */
+        real ylo = ymin[r] + (real)0, yhi = ymax[r] + (real)0;
+        real zlo = zmin[r] + (real)0, zhi = zmax[r] + (real)0;
+        real dy = yhi - ylo, dz = zhi - zlo;
         real nb = FLOOR((real)cnt[r] / (real)P->grid_occupancy);
         if (nb < 1) nb = 1;
         real w = SQRT((dy * dz) / nb);
@@ -135,8 +138,8 @@ int64_t SFX(orc_grid_build)(const orc_geom* g, const orc_params* P, int32_t n_in
         nz = axis_bins(dz, w);
         iwy = dy > 0 ? (real)ny / dy : 0;
         iwz = dz > 0 ? (real)nz / dz : 0;
-        y0 = ymin[r];
-        z0 = zmin[r];
+        y0 = ylo;
+        z0 = zlo;
       }
       meta_i[s * 4 + 0] = ny;
       meta_i[s * 4 + 1] = nz;

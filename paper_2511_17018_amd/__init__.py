@@ -1,0 +1,286 @@
+"""Python binding of libtpcca.so, the MI355X TPC sector tracker.
+
+Argument marshalling only: torch tensors supply device memory and the
+current HIP stream; every step of the tracking chain runs in the library's
+HIP kernels.  The names mirror the C ABI in include/tpcca.h:
+``grid_build`` -> tpc_grid_build, ``sector_track`` -> tpc_sector_track.
+If the library is not built, loading it raises RuntimeError; there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtpcca.so")
+N_ROWS = 152
+FLAG_DETERMINISTIC = 1
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded libtpcca.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2511_17018_amd.build` (hipcc, gfx950)")
+        _lib = C.CDLL(LIB_PATH)
+        _lib.tpc_status_string.restype = C.c_char_p
+        _lib.tpc_grid_bin_capacity.restype = C.c_int64
+        _lib.tpc_grid_workspace_bytes.restype = C.c_size_t
+        _lib.tpc_track_workspace_bytes.restype = C.c_size_t
+        _lib.tpc_track_workspace_layout.restype = C.c_int
+        _lib.tpc_grid_build.restype = C.c_int
+        _lib.tpc_sector_track.restype = C.c_int
+    return _lib
+
+
+class Geometry(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("row_x", C.c_float * N_ROWS), ("bz_tesla", C.c_float),
+                ("tan_half_sector", C.c_float), ("sigma_y2", C.c_float), ("sigma_z2", C.c_float)]
+
+
+class Params(C.Structure):
+    _fields_ = [("nf_win_y", C.c_float), ("nf_win_z", C.c_float), ("nf_chi2_max", C.c_float),
+                ("tc_chi2_pick", C.c_float), ("snp_max", C.c_float),
+                ("grid_occupancy", C.c_float), ("edge_margin", C.c_float),
+                ("search_margin", C.c_float), ("y_valid_margin", C.c_float),
+                ("min_chain", C.c_int32), ("tc_max_miss", C.c_int32),
+                ("min_tracklet_hits", C.c_int32), ("min_track_hits", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class Clusters(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("row", C.c_void_p),
+                ("charge", C.c_void_p)]
+
+
+class GridStruct(C.Structure):
+    _fields_ = [("sseg", C.c_void_p), ("row_off", C.c_void_p), ("meta", C.c_void_p),
+                ("bin_off", C.c_void_p), ("perm", C.c_void_p), ("ys", C.c_void_p),
+                ("zs", C.c_void_p), ("bin_cap", C.c_int64)]
+
+
+class TracksStruct(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("cov", C.c_void_p), ("chi2", C.c_void_p),
+                ("ndf", C.c_void_p), ("x_ref", C.c_void_p), ("hit_off", C.c_void_p),
+                ("hit_clu", C.c_void_p), ("clu2trk", C.c_void_p), ("cap_tracks", C.c_int64),
+                ("cap_hits", C.c_int64)]
+
+
+class TrackWsLayout(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "up", "dn", "up2", "dn2", "start", "tl_par", "tl_cov", "tl_chi2", "tl_nhit", "tl_rmin",
+        "tl_rmax", "tl_status", "tl_hit", "owner", "scratch", "total", "cap_tracklets")]
+
+
+RESULT_DTYPE = np.dtype([(n, np.int64) for n in (
+    "n_valid", "n_bad", "n_bins", "n_start", "n_tracklets_kept", "n_tracks", "n_hits",
+    "need_tracklets", "need_tracks", "need_hits")] + [("overflow", np.int32), ("reserved", np.int32)])
+RESULT_BYTES = RESULT_DTYPE.itemsize
+
+
+class TpcError(RuntimeError):
+    pass
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        raise TpcError(f"{what}: {lib().tpc_status_string(st).decode()} ({st})")
+
+
+def make_geometry(geom: dict) -> Geometry:
+    g = Geometry()
+    g.n_rows = int(geom["n_rows"])
+    rx = np.asarray(geom["row_x"], np.float32)
+    C.memmove(g.row_x, rx.ctypes.data, 4 * N_ROWS)
+    g.bz_tesla = float(geom["bz"])
+    g.tan_half_sector = float(geom["tan_half"])
+    g.sigma_y2 = float(geom["sigma_y2"])
+    g.sigma_z2 = float(geom["sigma_z2"])
+    return g
+
+
+def make_params(det: bool = True, **over) -> Params:
+    p = Params()
+    lib().tpc_default_params(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    p.flags = (p.flags | FLAG_DETERMINISTIC) if det else (p.flags & ~FLAG_DETERMINISTIC)
+    return p
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(0)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Batch:
+    """Clusters of several sector instances resident on the GPU."""
+    x: torch.Tensor
+    y: torch.Tensor
+    z: torch.Tensor
+    row: torch.Tensor      # int16 storage of uint16 row numbers
+    charge: torch.Tensor
+    inst_off_host: np.ndarray
+    inst_off: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.inst_off_host[-1])
+
+    @property
+    def n_inst(self) -> int:
+        return len(self.inst_off_host) - 1
+
+    def struct(self) -> Clusters:
+        return Clusters(_ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.row), _ptr(self.charge))
+
+    def slice(self, i: int) -> "Batch":
+        """Instance i alone (views, no copies of the cluster arrays)."""
+        a, b = int(self.inst_off_host[i]), int(self.inst_off_host[i + 1])
+        off = np.array([0, b - a], np.int64)
+        return Batch(self.x[a:b], self.y[a:b], self.z[a:b], self.row[a:b], self.charge[a:b],
+                     off, torch.from_numpy(off).to(self.x.device))
+
+
+def upload(x, y, z, row, charge, inst_off, device="cuda") -> Batch:
+    off = np.ascontiguousarray(inst_off, np.int64)
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).view(dt)).to(device)  # noqa: E731
+    return Batch(t(x, np.float32), t(y, np.float32), t(z, np.float32), t(row, np.int16),
+                 t(charge, np.int16), off, torch.from_numpy(off).to(device))
+
+
+@dataclass
+class Grid:
+    sseg: torch.Tensor
+    row_off: torch.Tensor
+    meta: torch.Tensor      # int32 [n_inst*152, 8]: ny, nz, bin_base, count, y0, z0, iwy, iwz (bits)
+    bin_off: torch.Tensor
+    perm: torch.Tensor
+    ys: torch.Tensor
+    zs: torch.Tensor
+
+    def struct(self) -> GridStruct:
+        return GridStruct(_ptr(self.sseg), _ptr(self.row_off), _ptr(self.meta), _ptr(self.bin_off),
+                          _ptr(self.perm), _ptr(self.ys), _ptr(self.zs), self.bin_off.numel())
+
+
+@dataclass
+class Tracks:
+    param: torch.Tensor
+    cov: torch.Tensor
+    chi2: torch.Tensor
+    ndf: torch.Tensor
+    x_ref: torch.Tensor
+    hit_off: torch.Tensor
+    hit_clu: torch.Tensor
+    clu2trk: torch.Tensor
+
+    def struct(self) -> TracksStruct:
+        return TracksStruct(_ptr(self.param), _ptr(self.cov), _ptr(self.chi2), _ptr(self.ndf),
+                            _ptr(self.x_ref), _ptr(self.hit_off), _ptr(self.hit_clu),
+                            _ptr(self.clu2trk), self.param.shape[0], self.hit_clu.numel())
+
+
+def alloc_grid(n_inst: int, n: int, device="cuda") -> Grid:
+    cap = int(lib().tpc_grid_bin_capacity(C.c_int32(n_inst), C.c_int64(n)))
+    i32 = dict(dtype=torch.int32, device=device)
+    return Grid(torch.empty(n, **i32), torch.empty(n_inst * (N_ROWS + 1), **i32),
+                torch.empty((n_inst * N_ROWS, 8), **i32), torch.empty(cap, **i32),
+                torch.empty(n, **i32), torch.empty(n, dtype=torch.float32, device=device),
+                torch.empty(n, dtype=torch.float32, device=device))
+
+
+def alloc_tracks(n: int, cap_tracks: int | None = None, cap_hits: int | None = None,
+                 device="cuda") -> Tracks:
+    ct = max(1, n // 10 + 16) if cap_tracks is None else cap_tracks
+    ch = n if cap_hits is None else cap_hits
+    f32 = dict(dtype=torch.float32, device=device)
+    i32 = dict(dtype=torch.int32, device=device)
+    return Tracks(torch.empty((ct, 5), **f32), torch.empty((ct, 15), **f32), torch.empty(ct, **f32),
+                  torch.empty(ct, **i32), torch.empty(ct, **f32), torch.empty(ct + 1, **i32),
+                  torch.empty(ch, **i32), torch.empty(n, **i32))
+
+
+class Workspace:
+    """Device scratch of one tracking call (grid and tracking parts)."""
+
+    def __init__(self, n_inst: int, n: int, cap_tracklets: int = 0, device="cuda"):
+        L = lib()
+        self.n_inst, self.n, self.cap_tracklets = n_inst, n, cap_tracklets
+        gb = int(L.tpc_grid_workspace_bytes(C.c_int32(n_inst), C.c_int64(n)))
+        tb = int(L.tpc_track_workspace_bytes(C.c_int32(n_inst), C.c_int64(n),
+                                             C.c_int64(cap_tracklets)))
+        self.grid_ws = torch.empty(max(gb, 256), dtype=torch.uint8, device=device)
+        self.track_ws = torch.empty(max(tb, 256), dtype=torch.uint8, device=device)
+        self.layout = TrackWsLayout()
+        _check(L.tpc_track_workspace_layout(C.c_int32(n_inst), C.c_int64(n),
+                                            C.c_int64(cap_tracklets), C.byref(self.layout)),
+               "tpc_track_workspace_layout")
+        self.result = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=device)
+
+    def view(self, name: str, dtype, count: int) -> torch.Tensor:
+        off = getattr(self.layout, name)
+        nbytes = count * torch.empty(0, dtype=dtype).element_size()
+        return self.track_ws[off:off + nbytes].view(dtype)
+
+    def read_result(self) -> np.void:
+        return np.frombuffer(self.result.cpu().numpy().tobytes(), RESULT_DTYPE)[0]
+
+
+def grid_build(geom: Geometry, params: Params, batch: Batch, grid: Grid, ws: Workspace) -> None:
+    """tpc_grid_build on the current stream (asynchronous)."""
+    gs = grid.struct()
+    _check(lib().tpc_grid_build(
+        C.byref(geom), C.byref(params), C.c_int32(batch.n_inst),
+        batch.inst_off_host.ctypes.data_as(C.c_void_p), _ptr(batch.inst_off), batch.struct(),
+        C.byref(gs), _ptr(ws.result), _ptr(ws.grid_ws), C.c_size_t(ws.grid_ws.numel()),
+        _stream()), "tpc_grid_build")
+
+
+def sector_track(geom: Geometry, params: Params, batch: Batch, grid: Grid, tracks: Tracks,
+                 ws: Workspace) -> None:
+    """tpc_sector_track on the current stream (asynchronous)."""
+    gs = grid.struct()
+    ts = tracks.struct()
+    _check(lib().tpc_sector_track(
+        C.byref(geom), C.byref(params), C.c_int32(batch.n_inst),
+        batch.inst_off_host.ctypes.data_as(C.c_void_p), _ptr(batch.inst_off), batch.struct(),
+        C.byref(gs), C.byref(ts), _ptr(ws.result), _ptr(ws.track_ws),
+        C.c_size_t(ws.track_ws.numel()), C.c_int64(ws.cap_tracklets), _stream()),
+        "tpc_sector_track")
+
+
+@dataclass
+class TrackRun:
+    grid: Grid
+    tracks: Tracks
+    ws: Workspace
+    result: np.void
+
+
+def track(geom: dict, batch: Batch, det: bool = True, cap_tracks=None, cap_hits=None,
+          cap_tracklets: int = 0, **param_over) -> TrackRun:
+    """Grid + sector tracking of a batch; synchronises and returns the result."""
+    g = make_geometry(geom)
+    p = make_params(det, **param_over)
+    dev = batch.x.device
+    grid = alloc_grid(batch.n_inst, batch.n, dev)
+    tracks = alloc_tracks(batch.n, cap_tracks, cap_hits, dev)
+    ws = Workspace(batch.n_inst, batch.n, cap_tracklets, dev)
+    grid_build(g, p, batch, grid, ws)
+    sector_track(g, p, batch, grid, tracks, ws)
+    torch.cuda.synchronize()
+    return TrackRun(grid, tracks, ws, ws.read_result())

@@ -1,0 +1,314 @@
+// Host side of the C ABI declared in include/tpcca.h: argument validation,
+// workspace carving, derived constants, dispatch to the deterministic or
+// production build of the kernels.  Allocates nothing.
+#include <math.h>
+#include <string.h>
+
+#include "tpc_internal.h"
+
+using namespace tpcca;
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+constexpr int64_t kScanTile = 2048;  // items per block of the scan kernels
+constexpr int64_t kMaxInstClusters = (int64_t)1 << 24;
+
+int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Carve {
+  int64_t off = 0;
+  int64_t take(int64_t bytes)
+  {
+    int64_t o = off;
+    off = align_up(off + (bytes > 0 ? bytes : 0));
+    return o;
+  }
+};
+
+int64_t default_cap(int32_t n_inst, int64_t n) { return n / 3 + n_inst; }
+
+struct GridWs {
+  int64_t cseg, seg_cnt, seg_mm, inst_bad, nb1, fill, scan_tmp, scan_len, total;
+};
+
+GridWs grid_ws(int32_t n_inst, int64_t n)
+{
+  const int64_t n_seg = (int64_t)n_inst * kRows;
+  const int64_t bin_cap = tpc_grid_bin_capacity(n_inst, n);
+  GridWs w;
+  Carve c;
+  w.cseg = c.take(4 * n);
+  w.seg_cnt = c.take(4 * n_seg);
+  w.seg_mm = c.take(16 * n_seg);
+  w.inst_bad = c.take(4 * (int64_t)n_inst);
+  w.nb1 = c.take(4 * n_seg);
+  w.fill = c.take(4 * bin_cap);
+  const int64_t big = bin_cap > n_seg ? bin_cap : n_seg;
+  w.scan_len = big / kScanTile + 2;
+  w.scan_tmp = c.take(8 * w.scan_len);
+  w.total = c.off;
+  return w;
+}
+
+struct TrackWs {
+  tpc_track_ws_layout pub;
+  int64_t tl_own, tsv, counters, scan_len;
+};
+
+TrackWs track_ws(int32_t n_inst, int64_t n, int64_t cap)
+{
+  if (cap <= 0) cap = default_cap(n_inst, n);
+  TrackWs w;
+  Carve c;
+  w.pub.up = c.take(4 * n);
+  w.pub.dn = c.take(4 * n);
+  w.pub.up2 = c.take(4 * n);
+  w.pub.dn2 = c.take(4 * n);
+  w.pub.start = c.take(4 * cap);
+  w.pub.tl_par = c.take(4 * 5 * cap);
+  w.pub.tl_cov = c.take(4 * 15 * cap);
+  w.pub.tl_chi2 = c.take(4 * cap);
+  w.pub.tl_nhit = c.take(4 * cap);
+  w.pub.tl_rmin = c.take(4 * cap);
+  w.pub.tl_rmax = c.take(4 * cap);
+  w.pub.tl_status = c.take(4 * cap);
+  w.pub.tl_hit = c.take(4 * (int64_t)kRows * cap);
+  w.pub.owner = c.take(8 * n);
+  w.tl_own = c.take(4 * cap);
+  w.tsv = c.take(8 * cap);
+  w.counters = c.take(8 * 8);
+  const int64_t big = n > cap ? n : cap;
+  w.scan_len = big / kScanTile + 2;
+  w.pub.scratch = c.take(8 * w.scan_len);
+  w.pub.total = c.off;
+  w.pub.cap_tracklets = cap;
+  return w;
+}
+
+tpc_status check_common(const tpc_geometry* g, const tpc_params* p, int32_t n_inst,
+                        const int64_t* off_h, const int64_t* off_d, const tpc_clusters& in,
+                        int64_t* n_out)
+{
+  if (!g || !p || !off_h || !off_d || n_inst < 1) return TPC_ERR_INVALID;
+  if (g->n_rows != kRows) return TPC_ERR_INVALID;
+  for (int r = 0; r + 1 < kRows; r++)
+    if (!(g->row_x[r + 1] > g->row_x[r])) return TPC_ERR_INVALID;
+  if (!(g->sigma_y2 > 0) || !(g->sigma_z2 > 0) || !(g->tan_half_sector > 0)) return TPC_ERR_INVALID;
+  if (off_h[0] != 0) return TPC_ERR_INVALID;
+  for (int32_t i = 0; i < n_inst; i++) {
+    int64_t sz = off_h[i + 1] - off_h[i];
+    if (sz < 0 || sz >= kMaxInstClusters) return TPC_ERR_INVALID;
+  }
+  const int64_t n = off_h[n_inst];
+  if (n >= ((int64_t)1 << 31) - 1) return TPC_ERR_INVALID;
+  if (n > 0 && (!in.y || !in.z || !in.row)) return TPC_ERR_INVALID;
+  if (p->min_chain < 3 || p->tc_max_miss < 1 || p->min_track_hits < 1 ||
+      p->min_tracklet_hits < 0 || !(p->grid_occupancy > 0) || !(p->snp_max > 0) ||
+      !(p->snp_max < 1) || !(p->search_margin >= 0))
+    return TPC_ERR_INVALID;
+  *n_out = n;
+  return TPC_OK;
+}
+
+Consts make_consts(const tpc_geometry* g, const tpc_params* p)
+{
+  Consts k;
+  memcpy(k.row_x, g->row_x, sizeof(k.row_x));
+  k.tan_half = g->tan_half_sector;
+  // derived once in binary64 and rounded (the CPU reference does the same)
+  k.kB = (float)(-0.299792458e-2 * (double)g->bz_tesla);
+  k.vy = g->sigma_y2;
+  k.vz = g->sigma_z2;
+  k.ivy = (float)(1.0 / (1.5 * (double)g->sigma_y2));
+  k.ivz = (float)(1.0 / (1.5 * (double)g->sigma_z2));
+  k.nf_win_y = p->nf_win_y;
+  k.nf_win_z = p->nf_win_z;
+  k.nf_chi2_max = p->nf_chi2_max;
+  k.tc_chi2_pick = p->tc_chi2_pick;
+  k.snp_max = p->snp_max;
+  k.grid_occupancy = p->grid_occupancy;
+  k.edge_margin = p->edge_margin;
+  k.search_margin = p->search_margin;
+  k.y_valid_margin = p->y_valid_margin;
+  k.min_chain = p->min_chain;
+  k.tc_max_miss = p->tc_max_miss;
+  k.min_tracklet_hits = p->min_tracklet_hits;
+  k.min_track_hits = p->min_track_hits;
+  return k;
+}
+
+template <class T>
+T* at(void* base, int64_t off)
+{
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+}  // namespace
+
+extern "C" {
+
+void tpc_default_params(tpc_params* p)
+{
+  if (!p) return;
+  p->nf_win_y = 3.0f;
+  p->nf_win_z = 3.5f;
+  p->nf_chi2_max = 13.8f;
+  p->tc_chi2_pick = 13.8f;
+  p->snp_max = 0.99f;
+  p->grid_occupancy = 2.0f;
+  p->edge_margin = 1.0f;
+  p->search_margin = 0.01f;
+  p->y_valid_margin = 2.0f;
+  p->min_chain = 3;
+  p->tc_max_miss = 10;
+  p->min_tracklet_hits = 10;
+  p->min_track_hits = 10;
+  p->flags = 0;
+}
+
+const char* tpc_status_string(tpc_status s)
+{
+  switch (s) {
+    case TPC_OK: return "ok";
+    case TPC_ERR_INVALID: return "invalid argument";
+    case TPC_ERR_UNSUPPORTED: return "unsupported mode";
+    case TPC_ERR_HIP: return "HIP runtime error";
+    case TPC_ERR_WORKSPACE: return "workspace too small";
+  }
+  return "unknown status";
+}
+
+int64_t tpc_grid_bin_capacity(int32_t n_inst, int64_t n_clusters)
+{
+  // per row at most 3*floor(n/2) + 8 bins plus one sentinel (see k_grid_meta)
+  return 2 * n_clusters + 16 * (int64_t)kRows * (n_inst > 0 ? n_inst : 0) + 16;
+}
+
+size_t tpc_grid_workspace_bytes(int32_t n_inst, int64_t n_clusters)
+{
+  if (n_inst < 1 || n_clusters < 0) return 0;
+  return (size_t)grid_ws(n_inst, n_clusters).total;
+}
+
+size_t tpc_track_workspace_bytes(int32_t n_inst, int64_t n_clusters, int64_t cap_tracklets)
+{
+  if (n_inst < 1 || n_clusters < 0) return 0;
+  return (size_t)track_ws(n_inst, n_clusters, cap_tracklets).pub.total;
+}
+
+tpc_status tpc_track_workspace_layout(int32_t n_inst, int64_t n_clusters, int64_t cap_tracklets,
+                                      tpc_track_ws_layout* out)
+{
+  if (!out || n_inst < 1 || n_clusters < 0) return TPC_ERR_INVALID;
+  *out = track_ws(n_inst, n_clusters, cap_tracklets).pub;
+  return TPC_OK;
+}
+
+tpc_status tpc_grid_build(const tpc_geometry* geom, const tpc_params* params, int32_t n_inst,
+                          const int64_t* inst_off_host, const int64_t* inst_off_dev,
+                          tpc_clusters in, const tpc_grid* grid, tpc_result* result_dev,
+                          void* ws_dev, size_t ws_bytes, void* stream)
+{
+  int64_t n = 0;
+  tpc_status st = check_common(geom, params, n_inst, inst_off_host, inst_off_dev, in, &n);
+  if (st != TPC_OK) return st;
+  if (!grid || !result_dev || !ws_dev) return TPC_ERR_INVALID;
+  if (n > 0 && (!grid->sseg || !grid->perm || !grid->ys || !grid->zs)) return TPC_ERR_INVALID;
+  if (!grid->row_off || !grid->meta || !grid->bin_off || grid->bin_cap < 1) return TPC_ERR_INVALID;
+  const GridWs w = grid_ws(n_inst, n);
+  if ((int64_t)ws_bytes < w.total) return TPC_ERR_WORKSPACE;
+  GridBufs b;
+  b.x = in.x;
+  b.y = in.y;
+  b.z = in.z;
+  b.row = in.row;
+  b.inst_off = inst_off_dev;
+  b.n_inst = n_inst;
+  b.n = n;
+  b.sseg = grid->sseg;
+  b.row_off = grid->row_off;
+  b.meta = grid->meta;
+  b.bin_off = grid->bin_off;
+  b.perm = grid->perm;
+  b.ys = grid->ys;
+  b.zs = grid->zs;
+  b.bin_cap = grid->bin_cap;
+  b.res = result_dev;
+  b.cseg = at<int32_t>(ws_dev, w.cseg);
+  b.seg_cnt = at<int32_t>(ws_dev, w.seg_cnt);
+  b.seg_mm = at<uint32_t>(ws_dev, w.seg_mm);
+  b.inst_bad = at<int32_t>(ws_dev, w.inst_bad);
+  b.nb1 = at<int32_t>(ws_dev, w.nb1);
+  b.fill = at<int32_t>(ws_dev, w.fill);
+  b.scan_tmp = at<int64_t>(ws_dev, w.scan_tmp);
+  b.scan_tmp_len = w.scan_len;
+  const Consts k = make_consts(geom, params);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = (params->flags & TPC_FLAG_DETERMINISTIC) ? det::grid_build(k, b, s)
+                                                           : prod::grid_build(k, b, s);
+  return e == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+}
+
+tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, int32_t n_inst,
+                            const int64_t* inst_off_host, const int64_t* inst_off_dev,
+                            tpc_clusters in, const tpc_grid* grid, const tpc_tracks* out,
+                            tpc_result* result_dev, void* ws_dev, size_t ws_bytes,
+                            int64_t cap_tracklets, void* stream)
+{
+  int64_t n = 0;
+  tpc_status st = check_common(geom, params, n_inst, inst_off_host, inst_off_dev, in, &n);
+  if (st != TPC_OK) return st;
+  if (!grid || !out || !result_dev || !ws_dev) return TPC_ERR_INVALID;
+  if (n > 0 && (!grid->sseg || !grid->perm || !grid->ys || !grid->zs || !out->clu2trk))
+    return TPC_ERR_INVALID;
+  if (!grid->row_off || !grid->meta || !grid->bin_off) return TPC_ERR_INVALID;
+  if (out->cap_tracks < 0 || out->cap_hits < 0 || !out->hit_off) return TPC_ERR_INVALID;
+  if (out->cap_tracks > 0 && (!out->param || !out->cov || !out->chi2 || !out->ndf || !out->x_ref))
+    return TPC_ERR_INVALID;
+  if (out->cap_hits > 0 && !out->hit_clu) return TPC_ERR_INVALID;
+  if (out->cap_tracks >= ((int64_t)1 << 31) || out->cap_hits >= ((int64_t)1 << 31))
+    return TPC_ERR_INVALID;
+  const TrackWs w = track_ws(n_inst, n, cap_tracklets);
+  if ((int64_t)ws_bytes < w.pub.total) return TPC_ERR_WORKSPACE;
+  TrackBufs b;
+  b.inst_off = inst_off_dev;
+  b.n_inst = n_inst;
+  b.n = n;
+  b.sseg = grid->sseg;
+  b.row_off = grid->row_off;
+  b.meta = grid->meta;
+  b.bin_off = grid->bin_off;
+  b.perm = grid->perm;
+  b.ys = grid->ys;
+  b.zs = grid->zs;
+  b.up = at<int32_t>(ws_dev, w.pub.up);
+  b.dn = at<int32_t>(ws_dev, w.pub.dn);
+  b.up2 = at<int32_t>(ws_dev, w.pub.up2);
+  b.dn2 = at<int32_t>(ws_dev, w.pub.dn2);
+  b.start = at<int32_t>(ws_dev, w.pub.start);
+  b.cap = w.pub.cap_tracklets;
+  b.tl_par = at<float>(ws_dev, w.pub.tl_par);
+  b.tl_cov = at<float>(ws_dev, w.pub.tl_cov);
+  b.tl_chi2 = at<float>(ws_dev, w.pub.tl_chi2);
+  b.tl_nhit = at<int32_t>(ws_dev, w.pub.tl_nhit);
+  b.tl_rmin = at<int32_t>(ws_dev, w.pub.tl_rmin);
+  b.tl_rmax = at<int32_t>(ws_dev, w.pub.tl_rmax);
+  b.tl_status = at<int32_t>(ws_dev, w.pub.tl_status);
+  b.tl_hit = at<int32_t>(ws_dev, w.pub.tl_hit);
+  b.owner = at<unsigned long long>(ws_dev, w.pub.owner);
+  b.tl_own = at<int32_t>(ws_dev, w.tl_own);
+  b.tsv = at<int64_t>(ws_dev, w.tsv);
+  b.counters = at<int64_t>(ws_dev, w.counters);
+  b.scan_tmp = at<int64_t>(ws_dev, w.pub.scratch);
+  b.scan_tmp_len = w.scan_len;
+  b.out = *out;
+  b.res = result_dev;
+  const Consts k = make_consts(geom, params);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = (params->flags & TPC_FLAG_DETERMINISTIC) ? det::sector_track(k, b, s)
+                                                           : prod::sector_track(k, b, s);
+  return e == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal interface between the C-ABI host code (tpc_api.cpp) and the two
+// builds of the kernels (tpc_kernels.hip compiled into namespaces det and
+// prod with different floating-point flags).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tpcca.h"
+
+namespace tpcca {
+
+constexpr int kRows = TPC_N_ROWS;
+constexpr int kBlock = 256;
+
+// Constants every kernel may need, passed by value in the kernel arguments.
+struct Consts {
+  float row_x[kRows];
+  float tan_half;
+  float kB;            // curvature per unit q/pT: (float)(-0.299792458e-2 * B)
+  float vy, vz;        // cluster variances
+  float ivy, ivz;      // (float)(1 / (1.5 * variance)) of the neighbour score
+  float nf_win_y, nf_win_z, nf_chi2_max;
+  float tc_chi2_pick, snp_max;
+  float grid_occupancy, edge_margin, search_margin, y_valid_margin;
+  int32_t min_chain, tc_max_miss, min_tracklet_hits, min_track_hits;
+};
+
+// Device buffers of one call.
+struct GridBufs {
+  const float *x, *y, *z;
+  const uint16_t* row;
+  const int64_t* inst_off;
+  int32_t n_inst;
+  int64_t n;
+  // outputs
+  int32_t* sseg;
+  int32_t* row_off;
+  tpc_row_meta* meta;
+  int32_t* bin_off;
+  int32_t* perm;
+  float *ys, *zs;
+  int64_t bin_cap;
+  tpc_result* res;
+  // workspace
+  int32_t* cseg;       // [n] segment of each input cluster, -1 invalid
+  int32_t* seg_cnt;    // [n_seg]
+  uint32_t* seg_mm;    // [4][n_seg] ordered-float min y, max y, min z, max z
+  int32_t* inst_bad;   // [n_inst]
+  int32_t* nb1;        // [n_seg] bins + 1 per segment, then their exclusive scan
+  int32_t* fill;       // [bin_cap]
+  int64_t* scan_tmp;   // scan partials
+  int64_t scan_tmp_len;
+};
+
+struct TrackBufs {
+  const int64_t* inst_off;
+  int32_t n_inst;
+  int64_t n;
+  // grid (inputs)
+  const int32_t* sseg;
+  const int32_t* row_off;
+  const tpc_row_meta* meta;
+  const int32_t* bin_off;
+  const int32_t* perm;
+  const float *ys, *zs;
+  // workspace
+  int32_t *up, *dn, *up2, *dn2;
+  int32_t* start;
+  int64_t cap;         // tracklet capacity
+  float* tl_par;       // [5][cap]
+  float* tl_cov;       // [15][cap]
+  float* tl_chi2;
+  int32_t *tl_nhit, *tl_rmin, *tl_rmax, *tl_status;
+  int32_t* tl_hit;     // [152][cap]
+  unsigned long long* owner;  // [n]
+  int32_t* tl_own;     // [cap] owned hits of accepted tracklets, 0 otherwise
+  int64_t* tsv;        // [cap] packed (track flag << 32 | owned hits), then its scan
+  int64_t* scan_tmp;
+  int64_t scan_tmp_len;
+  int64_t* counters;   // [8] device counters
+  // outputs
+  tpc_tracks out;
+  tpc_result* res;
+};
+
+// Scan partials needed for an array of n items.
+int64_t scan_partials(int64_t n);
+
+#define TPCCA_DECLARE_LAUNCHERS(NS)                                                  \
+  namespace NS {                                                                     \
+  hipError_t grid_build(const Consts& k, const GridBufs& b, hipStream_t s);         \
+  hipError_t sector_track(const Consts& k, const TrackBufs& b, hipStream_t s);      \
+  }
+
+TPCCA_DECLARE_LAUNCHERS(det)
+TPCCA_DECLARE_LAUNCHERS(prod)
+
+}  // namespace tpcca

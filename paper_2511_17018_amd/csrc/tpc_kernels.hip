@@ -1,0 +1,1071 @@
+// HIP kernels of the sector tracker for gfx950 (CDNA4, wave64).
+//
+// This file is compiled twice: into namespace tpcca::det with
+// -ffp-contract=off and correctly rounded division / square root (the
+// deterministic mode's compile-time part, Sec. 2 of the paper), and into
+// tpcca::prod with contraction and fast reciprocal allowed (production mode).
+// TPC_DET selects the run-time part: ordering kernels (per-bin sort after the
+// atomic scatter, scan-ordered compaction) instead of atomic append.
+//
+// Every floating-point expression on the deterministic path is written in the
+// operand order of the algorithm readings (R7-R11, R13-R20) so that, with
+// contraction off, each operation rounds exactly as in the CPU reference.
+#include "tpc_internal.h"
+
+#ifndef TPC_NS
+#error "TPC_NS must name the build (det or prod)"
+#endif
+#ifndef TPC_DET
+#error "TPC_DET must be 0 or 1"
+#endif
+
+namespace tpcca {
+namespace TPC_NS {
+
+namespace {
+
+constexpr int kItems = 8;                       // items per thread in scans
+constexpr int kTile = kBlock * kItems;          // items per block in scans
+constexpr int kStatItems = 1024;                // clusters per block in the row statistics
+// 1/6, 3/40 and 3/20 rounded to binary32
+constexpr float kSixth = 0x1.555556p-3f;
+constexpr float k3_40 = 0x1.333334p-4f;
+constexpr float k3_20 = 0x1.333334p-3f;
+
+enum { CNT_START = 0, CNT_TRACKS = 1 };
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+
+__device__ __forceinline__ int find_inst(const int64_t* off, int n_inst, int64_t c)
+{
+  int lo = 0, hi = n_inst;  // off[lo] <= c < off[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= c) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// order-preserving map of binary32 to uint32 (for atomic min / max)
+__device__ __forceinline__ uint32_t f2o(float f)
+{
+  uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float o2f(uint32_t o)
+{
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
+
+// R10: bin coordinate (monotone in q)
+__device__ __forceinline__ int bin_coord(float q, float q0, float iw, int n)
+{
+  float f = (q - q0) * iw;
+  if (!(f > 0.0f)) return 0;
+  if (f >= (float)(n - 1)) return n - 1;
+  return (int)f;
+}
+
+__device__ __forceinline__ int axis_bins(float d, float w)
+{
+  float t = ceilf(d / w);
+  if (t < 1.0f) return 1;
+  if (t > 65535.0f) return 65535;
+  return (int)t;
+}
+
+__device__ __forceinline__ int64_t shfl_up64(int64_t v, int d)
+{
+  int lo = __shfl_up((int)(uint32_t)v, d, 64);
+  int hi = __shfl_up((int)(v >> 32), d, 64);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* total)
+{
+  __shared__ int64_t s_w[kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int64_t y = shfl_up64(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_w[wid] = x;
+  __syncthreads();
+  int64_t wofs = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; w++) {
+    if (w < wid) wofs += s_w[w];
+    tot += s_w[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return x - v + wofs;
+}
+
+// ------------------------------------------------------------------ scans
+// Exclusive in-place scan of data[0, n) with n = min(n_max, *n_dev): tile
+// sums, one-block scan of the tile sums (total to *total_out), apply.
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const T* data, int64_t n_max,
+                                                        const int64_t* n_dev, int64_t* part)
+{
+  int64_t n = n_dev ? min(n_max, *n_dev) : n_max;
+  int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; k++)
+    if (base + k < n) s += (int64_t)data[base + k];
+  int64_t tot;
+  block_exclusive_scan(s, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_partials(int64_t* part, int64_t nb, int64_t* total_out)
+{
+  __shared__ int64_t s_w[16];
+  __shared__ int64_t s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
+    int64_t i = b0 + threadIdx.x;
+    int64_t v = i < nb ? part[i] : 0;
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int64_t y = shfl_up64(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[wid] = x;
+    __syncthreads();
+    int64_t wofs = 0, tot = 0;
+    for (int w = 0; w < 16; w++) {
+      if (w < wid) wofs += s_w[w];
+      tot += s_w[w];
+    }
+    int64_t carry = s_carry;
+    if (i < nb) part[i] = carry + x - v + wofs;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry = carry + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = s_carry;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_scan_apply(T* data, int64_t n_max, const int64_t* n_dev,
+                                                       const int64_t* part)
+{
+  int64_t n = n_dev ? min(n_max, *n_dev) : n_max;
+  if ((int64_t)blockIdx.x * kTile >= n) return;
+  int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+  T v[kItems];
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; k++) {
+    v[k] = base + k < n ? data[base + k] : T(0);
+    s += (int64_t)v[k];
+  }
+  int64_t tot;
+  int64_t ex = block_exclusive_scan(s, &tot) + part[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kItems; k++) {
+    if (base + k < n) data[base + k] = (T)ex;
+    ex += (int64_t)v[k];
+  }
+}
+
+template <class T>
+void scan_exclusive(T* data, int64_t n_max, const int64_t* n_dev, int64_t* total_out,
+                    int64_t* part, hipStream_t s)
+{
+  int64_t nb = (n_max + kTile - 1) / kTile;
+  if (nb == 0) nb = 1;
+  k_scan_reduce<T><<<dim3((unsigned)nb), kBlock, 0, s>>>(data, n_max, n_dev, part);
+  k_scan_partials<<<1, 1024, 0, s>>>(part, nb, total_out);
+  k_scan_apply<T><<<dim3((unsigned)nb), kBlock, 0, s>>>(data, n_max, n_dev, part);
+}
+
+unsigned blocks_for(int64_t n, int per = kBlock)
+{
+  int64_t b = (n + per - 1) / per;
+  return (unsigned)(b > 0 ? b : 1);
+}
+
+// ------------------------------------------------------------------ a1 grid
+
+__global__ void k_grid_clear(GridBufs b)
+{
+  const int64_t n_seg = (int64_t)b.n_inst * kRows;
+  for (int64_t s = gtid(); s < n_seg; s += (int64_t)gridDim.x * blockDim.x) {
+    b.seg_cnt[s] = 0;
+    b.seg_mm[s] = 0xFFFFFFFFu;
+    b.seg_mm[n_seg + s] = 0u;
+    b.seg_mm[2 * n_seg + s] = 0xFFFFFFFFu;
+    b.seg_mm[3 * n_seg + s] = 0u;
+    if (s < b.n_inst) b.inst_bad[s] = 0;
+  }
+  if (gtid() == 0) {
+    b.res->n_valid = 0;
+    b.res->n_bad = 0;
+    b.res->n_bins = 0;
+    b.res->overflow = 0;
+  }
+}
+
+// Row statistics: count and data box per (instance,row), validity of each
+// cluster.  Blocks aggregate in LDS for the instance of their first cluster.
+__global__ __launch_bounds__(kBlock) void k_grid_stats(Consts k, GridBufs b)
+{
+  __shared__ int s_cnt[kRows];
+  __shared__ uint32_t s_mm[4][kRows];
+  __shared__ int s_bad;
+  __shared__ int s_inst;
+  const int64_t n_seg = (int64_t)b.n_inst * kRows;
+  const int64_t c0 = (int64_t)blockIdx.x * kStatItems;
+  for (int r = threadIdx.x; r < kRows; r += blockDim.x) {
+    s_cnt[r] = 0;
+    s_mm[0][r] = 0xFFFFFFFFu;
+    s_mm[1][r] = 0u;
+    s_mm[2][r] = 0xFFFFFFFFu;
+    s_mm[3][r] = 0u;
+  }
+  if (threadIdx.x == 0) {
+    s_bad = 0;
+    s_inst = find_inst(b.inst_off, b.n_inst, c0);
+  }
+  __syncthreads();
+  const int i0 = s_inst;
+  const int64_t end0 = b.inst_off[i0 + 1];
+  for (int j = threadIdx.x; j < kStatItems; j += blockDim.x) {
+    int64_t c = c0 + j;
+    if (c >= b.n) break;
+    int i = c < end0 ? i0 : find_inst(b.inst_off, b.n_inst, c);
+    int row = b.row[c];
+    float y = b.y[c], z = b.z[c];
+    bool ok = row < kRows;
+    if (ok) {
+      float lim = k.row_x[row] * k.tan_half + k.y_valid_margin;
+      ok = fabsf(y) <= lim && fabsf(z) <= 1.0e5f;
+    }
+    if (!ok) {
+      b.cseg[c] = -1;
+      if (i == i0) atomicAdd(&s_bad, 1);
+      else atomicAdd(&b.inst_bad[i], 1);
+      continue;
+    }
+    int64_t seg = (int64_t)i * kRows + row;
+    b.cseg[c] = (int32_t)seg;
+    uint32_t oy = f2o(y), oz = f2o(z);
+    if (i == i0) {
+      atomicAdd(&s_cnt[row], 1);
+      atomicMin(&s_mm[0][row], oy);
+      atomicMax(&s_mm[1][row], oy);
+      atomicMin(&s_mm[2][row], oz);
+      atomicMax(&s_mm[3][row], oz);
+    } else {
+      atomicAdd(&b.seg_cnt[seg], 1);
+      atomicMin(&b.seg_mm[seg], oy);
+      atomicMax(&b.seg_mm[n_seg + seg], oy);
+      atomicMin(&b.seg_mm[2 * n_seg + seg], oz);
+      atomicMax(&b.seg_mm[3 * n_seg + seg], oz);
+    }
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < kRows; r += blockDim.x) {
+    if (s_cnt[r] == 0) continue;
+    int64_t seg = (int64_t)i0 * kRows + r;
+    atomicAdd(&b.seg_cnt[seg], s_cnt[r]);
+    atomicMin(&b.seg_mm[seg], s_mm[0][r]);
+    atomicMax(&b.seg_mm[n_seg + seg], s_mm[1][r]);
+    atomicMin(&b.seg_mm[2 * n_seg + seg], s_mm[2][r]);
+    atomicMax(&b.seg_mm[3 * n_seg + seg], s_mm[3][r]);
+  }
+  if (threadIdx.x == 0 && s_bad) atomicAdd(&b.inst_bad[i0], s_bad);
+}
+
+// Grid dimensions of each (instance,row) from its data box (R10).
+__global__ void k_grid_meta(Consts k, GridBufs b)
+{
+  const int64_t n_seg = (int64_t)b.n_inst * kRows;
+  const int64_t s = gtid();
+  if (s >= n_seg) return;
+  int cnt = b.seg_cnt[s];
+  int ny = 1, nz = 1;
+  float y0 = 0.0f, z0 = 0.0f, iwy = 0.0f, iwz = 0.0f;
+  if (cnt > 0) {
+    // + 0.0f turns a -0 extreme into +0 (one canonical zero)
+    float ymin = o2f(b.seg_mm[s]) + 0.0f, ymax = o2f(b.seg_mm[n_seg + s]) + 0.0f;
+    float zmin = o2f(b.seg_mm[2 * n_seg + s]) + 0.0f, zmax = o2f(b.seg_mm[3 * n_seg + s]) + 0.0f;
+    float dy = ymax - ymin, dz = zmax - zmin;
+    float nb = floorf((float)cnt / k.grid_occupancy);
+    if (nb < 1.0f) nb = 1.0f;
+    float w = sqrtf((dy * dz) / nb);
+    if (w < 1.0f) w = 1.0f;
+    float m = (dy > dz ? dy : dz) / nb;
+    if (w < m) w = m;
+    ny = axis_bins(dy, w);
+    nz = axis_bins(dz, w);
+    iwy = dy > 0.0f ? (float)ny / dy : 0.0f;
+    iwz = dz > 0.0f ? (float)nz / dz : 0.0f;
+    y0 = ymin;
+    z0 = zmin;
+    atomicAdd((unsigned long long*)&b.res->n_valid, (unsigned long long)cnt);
+  }
+  tpc_row_meta mt;
+  mt.ny = ny;
+  mt.nz = nz;
+  mt.bin_base = 0;
+  mt.count = cnt;
+  mt.y0 = y0;
+  mt.z0 = z0;
+  mt.iwy = iwy;
+  mt.iwz = iwz;
+  b.meta[s] = mt;
+  b.nb1[s] = ny * nz + 1;
+  if (s < b.n_inst)
+    atomicAdd((unsigned long long*)&b.res->n_bad, (unsigned long long)b.inst_bad[s]);
+}
+
+__global__ void k_grid_zero(GridBufs b)
+{
+  int64_t tot = b.res->n_bins;
+  if (tot > b.bin_cap) {
+    if (gtid() == 0) b.res->overflow |= 1;
+    return;
+  }
+  for (int64_t j = gtid(); j < tot; j += (int64_t)gridDim.x * blockDim.x) {
+    b.bin_off[j] = 0;
+    b.fill[j] = 0;
+  }
+}
+
+__global__ void k_grid_meta2(GridBufs b)
+{
+  if (b.res->overflow & 1) return;
+  const int64_t n_seg = (int64_t)b.n_inst * kRows;
+  const int64_t s = gtid();
+  if (s >= n_seg) return;
+  int base = b.nb1[s];
+  b.meta[s].bin_base = base;
+  if (s % kRows == kRows - 1) {
+    // the last sentinel of an instance counts its padding positions
+    const tpc_row_meta m = b.meta[s];
+    b.bin_off[base + m.ny * m.nz] = b.inst_bad[s / kRows];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_grid_hist(GridBufs b)
+{
+  if (b.res->overflow & 1) return;
+  const int64_t c = gtid();
+  if (c >= b.n) return;
+  int seg = b.cseg[c];
+  if (seg < 0) return;
+  const tpc_row_meta m = b.meta[seg];
+  int iy = bin_coord(b.y[c], m.y0, m.iwy, m.ny);
+  int iz = bin_coord(b.z[c], m.z0, m.iwz, m.nz);
+  atomicAdd(&b.bin_off[m.bin_base + iz * m.ny + iy], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_grid_scatter(GridBufs b)
+{
+  if (b.res->overflow & 1) return;
+  const int64_t c = gtid();
+  if (c >= b.n) return;
+  int seg = b.cseg[c];
+  if (seg < 0) return;
+  const tpc_row_meta m = b.meta[seg];
+  float y = b.y[c], z = b.z[c];
+  int iy = bin_coord(y, m.y0, m.iwy, m.ny);
+  int iz = bin_coord(z, m.z0, m.iwz, m.nz);
+  int j = m.bin_base + iz * m.ny + iy;
+  int pos = b.bin_off[j] + atomicAdd(&b.fill[j], 1);
+  b.sseg[pos] = seg;
+  b.perm[pos] = (int32_t)c;
+  b.ys[pos] = y;
+  b.zs[pos] = z;
+}
+
+__global__ void k_grid_rowoff(GridBufs b)
+{
+  if (b.res->overflow & 1) return;
+  const int64_t n_seg = (int64_t)b.n_inst * kRows;
+  const int64_t s = gtid();
+  if (s >= n_seg) return;
+  const int64_t i = s / kRows;
+  const int r = (int)(s % kRows);
+  const tpc_row_meta m = b.meta[s];
+  b.row_off[i * (kRows + 1) + r] = b.bin_off[m.bin_base];
+  if (r == kRows - 1) {
+    int end = b.bin_off[m.bin_base + m.ny * m.nz];
+    b.row_off[i * (kRows + 1) + kRows] = end;
+    for (int64_t p = end; p < b.inst_off[i + 1]; p++) {
+      b.sseg[p] = -1;
+      b.perm[p] = -1;
+      b.ys[p] = 0.0f;
+      b.zs[p] = 0.0f;
+    }
+  }
+}
+
+// Deterministic mode: order each bin by input index (the atomic scatter
+// leaves it in arrival order) -- an ordering kernel after a kernel whose
+// output order depends on concurrency (Sec. 2, run-time part).
+__global__ __launch_bounds__(kBlock) void k_grid_binsort(GridBufs b)
+{
+  if (b.res->overflow & 1) return;
+  const int64_t tot = b.res->n_bins;
+  const int64_t j = gtid();
+  if (j >= tot) return;
+  int a = b.bin_off[j];
+  int e = j + 1 < tot ? b.bin_off[j + 1] : (int)b.n;
+  if (e - a < 2) return;
+  for (int p = a + 1; p < e; p++) {
+    int kp = b.perm[p];
+    float ky = b.ys[p], kz = b.zs[p];
+    int q = p - 1;
+    while (q >= a && b.perm[q] > kp) {
+      b.perm[q + 1] = b.perm[q];
+      b.ys[q + 1] = b.ys[q];
+      b.zs[q + 1] = b.zs[q];
+      q--;
+    }
+    b.perm[q + 1] = kp;
+    b.ys[q + 1] = ky;
+    b.zs[q + 1] = kz;
+  }
+}
+
+// ------------------------------------------------------------------ a2..a4
+
+__global__ void k_track_init(TrackBufs b)
+{
+  if (gtid() == 0) {
+    b.res->n_start = 0;
+    b.res->n_tracklets_kept = 0;
+    b.res->n_tracks = 0;
+    b.res->n_hits = 0;
+    b.res->need_tracklets = 0;
+    b.res->need_tracks = 0;
+    b.res->need_hits = 0;
+    b.res->overflow &= 1;
+    for (int i = 0; i < 8; i++) b.counters[i] = 0;
+    if (b.out.hit_off) b.out.hit_off[0] = 0;
+  }
+}
+
+// NeighboursFinder (R11): best (u on r+1, d on r-1) straight-line pair.
+__global__ __launch_bounds__(kBlock) void k_neighbours(Consts k, TrackBufs b)
+{
+  const int64_t h = gtid();
+  if (h >= b.n) return;
+  int32_t bu = -1, bd = -1;
+  const int seg = b.sseg[h];
+  const int r = seg >= 0 ? seg % kRows : 0;
+  if (seg >= 0 && r > 0 && r < kRows - 1) {
+    const float yh = b.ys[h], zh = b.zs[h];
+    const float wy = k.nf_win_y, wz = k.nf_win_z;
+    const float wym = wy + k.search_margin, wzm = wz + k.search_margin;
+    const float cmax = k.nf_chi2_max, ivy = k.ivy, ivz = k.ivz;
+    const float xm = k.row_x[r - 1], x0 = k.row_x[r], xp = k.row_x[r + 1];
+    const float t = (x0 - xm) / (xp - xm);
+    const tpc_row_meta mu = b.meta[seg + 1];
+    const tpc_row_meta md = b.meta[seg - 1];
+    const int uylo = bin_coord(yh - wym, mu.y0, mu.iwy, mu.ny);
+    const int uyhi = bin_coord(yh + wym, mu.y0, mu.iwy, mu.ny);
+    const int uzlo = bin_coord(zh - wzm, mu.z0, mu.iwz, mu.nz);
+    const int uzhi = bin_coord(zh + wzm, mu.z0, mu.iwz, mu.nz);
+    const int dylo = bin_coord(yh - wym, md.y0, md.iwy, md.ny);
+    const int dyhi = bin_coord(yh + wym, md.y0, md.iwy, md.ny);
+    const int dzlo = bin_coord(zh - wzm, md.z0, md.iwz, md.nz);
+    const int dzhi = bin_coord(zh + wzm, md.z0, md.iwz, md.nz);
+    float bs = 0.0f;
+    int32_t bpu = 0, bpd = 0;
+    for (int izu = uzlo; izu <= uzhi; izu++) {
+      const int ub = mu.bin_base + izu * mu.ny;
+      const int ue = b.bin_off[ub + uyhi + 1];
+      for (int u = b.bin_off[ub + uylo]; u < ue; u++) {
+        const float yu = b.ys[u], zu = b.zs[u];
+        if (!(fabsf(yu - yh) <= wy && fabsf(zu - zh) <= wz)) continue;
+        for (int izd = dzlo; izd <= dzhi; izd++) {
+          const int db = md.bin_base + izd * md.ny;
+          const int de = b.bin_off[db + dyhi + 1];
+          for (int d = b.bin_off[db + dylo]; d < de; d++) {
+            const float yd = b.ys[d], zd = b.zs[d];
+            if (!(fabsf(yd - yh) <= wy && fabsf(zd - zh) <= wz)) continue;
+            const float ey = yh - (yd + (yu - yd) * t);
+            const float ez = zh - (zd + (zu - zd) * t);
+            const float sc = (ey * ey) * ivy + (ez * ez) * ivz;
+            if (!(sc <= cmax)) continue;
+            bool take = bu < 0 || sc < bs;
+            int32_t pu = 0, pd = 0;
+            if (!take && sc == bs) {
+              pu = b.perm[u];
+              pd = b.perm[d];
+              take = pu < bpu || (pu == bpu && pd < bpd);
+            }
+            if (take) {
+              if (bu < 0 || sc < bs) {
+                pu = b.perm[u];
+                pd = b.perm[d];
+              }
+              bu = u;
+              bd = d;
+              bs = sc;
+              bpu = pu;
+              bpd = pd;
+            }
+          }
+        }
+      }
+    }
+  }
+  b.up[h] = bu;
+  b.dn[h] = bd;
+}
+
+// NeighboursCleaner: mutual links only (reads the uncleaned arrays).
+__global__ __launch_bounds__(kBlock) void k_clean(TrackBufs b)
+{
+  const int64_t h = gtid();
+  if (h >= b.n) return;
+  int32_t u = b.up[h], d = b.dn[h];
+  b.up2[h] = (u >= 0 && b.dn[u] == (int32_t)h) ? u : -1;
+  b.dn2[h] = (d >= 0 && b.up[d] == (int32_t)h) ? d : -1;
+}
+
+__device__ __forceinline__ bool is_start(const TrackBufs& b, int min_chain, int64_t h)
+{
+  if (h >= b.n) return false;
+  if (b.dn2[h] != -1) return false;
+  int32_t q = b.up2[h];
+  if (q < 0) return false;
+  int len = 2;
+  while (len < min_chain) {
+    q = b.up2[q];
+    if (q < 0) return false;
+    len++;
+  }
+  return true;
+}
+
+// StartHitsFinder, deterministic: tile counts, scan, ordered write.
+__global__ __launch_bounds__(kBlock) void k_start_count(Consts k, TrackBufs b, int64_t* part)
+{
+  int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+  int64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; j++) s += is_start(b, k.min_chain, base + j) ? 1 : 0;
+  int64_t tot;
+  block_exclusive_scan(s, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_start_write(Consts k, TrackBufs b, const int64_t* part)
+{
+  int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+  bool f[kItems];
+  int64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; j++) {
+    f[j] = is_start(b, k.min_chain, base + j);
+    s += f[j] ? 1 : 0;
+  }
+  int64_t tot;
+  int64_t o = block_exclusive_scan(s, &tot) + part[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < kItems; j++) {
+    if (f[j]) {
+      if (o < b.cap) b.start[o] = (int32_t)(base + j);
+      o++;
+    }
+  }
+}
+
+// StartHitsFinder, production: wave ballot + one atomic per wave.
+__global__ __launch_bounds__(kBlock) void k_start_atomic(Consts k, TrackBufs b)
+{
+  const int64_t h = gtid();
+  bool f = is_start(b, k.min_chain, h);
+  unsigned long long m = __ballot(f);
+  const int lane = threadIdx.x & 63;
+  int64_t base = 0;
+  if (lane == 0 && m)
+    base = (int64_t)atomicAdd((unsigned long long*)&b.counters[CNT_START], (unsigned long long)__popcll(m));
+  base = __shfl(base, 0, 64);
+  if (f) {
+    int64_t o = base + __popcll(m & ((1ull << lane) - 1ull));
+    if (o < b.cap) b.start[o] = (int32_t)h;
+  }
+}
+
+__global__ void k_start_finish(TrackBufs b)
+{
+  int64_t S = b.counters[CNT_START];
+  b.res->n_start = S;
+  b.res->need_tracklets = S;
+  if (S > b.cap) b.res->overflow |= 2;
+}
+
+// ------------------------------------------------------------------ a5 tracklets
+
+struct KSt {
+  float p[5];
+  float c[15];
+};
+
+__device__ __forceinline__ constexpr int ci(int i, int j)
+{
+  return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+}
+
+// R7 + R8 (see the design notes for the exact operation order).
+__device__ __forceinline__ bool kprop(KSt& s, float x1, float x2, float kB, float smax)
+{
+  const float one = 1.0f;
+  const float dx = x2 - x1;
+  const float snp = s.p[2], tgl = s.p[3], qpt = s.p[4];
+  const float cc = kB * qpt;
+  const float s2 = snp + cc * dx;
+  if (!(fabsf(s2) < smax)) return false;
+  const float c1 = sqrtf((one - snp) * (one + snp));
+  const float c2 = sqrtf((one - s2) * (one + s2));
+  const float f = (snp + s2) / (c1 + c2);
+  const float dy = dx * f;
+  const float L = sqrtf(dx * dx + dy * dy);
+  const float lc = L * cc;
+  const float u2 = (lc * lc) * 0.25f;
+  const float g = one + u2 * (kSixth + u2 * k3_40);
+  const float sg = dx < 0.0f ? -one : one;
+  const float ds = (sg * L) * g;
+  const float h = (one + f * f) * 0.5f;
+  const float ic1 = one / c1, ic2 = one / c2;
+  const float dfs = h * (ic1 + ic2);
+  const float dfq = (h * (dx * ic2)) * kB;
+  const float dg = kSixth + u2 * k3_20;
+  const float dyl = dy / L;
+  const float hlc = 0.5f * lc;
+  const float Lg = L * dg;
+  const float a = dx * dfs;
+  const float dLs = dyl * a;
+  const float du2s = hlc * (dLs * cc);
+  const float d = tgl * (sg * (dLs * g + Lg * du2s));
+  const float bq = dx * dfq;
+  const float dLq = dyl * bq;
+  const float du2q = hlc * (dLq * cc + L * kB);
+  const float gq = tgl * (sg * (dLq * g + Lg * du2q));
+  const float e = ds;
+  const float hq = kB * dx;
+  s.p[0] = s.p[0] + dy;
+  s.p[1] = s.p[1] + tgl * ds;
+  s.p[2] = s2;
+  float B0[5], B1[5], B2[5];
+#pragma unroll
+  for (int j = 0; j < 5; j++) {
+    B0[j] = (s.c[ci(0, j)] + a * s.c[ci(2, j)]) + bq * s.c[ci(4, j)];
+    B1[j] = ((s.c[ci(1, j)] + d * s.c[ci(2, j)]) + e * s.c[ci(3, j)]) + gq * s.c[ci(4, j)];
+    B2[j] = s.c[ci(2, j)] + hq * s.c[ci(4, j)];
+  }
+  const float n30 = (s.c[ci(3, 0)] + a * s.c[ci(3, 2)]) + bq * s.c[ci(3, 4)];
+  const float n31 = ((s.c[ci(3, 1)] + d * s.c[ci(3, 2)]) + e * s.c[ci(3, 3)]) + gq * s.c[ci(3, 4)];
+  const float n32 = s.c[ci(3, 2)] + hq * s.c[ci(3, 4)];
+  const float n40 = (s.c[ci(4, 0)] + a * s.c[ci(4, 2)]) + bq * s.c[ci(4, 4)];
+  const float n41 = ((s.c[ci(4, 1)] + d * s.c[ci(4, 2)]) + e * s.c[ci(4, 3)]) + gq * s.c[ci(4, 4)];
+  const float n42 = s.c[ci(4, 2)] + hq * s.c[ci(4, 4)];
+  s.c[0] = (B0[0] + a * B0[2]) + bq * B0[4];
+  s.c[1] = (B1[0] + a * B1[2]) + bq * B1[4];
+  s.c[2] = ((B1[1] + d * B1[2]) + e * B1[3]) + gq * B1[4];
+  s.c[3] = (B2[0] + a * B2[2]) + bq * B2[4];
+  s.c[4] = ((B2[1] + d * B2[2]) + e * B2[3]) + gq * B2[4];
+  s.c[5] = B2[2] + hq * B2[4];
+  s.c[6] = n30;
+  s.c[7] = n31;
+  s.c[8] = n32;
+  s.c[10] = n40;
+  s.c[11] = n41;
+  s.c[12] = n42;
+  return true;
+}
+
+struct Innov {
+  float S00, S11, si00, si01, si11;
+};
+
+__device__ __forceinline__ Innov innov(const KSt& s, float vy, float vz)
+{
+  Innov q;
+  const float S00 = s.c[0] + vy, S01 = s.c[1], S11 = s.c[2] + vz;
+  const float det = S00 * S11 - S01 * S01;
+  q.S00 = S00;
+  q.S11 = S11;
+  q.si00 = S11 / det;
+  q.si01 = -(S01 / det);
+  q.si11 = S00 / det;
+  return q;
+}
+
+__device__ __forceinline__ float chi2_of(const Innov& q, float r0, float r1)
+{
+  return r0 * (q.si00 * r0 + q.si01 * r1) + r1 * (q.si01 * r0 + q.si11 * r1);
+}
+
+// R9
+__device__ __forceinline__ float kupdate(KSt& s, float my, float mz, float vy, float vz)
+{
+  const Innov q = innov(s, vy, vz);
+  const float r0 = my - s.p[0], r1 = mz - s.p[1];
+  const float chi2 = chi2_of(q, r0, r1);
+  float k0[5], k1[5], hc0[5], hc1[5];
+#pragma unroll
+  for (int i = 0; i < 5; i++) {
+    k0[i] = s.c[ci(i, 0)] * q.si00 + s.c[ci(i, 1)] * q.si01;
+    k1[i] = s.c[ci(i, 0)] * q.si01 + s.c[ci(i, 1)] * q.si11;
+    hc0[i] = s.c[ci(0, i)];
+    hc1[i] = s.c[ci(1, i)];
+  }
+#pragma unroll
+  for (int i = 0; i < 5; i++) s.p[i] = s.p[i] + (k0[i] * r0 + k1[i] * r1);
+#pragma unroll
+  for (int i = 0; i < 5; i++)
+#pragma unroll
+    for (int j = 0; j <= i; j++)
+      s.c[ci(i, j)] = s.c[ci(i, j)] - (k0[i] * hc0[j] + k1[i] * hc1[j]);
+  return chi2;
+}
+
+// R15: best cluster of row segment `seg` for the predicted state
+__device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b, int seg,
+                                           const KSt& st, const Innov& q)
+{
+  const float y = st.p[0], z = st.p[1];
+  const float pick = k.tc_chi2_pick;
+  const float wy = sqrtf(pick * q.S00) + k.search_margin;
+  const float wz = sqrtf(pick * q.S11) + k.search_margin;
+  const tpc_row_meta m = b.meta[seg];
+  const int ylo = bin_coord(y - wy, m.y0, m.iwy, m.ny);
+  const int yhi = bin_coord(y + wy, m.y0, m.iwy, m.ny);
+  const int zlo = bin_coord(z - wz, m.z0, m.iwz, m.nz);
+  const int zhi = bin_coord(z + wz, m.z0, m.iwz, m.nz);
+  int32_t best = -1, bperm = 0;
+  float bchi = 0.0f;
+  for (int iz = zlo; iz <= zhi; iz++) {
+    const int bb = m.bin_base + iz * m.ny;
+    const int e = b.bin_off[bb + yhi + 1];
+    for (int p = b.bin_off[bb + ylo]; p < e; p++) {
+      const float r0 = b.ys[p] - y, r1 = b.zs[p] - z;
+      const float ch = chi2_of(q, r0, r1);
+      if (!(ch <= pick)) continue;
+      if (best < 0 || ch < bchi) {
+        best = p;
+        bchi = ch;
+        bperm = b.perm[p];
+      } else if (ch == bchi) {
+        const int32_t pp = b.perm[p];
+        if (pp < bperm) {
+          best = p;
+          bperm = pp;
+        }
+      }
+    }
+  }
+  return best;
+}
+
+__device__ __forceinline__ void kinit_cov(KSt& s, float vy, float vz)
+{
+#pragma unroll
+  for (int j = 0; j < 15; j++) s.c[j] = 0.0f;
+  s.c[0] = vy;
+  s.c[2] = vz;
+  s.c[5] = 1.0f;
+  s.c[9] = 1.0f;
+  s.c[14] = 100.0f;
+}
+
+// TrackletConstructor (R13-R17): one lane per start hit.
+__global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
+{
+  const int64_t t = gtid();
+  const int64_t S = min(b.counters[CNT_START], b.cap);
+  if (t >= S) return;
+  const int64_t cap = b.cap;
+  const float kB = k.kB, vy = k.vy, vz = k.vz, smax = k.snp_max;
+  const float edge = k.edge_margin, tanh_ = k.tan_half;
+  int32_t* H = b.tl_hit + t;  // row r at H[r * cap]
+  const int32_t h0 = b.start[t];
+  const int seg0 = b.sseg[h0];
+  const int segbase = seg0 - seg0 % kRows;
+  const int r0 = seg0 % kRows;
+  const int32_t h2 = b.up2[b.up2[h0]];
+  KSt st;
+  {
+    const float dxi = k.row_x[r0 + 2] - k.row_x[r0];
+    const float dyi = b.ys[h2] - b.ys[h0];
+    const float dzi = b.zs[h2] - b.zs[h0];
+    const float Li = sqrtf(dxi * dxi + dyi * dyi);
+    st.p[0] = b.ys[h0];
+    st.p[1] = b.zs[h0];
+    st.p[2] = dyi / Li;
+    st.p[3] = dzi / Li;
+    st.p[4] = 0.0f;
+    kinit_cov(st, vy, vz);
+  }
+  float chi2 = 0.0f;
+  int n = 1, rmax = r0, rmin = r0, stat = 0;
+  H[(int64_t)r0 * cap] = h0;
+  int r = r0;
+  int32_t h = h0;
+  bool ok_up = true;
+  // phase 1: cleaned links, no cut (R14)
+  for (int32_t hn = b.up2[h]; hn >= 0; hn = b.up2[h]) {
+    if (!kprop(st, k.row_x[r], k.row_x[r + 1], kB, smax)) {
+      ok_up = false;
+      break;
+    }
+    r++;
+    chi2 += kupdate(st, b.ys[hn], b.zs[hn], vy, vz);
+    H[(int64_t)r * cap] = hn;
+    n++;
+    rmax = r;
+    h = hn;
+  }
+  KSt keep = st;
+  // phase 2: upward grid search (R15)
+  if (ok_up) {
+    int miss = 0;
+    while (r < kRows - 1) {
+      if (!kprop(st, k.row_x[r], k.row_x[r + 1], kB, smax)) break;
+      r++;
+      if (!(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) break;
+      const Innov q = innov(st, vy, vz);
+      const int32_t bh = ksearch(k, b, segbase + r, st, q);
+      if (bh >= 0) {
+        chi2 += kupdate(st, b.ys[bh], b.zs[bh], vy, vz);
+        H[(int64_t)r * cap] = bh;
+        n++;
+        rmax = r;
+        keep = st;
+        miss = 0;
+      } else {
+        H[(int64_t)r * cap] = -1;
+        if (++miss >= k.tc_max_miss) break;
+      }
+    }
+  }
+  // phase 3: back to the start row, then downward (R16)
+  st = keep;
+  r = rmax;
+  while (r > r0) {
+    if (!kprop(st, k.row_x[r], k.row_x[r - 1], kB, smax)) {
+      stat = 2;
+      break;
+    }
+    r--;
+  }
+  keep = st;  // output state (innermost hit)
+  if (stat == 0) {
+    int miss = 0;
+    while (r > 0) {
+      if (!kprop(st, k.row_x[r], k.row_x[r - 1], kB, smax)) break;
+      r--;
+      if (!(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) break;
+      const Innov q = innov(st, vy, vz);
+      const int32_t bh = ksearch(k, b, segbase + r, st, q);
+      if (bh >= 0) {
+        chi2 += kupdate(st, b.ys[bh], b.zs[bh], vy, vz);
+        H[(int64_t)r * cap] = bh;
+        n++;
+        rmin = r;
+        keep = st;
+        miss = 0;
+      } else {
+        H[(int64_t)r * cap] = -1;
+        if (++miss >= k.tc_max_miss) break;
+      }
+    }
+    if (n < k.min_tracklet_hits) stat = 1;
+    else if (!(chi2 >= 0.0f && chi2 <= 3.0e38f)) stat = 3;
+  }
+#pragma unroll
+  for (int j = 0; j < 5; j++) b.tl_par[j * cap + t] = keep.p[j];
+#pragma unroll
+  for (int j = 0; j < 15; j++) b.tl_cov[j * cap + t] = keep.c[j];
+  b.tl_chi2[t] = chi2;
+  b.tl_nhit[t] = n;
+  b.tl_rmin[t] = rmin;
+  b.tl_rmax[t] = rmax;
+  b.tl_status[t] = stat;
+}
+
+// ------------------------------------------------------------------ a6 selection
+
+__device__ __forceinline__ unsigned long long ts_key(const TrackBufs& b, int64_t t)
+{
+  const int32_t h0 = b.start[t];
+  const int seg0 = b.sseg[h0];
+  const int64_t lid = (int64_t)h0 - b.inst_off[seg0 / kRows];
+  const uint32_t bits = __float_as_uint(b.tl_chi2[t]);
+  return ((unsigned long long)(uint32_t)b.tl_nhit[t] << 56) |
+         ((unsigned long long)(~bits & 0x7FFFFFFFu) << 25) |
+         (unsigned long long)(0x1FFFFFFull - (unsigned long long)lid);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sel_prep(TrackBufs b)
+{
+  for (int64_t h = gtid(); h < b.n; h += (int64_t)gridDim.x * blockDim.x) {
+    b.owner[h] = 0ull;
+    b.out.clu2trk[h] = -1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sel_mark(TrackBufs b)
+{
+  const int64_t t = gtid();
+  const int64_t S = min(b.counters[CNT_START], b.cap);
+  if (t >= S || b.tl_status[t] != 0) return;
+  const unsigned long long key = ts_key(b, t);
+  const int r1 = b.tl_rmax[t];
+  for (int r = b.tl_rmin[t]; r <= r1; r++) {
+    const int32_t h = b.tl_hit[(int64_t)r * b.cap + t];
+    if (h >= 0) atomicMax(&b.owner[h], key);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sel_count(Consts k, TrackBufs b, int32_t* own_out)
+{
+  const int64_t t = gtid();
+  const int64_t S = min(b.counters[CNT_START], b.cap);
+  if (t >= S) return;
+  int own = 0;
+  if (b.tl_status[t] == 0) {
+    atomicAdd((unsigned long long*)&b.res->n_tracklets_kept, 1ull);
+    const unsigned long long key = ts_key(b, t);
+    const int r1 = b.tl_rmax[t];
+    for (int r = b.tl_rmin[t]; r <= r1; r++) {
+      const int32_t h = b.tl_hit[(int64_t)r * b.cap + t];
+      if (h >= 0 && b.owner[h] == key) own++;
+    }
+    if (own < k.min_track_hits) own = 0;
+  }
+  own_out[t] = own;
+  const int64_t v = own ? ((int64_t)1 << 32) | own : 0;
+#if TPC_DET
+  b.tsv[t] = v;
+#else
+  b.tsv[t] = own ? (int64_t)atomicAdd((unsigned long long*)&b.counters[CNT_TRACKS],
+                                      (unsigned long long)v)
+                 : 0;
+#endif
+}
+
+__global__ __launch_bounds__(kBlock) void k_sel_write(Consts k, TrackBufs b, const int32_t* own_in)
+{
+  const int64_t t = gtid();
+  const int64_t S = min(b.counters[CNT_START], b.cap);
+  if (t >= S) return;
+  const int own = own_in[t];
+  if (own == 0) return;
+  const int64_t v = b.tsv[t];
+  const int64_t kk = v >> 32;
+  const int64_t off = v & 0xFFFFFFFFll;
+  if (kk >= b.out.cap_tracks || off + own > b.out.cap_hits) return;
+  const int64_t cap = b.cap;
+#pragma unroll
+  for (int j = 0; j < 5; j++) b.out.param[kk * 5 + j] = b.tl_par[j * cap + t];
+#pragma unroll
+  for (int j = 0; j < 15; j++) b.out.cov[kk * 15 + j] = b.tl_cov[j * cap + t];
+  b.out.chi2[kk] = b.tl_chi2[t];
+  b.out.ndf[kk] = 2 * b.tl_nhit[t] - 5;
+  const int rmin = b.tl_rmin[t], rmax = b.tl_rmax[t];
+  b.out.x_ref[kk] = k.row_x[rmin];
+  const unsigned long long key = ts_key(b, t);
+  int64_t j = off;
+  for (int r = rmin; r <= rmax; r++) {
+    const int32_t h = b.tl_hit[(int64_t)r * cap + t];
+    if (h >= 0 && b.owner[h] == key) {
+      const int32_t c = b.perm[h];
+      b.out.hit_clu[j++] = c;
+      b.out.clu2trk[c] = (int32_t)kk;
+    }
+  }
+  b.out.hit_off[kk + 1] = (int32_t)(off + own);
+  atomicMax((unsigned long long*)&b.res->n_tracks, (unsigned long long)(kk + 1));
+  atomicMax((unsigned long long*)&b.res->n_hits, (unsigned long long)(off + own));
+}
+
+__global__ void k_sel_finish(TrackBufs b)
+{
+  const int64_t v = b.counters[CNT_TRACKS];
+  const int64_t nt = v >> 32, nh = v & 0xFFFFFFFFll;
+  b.res->need_tracks = nt;
+  b.res->need_hits = nh;
+  if (b.res->n_tracks < nt) {
+    if (nt > b.out.cap_tracks) b.res->overflow |= 4;
+    if (nh > b.out.cap_hits) b.res->overflow |= 8;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t grid_build(const Consts& k, const GridBufs& b, hipStream_t s)
+{
+  const int64_t n_seg = (int64_t)b.n_inst * kRows;
+  k_grid_clear<<<blocks_for(n_seg), kBlock, 0, s>>>(b);
+  if (b.n > 0) k_grid_stats<<<blocks_for(b.n, kStatItems), kBlock, 0, s>>>(k, b);
+  k_grid_meta<<<blocks_for(n_seg), kBlock, 0, s>>>(k, b);
+  scan_exclusive<int32_t>(b.nb1, n_seg, nullptr, &b.res->n_bins, b.scan_tmp, s);
+  k_grid_zero<<<blocks_for(b.bin_cap), kBlock, 0, s>>>(b);
+  k_grid_meta2<<<blocks_for(n_seg), kBlock, 0, s>>>(b);
+  if (b.n > 0) k_grid_hist<<<blocks_for(b.n), kBlock, 0, s>>>(b);
+  scan_exclusive<int32_t>(b.bin_off, b.bin_cap, &b.res->n_bins, nullptr, b.scan_tmp, s);
+  if (b.n > 0) k_grid_scatter<<<blocks_for(b.n), kBlock, 0, s>>>(b);
+  k_grid_rowoff<<<blocks_for(n_seg), kBlock, 0, s>>>(b);
+#if TPC_DET
+  k_grid_binsort<<<blocks_for(b.bin_cap), kBlock, 0, s>>>(b);
+#endif
+  return hipGetLastError();
+}
+
+hipError_t sector_track(const Consts& k, const TrackBufs& b, hipStream_t s)
+{
+  k_track_init<<<1, 64, 0, s>>>(b);
+  if (b.n > 0) {
+    k_neighbours<<<blocks_for(b.n), kBlock, 0, s>>>(k, b);
+    k_clean<<<blocks_for(b.n), kBlock, 0, s>>>(b);
+#if TPC_DET
+    const int64_t nb = (b.n + kTile - 1) / kTile;
+    k_start_count<<<(unsigned)nb, kBlock, 0, s>>>(k, b, b.scan_tmp);
+    k_scan_partials<<<1, 1024, 0, s>>>(b.scan_tmp, nb, &b.counters[CNT_START]);
+    k_start_write<<<(unsigned)nb, kBlock, 0, s>>>(k, b, b.scan_tmp);
+#else
+    k_start_atomic<<<blocks_for(b.n), kBlock, 0, s>>>(k, b);
+#endif
+  }
+  k_start_finish<<<1, 1, 0, s>>>(b);
+  k_sel_prep<<<blocks_for(b.n > 0 ? b.n : 1), kBlock, 0, s>>>(b);
+  if (b.cap > 0) {
+    k_tracklets<<<blocks_for(b.cap), kBlock, 0, s>>>(k, b);
+    k_sel_mark<<<blocks_for(b.cap), kBlock, 0, s>>>(b);
+    k_sel_count<<<blocks_for(b.cap), kBlock, 0, s>>>(k, b, b.tl_own);
+#if TPC_DET
+    scan_exclusive<int64_t>(b.tsv, b.cap, &b.counters[CNT_START], &b.counters[CNT_TRACKS],
+                            b.scan_tmp, s);
+#endif
+    k_sel_write<<<blocks_for(b.cap), kBlock, 0, s>>>(k, b, b.tl_own);
+  }
+  k_sel_finish<<<1, 1, 0, s>>>(b);
+  return hipGetLastError();
+}
+
+}  // namespace TPC_NS
+}  // namespace tpcca

@@ -1,0 +1,166 @@
+"""Element-by-element comparison of a GPU tracking run with the CPU oracle
+(test infrastructure: used by the GPU tests and the smoke check)."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+import paper_2511_17018_amd as tpc
+import synth
+
+G = synth.geometry()
+P = dict(oracle.DEFAULT_PARAMS)
+NR = 152
+
+
+def bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view(np.int32) if a.dtype == np.float32 else a
+
+
+def run_gpu(ev_or_arrays, det=True, device="cuda", **kw):
+    a = ev_or_arrays
+    batch = tpc.upload(a.x, a.y, a.z, a.row, a.charge, a.inst_off, device)
+    return tpc.track(G, batch, det=det, **kw)
+
+
+def gpu_arrays(run: tpc.TrackRun, n: int) -> dict:
+    """Everything a run produced, on the host."""
+    res = run.result
+    ws = run.ws
+    cap = ws.layout.cap_tracklets
+    S = int(min(res["n_start"], cap))
+    nb = int(res["n_bins"])
+    nt, nh = int(res["n_tracks"]), int(res["n_hits"])
+    h = lambda t: t.cpu().numpy()  # noqa: E731
+    i32, f32 = torch.int32, torch.float32
+    out = dict(
+        sseg=h(run.grid.sseg), perm=h(run.grid.perm), ys=h(run.grid.ys), zs=h(run.grid.zs),
+        row_off=h(run.grid.row_off), meta=h(run.grid.meta), bin_off=h(run.grid.bin_off)[:nb],
+        up=h(ws.view("up", i32, n)), dn=h(ws.view("dn", i32, n)),
+        up2=h(ws.view("up2", i32, n)), dn2=h(ws.view("dn2", i32, n)),
+        start=h(ws.view("start", i32, cap))[:S],
+        tl_par=h(ws.view("tl_par", f32, 5 * cap)).reshape(5, cap)[:, :S].T.copy(),
+        tl_cov=h(ws.view("tl_cov", f32, 15 * cap)).reshape(15, cap)[:, :S].T.copy(),
+        tl_chi2=h(ws.view("tl_chi2", f32, cap))[:S],
+        tl_nhit=h(ws.view("tl_nhit", i32, cap))[:S],
+        tl_rmin=h(ws.view("tl_rmin", i32, cap))[:S],
+        tl_rmax=h(ws.view("tl_rmax", i32, cap))[:S],
+        tl_status=h(ws.view("tl_status", i32, cap))[:S],
+        tl_hit=h(ws.view("tl_hit", i32, NR * cap)).reshape(NR, cap)[:, :S].T.copy(),
+        param=h(run.tracks.param)[:nt], cov=h(run.tracks.cov)[:nt], chi2=h(run.tracks.chi2)[:nt],
+        ndf=h(run.tracks.ndf)[:nt], x_ref=h(run.tracks.x_ref)[:nt],
+        hit_off=h(run.tracks.hit_off)[:nt + 1], hit_clu=h(run.tracks.hit_clu)[:nh],
+        clu2trk=h(run.tracks.clu2trk)[:n], result=res)
+    return out
+
+
+def _eq(name, a, b, errors):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    if a.shape != b.shape:
+        errors.append(f"{name}: shape {a.shape} vs {b.shape}")
+        return
+    if not np.array_equal(bits(a), bits(b)):
+        k = int(np.argmax((bits(a) != bits(b)).reshape(-1)))
+        errors.append(f"{name}: {int((bits(a) != bits(b)).sum())} differ, first flat index {k}: "
+                      f"{a.reshape(-1)[k]!r} vs {b.reshape(-1)[k]!r}")
+
+
+def compare_det(g: dict, o: oracle.ChainResult) -> list:
+    """Bit-exact comparison (deterministic mode) of every stage; returns errors."""
+    e = []
+    res = g["result"]
+    gr = o.grid
+    if int(res["n_bad"]) != gr.n_bad:
+        e.append(f"n_bad {res['n_bad']} vs {gr.n_bad}")
+    if int(res["n_bins"]) != gr.n_bins:
+        e.append(f"n_bins {res['n_bins']} vs {gr.n_bins}")
+        return e
+    if int(res["overflow"]) != 0:
+        e.append(f"overflow {res['overflow']}")
+    _eq("sseg", g["sseg"], gr.sseg, e)
+    _eq("perm", g["perm"], gr.perm, e)
+    _eq("ys", g["ys"], gr.ys, e)
+    _eq("zs", g["zs"], gr.zs, e)
+    _eq("row_off", g["row_off"], gr.row_off, e)
+    _eq("meta_i", g["meta"][:, :4], gr.meta_i, e)
+    _eq("meta_f", g["meta"][:, 4:], gr.meta_f.view(np.int32), e)
+    _eq("bin_off", g["bin_off"], gr.bin_off, e)
+    for k, v in (("up", o.up), ("dn", o.dn), ("up2", o.up2), ("dn2", o.dn2), ("start", o.start)):
+        _eq(k, g[k], v, e)
+    if e:
+        return e
+    tl = o.tracklets
+    _eq("tl_status", g["tl_status"], tl.status, e)
+    _eq("tl_nhit", g["tl_nhit"], tl.nhit, e)
+    _eq("tl_rmin", g["tl_rmin"], tl.rmin, e)
+    _eq("tl_rmax", g["tl_rmax"], tl.rmax, e)
+    if e:
+        return e
+    _eq("tl_par", g["tl_par"], tl.par, e)
+    _eq("tl_cov", g["tl_cov"], tl.cov, e)
+    _eq("tl_chi2", g["tl_chi2"], tl.chi2, e)
+    rows = np.arange(NR)[None, :]
+    m = (rows >= tl.rmin[:, None]) & (rows <= tl.rmax[:, None])
+    _eq("tl_hit", np.where(m, g["tl_hit"], -7), np.where(m, tl.hit, -7), e)
+    T = o.tracks
+    if int(res["need_tracks"]) != T.need_tracks or int(res["need_hits"]) != T.need_hits:
+        e.append(f"need {res['need_tracks']},{res['need_hits']} vs {T.need_tracks},{T.need_hits}")
+    for k, v in (("param", T.par), ("cov", T.cov), ("chi2", T.chi2), ("ndf", T.ndf),
+                 ("x_ref", T.x_ref), ("hit_off", T.hit_off), ("hit_clu", T.hit_clu),
+                 ("clu2trk", T.clu2trk)):
+        _eq(k, g[k], v, e)
+    return e
+
+
+def match_tracks(hit_off_a, hit_clu_a, hit_off_b, hit_clu_b, n):
+    """Match tracks of two outputs by shared clusters (>= 50 % of the smaller);
+    returns the fraction of clusters assigned differently (R30)."""
+    ca = np.full(n, -1)
+    cb = np.full(n, -1)
+    for k in range(len(hit_off_a) - 1):
+        ca[hit_clu_a[hit_off_a[k]:hit_off_a[k + 1]]] = k
+    for k in range(len(hit_off_b) - 1):
+        cb[hit_clu_b[hit_off_b[k]:hit_off_b[k + 1]]] = k
+    both = (ca >= 0) & (cb >= 0)
+    pairs, shared = np.unique(np.stack([ca[both], cb[both]], 1), axis=0, return_counts=True)
+    la = np.diff(hit_off_a)
+    lb = np.diff(hit_off_b)
+    match = {}
+    order = np.argsort(-shared, kind="stable")
+    used_b = set()
+    for i in order:
+        a, b = pairs[i]
+        if a in match or b in used_b:
+            continue
+        if shared[i] >= 0.5 * min(la[a], lb[b]):
+            match[a] = b
+            used_b.add(b)
+    mapped = np.array([match.get(k, -2) for k in range(len(la))] + [-1])
+    diff = np.where(ca >= 0, mapped[ca], -1) != cb
+    return float(diff.mean()) if n else 0.0
+
+
+def replay_params(g: dict, prec=64):
+    """binary64 replay of every kept GPU tracklet on its own hit list."""
+    floor = np.array([1, 1, 0.01, 0.01, 0.01])
+    rel = []
+    for t in np.nonzero(g["tl_status"] == 0)[0]:
+        h0 = g["start"][t]
+        r0 = int(g["sseg"][h0] % NR)
+        rmin, rmax = int(g["tl_rmin"][t]), int(g["tl_rmax"][t])
+        hy = np.zeros(NR, np.float32)
+        hz = np.zeros(NR, np.float32)
+        has = np.zeros(NR, np.uint8)
+        rows = np.arange(rmin, rmax + 1)
+        hh = g["tl_hit"][t, rows]
+        m = hh >= 0
+        hy[rows[m]] = g["ys"][hh[m]]
+        hz[rows[m]] = g["zs"][hh[m]]
+        has[rows[m]] = 1
+        ok, par, cov, chi2 = oracle.replay(G, P, r0, rmin, rmax, hy, hz, has, prec=prec)
+        if ok:
+            rel.append(np.abs(g["tl_par"][t] - par) / np.maximum(np.abs(par), floor))
+    return np.array(rel).reshape(-1, 5)
