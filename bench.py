@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X TPC sector tracker.
+
+Workload: 256 independent sector instances of very uneven occupancy (cluster
+counts log-uniform 1e3..4e5 per instance, noise 0-20 %, 15.65 M clusters,
+seeded synthetic helix events).  One step = the whole hot path (grid build,
+neighbours, cleaner, start hits, tracklet construction, selection) over the
+batch, with the clusters already resident in HBM.  Reported:
+
+  value        clusters/s of the batched deterministic path (one launch chain
+               for all 256 instances)
+  plain        clusters/s of 256 per-instance launch chains on one stream
+  prod         clusters/s of the batched production path, and det/prod ratio
+  roofline     the dominant kernel's algorithmic bytes per launch divided by
+               its average launch time (HIP events recorded on the kernel's
+               stream over a timed pass), against the 8 TB/s HBM peak
+  cpu_baseline the single-threaded CPU oracle on a sample of the instances
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TPC clusters/sec tracked, batched vs plain (deterministic FP32); refit grad tracks/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(name: str, c: dict) -> float | None:
+    """Algorithmic bytes one launch of `name` must move (per-unit figures
+    times the units of the launch; see the design notes)."""
+    N, S, Ht, E = c["N"], c["S"], c["Ht"], c["E"]
+    table = {
+        "grid_stats": 14 * N,                 # y, z, row in; segment id out
+        "grid_hist": 12 * N + 8 * N,          # segment id, y, z in; bin counter RMW
+        "grid_scatter": 12 * N + 8 * N + 16 * N,
+        "grid_binsort": 24 * N,
+        "neighbours": 24 * N + 8 * N,         # own + two neighbour rows' y,z; links out
+        "clean": 16 * N + 8 * N,
+        "tracklets": 4 * S + 16 * Ht + 8 * E + 88 * S,
+        "sel_mark": 4 * Ht + 16 * Ht,
+        "sel_count": 4 * Ht + 8 * Ht,
+    }
+    return table.get(name)
+
+
+def run(args) -> dict:
+    import torch
+
+    import paper_2511_17018_amd as tpc
+    import synth
+
+    t0 = time.time()
+    ev = synth.config4(scale=args.scale)
+    N, n_inst = ev.n, ev.n_inst
+    sha = hashlib.sha256(np.concatenate([ev.y.view(np.uint8), ev.z.view(np.uint8),
+                                         ev.row.view(np.uint8)]).tobytes()).hexdigest()
+    log(f"generated {N} clusters in {n_inst} instances ({time.time() - t0:.1f}s)")
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    L = tpc.lib()
+    geom = tpc.make_geometry(synth.geometry())
+    batch = tpc.upload(ev.x, ev.y, ev.z, ev.row, ev.charge, ev.inst_off, dev)
+    stream = torch.cuda.current_stream()
+    sp = C.c_void_p(stream.cuda_stream)
+
+    def prepared(b: "tpc.Batch", det: bool):
+        """Pre-marshalled argument tuples of one tracking call."""
+        p = tpc.make_params(det)
+        grid = tpc.alloc_grid(b.n_inst, b.n, dev)
+        tracks = tpc.alloc_tracks(b.n, device=dev)
+        ws = tpc.Workspace(b.n_inst, b.n, 0, dev)
+        keep = (p, grid, tracks, ws, b, grid.struct(), tracks.struct(), b.struct())
+        ga = (C.byref(geom), C.byref(p), C.c_int32(b.n_inst),
+              b.inst_off_host.ctypes.data_as(C.c_void_p), tpc._ptr(b.inst_off), keep[7],
+              C.byref(keep[5]), tpc._ptr(ws.result), tpc._ptr(ws.grid_ws),
+              C.c_size_t(ws.grid_ws.numel()), sp)
+        ta = (C.byref(geom), C.byref(p), C.c_int32(b.n_inst),
+              b.inst_off_host.ctypes.data_as(C.c_void_p), tpc._ptr(b.inst_off), keep[7],
+              C.byref(keep[5]), C.byref(keep[6]), tpc._ptr(ws.result), tpc._ptr(ws.track_ws),
+              C.c_size_t(ws.track_ws.numel()), C.c_int64(0), sp)
+        return keep, ga, ta
+
+    def step(preps):
+        for _, ga, ta in preps:
+            st = L.tpc_grid_build(*ga)
+            st2 = L.tpc_sector_track(*ta)
+            if st or st2:
+                raise RuntimeError(f"tracker call failed: {st} {st2}")
+
+    def timed(preps, steps, warmup, label):
+        for _ in range(warmup):
+            step(preps)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            step(preps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        log(f"{label}: {dt * 1e3:.3f} ms/step, {N / dt / 1e9:.3f} G clusters/s")
+        return dt
+
+    out = {}
+    # ---- batched, deterministic (the headline)
+    det_b = [prepared(batch, True)]
+    dt_det = timed(det_b, args.steps, args.warmup, "batched det")
+    res = det_b[0][0][3].read_result()
+    if int(res["overflow"]) or int(res["n_bad"]):
+        raise RuntimeError(f"unexpected status {res}")
+    # per-kernel times with HIP events (a second timed pass of the same steps)
+    assert L.tpc_profile_enable(1) == 0
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        step(det_b)
+    torch.cuda.synchronize()
+    rows = (tpc_kernel_time * 64)()
+    nk = L.tpc_profile_read(rows, 64)
+    L.tpc_profile_enable(0)
+    ktimes = {rows[i].name.decode(): (rows[i].total_ms, rows[i].launches) for i in range(nk)}
+    # counts for the byte model
+    ws = det_b[0][0][3]
+    cap = ws.layout.cap_tracklets
+    S = int(min(res["n_start"], cap))
+    i32 = torch.int32
+    nhit = ws.view("tl_nhit", i32, cap)[:S].to(torch.int64).sum().item()
+    ncand = ws.view("tl_ncand", i32, cap)[:S].to(torch.int64).sum().item()
+    counts = dict(N=N, S=S, Ht=nhit, E=ncand)
+    # dominant kernel
+    dom = max(ktimes.items(), key=lambda kv: kv[1][0])
+    name, (tot_ms, launches) = dom
+    avg_s = tot_ms / launches / 1e3
+    kb = kernel_bytes(name, counts)
+    achieved = kb / avg_s / 1e9 if kb else None
+    total_ms_per_step = sum(v[0] for v in ktimes.values()) / args.steps
+    roofline = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": None, "avg_launch_ms": avg_s * 1e3,
+                "alg_bytes_per_launch": kb, "counts": counts}
+    out["kernels_ms_per_step"] = {k: round(v[0] / args.steps, 4) for k, v in
+                                  sorted(ktimes.items(), key=lambda kv: -kv[1][0])}
+    out["kernels_sum_ms_per_step"] = round(total_ms_per_step, 4)
+    out["result"] = {k: int(res[k]) for k in ("n_valid", "n_start", "n_tracklets_kept",
+                                              "n_tracks", "n_hits")}
+    # ---- batched, production
+    if not args.no_prod:
+        prod_b = [prepared(batch, False)]
+        dt_prod = timed(prod_b, args.steps, args.warmup, "batched prod")
+        out["prod"] = {"value": N / dt_prod, "ms_per_step": dt_prod * 1e3,
+                       "det_over_prod_time": dt_det / dt_prod}
+        del prod_b
+    # ---- plain: one launch chain per instance
+    if not args.no_plain:
+        plain = [prepared(batch.slice(i), True) for i in range(n_inst)]
+        ps = max(1, min(args.steps, 3))
+        dt_plain = timed(plain, ps, 1, "plain det")
+        out["plain"] = {"value": N / dt_plain, "ms_per_step": dt_plain * 1e3, "steps": ps,
+                        "batched_over_plain": dt_plain / dt_det}
+        del plain
+    out.update(dt_det=dt_det, N=N, n_inst=n_inst, sha=sha, roofline=roofline)
+    return out, ev
+
+
+def cpu_baseline(ev, every: int) -> dict:
+    import oracle
+    import synth
+    g = synth.geometry()
+    sel = list(range(0, ev.n_inst, every))
+    n_tot, t_tot = 0, 0.0
+    for i in sel:
+        a, b = int(ev.inst_off[i]), int(ev.inst_off[i + 1])
+        off = np.array([0, b - a], np.int64)
+        t = time.perf_counter()
+        oracle.track(g, oracle.DEFAULT_PARAMS, off, ev.y[a:b], ev.z[a:b], ev.row[a:b])
+        t_tot += time.perf_counter() - t
+        n_tot += b - a
+    log(f"cpu oracle: {n_tot} clusters in {t_tot:.1f}s")
+    return {"value": n_tot / t_tot, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(sel)} of {ev.n_inst} instances (every {every}th), {n_tot} clusters, "
+                      "binary32 oracle, whole chain a1-a6, one thread"}
+
+
+class tpc_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("total_ms", C.c_double), ("launches", C.c_int64)]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=float, default=1.0, help="scale of the per-instance sizes")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-prod", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-every", type=int, default=4)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this tracker runs on one GPU; sector instances shard across "
+                                   "GPUs with no exchange, which this benchmark does not run",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    r, ev = run(args)
+    line = {
+        "metric": METRIC,
+        "value": r["N"] / r["dt_det"],
+        "unit": "clusters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["dt_det"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "256 uneven sector instances (log-uniform 1e3-4e5 clusters, "
+                               "noise 0-20%), batched deterministic chain",
+                   "n_clusters": r["N"], "n_instances": r["n_inst"], "mode": "deterministic",
+                   "path": "batched", "input_sha256": r["sha"]},
+        "roofline": r["roofline"],
+    }
+    for k in ("plain", "prod", "result", "kernels_ms_per_step", "kernels_sum_ms_per_step"):
+        if k in r:
+            line[k] = r[k]
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(ev, args.cpu_every)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -158,10 +158,12 @@ typedef struct {
  *   tl_par             f32[5][cap_tracklets]   tl_cov f32[15][cap_tracklets]
  *   tl_chi2            f32[cap_tracklets]      tl_nhit, tl_rmin, tl_rmax, tl_status i32
  *   tl_hit             i32[152][cap_tracklets] (valid for rmin <= row <= rmax)
+ *   tl_ncand           i32[cap_tracklets] grid candidates whose chi2 the extension
+ *                      searches evaluated (instrumentation for byte counts)
  *   owner              u64[n_clusters]  selection keys per position          */
 typedef struct {
   int64_t up, dn, up2, dn2, start;
-  int64_t tl_par, tl_cov, tl_chi2, tl_nhit, tl_rmin, tl_rmax, tl_status, tl_hit;
+  int64_t tl_par, tl_cov, tl_chi2, tl_nhit, tl_rmin, tl_rmax, tl_status, tl_hit, tl_ncand;
   int64_t owner;
   int64_t scratch;
   int64_t total;
@@ -202,6 +204,23 @@ tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, 
                             tpc_clusters in, const tpc_grid* grid, const tpc_tracks* out,
                             tpc_result* result_dev, void* ws_dev, size_t ws_bytes,
                             int64_t cap_tracklets, void* stream);
+
+/* Optional per-kernel timing for benchmarks.  tpc_profile_enable(1) creates
+ * a pool of HIP events (host call, once); afterwards every kernel the library
+ * enqueues is bracketed by two events recorded on the stream it is launched
+ * on, until the pool is used up.  tpc_profile_read synchronises those events
+ * and returns per kernel name the summed elapsed time and launch count since
+ * the previous read (at most max_entries rows; returns the number written, or
+ * a negative tpc_status).  tpc_profile_enable(0) stops recording and frees
+ * the pool.  Not thread-safe; profiling adds two event records per launch. */
+typedef struct {
+  char name[48];
+  double total_ms;
+  int64_t launches;
+} tpc_kernel_time;
+
+tpc_status tpc_profile_enable(int32_t on);
+int32_t tpc_profile_read(tpc_kernel_time* out, int32_t max_entries);
 
 #ifdef __cplusplus
 }

@@ -78,7 +78,8 @@ class TracksStruct(C.Structure):
 class TrackWsLayout(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "up", "dn", "up2", "dn2", "start", "tl_par", "tl_cov", "tl_chi2", "tl_nhit", "tl_rmin",
-        "tl_rmax", "tl_status", "tl_hit", "owner", "scratch", "total", "cap_tracklets")]
+        "tl_rmax", "tl_status", "tl_hit", "tl_ncand", "owner", "scratch", "total",
+        "cap_tracklets")]
 
 
 RESULT_DTYPE = np.dtype([(n, np.int64) for n in (

@@ -36,6 +36,8 @@ def build(verbose: bool = False) -> str:
     jobs = [
         ([_hipcc(), *COMMON, "-c", os.path.join(CSRC, "tpc_api.cpp"),
           "-o", os.path.join(BUILD, "tpc_api.o")], "tpc_api.o"),
+        ([_hipcc(), *COMMON, "-c", os.path.join(CSRC, "tpc_prof.cpp"),
+          "-o", os.path.join(BUILD, "tpc_prof.o")], "tpc_prof.o"),
         ([_hipcc(), *COMMON, *DET, "-c", os.path.join(CSRC, "tpc_kernels.hip"),
           "-o", os.path.join(BUILD, "tpc_kernels_det.o")], "tpc_kernels_det.o"),
         ([_hipcc(), *COMMON, *PROD, "-c", os.path.join(CSRC, "tpc_kernels.hip"),

@@ -74,6 +74,7 @@ TrackWs track_ws(int32_t n_inst, int64_t n, int64_t cap)
   w.pub.tl_rmax = c.take(4 * cap);
   w.pub.tl_status = c.take(4 * cap);
   w.pub.tl_hit = c.take(4 * (int64_t)kRows * cap);
+  w.pub.tl_ncand = c.take(4 * cap);
   w.pub.owner = c.take(8 * n);
   w.tl_own = c.take(4 * cap);
   w.tsv = c.take(8 * cap);
@@ -233,7 +234,9 @@ tpc_status tpc_grid_build(const tpc_geometry* geom, const tpc_params* params, in
   b.perm = grid->perm;
   b.ys = grid->ys;
   b.zs = grid->zs;
-  b.bin_cap = grid->bin_cap;
+  // the workspace's fill counters and scan partials are sized for this capacity
+  const int64_t ws_cap = tpc_grid_bin_capacity(n_inst, n);
+  b.bin_cap = grid->bin_cap < ws_cap ? grid->bin_cap : ws_cap;
   b.res = result_dev;
   b.cseg = at<int32_t>(ws_dev, w.cseg);
   b.seg_cnt = at<int32_t>(ws_dev, w.seg_cnt);
@@ -296,6 +299,7 @@ tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, 
   b.tl_rmax = at<int32_t>(ws_dev, w.pub.tl_rmax);
   b.tl_status = at<int32_t>(ws_dev, w.pub.tl_status);
   b.tl_hit = at<int32_t>(ws_dev, w.pub.tl_hit);
+  b.tl_ncand = at<int32_t>(ws_dev, w.pub.tl_ncand);
   b.owner = at<unsigned long long>(ws_dev, w.pub.owner);
   b.tl_own = at<int32_t>(ws_dev, w.tl_own);
   b.tsv = at<int64_t>(ws_dev, w.tsv);

@@ -72,6 +72,7 @@ struct TrackBufs {
   float* tl_chi2;
   int32_t *tl_nhit, *tl_rmin, *tl_rmax, *tl_status;
   int32_t* tl_hit;     // [152][cap]
+  int32_t* tl_ncand;   // [cap] candidates evaluated by the extension searches
   unsigned long long* owner;  // [n]
   int32_t* tl_own;     // [cap] owned hits of accepted tracklets, 0 otherwise
   int64_t* tsv;        // [cap] packed (track flag << 32 | owned hits), then its scan
@@ -82,6 +83,10 @@ struct TrackBufs {
   tpc_tracks out;
   tpc_result* res;
 };
+
+// Kernel timing hooks (tpc_profile_*): no-ops unless profiling is enabled.
+int prof_begin(hipStream_t s, const char* name);
+void prof_end(hipStream_t s, int slot);
 
 // Scan partials needed for an array of n items.
 int64_t scan_partials(int64_t n);

@@ -182,22 +182,31 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(T* data, int64_t n_max, c
   }
 }
 
+unsigned blocks_for(int64_t n, int per = kBlock)
+{
+  int64_t b = (n + per - 1) / per;
+  return (unsigned)(b > 0 ? b : 1);
+}
+
+// Launch with optional event timing (tpc_profile_enable).
+#define TPC_LAUNCH(name, grid, block, stream, kern, ...)   \
+  do {                                                     \
+    const int slot_ = prof_begin((stream), (name));        \
+    kern<<<(grid), (block), 0, (stream)>>>(__VA_ARGS__);   \
+    prof_end((stream), slot_);                             \
+  } while (0)
+
 template <class T>
 void scan_exclusive(T* data, int64_t n_max, const int64_t* n_dev, int64_t* total_out,
                     int64_t* part, hipStream_t s)
 {
   int64_t nb = (n_max + kTile - 1) / kTile;
   if (nb == 0) nb = 1;
-  k_scan_reduce<T><<<dim3((unsigned)nb), kBlock, 0, s>>>(data, n_max, n_dev, part);
-  k_scan_partials<<<1, 1024, 0, s>>>(part, nb, total_out);
-  k_scan_apply<T><<<dim3((unsigned)nb), kBlock, 0, s>>>(data, n_max, n_dev, part);
+  TPC_LAUNCH("scan_reduce", dim3((unsigned)nb), kBlock, s, k_scan_reduce<T>, data, n_max, n_dev, part);
+  TPC_LAUNCH("scan_partials", 1, 1024, s, k_scan_partials, part, nb, total_out);
+  TPC_LAUNCH("scan_apply", dim3((unsigned)nb), kBlock, s, k_scan_apply<T>, data, n_max, n_dev, part);
 }
 
-unsigned blocks_for(int64_t n, int per = kBlock)
-{
-  int64_t b = (n + per - 1) / per;
-  return (unsigned)(b > 0 ? b : 1);
-}
 
 // ------------------------------------------------------------------ a1 grid
 
@@ -743,7 +752,7 @@ __device__ __forceinline__ float kupdate(KSt& s, float my, float mz, float vy, f
 
 // R15: best cluster of row segment `seg` for the predicted state
 __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b, int seg,
-                                           const KSt& st, const Innov& q)
+                                           const KSt& st, const Innov& q, int& ncand)
 {
   const float y = st.p[0], z = st.p[1];
   const float pick = k.tc_chi2_pick;
@@ -759,7 +768,9 @@ __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b, 
   for (int iz = zlo; iz <= zhi; iz++) {
     const int bb = m.bin_base + iz * m.ny;
     const int e = b.bin_off[bb + yhi + 1];
-    for (int p = b.bin_off[bb + ylo]; p < e; p++) {
+    const int p0 = b.bin_off[bb + ylo];
+    ncand += e - p0;
+    for (int p = p0; p < e; p++) {
       const float r0 = b.ys[p] - y, r1 = b.zs[p] - z;
       const float ch = chi2_of(q, r0, r1);
       if (!(ch <= pick)) continue;
@@ -819,7 +830,7 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
     kinit_cov(st, vy, vz);
   }
   float chi2 = 0.0f;
-  int n = 1, rmax = r0, rmin = r0, stat = 0;
+  int n = 1, rmax = r0, rmin = r0, stat = 0, ncand = 0;
   H[(int64_t)r0 * cap] = h0;
   int r = r0;
   int32_t h = h0;
@@ -846,7 +857,7 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
       r++;
       if (!(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) break;
       const Innov q = innov(st, vy, vz);
-      const int32_t bh = ksearch(k, b, segbase + r, st, q);
+      const int32_t bh = ksearch(k, b, segbase + r, st, q, ncand);
       if (bh >= 0) {
         chi2 += kupdate(st, b.ys[bh], b.zs[bh], vy, vz);
         H[(int64_t)r * cap] = bh;
@@ -878,7 +889,7 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
       r--;
       if (!(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) break;
       const Innov q = innov(st, vy, vz);
-      const int32_t bh = ksearch(k, b, segbase + r, st, q);
+      const int32_t bh = ksearch(k, b, segbase + r, st, q, ncand);
       if (bh >= 0) {
         chi2 += kupdate(st, b.ys[bh], b.zs[bh], vy, vz);
         H[(int64_t)r * cap] = bh;
@@ -903,6 +914,7 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
   b.tl_rmin[t] = rmin;
   b.tl_rmax[t] = rmax;
   b.tl_status[t] = stat;
+  b.tl_ncand[t] = ncand;
 }
 
 // ------------------------------------------------------------------ a6 selection
@@ -1020,50 +1032,50 @@ __global__ void k_sel_finish(TrackBufs b)
 hipError_t grid_build(const Consts& k, const GridBufs& b, hipStream_t s)
 {
   const int64_t n_seg = (int64_t)b.n_inst * kRows;
-  k_grid_clear<<<blocks_for(n_seg), kBlock, 0, s>>>(b);
-  if (b.n > 0) k_grid_stats<<<blocks_for(b.n, kStatItems), kBlock, 0, s>>>(k, b);
-  k_grid_meta<<<blocks_for(n_seg), kBlock, 0, s>>>(k, b);
+  TPC_LAUNCH("grid_clear", blocks_for(n_seg), kBlock, s, k_grid_clear, b);
+  if (b.n > 0) TPC_LAUNCH("grid_stats", blocks_for(b.n, kStatItems), kBlock, s, k_grid_stats, k, b);
+  TPC_LAUNCH("grid_meta", blocks_for(n_seg), kBlock, s, k_grid_meta, k, b);
   scan_exclusive<int32_t>(b.nb1, n_seg, nullptr, &b.res->n_bins, b.scan_tmp, s);
-  k_grid_zero<<<blocks_for(b.bin_cap), kBlock, 0, s>>>(b);
-  k_grid_meta2<<<blocks_for(n_seg), kBlock, 0, s>>>(b);
-  if (b.n > 0) k_grid_hist<<<blocks_for(b.n), kBlock, 0, s>>>(b);
+  TPC_LAUNCH("grid_zero", blocks_for(b.bin_cap), kBlock, s, k_grid_zero, b);
+  TPC_LAUNCH("grid_meta2", blocks_for(n_seg), kBlock, s, k_grid_meta2, b);
+  if (b.n > 0) TPC_LAUNCH("grid_hist", blocks_for(b.n), kBlock, s, k_grid_hist, b);
   scan_exclusive<int32_t>(b.bin_off, b.bin_cap, &b.res->n_bins, nullptr, b.scan_tmp, s);
-  if (b.n > 0) k_grid_scatter<<<blocks_for(b.n), kBlock, 0, s>>>(b);
-  k_grid_rowoff<<<blocks_for(n_seg), kBlock, 0, s>>>(b);
+  if (b.n > 0) TPC_LAUNCH("grid_scatter", blocks_for(b.n), kBlock, s, k_grid_scatter, b);
+  TPC_LAUNCH("grid_rowoff", blocks_for(n_seg), kBlock, s, k_grid_rowoff, b);
 #if TPC_DET
-  k_grid_binsort<<<blocks_for(b.bin_cap), kBlock, 0, s>>>(b);
+  TPC_LAUNCH("grid_binsort", blocks_for(b.bin_cap), kBlock, s, k_grid_binsort, b);
 #endif
   return hipGetLastError();
 }
 
 hipError_t sector_track(const Consts& k, const TrackBufs& b, hipStream_t s)
 {
-  k_track_init<<<1, 64, 0, s>>>(b);
+  TPC_LAUNCH("track_init", 1, 64, s, k_track_init, b);
   if (b.n > 0) {
-    k_neighbours<<<blocks_for(b.n), kBlock, 0, s>>>(k, b);
-    k_clean<<<blocks_for(b.n), kBlock, 0, s>>>(b);
+    TPC_LAUNCH("neighbours", blocks_for(b.n), kBlock, s, k_neighbours, k, b);
+    TPC_LAUNCH("clean", blocks_for(b.n), kBlock, s, k_clean, b);
 #if TPC_DET
     const int64_t nb = (b.n + kTile - 1) / kTile;
-    k_start_count<<<(unsigned)nb, kBlock, 0, s>>>(k, b, b.scan_tmp);
-    k_scan_partials<<<1, 1024, 0, s>>>(b.scan_tmp, nb, &b.counters[CNT_START]);
-    k_start_write<<<(unsigned)nb, kBlock, 0, s>>>(k, b, b.scan_tmp);
+    TPC_LAUNCH("start_count", (unsigned)nb, kBlock, s, k_start_count, k, b, b.scan_tmp);
+    TPC_LAUNCH("scan_partials", 1, 1024, s, k_scan_partials, b.scan_tmp, nb, &b.counters[CNT_START]);
+    TPC_LAUNCH("start_write", (unsigned)nb, kBlock, s, k_start_write, k, b, b.scan_tmp);
 #else
-    k_start_atomic<<<blocks_for(b.n), kBlock, 0, s>>>(k, b);
+    TPC_LAUNCH("start_atomic", blocks_for(b.n), kBlock, s, k_start_atomic, k, b);
 #endif
   }
-  k_start_finish<<<1, 1, 0, s>>>(b);
-  k_sel_prep<<<blocks_for(b.n > 0 ? b.n : 1), kBlock, 0, s>>>(b);
+  TPC_LAUNCH("start_finish", 1, 1, s, k_start_finish, b);
+  TPC_LAUNCH("sel_prep", blocks_for(b.n > 0 ? b.n : 1), kBlock, s, k_sel_prep, b);
   if (b.cap > 0) {
-    k_tracklets<<<blocks_for(b.cap), kBlock, 0, s>>>(k, b);
-    k_sel_mark<<<blocks_for(b.cap), kBlock, 0, s>>>(b);
-    k_sel_count<<<blocks_for(b.cap), kBlock, 0, s>>>(k, b, b.tl_own);
+    TPC_LAUNCH("tracklets", blocks_for(b.cap), kBlock, s, k_tracklets, k, b);
+    TPC_LAUNCH("sel_mark", blocks_for(b.cap), kBlock, s, k_sel_mark, b);
+    TPC_LAUNCH("sel_count", blocks_for(b.cap), kBlock, s, k_sel_count, k, b, b.tl_own);
 #if TPC_DET
     scan_exclusive<int64_t>(b.tsv, b.cap, &b.counters[CNT_START], &b.counters[CNT_TRACKS],
                             b.scan_tmp, s);
 #endif
-    k_sel_write<<<blocks_for(b.cap), kBlock, 0, s>>>(k, b, b.tl_own);
+    TPC_LAUNCH("sel_write", blocks_for(b.cap), kBlock, s, k_sel_write, k, b, b.tl_own);
   }
-  k_sel_finish<<<1, 1, 0, s>>>(b);
+  TPC_LAUNCH("sel_finish", 1, 1, s, k_sel_finish, b);
   return hipGetLastError();
 }
 

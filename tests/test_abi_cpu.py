@@ -55,9 +55,9 @@ def test_workspace_sizes_grow_and_layout_is_ordered():
     assert lay.cap_tracklets == 5000 // 3 + 4
     offs = [getattr(lay, f) for f in ("up", "dn", "up2", "dn2", "start", "tl_par", "tl_cov",
                                       "tl_chi2", "tl_nhit", "tl_rmin", "tl_rmax", "tl_status",
-                                      "tl_hit", "owner", "scratch", "total")]
+                                      "tl_hit", "tl_ncand", "owner", "scratch", "total")]
     assert offs == sorted(offs) and all(o % 256 == 0 for o in offs)
-    assert lay.tl_hit + 4 * 152 * lay.cap_tracklets <= lay.owner
+    assert lay.tl_hit + 4 * 152 * lay.cap_tracklets <= lay.tl_ncand
     assert L.tpc_grid_bin_capacity(C.c_int32(2), C.c_int64(100)) >= 2 * 100 + 2 * 152 * 9
 
 
