@@ -208,6 +208,8 @@ def main():
     ap.add_argument("--no-prod", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-every", type=int, default=4)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -216,6 +218,14 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     r, ev = run(args)
+    if args.copy_calib:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
     line = {
         "metric": METRIC,
         "value": r["N"] / r["dt_det"],

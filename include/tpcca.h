@@ -33,7 +33,7 @@
  *   positions  the grid orders the valid clusters of instance i by
  *              (row, bin, input index) into positions
  *              [inst_off[i], inst_off[i] + n_valid_i); the remaining positions
- *              of the instance are padding (sseg = perm = -1, ys = zs = 0).
+ *              of the instance are padding (sseg = perm = -1, y = z = 0).
  *              Links and tracklet hits are positions; track hit lists and
  *              clu2trk use input indices.
  */
@@ -110,15 +110,15 @@ typedef struct {
  *   meta    [n_inst*152]
  *   bin_off [bin_cap]               bin_cap >= tpc_grid_bin_capacity()
  *   perm    [n_clusters]            input index of each position, -1 = padding
- *   ys, zs  [n_clusters]            cluster y, z in position order                   */
+ *   yz      [2*n_clusters]          cluster (y, z) pairs in position order, 8-byte
+ *                                   aligned                                          */
 typedef struct {
   int32_t* sseg;
   int32_t* row_off;
   tpc_row_meta* meta;
   int32_t* bin_off;
   int32_t* perm;
-  float* ys;
-  float* zs;
+  float* yz;
   int64_t bin_cap;
 } tpc_grid;
 
@@ -157,7 +157,7 @@ typedef struct {
  *   start              i32[cap_tracklets] start hits in list order
  *   tl_par             f32[5][cap_tracklets]   tl_cov f32[15][cap_tracklets]
  *   tl_chi2            f32[cap_tracklets]      tl_nhit, tl_rmin, tl_rmax, tl_status i32
- *   tl_hit             i32[152][cap_tracklets] (valid for rmin <= row <= rmax)
+ *   tl_hit             i32[cap_tracklets][152] (valid for rmin <= row <= rmax)
  *   tl_ncand           i32[cap_tracklets] grid candidates whose chi2 the extension
  *                      searches evaluated (instrumentation for byte counts)
  *   owner              u64[n_clusters]  selection keys per position          */

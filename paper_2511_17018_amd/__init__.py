@@ -64,8 +64,8 @@ class Clusters(C.Structure):
 
 class GridStruct(C.Structure):
     _fields_ = [("sseg", C.c_void_p), ("row_off", C.c_void_p), ("meta", C.c_void_p),
-                ("bin_off", C.c_void_p), ("perm", C.c_void_p), ("ys", C.c_void_p),
-                ("zs", C.c_void_p), ("bin_cap", C.c_int64)]
+                ("bin_off", C.c_void_p), ("perm", C.c_void_p), ("yz", C.c_void_p),
+                ("bin_cap", C.c_int64)]
 
 
 class TracksStruct(C.Structure):
@@ -170,12 +170,11 @@ class Grid:
     meta: torch.Tensor      # int32 [n_inst*152, 8]: ny, nz, bin_base, count, y0, z0, iwy, iwz (bits)
     bin_off: torch.Tensor
     perm: torch.Tensor
-    ys: torch.Tensor
-    zs: torch.Tensor
+    yz: torch.Tensor        # float32 [n, 2]: (y, z) of each position
 
     def struct(self) -> GridStruct:
         return GridStruct(_ptr(self.sseg), _ptr(self.row_off), _ptr(self.meta), _ptr(self.bin_off),
-                          _ptr(self.perm), _ptr(self.ys), _ptr(self.zs), self.bin_off.numel())
+                          _ptr(self.perm), _ptr(self.yz), self.bin_off.numel())
 
 
 @dataclass
@@ -200,8 +199,7 @@ def alloc_grid(n_inst: int, n: int, device="cuda") -> Grid:
     i32 = dict(dtype=torch.int32, device=device)
     return Grid(torch.empty(n, **i32), torch.empty(n_inst * (N_ROWS + 1), **i32),
                 torch.empty((n_inst * N_ROWS, 8), **i32), torch.empty(cap, **i32),
-                torch.empty(n, **i32), torch.empty(n, dtype=torch.float32, device=device),
-                torch.empty(n, dtype=torch.float32, device=device))
+                torch.empty(n, **i32), torch.empty((n, 2), dtype=torch.float32, device=device))
 
 
 def alloc_tracks(n: int, cap_tracks: int | None = None, cap_hits: int | None = None,

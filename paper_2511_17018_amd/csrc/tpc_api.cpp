@@ -139,6 +139,15 @@ Consts make_consts(const tpc_geometry* g, const tpc_params* p)
   return k;
 }
 
+int32_t device_cu_count()
+{
+  int dev = 0, cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1)
+    return 256;
+  return cu;
+}
+
 template <class T>
 T* at(void* base, int64_t off)
 {
@@ -215,7 +224,8 @@ tpc_status tpc_grid_build(const tpc_geometry* geom, const tpc_params* params, in
   tpc_status st = check_common(geom, params, n_inst, inst_off_host, inst_off_dev, in, &n);
   if (st != TPC_OK) return st;
   if (!grid || !result_dev || !ws_dev) return TPC_ERR_INVALID;
-  if (n > 0 && (!grid->sseg || !grid->perm || !grid->ys || !grid->zs)) return TPC_ERR_INVALID;
+  if (n > 0 && (!grid->sseg || !grid->perm || !grid->yz)) return TPC_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(grid->yz) % 8) return TPC_ERR_INVALID;
   if (!grid->row_off || !grid->meta || !grid->bin_off || grid->bin_cap < 1) return TPC_ERR_INVALID;
   const GridWs w = grid_ws(n_inst, n);
   if ((int64_t)ws_bytes < w.total) return TPC_ERR_WORKSPACE;
@@ -232,8 +242,7 @@ tpc_status tpc_grid_build(const tpc_geometry* geom, const tpc_params* params, in
   b.meta = grid->meta;
   b.bin_off = grid->bin_off;
   b.perm = grid->perm;
-  b.ys = grid->ys;
-  b.zs = grid->zs;
+  b.yz = reinterpret_cast<float2*>(grid->yz);
   // the workspace's fill counters and scan partials are sized for this capacity
   const int64_t ws_cap = tpc_grid_bin_capacity(n_inst, n);
   b.bin_cap = grid->bin_cap < ws_cap ? grid->bin_cap : ws_cap;
@@ -263,7 +272,7 @@ tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, 
   tpc_status st = check_common(geom, params, n_inst, inst_off_host, inst_off_dev, in, &n);
   if (st != TPC_OK) return st;
   if (!grid || !out || !result_dev || !ws_dev) return TPC_ERR_INVALID;
-  if (n > 0 && (!grid->sseg || !grid->perm || !grid->ys || !grid->zs || !out->clu2trk))
+  if (n > 0 && (!grid->sseg || !grid->perm || !grid->yz || !out->clu2trk))
     return TPC_ERR_INVALID;
   if (!grid->row_off || !grid->meta || !grid->bin_off) return TPC_ERR_INVALID;
   if (out->cap_tracks < 0 || out->cap_hits < 0 || !out->hit_off) return TPC_ERR_INVALID;
@@ -283,8 +292,8 @@ tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, 
   b.meta = grid->meta;
   b.bin_off = grid->bin_off;
   b.perm = grid->perm;
-  b.ys = grid->ys;
-  b.zs = grid->zs;
+  if (reinterpret_cast<uintptr_t>(grid->yz) % 8) return TPC_ERR_INVALID;
+  b.yz = reinterpret_cast<const float2*>(grid->yz);
   b.up = at<int32_t>(ws_dev, w.pub.up);
   b.dn = at<int32_t>(ws_dev, w.pub.dn);
   b.up2 = at<int32_t>(ws_dev, w.pub.up2);
@@ -308,6 +317,7 @@ tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, 
   b.scan_tmp_len = w.scan_len;
   b.out = *out;
   b.res = result_dev;
+  b.n_cu = device_cu_count();
   const Consts k = make_consts(geom, params);
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = (params->flags & TPC_FLAG_DETERMINISTIC) ? det::sector_track(k, b, s)

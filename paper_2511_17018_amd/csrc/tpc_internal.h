@@ -38,7 +38,7 @@ struct GridBufs {
   tpc_row_meta* meta;
   int32_t* bin_off;
   int32_t* perm;
-  float *ys, *zs;
+  float2* yz;
   int64_t bin_cap;
   tpc_result* res;
   // workspace
@@ -62,7 +62,7 @@ struct TrackBufs {
   const tpc_row_meta* meta;
   const int32_t* bin_off;
   const int32_t* perm;
-  const float *ys, *zs;
+  const float2* yz;
   // workspace
   int32_t *up, *dn, *up2, *dn2;
   int32_t* start;
@@ -79,6 +79,7 @@ struct TrackBufs {
   int64_t* scan_tmp;
   int64_t scan_tmp_len;
   int64_t* counters;   // [8] device counters
+  int32_t n_cu;        // compute units of the device (sizes persistent grids)
   // outputs
   tpc_tracks out;
   tpc_result* res;

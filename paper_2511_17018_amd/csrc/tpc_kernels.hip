@@ -4,12 +4,16 @@
 // -ffp-contract=off and correctly rounded division / square root (the
 // deterministic mode's compile-time part, Sec. 2 of the paper), and into
 // tpcca::prod with contraction and fast reciprocal allowed (production mode).
-// TPC_DET selects the run-time part: ordering kernels (per-bin sort after the
-// atomic scatter, scan-ordered compaction) instead of atomic append.
+// TPC_DET also selects the run-time part: an ordering kernel after the grid's
+// atomic scatter (per-bin sort by input index) and scan-ordered track
+// compaction; the production build skips the sort and appends tracks with
+// atomics.  Start hits are compacted in scan order in both builds.
 //
 // Every floating-point expression on the deterministic path is written in the
 // operand order of the algorithm readings (R7-R11, R13-R20) so that, with
 // contraction off, each operation rounds exactly as in the CPU reference.
+#include <algorithm>
+
 #include "tpc_internal.h"
 
 #ifndef TPC_NS
@@ -32,7 +36,8 @@ constexpr float kSixth = 0x1.555556p-3f;
 constexpr float k3_40 = 0x1.333334p-4f;
 constexpr float k3_20 = 0x1.333334p-3f;
 
-enum { CNT_START = 0, CNT_TRACKS = 1 };
+enum { CNT_START = 0, CNT_TRACKS = 1, CNT_TLQUEUE = 2 };
+constexpr int kTlBlocksPerCU = 8;   // resident blocks per CU of the persistent tracklet kernel
 
 // ------------------------------------------------------------------ helpers
 
@@ -399,8 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_scatter(GridBufs b)
   int pos = b.bin_off[j] + atomicAdd(&b.fill[j], 1);
   b.sseg[pos] = seg;
   b.perm[pos] = (int32_t)c;
-  b.ys[pos] = y;
-  b.zs[pos] = z;
+  b.yz[pos] = make_float2(y, z);
 }
 
 __global__ void k_grid_rowoff(GridBufs b)
@@ -419,8 +423,7 @@ __global__ void k_grid_rowoff(GridBufs b)
     for (int64_t p = end; p < b.inst_off[i + 1]; p++) {
       b.sseg[p] = -1;
       b.perm[p] = -1;
-      b.ys[p] = 0.0f;
-      b.zs[p] = 0.0f;
+      b.yz[p] = make_float2(0.0f, 0.0f);
     }
   }
 }
@@ -438,18 +441,16 @@ __global__ __launch_bounds__(kBlock) void k_grid_binsort(GridBufs b)
   int e = j + 1 < tot ? b.bin_off[j + 1] : (int)b.n;
   if (e - a < 2) return;
   for (int p = a + 1; p < e; p++) {
-    int kp = b.perm[p];
-    float ky = b.ys[p], kz = b.zs[p];
+    const int kp = b.perm[p];
+    const float2 kv = b.yz[p];
     int q = p - 1;
     while (q >= a && b.perm[q] > kp) {
       b.perm[q + 1] = b.perm[q];
-      b.ys[q + 1] = b.ys[q];
-      b.zs[q + 1] = b.zs[q];
+      b.yz[q + 1] = b.yz[q];
       q--;
     }
     b.perm[q + 1] = kp;
-    b.ys[q + 1] = ky;
-    b.zs[q + 1] = kz;
+    b.yz[q + 1] = kv;
   }
 }
 
@@ -472,15 +473,51 @@ __global__ void k_track_init(TrackBufs b)
 }
 
 // NeighboursFinder (R11): best (u on r+1, d on r-1) straight-line pair.
+// The down-row candidates inside the box are staged once per cluster in LDS
+// (thread-major layout, conflict-free); clusters with more than kNfStage of
+// them take the rescan path.  The pair choice is a total order, so the visit
+// order does not change the result.
+constexpr int kNfStage = 12;
+
+struct NfBest {
+  int32_t u = -1, d = -1, pu = 0, pd = 0;
+  float s = 0.0f;
+};
+
+__device__ __forceinline__ void nf_consider(const TrackBufs& b, NfBest& best, float sc, int32_t u,
+                                            int32_t d)
+{
+  if (best.u < 0 || sc < best.s) {
+    best.u = u;
+    best.d = d;
+    best.s = sc;
+    best.pu = b.perm[u];
+    best.pd = b.perm[d];
+  } else if (sc == best.s) {
+    const int32_t pu = b.perm[u], pd = b.perm[d];
+    if (pu < best.pu || (pu == best.pu && pd < best.pd)) {
+      best.u = u;
+      best.d = d;
+      best.pu = pu;
+      best.pd = pd;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_neighbours(Consts k, TrackBufs b)
 {
+  __shared__ float s_y[kNfStage][kBlock];
+  __shared__ float s_z[kNfStage][kBlock];
+  __shared__ int32_t s_i[kNfStage][kBlock];
   const int64_t h = gtid();
   if (h >= b.n) return;
-  int32_t bu = -1, bd = -1;
+  const int tx = threadIdx.x;
+  NfBest best;
   const int seg = b.sseg[h];
   const int r = seg >= 0 ? seg % kRows : 0;
   if (seg >= 0 && r > 0 && r < kRows - 1) {
-    const float yh = b.ys[h], zh = b.zs[h];
+    const float2 qh = b.yz[h];
+    const float yh = qh.x, zh = qh.y;
     const float wy = k.nf_win_y, wz = k.nf_win_z;
     const float wym = wy + k.search_margin, wzm = wz + k.search_margin;
     const float cmax = k.nf_chi2_max, ivy = k.ivy, ivz = k.ivz;
@@ -496,49 +533,60 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(Consts k, TrackBufs b)
     const int dyhi = bin_coord(yh + wym, md.y0, md.iwy, md.ny);
     const int dzlo = bin_coord(zh - wzm, md.z0, md.iwz, md.nz);
     const int dzhi = bin_coord(zh + wzm, md.z0, md.iwz, md.nz);
-    float bs = 0.0f;
-    int32_t bpu = 0, bpd = 0;
-    for (int izu = uzlo; izu <= uzhi; izu++) {
-      const int ub = mu.bin_base + izu * mu.ny;
-      const int ue = b.bin_off[ub + uyhi + 1];
-      for (int u = b.bin_off[ub + uylo]; u < ue; u++) {
-        const float yu = b.ys[u], zu = b.zs[u];
-        if (!(fabsf(yu - yh) <= wy && fabsf(zu - zh) <= wz)) continue;
-        for (int izd = dzlo; izd <= dzhi; izd++) {
-          const int db = md.bin_base + izd * md.ny;
-          const int de = b.bin_off[db + dyhi + 1];
-          for (int d = b.bin_off[db + dylo]; d < de; d++) {
-            const float yd = b.ys[d], zd = b.zs[d];
-            if (!(fabsf(yd - yh) <= wy && fabsf(zd - zh) <= wz)) continue;
-            const float ey = yh - (yd + (yu - yd) * t);
-            const float ez = zh - (zd + (zu - zd) * t);
-            const float sc = (ey * ey) * ivy + (ez * ez) * ivz;
-            if (!(sc <= cmax)) continue;
-            bool take = bu < 0 || sc < bs;
-            int32_t pu = 0, pd = 0;
-            if (!take && sc == bs) {
-              pu = b.perm[u];
-              pd = b.perm[d];
-              take = pu < bpu || (pu == bpu && pd < bpd);
+    // stage the down candidates
+    int nd = 0;
+    for (int izd = dzlo; izd <= dzhi; izd++) {
+      const int db = md.bin_base + izd * md.ny;
+      const int de = b.bin_off[db + dyhi + 1];
+      for (int d = b.bin_off[db + dylo]; d < de; d++) {
+        const float2 qd = b.yz[d];
+        const float yd = qd.x, zd = qd.y;
+        if (!(fabsf(yd - yh) <= wy && fabsf(zd - zh) <= wz)) continue;
+        if (nd < kNfStage) {
+          s_y[nd][tx] = yd;
+          s_z[nd][tx] = zd;
+          s_i[nd][tx] = d;
+        }
+        nd++;
+      }
+    }
+    if (nd > 0) {
+      for (int izu = uzlo; izu <= uzhi; izu++) {
+        const int ub = mu.bin_base + izu * mu.ny;
+        const int ue = b.bin_off[ub + uyhi + 1];
+        for (int u = b.bin_off[ub + uylo]; u < ue; u++) {
+          const float2 qu = b.yz[u];
+          const float yu = qu.x, zu = qu.y;
+          if (!(fabsf(yu - yh) <= wy && fabsf(zu - zh) <= wz)) continue;
+          if (nd <= kNfStage) {
+            for (int j = 0; j < nd; j++) {
+              const float yd = s_y[j][tx], zd = s_z[j][tx];
+              const float ey = yh - (yd + (yu - yd) * t);
+              const float ez = zh - (zd + (zu - zd) * t);
+              const float sc = (ey * ey) * ivy + (ez * ez) * ivz;
+              if (sc <= cmax) nf_consider(b, best, sc, u, s_i[j][tx]);
             }
-            if (take) {
-              if (bu < 0 || sc < bs) {
-                pu = b.perm[u];
-                pd = b.perm[d];
+          } else {
+            for (int izd = dzlo; izd <= dzhi; izd++) {
+              const int db = md.bin_base + izd * md.ny;
+              const int de = b.bin_off[db + dyhi + 1];
+              for (int d = b.bin_off[db + dylo]; d < de; d++) {
+                const float2 qd = b.yz[d];
+        const float yd = qd.x, zd = qd.y;
+                if (!(fabsf(yd - yh) <= wy && fabsf(zd - zh) <= wz)) continue;
+                const float ey = yh - (yd + (yu - yd) * t);
+                const float ez = zh - (zd + (zu - zd) * t);
+                const float sc = (ey * ey) * ivy + (ez * ez) * ivz;
+                if (sc <= cmax) nf_consider(b, best, sc, u, d);
               }
-              bu = u;
-              bd = d;
-              bs = sc;
-              bpu = pu;
-              bpd = pd;
             }
           }
         }
       }
     }
   }
-  b.up[h] = bu;
-  b.dn[h] = bd;
+  b.up[h] = best.u;
+  b.dn[h] = best.d;
 }
 
 // NeighboursCleaner: mutual links only (reads the uncleaned arrays).
@@ -596,23 +644,6 @@ __global__ __launch_bounds__(kBlock) void k_start_write(Consts k, TrackBufs b, c
       if (o < b.cap) b.start[o] = (int32_t)(base + j);
       o++;
     }
-  }
-}
-
-// StartHitsFinder, production: wave ballot + one atomic per wave.
-__global__ __launch_bounds__(kBlock) void k_start_atomic(Consts k, TrackBufs b)
-{
-  const int64_t h = gtid();
-  bool f = is_start(b, k.min_chain, h);
-  unsigned long long m = __ballot(f);
-  const int lane = threadIdx.x & 63;
-  int64_t base = 0;
-  if (lane == 0 && m)
-    base = (int64_t)atomicAdd((unsigned long long*)&b.counters[CNT_START], (unsigned long long)__popcll(m));
-  base = __shfl(base, 0, 64);
-  if (f) {
-    int64_t o = base + __popcll(m & ((1ull << lane) - 1ull));
-    if (o < b.cap) b.start[o] = (int32_t)h;
   }
 }
 
@@ -727,9 +758,8 @@ __device__ __forceinline__ float chi2_of(const Innov& q, float r0, float r1)
 }
 
 // R9
-__device__ __forceinline__ float kupdate(KSt& s, float my, float mz, float vy, float vz)
+__device__ __forceinline__ float kupdate_q(KSt& s, const Innov& q, float my, float mz)
 {
-  const Innov q = innov(s, vy, vz);
   const float r0 = my - s.p[0], r1 = mz - s.p[1];
   const float chi2 = chi2_of(q, r0, r1);
   float k0[5], k1[5], hc0[5], hc1[5];
@@ -748,6 +778,11 @@ __device__ __forceinline__ float kupdate(KSt& s, float my, float mz, float vy, f
     for (int j = 0; j <= i; j++)
       s.c[ci(i, j)] = s.c[ci(i, j)] - (k0[i] * hc0[j] + k1[i] * hc1[j]);
   return chi2;
+}
+
+__device__ __forceinline__ float kupdate(KSt& s, float my, float mz, float vy, float vz)
+{
+  return kupdate_q(s, innov(s, vy, vz), my, mz);
 }
 
 // R15: best cluster of row segment `seg` for the predicted state
@@ -771,7 +806,8 @@ __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b, 
     const int p0 = b.bin_off[bb + ylo];
     ncand += e - p0;
     for (int p = p0; p < e; p++) {
-      const float r0 = b.ys[p] - y, r1 = b.zs[p] - z;
+      const float2 qc = b.yz[p];
+      const float r0 = qc.x - y, r1 = qc.y - z;
       const float ch = chi2_of(q, r0, r1);
       if (!(ch <= pick)) continue;
       if (best < 0 || ch < bchi) {
@@ -801,16 +837,12 @@ __device__ __forceinline__ void kinit_cov(KSt& s, float vy, float vz)
   s.c[14] = 100.0f;
 }
 
-// TrackletConstructor (R13-R17): one lane per start hit.
-__global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
+// TrackletConstructor (R13-R17) for tracklet t (one lane).
+__device__ __forceinline__ bool tracklet_one(const Consts& k, const TrackBufs& b, const int64_t t)
 {
-  const int64_t t = gtid();
-  const int64_t S = min(b.counters[CNT_START], b.cap);
-  if (t >= S) return;
-  const int64_t cap = b.cap;
   const float kB = k.kB, vy = k.vy, vz = k.vz, smax = k.snp_max;
   const float edge = k.edge_margin, tanh_ = k.tan_half;
-  int32_t* H = b.tl_hit + t;  // row r at H[r * cap]
+  int32_t* H = b.tl_hit + t * kRows;  // hit slot of row r at H[r]
   const int32_t h0 = b.start[t];
   const int seg0 = b.sseg[h0];
   const int segbase = seg0 - seg0 % kRows;
@@ -819,11 +851,12 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
   KSt st;
   {
     const float dxi = k.row_x[r0 + 2] - k.row_x[r0];
-    const float dyi = b.ys[h2] - b.ys[h0];
-    const float dzi = b.zs[h2] - b.zs[h0];
+    const float2 q0 = b.yz[h0], q2 = b.yz[h2];
+    const float dyi = q2.x - q0.x;
+    const float dzi = q2.y - q0.y;
     const float Li = sqrtf(dxi * dxi + dyi * dyi);
-    st.p[0] = b.ys[h0];
-    st.p[1] = b.zs[h0];
+    st.p[0] = q0.x;
+    st.p[1] = q0.y;
     st.p[2] = dyi / Li;
     st.p[3] = dzi / Li;
     st.p[4] = 0.0f;
@@ -831,7 +864,7 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
   }
   float chi2 = 0.0f;
   int n = 1, rmax = r0, rmin = r0, stat = 0, ncand = 0;
-  H[(int64_t)r0 * cap] = h0;
+  H[r0] = h0;
   int r = r0;
   int32_t h = h0;
   bool ok_up = true;
@@ -842,8 +875,9 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
       break;
     }
     r++;
-    chi2 += kupdate(st, b.ys[hn], b.zs[hn], vy, vz);
-    H[(int64_t)r * cap] = hn;
+    const float2 qn = b.yz[hn];
+    chi2 += kupdate(st, qn.x, qn.y, vy, vz);
+    H[r] = hn;
     n++;
     rmax = r;
     h = hn;
@@ -859,14 +893,15 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
       const Innov q = innov(st, vy, vz);
       const int32_t bh = ksearch(k, b, segbase + r, st, q, ncand);
       if (bh >= 0) {
-        chi2 += kupdate(st, b.ys[bh], b.zs[bh], vy, vz);
-        H[(int64_t)r * cap] = bh;
+        const float2 qb = b.yz[bh];
+        chi2 += kupdate_q(st, q, qb.x, qb.y);
+        H[r] = bh;
         n++;
         rmax = r;
         keep = st;
         miss = 0;
       } else {
-        H[(int64_t)r * cap] = -1;
+        H[r] = -1;
         if (++miss >= k.tc_max_miss) break;
       }
     }
@@ -891,20 +926,22 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
       const Innov q = innov(st, vy, vz);
       const int32_t bh = ksearch(k, b, segbase + r, st, q, ncand);
       if (bh >= 0) {
-        chi2 += kupdate(st, b.ys[bh], b.zs[bh], vy, vz);
-        H[(int64_t)r * cap] = bh;
+        const float2 qb = b.yz[bh];
+        chi2 += kupdate_q(st, q, qb.x, qb.y);
+        H[r] = bh;
         n++;
         rmin = r;
         keep = st;
         miss = 0;
       } else {
-        H[(int64_t)r * cap] = -1;
+        H[r] = -1;
         if (++miss >= k.tc_max_miss) break;
       }
     }
     if (n < k.min_tracklet_hits) stat = 1;
     else if (!(chi2 >= 0.0f && chi2 <= 3.0e38f)) stat = 3;
   }
+  const int64_t cap = b.cap;
 #pragma unroll
   for (int j = 0; j < 5; j++) b.tl_par[j * cap + t] = keep.p[j];
 #pragma unroll
@@ -915,6 +952,29 @@ __global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
   b.tl_rmax[t] = rmax;
   b.tl_status[t] = stat;
   b.tl_ncand[t] = ncand;
+  return stat == 0;
+}
+
+// Persistent tracklet kernel: each wave takes the next 64 start hits from a
+// device queue until the list is exhausted (every wave reaches the exit once
+// the counter passes S), so long and short tracklets balance across CUs.
+__global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
+{
+  const int64_t S = min(b.counters[CNT_START], b.cap);
+  const int lane = threadIdx.x & 63;
+  int kept = 0;
+  for (;;) {
+    int64_t base = 0;
+    if (lane == 0)
+      base = (int64_t)atomicAdd((unsigned long long*)&b.counters[CNT_TLQUEUE], 64ull);
+    base = __shfl(base, 0, 64);
+    if (base >= S) break;
+    const int64_t t = base + lane;
+    if (t < S && tracklet_one(k, b, t)) kept++;
+  }
+  // one counter update per wave
+  for (int o = 32; o > 0; o >>= 1) kept += __shfl_xor(kept, o, 64);
+  if (lane == 0 && kept) atomicAdd((unsigned long long*)&b.res->n_tracklets_kept, (unsigned long long)kept);
 }
 
 // ------------------------------------------------------------------ a6 selection
@@ -938,49 +998,67 @@ __global__ __launch_bounds__(kBlock) void k_sel_prep(TrackBufs b)
   }
 }
 
+// The selection kernels run one wave per tracklet: the wave reads the
+// tracklet's hit slots (one 608-byte row) with consecutive lanes on
+// consecutive rows.
+constexpr int kWavesPerBlock = kBlock / 64;
+
+__device__ __forceinline__ int64_t wave_tracklet() { return (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); }
+
 __global__ __launch_bounds__(kBlock) void k_sel_mark(TrackBufs b)
 {
-  const int64_t t = gtid();
+  const int64_t t = wave_tracklet();
   const int64_t S = min(b.counters[CNT_START], b.cap);
   if (t >= S || b.tl_status[t] != 0) return;
   const unsigned long long key = ts_key(b, t);
+  const int lane = threadIdx.x & 63;
   const int r1 = b.tl_rmax[t];
-  for (int r = b.tl_rmin[t]; r <= r1; r++) {
-    const int32_t h = b.tl_hit[(int64_t)r * b.cap + t];
-    if (h >= 0) atomicMax(&b.owner[h], key);
+  const int32_t* H = b.tl_hit + t * kRows;
+  for (int r = b.tl_rmin[t] + lane; r <= r1; r += 64) {
+    const int32_t h = H[r];
+    // owners only grow: skip the atomic when a larger key is already there
+    if (h >= 0 && b.owner[h] < key) atomicMax(&b.owner[h], key);
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_sel_count(Consts k, TrackBufs b, int32_t* own_out)
 {
-  const int64_t t = gtid();
+  const int64_t t = wave_tracklet();
   const int64_t S = min(b.counters[CNT_START], b.cap);
   if (t >= S) return;
+  const int lane = threadIdx.x & 63;
   int own = 0;
   if (b.tl_status[t] == 0) {
-    atomicAdd((unsigned long long*)&b.res->n_tracklets_kept, 1ull);
     const unsigned long long key = ts_key(b, t);
     const int r1 = b.tl_rmax[t];
-    for (int r = b.tl_rmin[t]; r <= r1; r++) {
-      const int32_t h = b.tl_hit[(int64_t)r * b.cap + t];
-      if (h >= 0 && b.owner[h] == key) own++;
+    const int32_t* H = b.tl_hit + t * kRows;
+    for (int r0 = b.tl_rmin[t]; r0 <= r1; r0 += 64) {
+      const int r = r0 + lane;
+      bool o = false;
+      if (r <= r1) {
+        const int32_t h = H[r];
+        o = h >= 0 && b.owner[h] == key;
+      }
+      own += __popcll(__ballot(o));
     }
     if (own < k.min_track_hits) own = 0;
   }
-  own_out[t] = own;
-  const int64_t v = own ? ((int64_t)1 << 32) | own : 0;
+  if (lane == 0) {
+    own_out[t] = own;
+    const int64_t v = own ? ((int64_t)1 << 32) | own : 0;
 #if TPC_DET
-  b.tsv[t] = v;
+    b.tsv[t] = v;
 #else
-  b.tsv[t] = own ? (int64_t)atomicAdd((unsigned long long*)&b.counters[CNT_TRACKS],
-                                      (unsigned long long)v)
-                 : 0;
+    b.tsv[t] = own ? (int64_t)atomicAdd((unsigned long long*)&b.counters[CNT_TRACKS],
+                                        (unsigned long long)v)
+                   : 0;
 #endif
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_sel_write(Consts k, TrackBufs b, const int32_t* own_in)
 {
-  const int64_t t = gtid();
+  const int64_t t = wave_tracklet();
   const int64_t S = min(b.counters[CNT_START], b.cap);
   if (t >= S) return;
   const int own = own_in[t];
@@ -989,28 +1067,44 @@ __global__ __launch_bounds__(kBlock) void k_sel_write(Consts k, TrackBufs b, con
   const int64_t kk = v >> 32;
   const int64_t off = v & 0xFFFFFFFFll;
   if (kk >= b.out.cap_tracks || off + own > b.out.cap_hits) return;
+  const int lane = threadIdx.x & 63;
   const int64_t cap = b.cap;
-#pragma unroll
-  for (int j = 0; j < 5; j++) b.out.param[kk * 5 + j] = b.tl_par[j * cap + t];
-#pragma unroll
-  for (int j = 0; j < 15; j++) b.out.cov[kk * 15 + j] = b.tl_cov[j * cap + t];
-  b.out.chi2[kk] = b.tl_chi2[t];
-  b.out.ndf[kk] = 2 * b.tl_nhit[t] - 5;
+  if (lane < 5) b.out.param[kk * 5 + lane] = b.tl_par[lane * cap + t];
+  if (lane < 15) b.out.cov[kk * 15 + lane] = b.tl_cov[lane * cap + t];
   const int rmin = b.tl_rmin[t], rmax = b.tl_rmax[t];
-  b.out.x_ref[kk] = k.row_x[rmin];
-  const unsigned long long key = ts_key(b, t);
-  int64_t j = off;
-  for (int r = rmin; r <= rmax; r++) {
-    const int32_t h = b.tl_hit[(int64_t)r * cap + t];
-    if (h >= 0 && b.owner[h] == key) {
-      const int32_t c = b.perm[h];
-      b.out.hit_clu[j++] = c;
-      b.out.clu2trk[c] = (int32_t)kk;
+  if (lane == 0) {
+    b.out.chi2[kk] = b.tl_chi2[t];
+    b.out.ndf[kk] = 2 * b.tl_nhit[t] - 5;
+    b.out.x_ref[kk] = k.row_x[rmin];
+    b.out.hit_off[kk + 1] = (int32_t)(off + own);
+    // with enough capacity every track is written and the totals are the
+    // counts; only a truncated output needs the largest written index
+    const int64_t tot = b.counters[CNT_TRACKS];
+    if ((tot >> 32) > b.out.cap_tracks || (tot & 0xFFFFFFFFll) > b.out.cap_hits) {
+      atomicMax((unsigned long long*)&b.res->n_tracks, (unsigned long long)(kk + 1));
+      atomicMax((unsigned long long*)&b.res->n_hits, (unsigned long long)(off + own));
     }
   }
-  b.out.hit_off[kk + 1] = (int32_t)(off + own);
-  atomicMax((unsigned long long*)&b.res->n_tracks, (unsigned long long)(kk + 1));
-  atomicMax((unsigned long long*)&b.res->n_hits, (unsigned long long)(off + own));
+  const unsigned long long key = ts_key(b, t);
+  const int32_t* H = b.tl_hit + t * kRows;
+  int64_t j = off;
+  for (int r0 = rmin; r0 <= rmax; r0 += 64) {
+    const int r = r0 + lane;
+    int32_t h = -1;
+    bool o = false;
+    if (r <= rmax) {
+      h = H[r];
+      o = h >= 0 && b.owner[h] == key;
+    }
+    const unsigned long long m = __ballot(o);
+    if (o) {
+      const int64_t slot = j + __popcll(m & ((1ull << lane) - 1ull));
+      const int32_t c = b.perm[h];
+      b.out.hit_clu[slot] = c;
+      b.out.clu2trk[c] = (int32_t)kk;
+    }
+    j += __popcll(m);
+  }
 }
 
 __global__ void k_sel_finish(TrackBufs b)
@@ -1019,7 +1113,10 @@ __global__ void k_sel_finish(TrackBufs b)
   const int64_t nt = v >> 32, nh = v & 0xFFFFFFFFll;
   b.res->need_tracks = nt;
   b.res->need_hits = nh;
-  if (b.res->n_tracks < nt) {
+  if (nt <= b.out.cap_tracks && nh <= b.out.cap_hits) {
+    b.res->n_tracks = nt;
+    b.res->n_hits = nh;
+  } else {
     if (nt > b.out.cap_tracks) b.res->overflow |= 4;
     if (nh > b.out.cap_hits) b.res->overflow |= 8;
   }
@@ -1054,26 +1151,26 @@ hipError_t sector_track(const Consts& k, const TrackBufs& b, hipStream_t s)
   if (b.n > 0) {
     TPC_LAUNCH("neighbours", blocks_for(b.n), kBlock, s, k_neighbours, k, b);
     TPC_LAUNCH("clean", blocks_for(b.n), kBlock, s, k_clean, b);
-#if TPC_DET
+    // ordered compaction in both modes: start-list order sets the tracklet
+    // kernel's memory locality, so the scan is cheaper than atomic append
     const int64_t nb = (b.n + kTile - 1) / kTile;
     TPC_LAUNCH("start_count", (unsigned)nb, kBlock, s, k_start_count, k, b, b.scan_tmp);
     TPC_LAUNCH("scan_partials", 1, 1024, s, k_scan_partials, b.scan_tmp, nb, &b.counters[CNT_START]);
     TPC_LAUNCH("start_write", (unsigned)nb, kBlock, s, k_start_write, k, b, b.scan_tmp);
-#else
-    TPC_LAUNCH("start_atomic", blocks_for(b.n), kBlock, s, k_start_atomic, k, b);
-#endif
   }
   TPC_LAUNCH("start_finish", 1, 1, s, k_start_finish, b);
   TPC_LAUNCH("sel_prep", blocks_for(b.n > 0 ? b.n : 1), kBlock, s, k_sel_prep, b);
   if (b.cap > 0) {
-    TPC_LAUNCH("tracklets", blocks_for(b.cap), kBlock, s, k_tracklets, k, b);
-    TPC_LAUNCH("sel_mark", blocks_for(b.cap), kBlock, s, k_sel_mark, b);
-    TPC_LAUNCH("sel_count", blocks_for(b.cap), kBlock, s, k_sel_count, k, b, b.tl_own);
+    const int64_t tl_blocks = std::min<int64_t>(blocks_for(b.cap), (int64_t)b.n_cu * kTlBlocksPerCU);
+    TPC_LAUNCH("tracklets", (unsigned)tl_blocks, kBlock, s, k_tracklets, k, b);
+    const unsigned wblocks = blocks_for(b.cap, kWavesPerBlock);
+    TPC_LAUNCH("sel_mark", wblocks, kBlock, s, k_sel_mark, b);
+    TPC_LAUNCH("sel_count", wblocks, kBlock, s, k_sel_count, k, b, b.tl_own);
 #if TPC_DET
     scan_exclusive<int64_t>(b.tsv, b.cap, &b.counters[CNT_START], &b.counters[CNT_TRACKS],
                             b.scan_tmp, s);
 #endif
-    TPC_LAUNCH("sel_write", blocks_for(b.cap), kBlock, s, k_sel_write, k, b, b.tl_own);
+    TPC_LAUNCH("sel_write", wblocks, kBlock, s, k_sel_write, k, b, b.tl_own);
   }
   TPC_LAUNCH("sel_finish", 1, 1, s, k_sel_finish, b);
   return hipGetLastError();

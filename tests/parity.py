@@ -36,7 +36,8 @@ def gpu_arrays(run: tpc.TrackRun, n: int) -> dict:
     h = lambda t: t.cpu().numpy()  # noqa: E731
     i32, f32 = torch.int32, torch.float32
     out = dict(
-        sseg=h(run.grid.sseg), perm=h(run.grid.perm), ys=h(run.grid.ys), zs=h(run.grid.zs),
+        sseg=h(run.grid.sseg), perm=h(run.grid.perm), ys=h(run.grid.yz)[:, 0].copy(),
+        zs=h(run.grid.yz)[:, 1].copy(),
         row_off=h(run.grid.row_off), meta=h(run.grid.meta), bin_off=h(run.grid.bin_off)[:nb],
         up=h(ws.view("up", i32, n)), dn=h(ws.view("dn", i32, n)),
         up2=h(ws.view("up2", i32, n)), dn2=h(ws.view("dn2", i32, n)),
@@ -48,7 +49,7 @@ def gpu_arrays(run: tpc.TrackRun, n: int) -> dict:
         tl_rmin=h(ws.view("tl_rmin", i32, cap))[:S],
         tl_rmax=h(ws.view("tl_rmax", i32, cap))[:S],
         tl_status=h(ws.view("tl_status", i32, cap))[:S],
-        tl_hit=h(ws.view("tl_hit", i32, NR * cap)).reshape(NR, cap)[:, :S].T.copy(),
+        tl_hit=h(ws.view("tl_hit", i32, NR * cap)).reshape(cap, NR)[:S].copy(),
         param=h(run.tracks.param)[:nt], cov=h(run.tracks.cov)[:nt], chi2=h(run.tracks.chi2)[:nt],
         ndf=h(run.tracks.ndf)[:nt], x_ref=h(run.tracks.x_ref)[:nt],
         hit_off=h(run.tracks.hit_off)[:nt + 1], hit_clu=h(run.tracks.hit_clu)[:nh],

@@ -67,7 +67,7 @@ def _args(geom=None, n_inst=1, off=(0, 10)):
     off = np.array(off, np.int64)
     dummy = C.c_void_p(0x1000)   # never dereferenced: validation fails first
     cl = tpc.Clusters(dummy, dummy, dummy, dummy, dummy)
-    gs = tpc.GridStruct(dummy, dummy, dummy, dummy, dummy, dummy, dummy, 100)
+    gs = tpc.GridStruct(dummy, dummy, dummy, dummy, dummy, dummy, 100)
     return g, p, off, cl, gs, dummy
 
 
