@@ -32,11 +32,14 @@ def build(force: bool = True, src: str | None = None, out: str | None = None) ->
     if not force and os.path.exists(out):
         return out
     src = src or os.path.join(HERE, "tpc_oracle.c")
+    refit = os.path.join(HERE, "tpc_refit.c")
     objs = []
-    for tag, defs in (("f32", []), ("f64", ["-DORC_F64"])):
-        obj = out + f".{tag}.o"
-        subprocess.run(["gcc", *CFLAGS, *defs, "-I", HERE, "-c", src, "-o", obj], check=True)
-        objs.append(obj)
+    for name, tags in ((src, (("f32", []), ("f64", ["-DORC_F64"]))),
+                       (refit, (("rf32", []), ("rf64", ["-DORC_F64"]), ("rc128", ["-DORC_C128"])))):
+        for tag, defs in tags:
+            obj = out + f".{tag}.o"
+            subprocess.run(["gcc", *CFLAGS, *defs, "-I", HERE, "-c", name, "-o", obj], check=True)
+            objs.append(obj)
     tmp = out + ".tmp"
     subprocess.run(["gcc", "-shared", "-o", tmp, *objs, "-lm"], check=True)
     os.replace(tmp, out)
@@ -340,3 +343,76 @@ def update(geom, p, c, my, mz, prec=64):
     f.restype = sc
     ch = f(C.byref(g), _p(p), _p(c), sc(my), sc(mz))
     return float(ch), p, c
+
+
+# ----------------------------------------------------------------------------
+# refit (a8) and its adjoint (a9)
+
+def _refit_args(geom, params, ev_like, hit_off, hit_clu, seed, dmap):
+    g, P = make_geom(geom), params if isinstance(params, Params) else make_params(**params)
+    arrs = dict(hit_off=np.ascontiguousarray(hit_off, np.int32),
+                hit_clu=np.ascontiguousarray(hit_clu, np.int32),
+                sector=np.ascontiguousarray(ev_like.sector, np.uint8),
+                x=np.ascontiguousarray(ev_like.x, np.float32),
+                y=np.ascontiguousarray(ev_like.y, np.float32),
+                z=np.ascontiguousarray(ev_like.z, np.float32),
+                row=np.ascontiguousarray(ev_like.row, np.uint16),
+                seed=np.ascontiguousarray(seed, np.float32),
+                dmap=np.ascontiguousarray(dmap, np.float32))
+    return g, P, arrs
+
+
+def refit(geom, params, ev_like, hit_off, hit_clu, seed, dmap, prec=32):
+    """Forward refit: (chi2[n], status[n], ckpt[n_hits, 20])."""
+    g, P, a = _refit_args(geom, params, ev_like, hit_off, hit_clu, seed, dmap)
+    n = len(a["hit_off"]) - 1
+    nh = int(a["hit_off"][-1])
+    dt = _dt(prec)
+    chi2 = np.zeros(max(n, 1), dt)
+    status = np.zeros(max(n, 1), np.int32)
+    ckpt = np.zeros((max(nh, 1), 20), dt)
+    f = _fn("orc_refit", prec)
+    f.restype = None
+    f(C.byref(g), C.byref(P), C.c_int64(n), _p(a["hit_off"]), _p(a["hit_clu"]), _p(a["sector"]),
+      _p(a["x"]), _p(a["y"]), _p(a["z"]), _p(a["row"]), _p(a["seed"]), _p(a["dmap"]), _p(chi2),
+      _p(status), _p(ckpt))
+    return chi2[:n], status[:n], ckpt[:nh]
+
+
+REFIT_WHICH = {"x": 0, "y": 1, "z": 2, "map": 3}
+
+
+def refit_loss(geom, params, ev_like, hit_off, hit_clu, seed, dmap, w, which=None, idx=-1,
+               h=0.0, mode="f64"):
+    """sum_t w_t chi2_t with one input perturbed by h (mode f64 / f32), or
+    the complex-step derivative w.r.t. that input (mode c128)."""
+    g, P, a = _refit_args(geom, params, ev_like, hit_off, hit_clu, seed, dmap)
+    n = len(a["hit_off"]) - 1
+    w = np.ascontiguousarray(w, np.float64)
+    f = getattr(lib(), f"orc_refit_loss_{mode}")
+    f.restype = C.c_double
+    return f(C.byref(g), C.byref(P), C.c_int64(n), _p(a["hit_off"]), _p(a["hit_clu"]),
+             _p(a["sector"]), _p(a["x"]), _p(a["y"]), _p(a["z"]), _p(a["row"]), _p(a["seed"]),
+             _p(a["dmap"]), _p(w), C.c_int(-1 if which is None else REFIT_WHICH[which]),
+             C.c_int64(idx), C.c_double(h))
+
+
+def refit_grad(geom, params, ev_like, hit_off, hit_clu, seed, dmap, w=None):
+    """binary64 forward + reverse pass: (chi2, status, gmap[152,18], gx, gy, gz)."""
+    chi2, status, ckpt = refit(geom, params, ev_like, hit_off, hit_clu, seed, dmap, prec=64)
+    g, P, a = _refit_args(geom, params, ev_like, hit_off, hit_clu, seed, dmap)
+    n = len(a["hit_off"]) - 1
+    nc = len(a["x"])
+    w = np.ones(n) if w is None else np.ascontiguousarray(w, np.float64)
+    gmap = np.zeros(g.n_rows * 18)
+    gx = np.zeros(max(nc, 1))
+    gy = np.zeros(max(nc, 1))
+    gz = np.zeros(max(nc, 1))
+    f = lib().orc_refit_grad_f64
+    f.restype = None
+    ck = np.ascontiguousarray(ckpt, np.float64) if len(ckpt) else np.zeros((1, 20))
+    f(C.byref(g), C.byref(P), C.c_int64(n), _p(a["hit_off"]), _p(a["hit_clu"]), _p(a["sector"]),
+      _p(a["x"]), _p(a["y"]), _p(a["z"]), _p(a["row"]), _p(a["seed"]), _p(a["dmap"]), _p(ck),
+      _p(np.ascontiguousarray(status, np.int32)), _p(w), C.c_int64(nc), _p(gmap), _p(gx), _p(gy),
+      _p(gz))
+    return chi2, status, gmap.reshape(g.n_rows, 18), gx[:nc], gy[:nc], gz[:nc]

@@ -384,9 +384,9 @@ def distortion_map(rng, amp=1.0) -> np.ndarray:
 
 
 def config5(rep=0, n_found=200_000, min_hits=10, smear=True, amp=1.0) -> Event:
-    """Found-track hit lists (MC truth, one list per track and sector instance)
-    for the Kalman refit; true hits lie on planes x_r + D_true[r][k] while the
-    clusters record x_r."""
+    """Found-track hit lists (MC truth, one list per track and sector instance,
+    the part of the outgoing leg with |snp| < 0.95) for the Kalman refit; true
+    hits lie on planes x_r + D_true[r][k] while the clusters record x_r."""
     seed = SEED_BASE + 5 + 0x100 * rep
     rng = np.random.Generator(np.random.PCG64(seed))
     geom = geometry()
@@ -396,6 +396,10 @@ def config5(rep=0, n_found=200_000, min_hits=10, smear=True, amp=1.0) -> Event:
     while got < n_found:
         trk = _central_tracks(rng, 8000, rng.normal(0, 5.0))
         cr = _chunked_crossings(trk, geom["row_x"], dist=D)
+        # a tracker follows a track while |snp| stays well below 1 (loopers
+        # turn over at the end of the outgoing leg): keep that part
+        keep = np.abs(cr["snp"]) < 0.95
+        cr = {k: v[keep] for k, v in cr.items()}
         cr["trk"] = cr["trk"] + id0
         id0 += 8000
         parts_trk.append(trk)
