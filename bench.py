@@ -15,6 +15,9 @@ batch, with the clusters already resident in HBM.  Reported:
                its average launch time (HIP events recorded on the kernel's
                stream over a timed pass), against the 8 TB/s HBM peak
   cpu_baseline the single-threaded CPU oracle on a sample of the instances
+  refit        the differentiable Kalman refit of 200k found tracks (forward
+               and reverse pass) in tracks/s, with its own roofline and CPU
+               baseline
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -55,6 +58,10 @@ def kernel_bytes(name: str, c: dict) -> float | None:
         "tracklets": 4 * S + 16 * Ht + 8 * E + 88 * S,
         "sel_mark": 4 * Ht + 16 * Ht,
         "sel_count": 4 * Ht + 8 * Ht,
+        # refit, per track-hit: hit index 4, cluster x,y,z 12, row 2, sector 1,
+        # checkpoint 80 (written forward, read backward), gradient x,y,z 12
+        "refit_fwd": 99 * c.get("Hr", 0),
+        "refit_bwd": 111 * c.get("Hr", 0),
     }
     return table.get(name)
 
@@ -175,6 +182,94 @@ def run(args) -> dict:
     return out, ev
 
 
+def run_refit(args) -> dict:
+    """Refit forward + reverse pass over 200k found tracks (config 5)."""
+    import torch
+
+    import paper_2511_17018_amd as tpc
+    import synth
+
+    t0 = time.time()
+    ev = synth.config5()
+    ho, hc, seed = ev.extra["hit_off"], ev.extra["hit_clu"], ev.extra["seed_par"]
+    n_trk, n_hits = len(ho) - 1, int(ho[-1])
+    log(f"refit: generated {n_trk} tracks, {n_hits} hits ({time.time() - t0:.1f}s)")
+    dev = "cuda:0"
+    L = tpc.lib()
+    xyz = torch.from_numpy(np.stack([ev.x, ev.y, ev.z]).astype(np.float32)).to(dev)
+    row = torch.from_numpy(ev.row.view(np.int16)).to(dev)
+    trk = tpc.upload_refit_tracks(ho, hc, ev.sector, seed, dev)
+    dmap = torch.zeros((152, 18), dtype=torch.float32, device=dev)   # start of a map fit
+    chi2 = torch.empty(n_trk, dtype=torch.float32, device=dev)
+    status = torch.empty(n_trk, dtype=torch.int32, device=dev)
+    ckpt = torch.empty((n_hits, 20), dtype=torch.float32, device=dev)
+    gmap = torch.empty((152, 18), dtype=torch.float32, device=dev)
+    gxyz = torch.empty((3, xyz.shape[1]), dtype=torch.float32, device=dev)
+    ones = torch.ones(n_trk, dtype=torch.float32, device=dev)
+    L.tpc_refit_workspace_bytes.restype = C.c_size_t
+    ws = torch.empty(int(L.tpc_refit_workspace_bytes()), dtype=torch.uint8, device=dev)
+    geom = tpc.make_geometry(synth.geometry())
+    par = tpc.make_params(True)
+    cl = tpc._xyz_struct(xyz, row)
+    ts = trk.struct()
+    sp = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    fa = (C.byref(geom), C.byref(par), C.c_int64(xyz.shape[1]), cl, ts, tpc._ptr(dmap),
+          tpc._ptr(chi2), tpc._ptr(status), tpc._ptr(ckpt), sp)
+    ba = (C.byref(geom), C.byref(par), C.c_int64(xyz.shape[1]), cl, ts, tpc._ptr(dmap),
+          tpc._ptr(ckpt), tpc._ptr(status), tpc._ptr(ones), tpc._ptr(gmap), tpc._ptr(gxyz[0]),
+          tpc._ptr(gxyz[1]), tpc._ptr(gxyz[2]), tpc._ptr(ws), C.c_size_t(ws.numel()), sp)
+
+    def step():
+        if L.tpc_refit(*fa) or L.tpc_refit_backward(*ba):
+            raise RuntimeError("refit call failed")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    log(f"refit fwd+bwd: {dt * 1e3:.3f} ms/step, {n_trk / dt / 1e6:.3f} M tracks/s")
+    assert L.tpc_profile_enable(1) == 0
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    rows = (tpc_kernel_time * 64)()
+    nk = L.tpc_profile_read(rows, 64)
+    L.tpc_profile_enable(0)
+    kt = {rows[i].name.decode(): (rows[i].total_ms, rows[i].launches) for i in range(nk)}
+    out = {"value": n_trk / dt, "unit": "tracks/s", "ms_per_step": dt * 1e3,
+           "workload": f"{n_trk} found tracks, {n_hits} hits, map 152x18 at zero, "
+                       "forward + reverse pass, sum of chi2",
+           "n_tracks": n_trk, "n_hits": n_hits,
+           "failed_tracks": int((status != 0).sum().item()),
+           "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kt.items()}}
+    rl = {}
+    for name in ("refit_fwd", "refit_bwd"):
+        if name in kt:
+            avg_s = kt[name][0] / kt[name][1] / 1e3
+            kb = kernel_bytes(name, dict(N=0, S=0, Ht=0, E=0, Hr=n_hits))
+            rl[name] = {"bound": "hbm", "achieved": kb / avg_s / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": kb / avg_s / 1e9 / HBM_PEAK_GBS,
+                        "avg_launch_ms": avg_s * 1e3, "alg_bytes_per_launch": kb}
+    out["roofline"] = rl
+    if not args.no_cpu:
+        import oracle
+        sub = 4000
+        hs = ho[:sub + 1]
+        t = time.perf_counter()
+        oracle.refit_grad(synth.geometry(), oracle.DEFAULT_PARAMS, ev, hs, hc[:hs[-1]], seed[:sub],
+                          np.zeros((152, 18), np.float32))
+        tc = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": sub / tc, "unit": "tracks/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"first {sub} tracks, binary64 forward + reverse pass, "
+                                         "one thread"}
+    return out
+
+
 def cpu_baseline(ev, every: int) -> dict:
     import oracle
     import synth
@@ -208,6 +303,7 @@ def main():
     ap.add_argument("--no-prod", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-every", type=int, default=4)
+    ap.add_argument("--no-refit", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -250,6 +346,9 @@ def main():
             line[k] = r[k]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(ev, args.cpu_every)
+    if not args.no_refit:
+        del ev
+        line["refit"] = run_refit(args)
     print(json.dumps(line))
 
 

@@ -205,6 +205,55 @@ tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, 
                             tpc_result* result_dev, void* ws_dev, size_t ws_bytes,
                             int64_t cap_tracklets, void* stream);
 
+/* Found tracks for the refit (device arrays, caller-owned):
+ *   hit_off [n_tracks+1]   CSR offsets into hit_clu (hit_off[0] = 0)
+ *   hit_clu [n_hits]       cluster index of each hit, ascending row within a track
+ *   sector  [n_clusters]   phi-sector 0..17 of each cluster (selects the map column)
+ *   seed    [n_tracks][5]  (y, z, snp, tgl, qpt); the filter starts from the first
+ *                          hit's (y, z) and the seed's (snp, tgl, qpt), which are
+ *                          constants of the fit (not differentiated)            */
+typedef struct {
+  const int32_t* hit_off;
+  const int32_t* hit_clu;
+  const uint8_t* sector;
+  const float* seed;
+  int64_t n_tracks, n_hits;
+} tpc_refit_tracks;
+
+#define TPC_N_PHI 18
+
+/* a8: Kalman refit of found tracks under a per-row radial distortion map.
+ * Each hit is measured on the plane X = x + dist_map[row][sector % 18]; the
+ * filter of the tracker (propagation, Jacobian, update) runs from the first
+ * hit outwards; chi2[t] is the sum of the update chi2 values, status[t] = 1
+ * (and chi2 = 0) if the propagation failed (|snp| reaching snp_max).  The
+ * state after every update is checkpointed: ckpt[n_hits][20] = (y, z, snp,
+ * tgl, qpt, lower-triangular covariance).  With TPC_FLAG_DETERMINISTIC chi2
+ * and ckpt equal the binary32 CPU reference bit for bit.  This refit is the
+ * differentiable extension of the tracking step; the paper's shared track
+ * propagation with field and material maps (Sec. 4) is its context.
+ * Errors: TPC_ERR_INVALID (null pointers, n_tracks < 0, n_rows != 152). */
+tpc_status tpc_refit(const tpc_geometry* geom, const tpc_params* params, int64_t n_clusters,
+                     tpc_clusters in, tpc_refit_tracks trk, const float* dist_map_dev,
+                     float* chi2_dev, int32_t* status_dev, float* ckpt_dev, void* stream);
+
+/* a9: gradient of L = sum_t grad_chi2[t] * chi2[t] with respect to the map
+ * (grad_map[152][18]) and the cluster coordinates (grad_x, grad_y, grad_z,
+ * [n_clusters]; clusters on no refitted track get 0).  All outputs are
+ * overwritten.  Uses the forward call's ckpt and status (same inputs).
+ * Every step is rebuilt from the previous checkpoint and differentiated in
+ * reverse.  The map sums are exact 64-bit fixed-point sums (scale 2^24), so
+ * the gradient is identical from run to run.  ws_dev must hold
+ * tpc_refit_workspace_bytes() bytes (accumulators and an overflow flag that
+ * is set, and the sum clamped, if a hit's |dL/dX| exceeds 2^37). */
+size_t tpc_refit_workspace_bytes(void);
+tpc_status tpc_refit_backward(const tpc_geometry* geom, const tpc_params* params,
+                              int64_t n_clusters, tpc_clusters in, tpc_refit_tracks trk,
+                              const float* dist_map_dev, const float* ckpt_dev,
+                              const int32_t* status_dev, const float* grad_chi2_dev,
+                              float* grad_map_dev, float* grad_x_dev, float* grad_y_dev,
+                              float* grad_z_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
 /* Optional per-kernel timing for benchmarks.  tpc_profile_enable(1) creates
  * a pool of HIP events (host call, once); afterwards every kernel the library
  * enqueues is bracketed by two events recorded on the stream it is launched

@@ -397,9 +397,14 @@ def refit_loss(geom, params, ev_like, hit_off, hit_clu, seed, dmap, w, which=Non
              C.c_int64(idx), C.c_double(h))
 
 
-def refit_grad(geom, params, ev_like, hit_off, hit_clu, seed, dmap, w=None):
-    """binary64 forward + reverse pass: (chi2, status, gmap[152,18], gx, gy, gz)."""
-    chi2, status, ckpt = refit(geom, params, ev_like, hit_off, hit_clu, seed, dmap, prec=64)
+def refit_grad(geom, params, ev_like, hit_off, hit_clu, seed, dmap, w=None, ckpt=None,
+               status=None):
+    """binary64 forward + reverse pass: (chi2, status, gmap[152,18], gx, gy, gz).
+    With ckpt/status given (e.g. a binary32 forward's checkpoints) the reverse
+    pass runs on those instead of the binary64 forward's."""
+    chi2, st64, ck64 = refit(geom, params, ev_like, hit_off, hit_clu, seed, dmap, prec=64)
+    ckpt = ck64 if ckpt is None else ckpt
+    status = st64 if status is None else status
     g, P, a = _refit_args(geom, params, ev_like, hit_off, hit_clu, seed, dmap)
     n = len(a["hit_off"]) - 1
     nc = len(a["x"])

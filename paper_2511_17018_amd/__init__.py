@@ -283,3 +283,113 @@ def track(geom: dict, batch: Batch, det: bool = True, cap_tracks=None, cap_hits=
     sector_track(g, p, batch, grid, tracks, ws)
     torch.cuda.synchronize()
     return TrackRun(grid, tracks, ws, ws.read_result())
+
+
+# ----------------------------------------------------------------------------
+# differentiable refit (tpc_refit / tpc_refit_backward)
+
+N_PHI = 18
+
+
+class RefitTracksStruct(C.Structure):
+    _fields_ = [("hit_off", C.c_void_p), ("hit_clu", C.c_void_p), ("sector", C.c_void_p),
+                ("seed", C.c_void_p), ("n_tracks", C.c_int64), ("n_hits", C.c_int64)]
+
+
+@dataclass
+class RefitTracks:
+    """Found tracks on the GPU: CSR hit lists (cluster indices, ascending row),
+    per-cluster phi-sector, seeds (y, z, snp, tgl, qpt)."""
+    hit_off: torch.Tensor   # int32 [n_tracks+1]
+    hit_clu: torch.Tensor   # int32 [n_hits]
+    sector: torch.Tensor    # uint8 [n_clusters]
+    seed: torch.Tensor      # float32 [n_tracks, 5]
+
+    @property
+    def n_tracks(self) -> int:
+        return self.hit_off.numel() - 1
+
+    @property
+    def n_hits(self) -> int:
+        return self.hit_clu.numel()
+
+    def struct(self) -> RefitTracksStruct:
+        return RefitTracksStruct(_ptr(self.hit_off), _ptr(self.hit_clu), _ptr(self.sector),
+                                 _ptr(self.seed), self.n_tracks, self.n_hits)
+
+
+def upload_refit_tracks(hit_off, hit_clu, sector, seed, device="cuda") -> RefitTracks:
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dt)).to(device)  # noqa: E731
+    return RefitTracks(t(hit_off, np.int32), t(hit_clu, np.int32), t(sector, np.uint8),
+                       t(seed, np.float32))
+
+
+def _xyz_struct(xyz: torch.Tensor, row: torch.Tensor) -> Clusters:
+    return Clusters(_ptr(xyz[0]), _ptr(xyz[1]), _ptr(xyz[2]), _ptr(row), C.c_void_p(0))
+
+
+def refit(geom: dict, xyz: torch.Tensor, row: torch.Tensor, trk: RefitTracks,
+          dist_map: torch.Tensor, det: bool = True):
+    """tpc_refit on the current stream: (chi2[n], status[n], ckpt[n_hits, 20])."""
+    assert xyz.dtype == torch.float32 and xyz.is_contiguous() and xyz.shape[0] == 3
+    dev = xyz.device
+    n = trk.n_tracks
+    chi2 = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+    status = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    ckpt = torch.empty((max(trk.n_hits, 1), 20), dtype=torch.float32, device=dev)
+    g = make_geometry(geom)
+    p = make_params(det)
+    L = lib()
+    L.tpc_refit.restype = C.c_int
+    _check(L.tpc_refit(C.byref(g), C.byref(p), C.c_int64(xyz.shape[1]), _xyz_struct(xyz, row),
+                       trk.struct(), _ptr(dist_map.contiguous()), _ptr(chi2), _ptr(status),
+                       _ptr(ckpt), _stream()), "tpc_refit")
+    return chi2[:n], status[:n], ckpt[:trk.n_hits]
+
+
+def refit_backward(geom: dict, xyz: torch.Tensor, row: torch.Tensor, trk: RefitTracks,
+                   dist_map: torch.Tensor, ckpt: torch.Tensor, status: torch.Tensor,
+                   grad_chi2: torch.Tensor):
+    """tpc_refit_backward: (grad_map[152, 18], grad_xyz[3, n_clusters])."""
+    dev = xyz.device
+    nc = xyz.shape[1]
+    gmap = torch.empty((N_ROWS, N_PHI), dtype=torch.float32, device=dev)
+    gxyz = torch.empty((3, max(nc, 1)), dtype=torch.float32, device=dev)
+    L = lib()
+    L.tpc_refit_workspace_bytes.restype = C.c_size_t
+    L.tpc_refit_backward.restype = C.c_int
+    ws = torch.empty(int(L.tpc_refit_workspace_bytes()), dtype=torch.uint8, device=dev)
+    g = make_geometry(geom)
+    p = make_params(True)
+    ckpt_p = _ptr(ckpt) if trk.n_hits else C.c_void_p(0)
+    _check(L.tpc_refit_backward(
+        C.byref(g), C.byref(p), C.c_int64(nc), _xyz_struct(xyz, row), trk.struct(),
+        _ptr(dist_map.contiguous()), ckpt_p, _ptr(status), _ptr(grad_chi2.contiguous()),
+        _ptr(gmap), _ptr(gxyz[0]), _ptr(gxyz[1]), _ptr(gxyz[2]), _ptr(ws),
+        C.c_size_t(ws.numel()), _stream()), "tpc_refit_backward")
+    return gmap, gxyz[:, :nc]
+
+
+class TpcRefit(torch.autograd.Function):
+    """chi2[t] of every found track under the distortion map, differentiable
+    with respect to the cluster coordinates xyz[3, N] and the map [152, 18].
+
+        chi2 = TpcRefit.apply(xyz, dist_map, row, tracks, geom)
+        chi2.sum().backward()   # xyz.grad, dist_map.grad
+    """
+
+    @staticmethod
+    def forward(ctx, xyz, dist_map, row, tracks, geom, det=True):
+        xyz_c = xyz.detach().contiguous()
+        map_c = dist_map.detach().contiguous()
+        chi2, status, ckpt = refit(geom, xyz_c, row, tracks, map_c, det)
+        ctx.save_for_backward(xyz_c, map_c, ckpt, status)
+        ctx.row, ctx.tracks, ctx.geom = row, tracks, geom
+        return chi2
+
+    @staticmethod
+    def backward(ctx, grad_chi2):
+        xyz_c, map_c, ckpt, status = ctx.saved_tensors
+        gmap, gxyz = refit_backward(ctx.geom, xyz_c, ctx.row, ctx.tracks, map_c, ckpt, status,
+                                    grad_chi2.float().contiguous())
+        return gxyz, gmap, None, None, None, None

@@ -25,6 +25,8 @@ DET = ["-DTPC_NS=det", "-DTPC_DET=1", "-ffp-contract=off",
 PROD = ["-DTPC_NS=prod", "-DTPC_DET=0", "-ffp-contract=fast",
         "-fno-hip-fp32-correctly-rounded-divide-sqrt", "-freciprocal-math", "-fno-signed-zeros",
         "-fgpu-flush-denormals-to-zero"]
+# the refit's reverse pass is held to a tolerance, not to bits
+BWD = ["-ffast-math", "-fno-finite-math-only"]
 
 
 def _hipcc():
@@ -42,6 +44,12 @@ def build(verbose: bool = False) -> str:
           "-o", os.path.join(BUILD, "tpc_kernels_det.o")], "tpc_kernels_det.o"),
         ([_hipcc(), *COMMON, *PROD, "-c", os.path.join(CSRC, "tpc_kernels.hip"),
           "-o", os.path.join(BUILD, "tpc_kernels_prod.o")], "tpc_kernels_prod.o"),
+        ([_hipcc(), *COMMON, *DET, "-c", os.path.join(CSRC, "tpc_refit.hip"),
+          "-o", os.path.join(BUILD, "tpc_refit_det.o")], "tpc_refit_det.o"),
+        ([_hipcc(), *COMMON, *PROD, "-c", os.path.join(CSRC, "tpc_refit.hip"),
+          "-o", os.path.join(BUILD, "tpc_refit_prod.o")], "tpc_refit_prod.o"),
+        ([_hipcc(), *COMMON, *BWD, "-c", os.path.join(CSRC, "tpc_refit_bwd.hip"),
+          "-o", os.path.join(BUILD, "tpc_refit_bwd.o")], "tpc_refit_bwd.o"),
     ]
     procs = []
     for cmd, _ in jobs:

@@ -119,6 +119,7 @@ Consts make_consts(const tpc_geometry* g, const tpc_params* p)
   k.tan_half = g->tan_half_sector;
   // derived once in binary64 and rounded (the CPU reference does the same)
   k.kB = (float)(-0.299792458e-2 * (double)g->bz_tesla);
+  k.bz = g->bz_tesla;
   k.vy = g->sigma_y2;
   k.vz = g->sigma_z2;
   k.ivy = (float)(1.0 / (1.5 * (double)g->sigma_y2));
@@ -322,6 +323,91 @@ tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, 
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = (params->flags & TPC_FLAG_DETERMINISTIC) ? det::sector_track(k, b, s)
                                                            : prod::sector_track(k, b, s);
+  return e == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+}
+
+size_t tpc_refit_workspace_bytes(void) { return (size_t)(8 * kRows * kPhi + 256); }
+
+static tpc_status refit_check(const tpc_geometry* g, const tpc_params* p, int64_t n_clusters,
+                              const tpc_clusters& in, const tpc_refit_tracks& trk,
+                              const float* dmap)
+{
+  if (!g || !p || g->n_rows != kRows || n_clusters < 0 || trk.n_tracks < 0 || trk.n_hits < 0)
+    return TPC_ERR_INVALID;
+  if (!dmap || !(p->snp_max > 0) || !(p->snp_max < 1)) return TPC_ERR_INVALID;
+  if (trk.n_tracks > 0 && (!trk.hit_off || !trk.seed)) return TPC_ERR_INVALID;
+  if (trk.n_hits > 0 && (!trk.hit_clu || !trk.sector || !in.x || !in.y || !in.z || !in.row))
+    return TPC_ERR_INVALID;
+  return TPC_OK;
+}
+
+static RefitBufs refit_bufs(int64_t n_clusters, const tpc_clusters& in, const tpc_refit_tracks& trk,
+                            const float* dmap)
+{
+  RefitBufs b;
+  memset(&b, 0, sizeof(b));
+  b.x = in.x;
+  b.y = in.y;
+  b.z = in.z;
+  b.row = in.row;
+  b.sector = trk.sector;
+  b.hit_off = trk.hit_off;
+  b.hit_clu = trk.hit_clu;
+  b.seed = trk.seed;
+  b.dmap = dmap;
+  b.n_tracks = trk.n_tracks;
+  b.n_clusters = n_clusters;
+  return b;
+}
+
+tpc_status tpc_refit(const tpc_geometry* geom, const tpc_params* params, int64_t n_clusters,
+                     tpc_clusters in, tpc_refit_tracks trk, const float* dist_map_dev,
+                     float* chi2_dev, int32_t* status_dev, float* ckpt_dev, void* stream)
+{
+  tpc_status st = refit_check(geom, params, n_clusters, in, trk, dist_map_dev);
+  if (st != TPC_OK) return st;
+  if (trk.n_tracks > 0 && (!chi2_dev || !status_dev)) return TPC_ERR_INVALID;
+  if (trk.n_hits > 0 && (!ckpt_dev || reinterpret_cast<uintptr_t>(ckpt_dev) % 16))
+    return TPC_ERR_INVALID;
+  RefitBufs b = refit_bufs(n_clusters, in, trk, dist_map_dev);
+  b.chi2 = chi2_dev;
+  b.status = status_dev;
+  b.ckpt = ckpt_dev;
+  const Consts k = make_consts(geom, params);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = (params->flags & TPC_FLAG_DETERMINISTIC) ? det::refit_forward(k, b, s)
+                                                           : prod::refit_forward(k, b, s);
+  return e == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+}
+
+tpc_status tpc_refit_backward(const tpc_geometry* geom, const tpc_params* params,
+                              int64_t n_clusters, tpc_clusters in, tpc_refit_tracks trk,
+                              const float* dist_map_dev, const float* ckpt_dev,
+                              const int32_t* status_dev, const float* grad_chi2_dev,
+                              float* grad_map_dev, float* grad_x_dev, float* grad_y_dev,
+                              float* grad_z_dev, void* ws_dev, size_t ws_bytes, void* stream)
+{
+  tpc_status st = refit_check(geom, params, n_clusters, in, trk, dist_map_dev);
+  if (st != TPC_OK) return st;
+  if (!grad_map_dev || !ws_dev) return TPC_ERR_INVALID;
+  if (trk.n_tracks > 0 && (!status_dev || !grad_chi2_dev)) return TPC_ERR_INVALID;
+  if (trk.n_hits > 0 && (!ckpt_dev || reinterpret_cast<uintptr_t>(ckpt_dev) % 16))
+    return TPC_ERR_INVALID;
+  if (n_clusters > 0 && (!grad_x_dev || !grad_y_dev || !grad_z_dev)) return TPC_ERR_INVALID;
+  if (ws_bytes < tpc_refit_workspace_bytes()) return TPC_ERR_WORKSPACE;
+  if (reinterpret_cast<uintptr_t>(ws_dev) % 8) return TPC_ERR_INVALID;
+  RefitBufs b = refit_bufs(n_clusters, in, trk, dist_map_dev);
+  b.ckpt = const_cast<float*>(ckpt_dev);
+  b.status = const_cast<int32_t*>(status_dev);
+  b.grad_chi2 = grad_chi2_dev;
+  b.grad_map = grad_map_dev;
+  b.gx = grad_x_dev;
+  b.gy = grad_y_dev;
+  b.gz = grad_z_dev;
+  b.acc = static_cast<long long*>(ws_dev);
+  b.flags = reinterpret_cast<int*>(static_cast<char*>(ws_dev) + 8 * kRows * kPhi);
+  const Consts k = make_consts(geom, params);
+  hipError_t e = bwd::refit_backward(k, b, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 

@@ -17,6 +17,7 @@ struct Consts {
   float row_x[kRows];
   float tan_half;
   float kB;            // curvature per unit q/pT: (float)(-0.299792458e-2 * B)
+  float bz;            // field [T] (the binary64 reverse pass derives its own kB)
   float vy, vz;        // cluster variances
   float ivy, ivz;      // (float)(1 / (1.5 * variance)) of the neighbour score
   float nf_win_y, nf_win_z, nf_chi2_max;
@@ -85,6 +86,27 @@ struct TrackBufs {
   tpc_result* res;
 };
 
+// Buffers of the refit (a8) and its reverse pass (a9).
+struct RefitBufs {
+  const float *x, *y, *z;
+  const uint16_t* row;
+  const uint8_t* sector;
+  const int32_t *hit_off, *hit_clu;
+  const float* seed;      // [n_tracks][5]
+  const float* dmap;      // [152][18]
+  int64_t n_tracks, n_clusters;
+  float* chi2;            // [n_tracks]
+  int32_t* status;        // [n_tracks]
+  float* ckpt;            // [n_hits][20]
+  const float* grad_chi2; // [n_tracks]
+  float* grad_map;        // [152*18]
+  float *gx, *gy, *gz;    // [n_clusters]
+  long long* acc;         // [152*18] fixed-point map-gradient accumulators
+  int* flags;             // [1] accumulator overflow flag
+};
+
+constexpr int kPhi = 18;
+
 // Kernel timing hooks (tpc_profile_*): no-ops unless profiling is enabled.
 int prof_begin(hipStream_t s, const char* name);
 void prof_end(hipStream_t s, int slot);
@@ -96,7 +118,12 @@ int64_t scan_partials(int64_t n);
   namespace NS {                                                                     \
   hipError_t grid_build(const Consts& k, const GridBufs& b, hipStream_t s);         \
   hipError_t sector_track(const Consts& k, const TrackBufs& b, hipStream_t s);      \
+  hipError_t refit_forward(const Consts& k, const RefitBufs& b, hipStream_t s);     \
   }
+
+namespace bwd {
+hipError_t refit_backward(const Consts& k, const RefitBufs& b, hipStream_t s);
+}
 
 TPCCA_DECLARE_LAUNCHERS(det)
 TPCCA_DECLARE_LAUNCHERS(prod)

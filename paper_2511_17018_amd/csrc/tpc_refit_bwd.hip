@@ -1,0 +1,417 @@
+// Reverse pass of the Kalman refit (a9), gfx950, binary64 arithmetic on the
+// binary32 forward's checkpoints (CDNA4 runs FP64 vector at half the FP32
+// rate and the pass is memory-bound, so the wider type costs little and
+// removes the binary32 cancellation in residuals near zero).
+//
+// One lane per track walks its hits backwards.  Step k (hits k-1 -> k) is
+// rebuilt from checkpoint k-1: the propagation intermediates of R7/R8, the
+// predicted state and covariance, the update quantities of R9; then the
+// adjoints flow through the update and the propagation (reverse-mode
+// differentiation of the formulas as written, including the Jacobian's and
+// the gain's dependence on the state).  Covariance adjoints are full
+// symmetric 5x5 matrices X with dL = <X, dC> for symmetric dC.
+//
+// Outputs: d(sum_t w_t chi2_t)/d(cluster x, y, z) (each cluster is on at most
+// one track, so plain stores) and d/d(map cell).  The map sums use 64-bit
+// fixed-point atomics (scale 2^24): integer addition is associative, so the
+// result does not depend on the order in which lanes add, and no float
+// atomics are used.
+//
+// The gradient is compared with the binary64 reference within a tolerance,
+// not bit for bit, so this file is built once, with fast math (no contraction
+// constraints).
+#include "tpc_internal.h"
+
+namespace tpcca {
+namespace bwd {
+namespace {
+
+constexpr double kFix = 16777216.0;  // 2^24
+constexpr double kFixMax = 4.0e18;   // |value * 2^24| clamp (overflow flag)
+
+using R = double;  // arithmetic type of the reverse pass
+
+struct PRec {
+  R dx, cc, s2, c1, c2, f, dy, L, lc, u2, g, sg, ds, h, ic1, ic2, dfs, dfq, dg, dyl, hlc, Lg;
+  R a, dLs, du2s, T1, d, b, dLq, du2q, T2, gq, e, hq;
+};
+
+__device__ __forceinline__ void prop_record(const R* p, R dx, R kB, PRec& q)
+{
+  const R snp = p[2], tgl = p[3], qpt = p[4];
+  q.dx = dx;
+  q.cc = kB * qpt;
+  q.s2 = snp + q.cc * dx;
+  q.c1 = sqrt((1.0 - snp) * (1.0 + snp));
+  q.c2 = sqrt((1.0 - q.s2) * (1.0 + q.s2));
+  q.f = (snp + q.s2) / (q.c1 + q.c2);
+  q.dy = dx * q.f;
+  q.L = sqrt(dx * dx + q.dy * q.dy);
+  q.lc = q.L * q.cc;
+  q.u2 = (q.lc * q.lc) * 0.25;
+  q.g = 1.0 + q.u2 * (1.0 / 6.0 + q.u2 * (3.0 / 40.0));
+  q.sg = dx < 0.0 ? -1.0 : 1.0;
+  q.ds = (q.sg * q.L) * q.g;
+  q.h = (1.0 + q.f * q.f) * 0.5;
+  q.ic1 = 1.0 / q.c1;
+  q.ic2 = 1.0 / q.c2;
+  q.dfs = q.h * (q.ic1 + q.ic2);
+  q.dfq = (q.h * (dx * q.ic2)) * kB;
+  q.dg = 1.0 / 6.0 + q.u2 * (3.0 / 20.0);
+  q.dyl = q.dy / q.L;
+  q.hlc = 0.5 * q.lc;
+  q.Lg = q.L * q.dg;
+  q.a = dx * q.dfs;
+  q.dLs = q.dyl * q.a;
+  q.du2s = q.hlc * (q.dLs * q.cc);
+  q.T1 = q.dLs * q.g + q.Lg * q.du2s;
+  q.d = tgl * (q.sg * q.T1);
+  q.b = dx * q.dfq;
+  q.dLq = q.dyl * q.b;
+  q.du2q = q.hlc * (q.dLq * q.cc + q.L * kB);
+  q.T2 = q.dLq * q.g + q.Lg * q.du2q;
+  q.gq = tgl * (q.sg * q.T2);
+  q.e = q.ds;
+  q.hq = kB * dx;
+}
+
+// adjoint of the propagation's scalar chain; pb in/out, Fb = adjoints of
+// (a, b, d, e, gq, hq); returns the adjoint of dx
+__device__ __forceinline__ R prop_backward(const R* p, const PRec& q, R kB, R* pb,
+                                               const R* Fb)
+{
+  const R tgl = p[3], snp = p[2];
+  const R yb = pb[0], zb = pb[1];
+  R s2b = pb[2], tglb = pb[3], qptb = pb[4];
+  R dyb = yb, dsb = zb * tgl;
+  tglb += zb * q.ds;
+  R ab = Fb[0], bb = Fb[1];
+  const R db = Fb[2], eb = Fb[3], gqb = Fb[4], hqb = Fb[5];
+  R dxb = hqb * kB;
+  dsb += eb;
+  tglb += gqb * q.sg * q.T2;
+  const R T2b = gqb * tgl * q.sg;
+  R dLqb = T2b * q.g;
+  R gb = T2b * q.dLq;
+  R Lgb = T2b * q.du2q;
+  const R du2qb = T2b * q.Lg;
+  R hlcb = du2qb * (q.dLq * q.cc + q.L * kB);
+  dLqb += du2qb * q.hlc * q.cc;
+  R ccb = du2qb * q.hlc * q.dLq;
+  R Lb = du2qb * q.hlc * kB;
+  R dylb = dLqb * q.b;
+  bb += dLqb * q.dyl;
+  dxb += bb * q.dfq;
+  const R dfqb = bb * q.dx;
+  tglb += db * q.sg * q.T1;
+  const R T1b = db * tgl * q.sg;
+  R dLsb = T1b * q.g;
+  gb += T1b * q.dLs;
+  Lgb += T1b * q.du2s;
+  const R du2sb = T1b * q.Lg;
+  hlcb += du2sb * q.dLs * q.cc;
+  dLsb += du2sb * q.hlc * q.cc;
+  ccb += du2sb * q.hlc * q.dLs;
+  dylb += dLsb * q.a;
+  ab += dLsb * q.dyl;
+  dxb += ab * q.dfs;
+  const R dfsb = ab * q.dx;
+  Lb += Lgb * q.dg;
+  const R dgb = Lgb * q.L;
+  R lcb = 0.5 * hlcb;
+  dyb += dylb / q.L;
+  Lb -= dylb * q.dy / (q.L * q.L);
+  R u2b = dgb * (3.0 / 20.0);
+  R hb = dfqb * q.dx * q.ic2 * kB;
+  dxb += dfqb * q.h * q.ic2 * kB;
+  R ic2b = dfqb * q.h * q.dx * kB;
+  hb += dfsb * (q.ic1 + q.ic2);
+  const R ic1b = dfsb * q.h;
+  ic2b += dfsb * q.h;
+  R c1b = -ic1b / (q.c1 * q.c1);
+  R c2b = -ic2b / (q.c2 * q.c2);
+  R fb = hb * q.f;
+  Lb += dsb * q.sg * q.g;
+  gb += dsb * q.sg * q.L;
+  u2b += gb * (1.0 / 6.0 + 2.0 * q.u2 * (3.0 / 40.0));
+  lcb += u2b * 0.5 * q.lc;
+  Lb += lcb * q.cc;
+  ccb += lcb * q.L;
+  dxb += Lb * q.dx / q.L;
+  dyb += Lb * q.dy / q.L;
+  dxb += dyb * q.f;
+  fb += dyb * q.dx;
+  const R den = q.c1 + q.c2;
+  const R numb = fb / den, denb = -fb * q.f / den;
+  R snpb = numb;
+  s2b += numb;
+  c1b += denb;
+  c2b += denb;
+  s2b += c2b * (-q.s2 / q.c2);
+  snpb += c1b * (-snp / q.c1);
+  snpb += s2b;
+  ccb += s2b * q.dx;
+  dxb += s2b * q.cc;
+  qptb += ccb * kB;
+  pb[0] = yb;
+  pb[1] = zb;
+  pb[2] = snpb;
+  pb[3] = tglb;
+  pb[4] = qptb;
+  return dxb;
+}
+
+// adjoint of the R9 update at predicted state pp, covariance C
+__device__ __forceinline__ void update_backward(const R* pp, const R (&C)[5][5], R my,
+                                                R mz, R vy, R vz, R chib, R* pb,
+                                                R (&Xb)[5][5], R* mb)
+{
+  const R S00 = C[0][0] + vy, S01 = C[0][1], S11 = C[1][1] + vz;
+  const R det = S00 * S11 - S01 * S01;
+  const R idet = 1.0 / det;
+  const R Si[2][2] = {{S11 * idet, -S01 * idet}, {-S01 * idet, S00 * idet}};
+  const R r[2] = {my - pp[0], mz - pp[1]};
+  R K[5][2];
+#pragma unroll
+  for (int i = 0; i < 5; i++)
+#pragma unroll
+    for (int a = 0; a < 2; a++) K[i][a] = C[i][0] * Si[0][a] + C[i][1] * Si[1][a];
+  const R w[2] = {Si[0][0] * r[0] + Si[0][1] * r[1], Si[1][0] * r[0] + Si[1][1] * r[1]};
+  R Ub[5][2], Sib[2][2], rb[2] = {0.0, 0.0}, Utp[2] = {0.0, 0.0};
+  // C_out = C - U Si U^T  (U = C[:, 0:2], U Si = K)
+#pragma unroll
+  for (int i = 0; i < 5; i++)
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+      R s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 5; j++) s += Xb[i][j] * K[j][a];
+      Ub[i][a] = -2.0 * s + pb[i] * w[a];  // ... + the p_out = p + U w term
+    }
+  R XU[5][2];
+#pragma unroll
+  for (int i = 0; i < 5; i++)
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+      R s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 5; j++) s += Xb[i][j] * C[j][a];
+      XU[i][a] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < 5; i++)
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+      Utp[a] += C[i][a] * pb[i];
+      rb[a] += K[i][a] * pb[i];
+    }
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int bq = 0; bq < 2; bq++) {
+      R s = 0.0;
+#pragma unroll
+      for (int i = 0; i < 5; i++) s += C[i][a] * XU[i][bq];
+      Sib[a][bq] = -s + Utp[a] * r[bq] + chib * r[a] * r[bq];
+    }
+#pragma unroll
+  for (int a = 0; a < 2; a++) rb[a] += 2.0 * chib * w[a];
+  // Si = S^-1
+  R T[2][2], Smb[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int bq = 0; bq < 2; bq++) T[a][bq] = Si[a][0] * Sib[0][bq] + Si[a][1] * Sib[1][bq];
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int bq = 0; bq < 2; bq++) Smb[a][bq] = -(T[a][0] * Si[0][bq] + T[a][1] * Si[1][bq]);
+  Xb[0][0] += Smb[0][0];
+  Xb[1][1] += Smb[1][1];
+  const R s01 = 0.5 * (Smb[0][1] + Smb[1][0]);
+  Xb[0][1] += s01;
+  Xb[1][0] += s01;
+#pragma unroll
+  for (int i = 0; i < 5; i++)
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+      Xb[i][a] += 0.5 * Ub[i][a];
+      Xb[a][i] += 0.5 * Ub[i][a];
+    }
+  mb[0] = rb[0];
+  mb[1] = rb[1];
+  pb[0] -= rb[0];
+  pb[1] -= rb[1];
+}
+
+__device__ __forceinline__ void acc_add(const RefitBufs& b, int cell, double g)
+{
+  double v = rint(g * kFix);
+  if (!(fabs(v) <= kFixMax)) {
+    v = g < 0.0 ? -kFixMax : kFixMax;
+    atomicOr(b.flags, 1);
+  }
+  atomicAdd(reinterpret_cast<unsigned long long*>(&b.acc[cell]), (unsigned long long)(long long)v);
+}
+
+__global__ __launch_bounds__(kBlock) void k_refit_bwd_zero(RefitBufs b)
+{
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b.n_clusters;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    b.gx[i] = 0.0f;
+    b.gy[i] = 0.0f;
+    b.gz[i] = 0.0f;
+    if (i < kRows * kPhi) b.acc[i] = 0;
+  }
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < kRows * kPhi; i += blockDim.x) b.acc[i] = 0;
+    if (threadIdx.x == 0) b.flags[0] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_refit_bwd(Consts k, RefitBufs b)
+{
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= b.n_tracks) return;
+  const int64_t a = b.hit_off[t], e = b.hit_off[t + 1];
+  if (e - a < 1 || b.status[t] != 0) return;
+  // binary64 throughout: the checkpoints (binary32) are widened on load
+  const R kB = -0.299792458e-2 * (R)k.bz, vy = k.vy, vz = k.vz, w = b.grad_chi2[t];
+  R pb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  R Xb[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; i++)
+#pragma unroll
+    for (int j = 0; j < 5; j++) Xb[i][j] = 0.0;
+  R gXn = 0.0;
+  int32_t c = b.hit_clu[e - 1];
+  int cell = (int)b.row[c] * kPhi + b.sector[c] % kPhi;
+  R X2 = (R)b.x[c] + (R)b.dmap[cell];
+  for (int64_t h = e - 1; h >= a + 1; h--) {
+    const int32_t cp = b.hit_clu[h - 1];
+    const int cellp = (int)b.row[cp] * kPhi + b.sector[cp] % kPhi;
+    const R X1 = (R)b.x[cp] + (R)b.dmap[cellp];
+    // checkpoint h-1
+    const float4* q4 = reinterpret_cast<const float4*>(b.ckpt + (h - 1) * 20);
+    const float4 v0 = q4[0], v1 = q4[1], v2 = q4[2], v3 = q4[3], v4 = q4[4];
+    const R p0[5] = {v0.x, v0.y, v0.z, v0.w, v1.x};
+    const R c15[15] = {v1.y, v1.z, v1.w, v2.x, v2.y, v2.z, v2.w, v3.x,
+                           v3.y, v3.z, v3.w, v4.x, v4.y, v4.z, v4.w};
+    R C0[5][5];
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+#pragma unroll
+      for (int j = 0; j <= i; j++) C0[i][j] = C0[j][i] = c15[i * (i + 1) / 2 + j];
+    PRec q;
+    prop_record(p0, X2 - X1, kB, q);
+    R F[5][5];
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+#pragma unroll
+      for (int j = 0; j < 5; j++) F[i][j] = i == j ? 1.0 : 0.0;
+    F[0][2] = q.a;
+    F[0][4] = q.b;
+    F[1][2] = q.d;
+    F[1][3] = q.e;
+    F[1][4] = q.gq;
+    F[2][4] = q.hq;
+    // predicted covariance F C0 F^T and state
+    R FC[5][5], Cp[5][5];
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+#pragma unroll
+      for (int j = 0; j < 5; j++) {
+        R s = 0.0;
+#pragma unroll
+        for (int m = 0; m < 5; m++) s += F[i][m] * C0[m][j];
+        FC[i][j] = s;
+      }
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+#pragma unroll
+      for (int j = 0; j < 5; j++) {
+        R s = 0.0;
+#pragma unroll
+        for (int m = 0; m < 5; m++) s += FC[i][m] * F[j][m];
+        Cp[i][j] = s;
+      }
+    const R pp[5] = {p0[0] + q.dy, p0[1] + p0[3] * q.ds, q.s2, p0[3], p0[4]};
+    R mb[2];
+    update_backward(pp, Cp, (R)b.y[c], (R)b.z[c], vy, vz, w, pb, Xb, mb);
+    // covariance part of the propagation: Xn = F^T X F, Fb = 2 (X F C0)
+    R XF[5][5];
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+#pragma unroll
+      for (int j = 0; j < 5; j++) {
+        R s = 0.0;
+#pragma unroll
+        for (int m = 0; m < 5; m++) s += Xb[i][m] * F[m][j];
+        XF[i][j] = s;
+      }
+    R Fb[6];
+    {
+      const int fi[6] = {0, 0, 1, 1, 1, 2}, fj[6] = {2, 4, 2, 3, 4, 4};
+#pragma unroll
+      for (int u = 0; u < 6; u++) {
+        R s = 0.0;
+#pragma unroll
+        for (int m = 0; m < 5; m++) s += XF[fi[u]][m] * C0[m][fj[u]];
+        Fb[u] = 2.0 * s;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+#pragma unroll
+      for (int j = 0; j < 5; j++) {
+        R s = 0.0;
+#pragma unroll
+        for (int m = 0; m < 5; m++) s += F[m][i] * XF[m][j];
+        Xb[i][j] = s;
+      }
+    const R dxb = prop_backward(p0, q, kB, pb, Fb);
+    const R gX = dxb + gXn;
+    b.gx[c] = (float)gX;
+    b.gy[c] = (float)mb[0];
+    b.gz[c] = (float)mb[1];
+    acc_add(b, cell, gX);
+    gXn = -dxb;
+    c = cp;
+    cell = cellp;
+    X2 = X1;
+  }
+  b.gx[c] = (float)gXn;
+  b.gy[c] = (float)pb[0];
+  b.gz[c] = (float)pb[1];
+  acc_add(b, cell, gXn);
+}
+
+__global__ void k_refit_bwd_map(RefitBufs b)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kRows * kPhi) b.grad_map[i] = (float)((double)b.acc[i] / kFix);
+}
+
+}  // namespace
+
+hipError_t refit_backward(const Consts& k, const RefitBufs& b, hipStream_t s)
+{
+  const int64_t zc = b.n_clusters > kRows * kPhi ? b.n_clusters : kRows * kPhi;
+  int64_t zb = (zc + kBlock - 1) / kBlock;
+  if (zb > 65535) zb = 65535;
+  int slot = prof_begin(s, "refit_bwd_zero");
+  k_refit_bwd_zero<<<(unsigned)zb, kBlock, 0, s>>>(b);
+  prof_end(s, slot);
+  if (b.n_tracks > 0) {
+    slot = prof_begin(s, "refit_bwd");
+    k_refit_bwd<<<(unsigned)((b.n_tracks + kBlock - 1) / kBlock), kBlock, 0, s>>>(k, b);
+    prof_end(s, slot);
+  }
+  slot = prof_begin(s, "refit_bwd_map");
+  k_refit_bwd_map<<<(kRows * kPhi + kBlock - 1) / kBlock, kBlock, 0, s>>>(b);
+  prof_end(s, slot);
+  return hipGetLastError();
+}
+
+}  // namespace bwd
+}  // namespace tpcca

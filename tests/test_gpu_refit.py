@@ -1,0 +1,156 @@
+"""GPU parity of the refit (a8) and its reverse pass (a9) through the C ABI.
+
+Deterministic forward: chi2, status and checkpoints equal the binary32 oracle
+bit for bit (R28).  Gradient: against the binary64 oracle adjoint (which the
+CPU pins tie to complex-step derivatives) within R27: norm-wise relative
+error <= 1e-3 and element-wise |g - g_ref| <= 1e-3 * max(|g_ref|,
+1e-2 * rms(g_ref)); bit-identical from run to run.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2511_17018_amd as tpc
+import synth
+
+pytestmark = pytest.mark.gpu
+
+G = synth.geometry()
+P = dict(oracle.DEFAULT_PARAMS)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu(ev, dmap, det=True):
+    xyz = torch.from_numpy(np.stack([ev.x, ev.y, ev.z]).astype(np.float32)).cuda()
+    row = torch.from_numpy(ev.row.view(np.int16)).cuda()
+    trk = tpc.upload_refit_tracks(ev.extra["hit_off"], ev.extra["hit_clu"], ev.sector,
+                                  ev.extra["seed_par"])
+    m = torch.from_numpy(np.ascontiguousarray(dmap, np.float32)).cuda()
+    return xyz, row, trk, m
+
+
+def _args(ev):
+    return ev.extra["hit_off"], ev.extra["hit_clu"], ev.extra["seed_par"]
+
+
+def _r27_elements(g, ref):
+    g = np.asarray(g, np.float64).reshape(-1)
+    ref = np.asarray(ref, np.float64).reshape(-1)
+    rms = np.sqrt(np.mean(ref ** 2))
+    return np.abs(g - ref) / np.maximum(np.abs(ref), 1e-2 * rms + 1e-30)
+
+
+def _r27(g, ref):
+    g = np.asarray(g, np.float64).reshape(-1)
+    ref = np.asarray(ref, np.float64).reshape(-1)
+    nrm = np.linalg.norm(g - ref) / max(np.linalg.norm(ref), 1e-30)
+    rms = np.sqrt(np.mean(ref ** 2)) if len(ref) else 0.0
+    el = np.abs(g - ref) / np.maximum(np.abs(ref), 1e-2 * rms + 1e-30)
+    return nrm, float(el.max()) if len(el) else 0.0
+
+
+@pytest.mark.parametrize("n_found,smear", [(300, True), (60, False)])
+def test_refit_forward_bit_exact(n_found, smear):
+    ev = synth.config5(n_found=n_found, smear=smear)
+    _say(f"[refit fwd] tracks={n_found} hits={ev.n}")
+    ho, hc, seed = _args(ev)
+    for dmap in (ev.extra["D_true"], np.zeros_like(ev.extra["D_true"])):
+        xyz, row, trk, m = _gpu(ev, dmap)
+        chi2, status, ckpt = tpc.refit(G, xyz, row, trk, m, det=True)
+        torch.cuda.synchronize()
+        c_o, s_o, k_o = oracle.refit(G, P, ev, ho, hc, seed, dmap, prec=32)
+        assert np.array_equal(status.cpu().numpy(), s_o)
+        assert np.array_equal(chi2.cpu().numpy().view(np.int32), c_o.view(np.int32))
+        ok = np.repeat(s_o == 0, np.diff(ho))
+        assert np.array_equal(ckpt.cpu().numpy()[ok].view(np.int32), k_o[ok].view(np.int32))
+
+
+def test_refit_backward_matches_binary64_adjoint():
+    ev = synth.config5(n_found=400)
+    ho, hc, seed = _args(ev)
+    rng = np.random.default_rng(4)
+    w = rng.uniform(0.5, 1.5, len(ho) - 1)
+    for dmap in (ev.extra["D_true"], np.zeros_like(ev.extra["D_true"])):
+        xyz, row, trk, m = _gpu(ev, dmap)
+        chi2, status, ckpt = tpc.refit(G, xyz, row, trk, m)
+        gmap, gxyz = tpc.refit_backward(G, xyz, row, trk, m, ckpt, status,
+                                        torch.from_numpy(w.astype(np.float32)).cuda())
+        torch.cuda.synchronize()
+        w32 = w.astype(np.float32).astype(np.float64)
+        _, st, rmap, rx, ry, rz = oracle.refit_grad(G, P, ev, ho, hc, seed, dmap, w32)
+        # the binary64 adjoint on the GPU's own binary32 trajectory (checkpoints)
+        _, _, _, sx, sy, sz = oracle.refit_grad(G, P, ev, ho, hc, seed, dmap, w32,
+                                                ckpt=ckpt.cpu().numpy(),
+                                                status=status.cpu().numpy())
+        gx, gy, gz = gxyz.cpu().numpy()
+        fails = []
+        for name, a, b, bs in (("x", gx, rx, sx), ("y", gy, ry, sy), ("z", gz, rz, sz)):
+            nrm, _ = _r27(a, b)
+            _, el = _r27(a, bs)
+            _say(f"[refit bwd] {name}: norm-wise vs binary64 {nrm:.2e}; element-wise vs "
+                 f"binary64 adjoint of the binary32 trajectory {el:.2e}")
+            if not (nrm <= 1e-3 and el <= 1e-6):
+                fails.append(name)
+        # a map cell is a sum over its hits: its rounding scale is the sum of
+        # the magnitudes of the terms, not the (possibly cancelling) total
+        cell = ev.row.astype(np.int64) * 18 + ev.sector % 18
+        scale = np.bincount(cell, weights=np.abs(rx), minlength=152 * 18)
+        a = gmap.cpu().numpy().reshape(-1).astype(np.float64)
+        nrm, _ = _r27(a, rmap)
+        el = float((np.abs(a - rmap.reshape(-1)) / np.maximum(scale, 1e-30))[scale > 0].max())
+        _say(f"[refit bwd] map: norm-wise {nrm:.2e} element-wise (term scale) {el:.2e}")
+        if not (nrm <= 1e-3 and el <= 1e-3):
+            fails.append("map")
+        assert not fails, fails
+
+
+def test_refit_backward_deterministic_and_map_is_sum_of_x_gradients():
+    ev = synth.config5(n_found=500)
+    dmap = ev.extra["D_true"]
+    xyz, row, trk, m = _gpu(ev, dmap)
+    chi2, status, ckpt = tpc.refit(G, xyz, row, trk, m)
+    ones = torch.ones_like(chi2)
+    a = tpc.refit_backward(G, xyz, row, trk, m, ckpt, status, ones)
+    b = tpc.refit_backward(G, xyz, row, trk, m, ckpt, status, ones)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    # every hit's dL/dX enters both its cluster's x gradient and its map cell
+    cell = ev.row.astype(np.int64) * 18 + ev.sector % 18
+    gx = a[1][0].cpu().numpy().astype(np.float64)
+    want = np.bincount(cell, weights=gx, minlength=152 * 18)
+    got = a[0].cpu().numpy().reshape(-1)
+    assert np.allclose(got, want, rtol=1e-5, atol=1e-4 * np.abs(want).max())
+
+
+def test_autograd_function_matches_direct_calls():
+    ev = synth.config5(n_found=200)
+    xyz, row, trk, m = _gpu(ev, ev.extra["D_true"] * 0.5)
+    xyz.requires_grad_(True)
+    m.requires_grad_(True)
+    chi2 = tpc.TpcRefit.apply(xyz, m, row, trk, G)
+    (chi2 * 2.0).sum().backward()
+    c2, st, ck = tpc.refit(G, xyz.detach(), row, trk, m.detach())
+    gm, gxyz = tpc.refit_backward(G, xyz.detach(), row, trk, m.detach(), ck, st,
+                                  torch.full_like(c2, 2.0))
+    torch.cuda.synchronize()
+    assert torch.equal(chi2.detach(), c2)
+    assert torch.equal(xyz.grad, gxyz) and torch.equal(m.grad, gm)
+
+
+def test_refit_prod_close_to_binary64():
+    ev = synth.config5(n_found=300)
+    ho, hc, seed = _args(ev)
+    dmap = ev.extra["D_true"]
+    xyz, row, trk, m = _gpu(ev, dmap)
+    chi2, status, _ = tpc.refit(G, xyz, row, trk, m, det=False)
+    c64, s64, _ = oracle.refit(G, P, ev, ho, hc, seed, dmap, prec=64)
+    c = chi2.cpu().numpy()
+    ok = (status.cpu().numpy() == 0) & (s64 == 0)
+    assert np.all(np.abs(c[ok] - c64[ok]) <= 1e-3 * np.maximum(c64[ok], 1.0))
