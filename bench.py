@@ -8,8 +8,10 @@ neighbours, cleaner, start hits, tracklet construction, selection) over the
 batch, with the clusters already resident in HBM.  Reported:
 
   value        clusters/s of the batched deterministic path (one launch chain
-               for all 256 instances)
-  plain        clusters/s of 256 per-instance launch chains on one stream
+               for all 256 instances, captured in a HIP graph, launch
+               parameters from the autotuner); batched_eager without the graph
+  plain        clusters/s of 256 per-instance launch chains on one stream,
+               eager and graph-captured
   prod         clusters/s of the batched production path, and det/prod ratio
   roofline     the dominant kernel's algorithmic bytes per launch divided by
                its average launch time (HIP events recorded on the kernel's
@@ -71,6 +73,8 @@ def run(args) -> dict:
 
     import paper_2511_17018_amd as tpc
     import synth
+    from paper_2511_17018_amd import autotune
+    from paper_2511_17018_amd.runtime import Chain, GraphChain, plain_chains
 
     t0 = time.time()
     ev = synth.config4(scale=args.scale)
@@ -81,103 +85,96 @@ def run(args) -> dict:
     dev = "cuda:0"
     torch.cuda.set_device(0)
     L = tpc.lib()
-    geom = tpc.make_geometry(synth.geometry())
+    geom = synth.geometry()
     batch = tpc.upload(ev.x, ev.y, ev.z, ev.row, ev.charge, ev.inst_off, dev)
-    stream = torch.cuda.current_stream()
-    sp = C.c_void_p(stream.cuda_stream)
+    stream = torch.cuda.Stream(dev)
 
-    def prepared(b: "tpc.Batch", det: bool):
-        """Pre-marshalled argument tuples of one tracking call."""
-        p = tpc.make_params(det)
-        grid = tpc.alloc_grid(b.n_inst, b.n, dev)
-        tracks = tpc.alloc_tracks(b.n, device=dev)
-        ws = tpc.Workspace(b.n_inst, b.n, 0, dev)
-        keep = (p, grid, tracks, ws, b, grid.struct(), tracks.struct(), b.struct())
-        ga = (C.byref(geom), C.byref(p), C.c_int32(b.n_inst),
-              b.inst_off_host.ctypes.data_as(C.c_void_p), tpc._ptr(b.inst_off), keep[7],
-              C.byref(keep[5]), tpc._ptr(ws.result), tpc._ptr(ws.grid_ws),
-              C.c_size_t(ws.grid_ws.numel()), sp)
-        ta = (C.byref(geom), C.byref(p), C.c_int32(b.n_inst),
-              b.inst_off_host.ctypes.data_as(C.c_void_p), tpc._ptr(b.inst_off), keep[7],
-              C.byref(keep[5]), C.byref(keep[6]), tpc._ptr(ws.result), tpc._ptr(ws.track_ws),
-              C.c_size_t(ws.track_ws.numel()), C.c_int64(0), sp)
-        return keep, ga, ta
-
-    def step(preps):
-        for _, ga, ta in preps:
-            st = L.tpc_grid_build(*ga)
-            st2 = L.tpc_sector_track(*ta)
-            if st or st2:
-                raise RuntimeError(f"tracker call failed: {st} {st2}")
-
-    def timed(preps, steps, warmup, label):
-        for _ in range(warmup):
-            step(preps)
-        torch.cuda.synchronize()
+    def timed(fn, steps, warmup, label):
+        with torch.cuda.stream(stream):
+            for _ in range(warmup):
+                fn()
+        stream.synchronize()
         t = time.perf_counter()
-        for _ in range(steps):
-            step(preps)
-        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            for _ in range(steps):
+                fn()
+        stream.synchronize()
         dt = (time.perf_counter() - t) / steps
         log(f"{label}: {dt * 1e3:.3f} ms/step, {N / dt / 1e9:.3f} G clusters/s")
         return dt
 
     out = {}
-    # ---- batched, deterministic (the headline)
-    det_b = [prepared(batch, True)]
-    dt_det = timed(det_b, args.steps, args.warmup, "batched det")
-    res = det_b[0][0][3].read_result()
+    # ---- autotuned launch parameters (performance-only; outputs checked identical)
+    tuned = autotune.tune(geom, batch, stream=stream, use_cache=not args.retune, log=log)
+    tp = dict(grid_occupancy=tuned["grid_occupancy"], tl_blocks_per_cu=tuned["tl_blocks_per_cu"])
+    out["autotune"] = {k: tuned[k] for k in ("grid_occupancy", "tl_blocks_per_cu", "ms",
+                                             "default_ms")}
+    # ---- batched, deterministic
+    det_c = Chain(geom, batch, True, stream, **tp)
+    dt_eager = timed(det_c.enqueue, args.steps, args.warmup, "batched det (eager)")
+    res = det_c.result()
     if int(res["overflow"]) or int(res["n_bad"]):
         raise RuntimeError(f"unexpected status {res}")
-    # per-kernel times with HIP events (a second timed pass of the same steps)
+    graph = GraphChain([det_c], stream)
+    dt_det = timed(graph.replay, args.steps, args.warmup, "batched det (graph)")
+    out["batched_eager"] = {"value": N / dt_eager, "ms_per_step": dt_eager * 1e3}
+    # per-kernel times with HIP events (a second timed pass of the same steps, eager)
     assert L.tpc_profile_enable(1) == 0
-    torch.cuda.synchronize()
-    for _ in range(args.steps):
-        step(det_b)
-    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for _ in range(args.steps):
+            det_c.enqueue()
+    stream.synchronize()
     rows = (tpc_kernel_time * 64)()
     nk = L.tpc_profile_read(rows, 64)
     L.tpc_profile_enable(0)
     ktimes = {rows[i].name.decode(): (rows[i].total_ms, rows[i].launches) for i in range(nk)}
     # counts for the byte model
-    ws = det_b[0][0][3]
+    ws = det_c.ws
     cap = ws.layout.cap_tracklets
     S = int(min(res["n_start"], cap))
     i32 = torch.int32
     nhit = ws.view("tl_nhit", i32, cap)[:S].to(torch.int64).sum().item()
     ncand = ws.view("tl_ncand", i32, cap)[:S].to(torch.int64).sum().item()
     counts = dict(N=N, S=S, Ht=nhit, E=ncand)
-    # dominant kernel
     dom = max(ktimes.items(), key=lambda kv: kv[1][0])
     name, (tot_ms, launches) = dom
     avg_s = tot_ms / launches / 1e3
     kb = kernel_bytes(name, counts)
     achieved = kb / avg_s / 1e9 if kb else None
-    total_ms_per_step = sum(v[0] for v in ktimes.values()) / args.steps
     roofline = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                 "traffic": None, "avg_launch_ms": avg_s * 1e3,
                 "alg_bytes_per_launch": kb, "counts": counts}
     out["kernels_ms_per_step"] = {k: round(v[0] / args.steps, 4) for k, v in
                                   sorted(ktimes.items(), key=lambda kv: -kv[1][0])}
-    out["kernels_sum_ms_per_step"] = round(total_ms_per_step, 4)
+    out["kernels_sum_ms_per_step"] = round(sum(v[0] for v in ktimes.values()) / args.steps, 4)
     out["result"] = {k: int(res[k]) for k in ("n_valid", "n_start", "n_tracklets_kept",
                                               "n_tracks", "n_hits")}
+    del graph, det_c
     # ---- batched, production
     if not args.no_prod:
-        prod_b = [prepared(batch, False)]
-        dt_prod = timed(prod_b, args.steps, args.warmup, "batched prod")
+        prod_c = Chain(geom, batch, False, stream, **tp)
+        dt_prod = timed(prod_c.enqueue, args.steps, args.warmup, "batched prod (eager)")
         out["prod"] = {"value": N / dt_prod, "ms_per_step": dt_prod * 1e3,
-                       "det_over_prod_time": dt_det / dt_prod}
-        del prod_b
-    # ---- plain: one launch chain per instance
+                       "det_eager_over_prod_eager_time": dt_eager / dt_prod}
+        del prod_c
+    # ---- plain: one launch chain per instance, eager and graph-captured
     if not args.no_plain:
-        plain = [prepared(batch.slice(i), True) for i in range(n_inst)]
+        plain = plain_chains(geom, batch, True, stream)
         ps = max(1, min(args.steps, 3))
-        dt_plain = timed(plain, ps, 1, "plain det")
+
+        def run_plain():
+            for c in plain:
+                c.enqueue()
+
+        dt_plain = timed(run_plain, ps, 1, "plain det (eager)")
+        pg = GraphChain(plain, stream)
+        dt_plain_g = timed(pg.replay, ps, 1, "plain det (graph)")
         out["plain"] = {"value": N / dt_plain, "ms_per_step": dt_plain * 1e3, "steps": ps,
-                        "batched_over_plain": dt_plain / dt_det}
-        del plain
+                        "graph_value": N / dt_plain_g, "graph_ms_per_step": dt_plain_g * 1e3,
+                        "batched_over_plain": dt_plain / dt_det,
+                        "batched_over_plain_graph": dt_plain_g / dt_det}
+        del pg, plain
     out.update(dt_det=dt_det, N=N, n_inst=n_inst, sha=sha, roofline=roofline)
     return out, ev
 
@@ -304,6 +301,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-every", type=int, default=4)
     ap.add_argument("--no-refit", action="store_true")
+    ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -336,12 +334,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "256 uneven sector instances (log-uniform 1e3-4e5 clusters, "
-                               "noise 0-20%), batched deterministic chain",
+                               "noise 0-20%), batched deterministic chain, graph-captured, "
+                               "autotuned launch parameters",
                    "n_clusters": r["N"], "n_instances": r["n_inst"], "mode": "deterministic",
-                   "path": "batched", "input_sha256": r["sha"]},
+                   "path": "batched+graph", "input_sha256": r["sha"]},
         "roofline": r["roofline"],
     }
-    for k in ("plain", "prod", "result", "kernels_ms_per_step", "kernels_sum_ms_per_step"):
+    for k in ("batched_eager", "autotune", "plain", "prod", "result", "kernels_ms_per_step",
+              "kernels_sum_ms_per_step"):
         if k in r:
             line[k] = r[k]
     if not args.no_cpu:

@@ -79,7 +79,10 @@ typedef struct {
  * neighbour windows 3.0 / 3.5 cm and score cut 13.8, tracklet chi2 cut 13.8,
  * |snp| < 0.99, grid occupancy 2, sector-edge margin 1 cm, window margin
  * 0.01 cm, cluster validity margin 2 cm, chains >= 3 hits, 10 consecutive
- * misses, >= 10 hits per tracklet and per track, flags 0. */
+ * misses, >= 10 hits per tracklet and per track, flags 0, and the
+ * performance-only tl_blocks_per_cu = 0 (the library's default, 8 resident
+ * blocks per compute unit for the persistent tracklet kernel).  Results do
+ * not depend on grid_occupancy (the bin size) or tl_blocks_per_cu. */
 typedef struct {
   float nf_win_y, nf_win_z, nf_chi2_max;
   float tc_chi2_pick, snp_max;
@@ -88,6 +91,7 @@ typedef struct {
   float y_valid_margin;
   int32_t min_chain, tc_max_miss, min_tracklet_hits, min_track_hits;
   uint32_t flags;
+  int32_t tl_blocks_per_cu;
 } tpc_params;
 
 /* Clusters: device SoA, n_clusters entries each (charge is carried, unused). */
@@ -108,7 +112,7 @@ typedef struct {
  *   sseg    [n_clusters]            instance*152 + row of each position, -1 = padding
  *   row_off [n_inst*153]            first position of each (instance,row); entry 152 = end
  *   meta    [n_inst*152]
- *   bin_off [bin_cap]               bin_cap >= tpc_grid_bin_capacity()
+ *   bin_off [bin_cap]               bin_cap >= tpc_grid_bin_capacity(params, ...)
  *   perm    [n_clusters]            input index of each position, -1 = padding
  *   yz      [2*n_clusters]          cluster (y, z) pairs in position order, 8-byte
  *                                   aligned                                          */
@@ -176,8 +180,8 @@ const char* tpc_status_string(tpc_status s);
 /* Size queries (no device work).  cap_tracklets <= 0 selects the proven
  * bound n_clusters/3 + n_inst (every start hit heads a disjoint chain of at
  * least three clusters). */
-int64_t tpc_grid_bin_capacity(int32_t n_inst, int64_t n_clusters);
-size_t tpc_grid_workspace_bytes(int32_t n_inst, int64_t n_clusters);
+int64_t tpc_grid_bin_capacity(const tpc_params* params, int32_t n_inst, int64_t n_clusters);
+size_t tpc_grid_workspace_bytes(const tpc_params* params, int32_t n_inst, int64_t n_clusters);
 size_t tpc_track_workspace_bytes(int32_t n_inst, int64_t n_clusters, int64_t cap_tracklets);
 tpc_status tpc_track_workspace_layout(int32_t n_inst, int64_t n_clusters, int64_t cap_tracklets,
                                       tpc_track_ws_layout* out);

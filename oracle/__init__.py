@@ -145,7 +145,7 @@ def grid_build(geom, params, inst_off, y, z, row, prec=32) -> Grid:
     row_off = np.empty(n_inst * (nr + 1), np.int32)
     meta_i = np.empty((n_inst * nr, 4), np.int32)
     meta_f = np.empty((n_inst * nr, 4), dt)
-    cap = 2 * n + 16 * nr * n_inst + 16
+    cap = int(np.ceil(5.0 * n / P.grid_occupancy)) + 10 * nr * n_inst + 16
     bin_off = np.empty(cap, np.int32)
     nbad = C.c_int64(0)
     f = _fn("orc_grid_build", prec)

@@ -54,7 +54,7 @@ class Params(C.Structure):
                 ("search_margin", C.c_float), ("y_valid_margin", C.c_float),
                 ("min_chain", C.c_int32), ("tc_max_miss", C.c_int32),
                 ("min_tracklet_hits", C.c_int32), ("min_track_hits", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("tl_blocks_per_cu", C.c_int32)]
 
 
 class Clusters(C.Structure):
@@ -194,8 +194,9 @@ class Tracks:
                             _ptr(self.clu2trk), self.param.shape[0], self.hit_clu.numel())
 
 
-def alloc_grid(n_inst: int, n: int, device="cuda") -> Grid:
-    cap = int(lib().tpc_grid_bin_capacity(C.c_int32(n_inst), C.c_int64(n)))
+def alloc_grid(n_inst: int, n: int, device="cuda", params: Params | None = None) -> Grid:
+    p = params if params is not None else make_params()
+    cap = int(lib().tpc_grid_bin_capacity(C.byref(p), C.c_int32(n_inst), C.c_int64(n)))
     i32 = dict(dtype=torch.int32, device=device)
     return Grid(torch.empty(n, **i32), torch.empty(n_inst * (N_ROWS + 1), **i32),
                 torch.empty((n_inst * N_ROWS, 8), **i32), torch.empty(cap, **i32),
@@ -216,10 +217,12 @@ def alloc_tracks(n: int, cap_tracks: int | None = None, cap_hits: int | None = N
 class Workspace:
     """Device scratch of one tracking call (grid and tracking parts)."""
 
-    def __init__(self, n_inst: int, n: int, cap_tracklets: int = 0, device="cuda"):
+    def __init__(self, n_inst: int, n: int, cap_tracklets: int = 0, device="cuda",
+                 params: Params | None = None):
         L = lib()
         self.n_inst, self.n, self.cap_tracklets = n_inst, n, cap_tracklets
-        gb = int(L.tpc_grid_workspace_bytes(C.c_int32(n_inst), C.c_int64(n)))
+        p = params if params is not None else make_params()
+        gb = int(L.tpc_grid_workspace_bytes(C.byref(p), C.c_int32(n_inst), C.c_int64(n)))
         tb = int(L.tpc_track_workspace_bytes(C.c_int32(n_inst), C.c_int64(n),
                                              C.c_int64(cap_tracklets)))
         self.grid_ws = torch.empty(max(gb, 256), dtype=torch.uint8, device=device)
@@ -276,9 +279,9 @@ def track(geom: dict, batch: Batch, det: bool = True, cap_tracks=None, cap_hits=
     g = make_geometry(geom)
     p = make_params(det, **param_over)
     dev = batch.x.device
-    grid = alloc_grid(batch.n_inst, batch.n, dev)
+    grid = alloc_grid(batch.n_inst, batch.n, dev, p)
     tracks = alloc_tracks(batch.n, cap_tracks, cap_hits, dev)
-    ws = Workspace(batch.n_inst, batch.n, cap_tracklets, dev)
+    ws = Workspace(batch.n_inst, batch.n, cap_tracklets, dev, p)
     grid_build(g, p, batch, grid, ws)
     sector_track(g, p, batch, grid, tracks, ws)
     torch.cuda.synchronize()

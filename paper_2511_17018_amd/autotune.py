@@ -1,0 +1,93 @@
+"""Autotuner of the performance-only launch parameters.
+
+Candidates are (grid_occupancy, tl_blocks_per_cu): the clusters per grid
+bin, which trades bins scanned against clusters examined in every window
+search, and the resident blocks per compute unit of the persistent
+tracklet kernel.  Results do not depend on either (the window queries are
+widened to whole bins and filtered geometrically, and tracklet outputs go
+to fixed slots), and the tuner checks that: every candidate's
+deterministic output must equal the default's bit for bit, or it is
+discarded.  The objective is the median time of the whole chain; results
+are cached per (GPU architecture, size class) in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from .runtime import Chain, same_outputs
+
+DEFAULT_CANDIDATES = [(occ, bpc) for occ in (0.5, 1.0, 2.0, 4.0) for bpc in (4, 8, 16)]
+CACHE = os.environ.get("TPCCA_TUNE_CACHE",
+                       os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json"))
+
+
+def arch_name(device=0) -> str:
+    return torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+
+
+def size_class(n_clusters: int, n_inst: int) -> str:
+    return f"n2^{max(0, round(math.log2(max(n_clusters, 1))))}_i2^{round(math.log2(max(n_inst, 1)))}"
+
+
+def _load() -> dict:
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _time(chain: Chain, steps: int) -> float:
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    with torch.cuda.stream(chain.stream):
+        chain.enqueue()
+        for a, b in ev:
+            a.record(chain.stream)
+            chain.enqueue()
+            b.record(chain.stream)
+    chain.stream.synchronize()
+    t = sorted(a.elapsed_time(b) for a, b in ev)
+    return t[len(t) // 2]
+
+
+def tune(geom: dict, batch, steps: int = 5, candidates=None, stream=None, use_cache=True,
+         log=None) -> dict:
+    """Best (grid_occupancy, tl_blocks_per_cu) for this batch's size class."""
+    key = f"{arch_name()}/{size_class(batch.n, batch.n_inst)}"
+    cache = _load()
+    if use_cache and key in cache:
+        return cache[key]
+    stream = stream or torch.cuda.current_stream()
+    ref_chain = Chain(geom, batch, True, stream)
+    with torch.cuda.stream(stream):
+        ref_chain.enqueue()
+    stream.synchronize()
+    ref = ref_chain.outputs()
+    ref_ms = _time(ref_chain, steps)
+    del ref_chain
+    trials = []
+    for occ, bpc in candidates or DEFAULT_CANDIDATES:
+        ch = Chain(geom, batch, True, stream, grid_occupancy=occ, tl_blocks_per_cu=bpc)
+        ms = _time(ch, steps)
+        ok = same_outputs(ch.outputs(), ref)
+        trials.append({"grid_occupancy": occ, "tl_blocks_per_cu": bpc, "ms": ms, "identical": ok})
+        if log:
+            log(f"tune {key}: occupancy {occ} blocks/CU {bpc}: {ms:.3f} ms "
+                f"{'identical' if ok else 'DIFFERENT (discarded)'}")
+        del ch
+    good = [t for t in trials if t["identical"]]
+    best = min(good, key=lambda t: t["ms"])
+    entry = {"grid_occupancy": best["grid_occupancy"], "tl_blocks_per_cu": best["tl_blocks_per_cu"],
+             "ms": best["ms"], "default_ms": ref_ms, "trials": trials}
+    cache[key] = entry
+    try:
+        with open(CACHE, "w") as f:
+            json.dump(cache, f, indent=1)
+    except OSError:
+        pass
+    return entry

@@ -8,6 +8,9 @@
 
 using namespace tpcca;
 
+extern "C" int64_t tpc_grid_bin_capacity(const tpc_params* params, int32_t n_inst,
+                                         int64_t n_clusters);
+
 namespace {
 
 constexpr int64_t kAlign = 256;
@@ -32,10 +35,10 @@ struct GridWs {
   int64_t cseg, seg_cnt, seg_mm, inst_bad, nb1, fill, scan_tmp, scan_len, total;
 };
 
-GridWs grid_ws(int32_t n_inst, int64_t n)
+GridWs grid_ws(const tpc_params* p, int32_t n_inst, int64_t n)
 {
   const int64_t n_seg = (int64_t)n_inst * kRows;
-  const int64_t bin_cap = tpc_grid_bin_capacity(n_inst, n);
+  const int64_t bin_cap = tpc_grid_bin_capacity(p, n_inst, n);
   GridWs w;
   Carve c;
   w.cseg = c.take(4 * n);
@@ -106,7 +109,8 @@ tpc_status check_common(const tpc_geometry* g, const tpc_params* p, int32_t n_in
   if (n > 0 && (!in.y || !in.z || !in.row)) return TPC_ERR_INVALID;
   if (p->min_chain < 3 || p->tc_max_miss < 1 || p->min_track_hits < 1 ||
       p->min_tracklet_hits < 0 || !(p->grid_occupancy > 0) || !(p->snp_max > 0) ||
-      !(p->snp_max < 1) || !(p->search_margin >= 0))
+      !(p->snp_max < 1) || !(p->search_margin >= 0) || p->tl_blocks_per_cu < 0 ||
+      p->tl_blocks_per_cu > 64)
     return TPC_ERR_INVALID;
   *n_out = n;
   return TPC_OK;
@@ -137,6 +141,7 @@ Consts make_consts(const tpc_geometry* g, const tpc_params* p)
   k.tc_max_miss = p->tc_max_miss;
   k.min_tracklet_hits = p->min_tracklet_hits;
   k.min_track_hits = p->min_track_hits;
+  k.tl_blocks_per_cu = p->tl_blocks_per_cu > 0 ? p->tl_blocks_per_cu : 8;
   return k;
 }
 
@@ -176,6 +181,7 @@ void tpc_default_params(tpc_params* p)
   p->min_tracklet_hits = 10;
   p->min_track_hits = 10;
   p->flags = 0;
+  p->tl_blocks_per_cu = 0;
 }
 
 const char* tpc_status_string(tpc_status s)
@@ -190,16 +196,20 @@ const char* tpc_status_string(tpc_status s)
   return "unknown status";
 }
 
-int64_t tpc_grid_bin_capacity(int32_t n_inst, int64_t n_clusters)
+int64_t tpc_grid_bin_capacity(const tpc_params* params, int32_t n_inst, int64_t n_clusters)
 {
-  // per row at most 3*floor(n/2) + 8 bins plus one sentinel (see k_grid_meta)
-  return 2 * n_clusters + 16 * (int64_t)kRows * (n_inst > 0 ? n_inst : 0) + 16;
+  // A row of n clusters has nb = max(1, floor(n / occupancy)) and a bin width w
+  // with dy*dz/w^2 <= nb, dy/w <= nb, dz/w <= nb, so with one step of rounding
+  // in each ceil: ny*nz <= (dy/w + 2)(dz/w + 2) <= 5 nb + 4; plus a sentinel.
+  const double occ = params && params->grid_occupancy > 0 ? params->grid_occupancy : 2.0;
+  const int64_t rows = (int64_t)kRows * (n_inst > 0 ? n_inst : 0);
+  return (int64_t)ceil(5.0 * (double)n_clusters / occ) + 10 * rows + 16;
 }
 
-size_t tpc_grid_workspace_bytes(int32_t n_inst, int64_t n_clusters)
+size_t tpc_grid_workspace_bytes(const tpc_params* params, int32_t n_inst, int64_t n_clusters)
 {
   if (n_inst < 1 || n_clusters < 0) return 0;
-  return (size_t)grid_ws(n_inst, n_clusters).total;
+  return (size_t)grid_ws(params, n_inst, n_clusters).total;
 }
 
 size_t tpc_track_workspace_bytes(int32_t n_inst, int64_t n_clusters, int64_t cap_tracklets)
@@ -228,7 +238,7 @@ tpc_status tpc_grid_build(const tpc_geometry* geom, const tpc_params* params, in
   if (n > 0 && (!grid->sseg || !grid->perm || !grid->yz)) return TPC_ERR_INVALID;
   if (reinterpret_cast<uintptr_t>(grid->yz) % 8) return TPC_ERR_INVALID;
   if (!grid->row_off || !grid->meta || !grid->bin_off || grid->bin_cap < 1) return TPC_ERR_INVALID;
-  const GridWs w = grid_ws(n_inst, n);
+  const GridWs w = grid_ws(params, n_inst, n);
   if ((int64_t)ws_bytes < w.total) return TPC_ERR_WORKSPACE;
   GridBufs b;
   b.x = in.x;
@@ -245,7 +255,7 @@ tpc_status tpc_grid_build(const tpc_geometry* geom, const tpc_params* params, in
   b.perm = grid->perm;
   b.yz = reinterpret_cast<float2*>(grid->yz);
   // the workspace's fill counters and scan partials are sized for this capacity
-  const int64_t ws_cap = tpc_grid_bin_capacity(n_inst, n);
+  const int64_t ws_cap = tpc_grid_bin_capacity(params, n_inst, n);
   b.bin_cap = grid->bin_cap < ws_cap ? grid->bin_cap : ws_cap;
   b.res = result_dev;
   b.cseg = at<int32_t>(ws_dev, w.cseg);

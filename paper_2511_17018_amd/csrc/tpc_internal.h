@@ -24,6 +24,7 @@ struct Consts {
   float tc_chi2_pick, snp_max;
   float grid_occupancy, edge_margin, search_margin, y_valid_margin;
   int32_t min_chain, tc_max_miss, min_tracklet_hits, min_track_hits;
+  int32_t tl_blocks_per_cu;  // resident blocks per CU of the persistent tracklet kernel
 };
 
 // Device buffers of one call.

@@ -33,7 +33,6 @@ constexpr int kTile = kBlock * kItems;          // items per block in scans
 constexpr int kStatItems = 1024;                // clusters per block in the row statistics
 
 enum { CNT_START = 0, CNT_TRACKS = 1, CNT_TLQUEUE = 2 };
-constexpr int kTlBlocksPerCU = 8;   // resident blocks per CU of the persistent tracklet kernel
 
 // ------------------------------------------------------------------ helpers
 
@@ -1020,7 +1019,7 @@ hipError_t sector_track(const Consts& k, const TrackBufs& b, hipStream_t s)
   TPC_LAUNCH("start_finish", 1, 1, s, k_start_finish, b);
   TPC_LAUNCH("sel_prep", blocks_for(b.n > 0 ? b.n : 1), kBlock, s, k_sel_prep, b);
   if (b.cap > 0) {
-    const int64_t tl_blocks = std::min<int64_t>(blocks_for(b.cap), (int64_t)b.n_cu * kTlBlocksPerCU);
+    const int64_t tl_blocks = std::min<int64_t>(blocks_for(b.cap), (int64_t)b.n_cu * k.tl_blocks_per_cu);
     TPC_LAUNCH("tracklets", (unsigned)tl_blocks, kBlock, s, k_tracklets, k, b);
     const unsigned wblocks = blocks_for(b.cap, kWavesPerBlock);
     TPC_LAUNCH("sel_mark", wblocks, kBlock, s, k_sel_mark, b);

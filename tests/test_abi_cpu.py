@@ -58,7 +58,10 @@ def test_workspace_sizes_grow_and_layout_is_ordered():
                                       "tl_hit", "tl_ncand", "owner", "scratch", "total")]
     assert offs == sorted(offs) and all(o % 256 == 0 for o in offs)
     assert lay.tl_hit + 4 * 152 * lay.cap_tracklets <= lay.tl_ncand
-    assert L.tpc_grid_bin_capacity(C.c_int32(2), C.c_int64(100)) >= 2 * 100 + 2 * 152 * 9
+    p = tpc.make_params()
+    assert L.tpc_grid_bin_capacity(C.byref(p), C.c_int32(2), C.c_int64(100)) >= 5 * 50 + 2 * 152 * 9
+    p.grid_occupancy = 0.5
+    assert L.tpc_grid_bin_capacity(C.byref(p), C.c_int32(2), C.c_int64(100)) >= 5 * 200 + 2 * 152 * 9
 
 
 def _args(geom=None, n_inst=1, off=(0, 10)):
