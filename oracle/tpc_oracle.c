@@ -472,7 +472,8 @@ void SFX(orc_tracklets)(const orc_geom* g, const orc_params* P, int64_t S, const
 
 /* ------------------------------------------------------------------------ */
 /* a6 -- TrackletSelector, R20.  key = (nhit, smaller chi2, smaller
- * instance-local start position); each hit is owned by the kept tracklet
+ * instance-local input index of the start hit: independent of the grid);
+ * each hit is owned by the kept tracklet
  * with the largest key; a tracklet owning >= min_track_hits hits becomes a
  * track.  Tracks are emitted in tracklet order with their owned hits in
  * ascending row order (input indices); clu2trk[input index] = track or -1. */
@@ -502,7 +503,7 @@ int64_t SFX(orc_select)(const orc_geom* g, const orc_params* P, int64_t n, int64
     keys[t] = 0;
     if (status[t] != 0) continue;
     int32_t s0 = sseg[start[t]];
-    int64_t lid = start[t] - inst_off[s0 / NR];
+    int64_t lid = perm[start[t]] - inst_off[s0 / NR];
     keys[t] = ts_key(nhit[t], chi2[t], lid);
     for (int r = rmin[t]; r <= rmax[t]; r++) {
       int32_t h = hit[t * NR + r];

@@ -20,7 +20,7 @@ import torch
 
 from .runtime import Chain, same_outputs
 
-DEFAULT_CANDIDATES = [(occ, bpc) for occ in (0.5, 1.0, 2.0, 4.0) for bpc in (4, 8, 16)]
+DEFAULT_CANDIDATES = [(occ, bpc) for occ in (0.25, 0.5, 1.0, 2.0) for bpc in (2, 4, 8)]
 CACHE = os.environ.get("TPCCA_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json"))
 

@@ -841,7 +841,8 @@ __device__ __forceinline__ unsigned long long ts_key(const TrackBufs& b, int64_t
 {
   const int32_t h0 = b.start[t];
   const int seg0 = b.sseg[h0];
-  const int64_t lid = (int64_t)h0 - b.inst_off[seg0 / kRows];
+  // instance-local input index of the start hit (independent of the grid)
+  const int64_t lid = (int64_t)b.perm[h0] - b.inst_off[seg0 / kRows];
   const uint32_t bits = __float_as_uint(b.tl_chi2[t]);
   return ((unsigned long long)(uint32_t)b.tl_nhit[t] << 56) |
          ((unsigned long long)(~bits & 0x7FFFFFFFu) << 25) |

@@ -92,7 +92,21 @@ class GraphChain:
             self.graph.replay()
 
 
+def canonical_tracks(o: dict) -> dict:
+    """Tracks as {tuple of input indices: parameter bits}: equal for two runs
+    whose outputs differ only in track order (e.g. another grid bin size)."""
+    ho, hc, par = o["hit_off"], o["hit_clu"], o["param"]
+    return {tuple(hc[ho[k]:ho[k + 1]].tolist()): par[k].view(np.int32).tobytes()
+            for k in range(len(ho) - 1)}
+
+
 def same_outputs(a: dict, b: dict) -> bool:
-    return all(np.array_equal(a[k].view(np.int32) if a[k].dtype == np.float32 else a[k],
-                              b[k].view(np.int32) if b[k].dtype == np.float32 else b[k])
-               for k in ("hit_off", "hit_clu", "param", "clu2trk"))
+    """Same tracks (hit sets, parameter bits) and the same cluster partition."""
+    if canonical_tracks(a) != canonical_tracks(b):
+        return False
+    ca, cb = a["clu2trk"], b["clu2trk"]
+    if not np.array_equal(ca < 0, cb < 0):
+        return False
+    m = ca >= 0
+    pairs = np.unique(np.stack([ca[m], cb[m]], 1), axis=0)
+    return len(pairs) == len(np.unique(ca[m])) == len(np.unique(cb[m]))

@@ -500,7 +500,8 @@ def test_selection_matches_brute_force_ownership():
         if tl.status[t] != 0:
             continue
         inst = r.grid.sseg[st[t]] // 152
-        key = (int(tl.nhit[t]), -float(np.float32(tl.chi2[t])), -(int(st[t]) - int(ev.inst_off[inst])))
+        key = (int(tl.nhit[t]), -float(np.float32(tl.chi2[t])),
+               -(int(r.grid.perm[st[t]]) - int(ev.inst_off[inst])))
         for rr in range(tl.rmin[t], tl.rmax[t] + 1):
             h = tl.hit[t, rr]
             if h >= 0 and (h not in best or key > best[h][0]):
