@@ -71,7 +71,8 @@ static int k_propagate(kst* s, real x1, real x2, real kB, real snp_max)
   real snp = s->p[2], tgl = s->p[3], qpt = s->p[4];
   real cc = kB * qpt;
   real s2 = snp + cc * dx;
-  if (!(FABS(s2) < RE(snp_max))) return 0;
+  /* the step is defined only for |sin phi| < 1 at both ends (cos phi real) */
+  if (!(FABS(snp) < RE(snp_max)) || !(FABS(s2) < RE(snp_max))) return 0;
   real c1 = SQRT((one - snp) * (one + snp));
   real c2 = SQRT((one - s2) * (one + s2));
   real f = (snp + s2) / (c1 + c2);

@@ -28,7 +28,9 @@ __device__ __forceinline__ bool kprop(KSt& s, float x1, float x2, float kB, floa
   const float snp = s.p[2], tgl = s.p[3], qpt = s.p[4];
   const float cc = kB * qpt;
   const float s2 = snp + cc * dx;
-  if (!(fabsf(s2) < smax)) return false;
+  // defined only for |snp| < 1 at both ends of the step (after an update
+  // the incoming state may lie outside)
+  if (!(fabsf(snp) < smax) || !(fabsf(s2) < smax)) return false;
   const float c1 = sqrtf((one - snp) * (one + snp));
   const float c2 = sqrtf((one - s2) * (one + s2));
   const float f = (snp + s2) / (c1 + c2);

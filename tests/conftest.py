@@ -15,7 +15,11 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session", autouse=True)
 def _oracle_built():
+    import glob
+
     import oracle
-    if not os.path.exists(oracle.LIB):
+    srcs = glob.glob(os.path.join(ROOT, "oracle", "*.[ch]"))
+    if (not os.path.exists(oracle.LIB)
+            or max(os.path.getmtime(f) for f in srcs) > os.path.getmtime(oracle.LIB)):
         oracle.build()
     yield

@@ -94,6 +94,38 @@ def test_propagation_refuses_snp_overflow():
     assert not ok and np.array_equal(p, st)
 
 
+def test_propagation_refuses_state_outside_domain():
+    # cos(phi) = sqrt(1 - snp^2) must exist at the start of the step too: an
+    # update can leave |snp| >= snp_max, and a step that brings it back into
+    # range must still fail (it would otherwise return NaN for y and z)
+    # (kB < 0: q/pt of the sign of snp turns it back towards zero, so the
+    # end point of each of these steps is inside the domain)
+    for snp0 in (0.995, 1.02, -1.03):
+        st = np.array([1.0, 2.0, snp0, 0.1, np.sign(snp0) * 20.0])
+        for prec in (32, 64):
+            ok, p, c = oracle.propagate(G, P, st, _cov0(), 100.0, 102.0, prec=prec)
+            assert not ok and np.array_equal(p, st.astype(p.dtype)), (snp0, prec)
+    # just inside the domain the step is taken
+    st = np.array([1.0, 2.0, 0.989, 0.1, 20.0])
+    ok, p, _ = oracle.propagate(G, P, st, _cov0(), 100.0, 102.0, prec=64)
+    assert ok and np.isfinite(p).all() and p[2] < 0.989
+
+
+def test_dense_event_outputs_are_finite():
+    # a dense wedge (1500 tracks) where updates push some states past
+    # |snp| = 1: every accepted tracklet and every track has finite
+    # parameters, covariance and chi2
+    ev = synth.config1(n_tracks=1500)
+    o = oracle.track(G, P, ev.inst_off, ev.y, ev.z, ev.row)
+    tl = o.tracklets
+    acc = tl.status == 0
+    assert acc.sum() > 1000
+    assert np.isfinite(tl.par[acc]).all() and np.isfinite(tl.cov[acc]).all()
+    assert np.isfinite(tl.chi2[acc]).all()
+    T = o.tracks
+    assert np.isfinite(T.par).all() and np.isfinite(T.cov).all() and np.isfinite(T.chi2).all()
+
+
 # --------------------------------------------------------------- P3 Jacobian
 def _jacobian(st, x1, x2, prec=64):
     F = np.zeros((5, 5))
