@@ -106,8 +106,8 @@ def run(args) -> dict:
     out = {}
     # ---- autotuned launch parameters (performance-only; outputs checked identical)
     tuned = autotune.tune(geom, batch, stream=stream, use_cache=not args.retune, log=log)
-    tp = dict(grid_occupancy=tuned["grid_occupancy"], tl_blocks_per_cu=tuned["tl_blocks_per_cu"])
-    out["autotune"] = {k: tuned[k] for k in ("grid_occupancy", "tl_blocks_per_cu", "ms",
+    tp = dict(grid_occupancy=tuned["grid_occupancy"], tl_chunk=tuned["tl_chunk"])
+    out["autotune"] = {k: tuned[k] for k in ("grid_occupancy", "tl_chunk", "ms",
                                              "default_ms")}
     # ---- batched, deterministic
     det_c = Chain(geom, batch, True, stream, **tp)

@@ -80,9 +80,9 @@ typedef struct {
  * |snp| < 0.99, grid occupancy 2, sector-edge margin 1 cm, window margin
  * 0.01 cm, cluster validity margin 2 cm, chains >= 3 hits, 10 consecutive
  * misses, >= 10 hits per tracklet and per track, flags 0, and the
- * performance-only tl_blocks_per_cu = 0 (the library's default, 8 resident
- * blocks per compute unit for the persistent tracklet kernel).  Results do
- * not depend on grid_occupancy (the bin size) or tl_blocks_per_cu. */
+ * performance-only tl_chunk = 0 (tracklets per workgroup of the tracklet
+ * kernel: 64, 128 or 256; 0 selects 256).  Results do not depend on
+ * grid_occupancy (the bin size) or tl_chunk. */
 typedef struct {
   float nf_win_y, nf_win_z, nf_chi2_max;
   float tc_chi2_pick, snp_max;
@@ -91,7 +91,7 @@ typedef struct {
   float y_valid_margin;
   int32_t min_chain, tc_max_miss, min_tracklet_hits, min_track_hits;
   uint32_t flags;
-  int32_t tl_blocks_per_cu;
+  int32_t tl_chunk;
 } tpc_params;
 
 /* Clusters: device SoA, n_clusters entries each (charge is carried, unused). */
@@ -161,7 +161,8 @@ typedef struct {
  *   start              i32[cap_tracklets] start hits in list order
  *   tl_par             f32[5][cap_tracklets]   tl_cov f32[15][cap_tracklets]
  *   tl_chi2            f32[cap_tracklets]      tl_nhit, tl_rmin, tl_rmax, tl_status i32
- *   tl_hit             i32[cap_tracklets][152] (valid for rmin <= row <= rmax)
+ *   tl_hit             i32[152][cap_tracklets] (row-major by row: slot of row r of
+ *                      tracklet t at r * cap_tracklets + t; valid for rmin <= r <= rmax)
  *   tl_ncand           i32[cap_tracklets] grid candidates whose chi2 the extension
  *                      searches evaluated (instrumentation for byte counts)
  *   owner              u64[n_clusters]  selection keys per position          */

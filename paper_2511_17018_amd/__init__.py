@@ -54,7 +54,7 @@ class Params(C.Structure):
                 ("search_margin", C.c_float), ("y_valid_margin", C.c_float),
                 ("min_chain", C.c_int32), ("tc_max_miss", C.c_int32),
                 ("min_tracklet_hits", C.c_int32), ("min_track_hits", C.c_int32),
-                ("flags", C.c_uint32), ("tl_blocks_per_cu", C.c_int32)]
+                ("flags", C.c_uint32), ("tl_chunk", C.c_int32)]
 
 
 class Clusters(C.Structure):

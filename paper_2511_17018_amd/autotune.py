@@ -1,11 +1,12 @@
 """Autotuner of the performance-only launch parameters.
 
-Candidates are (grid_occupancy, tl_blocks_per_cu): the clusters per grid
-bin, which trades bins scanned against clusters examined in every window
-search, and the resident blocks per compute unit of the persistent
-tracklet kernel.  Results do not depend on either (the window queries are
-widened to whole bins and filtered geometrically, and tracklet outputs go
-to fixed slots), and the tuner checks that: every candidate's
+Candidates are (grid_occupancy, tl_chunk): the clusters per grid bin,
+which trades bins scanned against clusters examined in every window
+search, and the tracklets per workgroup of the row-sweeping tracklet
+kernel, which trades rows staged per tracklet against lanes idle in a
+sweep.  Results do not depend on either (the window queries are widened to
+whole bins and filtered geometrically, and tracklet outputs go to fixed
+slots), and the tuner checks that: every candidate's
 deterministic output must equal the default's bit for bit, or it is
 discarded.  The objective is the median time of the whole chain; results
 are cached per (GPU architecture, size class) in a JSON file.
@@ -20,7 +21,7 @@ import torch
 
 from .runtime import Chain, same_outputs
 
-DEFAULT_CANDIDATES = [(occ, bpc) for occ in (0.25, 0.5, 1.0, 2.0) for bpc in (2, 4, 8)]
+DEFAULT_CANDIDATES = [(occ, chunk) for occ in (0.25, 0.5, 1.0, 2.0) for chunk in (64, 128, 256)]
 CACHE = os.environ.get("TPCCA_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json"))
 
@@ -57,7 +58,7 @@ def _time(chain: Chain, steps: int) -> float:
 
 def tune(geom: dict, batch, steps: int = 5, candidates=None, stream=None, use_cache=True,
          log=None) -> dict:
-    """Best (grid_occupancy, tl_blocks_per_cu) for this batch's size class."""
+    """Best (grid_occupancy, tl_chunk) for this batch's size class."""
     key = f"{arch_name()}/{size_class(batch.n, batch.n_inst)}"
     cache = _load()
     if use_cache and key in cache:
@@ -71,18 +72,18 @@ def tune(geom: dict, batch, steps: int = 5, candidates=None, stream=None, use_ca
     ref_ms = _time(ref_chain, steps)
     del ref_chain
     trials = []
-    for occ, bpc in candidates or DEFAULT_CANDIDATES:
-        ch = Chain(geom, batch, True, stream, grid_occupancy=occ, tl_blocks_per_cu=bpc)
+    for occ, chunk in candidates or DEFAULT_CANDIDATES:
+        ch = Chain(geom, batch, True, stream, grid_occupancy=occ, tl_chunk=chunk)
         ms = _time(ch, steps)
         ok = same_outputs(ch.outputs(), ref)
-        trials.append({"grid_occupancy": occ, "tl_blocks_per_cu": bpc, "ms": ms, "identical": ok})
+        trials.append({"grid_occupancy": occ, "tl_chunk": chunk, "ms": ms, "identical": ok})
         if log:
-            log(f"tune {key}: occupancy {occ} blocks/CU {bpc}: {ms:.3f} ms "
+            log(f"tune {key}: occupancy {occ} chunk {chunk}: {ms:.3f} ms "
                 f"{'identical' if ok else 'DIFFERENT (discarded)'}")
         del ch
     good = [t for t in trials if t["identical"]]
     best = min(good, key=lambda t: t["ms"])
-    entry = {"grid_occupancy": best["grid_occupancy"], "tl_blocks_per_cu": best["tl_blocks_per_cu"],
+    entry = {"grid_occupancy": best["grid_occupancy"], "tl_chunk": best["tl_chunk"],
              "ms": best["ms"], "default_ms": ref_ms, "trials": trials}
     cache[key] = entry
     try:

@@ -56,7 +56,7 @@ GridWs grid_ws(const tpc_params* p, int32_t n_inst, int64_t n)
 
 struct TrackWs {
   tpc_track_ws_layout pub;
-  int64_t tl_own, tsv, counters, scan_len;
+  int64_t tl_own, tsv, tl_first, chunk_off, counters, scan_len;
 };
 
 TrackWs track_ws(int32_t n_inst, int64_t n, int64_t cap)
@@ -81,6 +81,8 @@ TrackWs track_ws(int32_t n_inst, int64_t n, int64_t cap)
   w.pub.owner = c.take(8 * n);
   w.tl_own = c.take(4 * cap);
   w.tsv = c.take(8 * cap);
+  w.tl_first = c.take(8 * ((int64_t)n_inst + 1));
+  w.chunk_off = c.take(8 * ((int64_t)n_inst + 1));
   w.counters = c.take(8 * 8);
   const int64_t big = n > cap ? n : cap;
   w.scan_len = big / kScanTile + 2;
@@ -109,8 +111,8 @@ tpc_status check_common(const tpc_geometry* g, const tpc_params* p, int32_t n_in
   if (n > 0 && (!in.y || !in.z || !in.row)) return TPC_ERR_INVALID;
   if (p->min_chain < 3 || p->tc_max_miss < 1 || p->min_track_hits < 1 ||
       p->min_tracklet_hits < 0 || !(p->grid_occupancy > 0) || !(p->snp_max > 0) ||
-      !(p->snp_max < 1) || !(p->search_margin >= 0) || p->tl_blocks_per_cu < 0 ||
-      p->tl_blocks_per_cu > 64)
+      !(p->snp_max < 1) || !(p->search_margin >= 0) ||
+      (p->tl_chunk != 0 && p->tl_chunk != 64 && p->tl_chunk != 128 && p->tl_chunk != 256))
     return TPC_ERR_INVALID;
   *n_out = n;
   return TPC_OK;
@@ -141,17 +143,8 @@ Consts make_consts(const tpc_geometry* g, const tpc_params* p)
   k.tc_max_miss = p->tc_max_miss;
   k.min_tracklet_hits = p->min_tracklet_hits;
   k.min_track_hits = p->min_track_hits;
-  k.tl_blocks_per_cu = p->tl_blocks_per_cu > 0 ? p->tl_blocks_per_cu : 8;
+  k.tl_chunk = p->tl_chunk > 0 ? p->tl_chunk : 256;
   return k;
-}
-
-int32_t device_cu_count()
-{
-  int dev = 0, cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 256;
-  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1)
-    return 256;
-  return cu;
 }
 
 template <class T>
@@ -181,7 +174,7 @@ void tpc_default_params(tpc_params* p)
   p->min_tracklet_hits = 10;
   p->min_track_hits = 10;
   p->flags = 0;
-  p->tl_blocks_per_cu = 0;
+  p->tl_chunk = 0;
 }
 
 const char* tpc_status_string(tpc_status s)
@@ -323,12 +316,13 @@ tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, 
   b.owner = at<unsigned long long>(ws_dev, w.pub.owner);
   b.tl_own = at<int32_t>(ws_dev, w.tl_own);
   b.tsv = at<int64_t>(ws_dev, w.tsv);
+  b.tl_first = at<int64_t>(ws_dev, w.tl_first);
+  b.chunk_off = at<int64_t>(ws_dev, w.chunk_off);
   b.counters = at<int64_t>(ws_dev, w.counters);
   b.scan_tmp = at<int64_t>(ws_dev, w.pub.scratch);
   b.scan_tmp_len = w.scan_len;
   b.out = *out;
   b.res = result_dev;
-  b.n_cu = device_cu_count();
   const Consts k = make_consts(geom, params);
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = (params->flags & TPC_FLAG_DETERMINISTIC) ? det::sector_track(k, b, s)

@@ -24,7 +24,7 @@ struct Consts {
   float tc_chi2_pick, snp_max;
   float grid_occupancy, edge_margin, search_margin, y_valid_margin;
   int32_t min_chain, tc_max_miss, min_tracklet_hits, min_track_hits;
-  int32_t tl_blocks_per_cu;  // resident blocks per CU of the persistent tracklet kernel
+  int32_t tl_chunk;    // tracklets per workgroup of the tracklet kernel (64, 128, 256)
 };
 
 // Device buffers of one call.
@@ -73,15 +73,16 @@ struct TrackBufs {
   float* tl_cov;       // [15][cap]
   float* tl_chi2;
   int32_t *tl_nhit, *tl_rmin, *tl_rmax, *tl_status;
-  int32_t* tl_hit;     // [152][cap]
+  int32_t* tl_hit;     // [152][cap]: hit slot of row r of tracklet t at r * cap + t
   int32_t* tl_ncand;   // [cap] candidates evaluated by the extension searches
   unsigned long long* owner;  // [n]
   int32_t* tl_own;     // [cap] owned hits of accepted tracklets, 0 otherwise
   int64_t* tsv;        // [cap] packed (track flag << 32 | owned hits), then its scan
   int64_t* scan_tmp;
   int64_t scan_tmp_len;
+  int64_t* tl_first;   // [n_inst + 1] first tracklet of each instance
+  int64_t* chunk_off;  // [n_inst + 1] first tracklet chunk of each instance
   int64_t* counters;   // [8] device counters
-  int32_t n_cu;        // compute units of the device (sizes persistent grids)
   // outputs
   tpc_tracks out;
   tpc_result* res;

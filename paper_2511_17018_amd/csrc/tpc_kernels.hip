@@ -32,7 +32,7 @@ constexpr int kItems = 8;                       // items per thread in scans
 constexpr int kTile = kBlock * kItems;          // items per block in scans
 constexpr int kStatItems = 1024;                // clusters per block in the row statistics
 
-enum { CNT_START = 0, CNT_TRACKS = 1, CNT_TLQUEUE = 2 };
+enum { CNT_START = 0, CNT_TRACKS = 1, CNT_CHUNKS = 2 };
 
 // ------------------------------------------------------------------ helpers
 
@@ -654,60 +654,133 @@ __global__ void k_start_finish(TrackBufs b)
 
 #include "tpc_kalman.h"
 
-// R15: best cluster of row segment `seg` for the predicted state
-__device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b, int seg,
-                                           const KSt& st, const Innov& q, int& ncand)
+// R15: best cluster of one row for the predicted state.  `off` holds the
+// row's ny*nz+1 bin boundaries and `yz` the cluster positions, both in one
+// index space whose index p is grid position pos0 + p (the LDS copy of a row
+// starts at its first position; the global arrays at zero).  The pick is a
+// total order -- smallest chi2, then smallest input index -- so the scan
+// order does not matter; the input index is read only on an exact tie.
+__device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b,
+                                           const tpc_row_meta& m, const int32_t* off,
+                                           const float2* yz, int32_t pos0, const KSt& st,
+                                           const Innov& q, int& ncand)
 {
   const float y = st.p[0], z = st.p[1];
   const float pick = k.tc_chi2_pick;
   const float wy = sqrtf(pick * q.S00) + k.search_margin;
   const float wz = sqrtf(pick * q.S11) + k.search_margin;
-  const tpc_row_meta m = b.meta[seg];
   const int ylo = bin_coord(y - wy, m.y0, m.iwy, m.ny);
   const int yhi = bin_coord(y + wy, m.y0, m.iwy, m.ny);
   const int zlo = bin_coord(z - wz, m.z0, m.iwz, m.nz);
   const int zhi = bin_coord(z + wz, m.z0, m.iwz, m.nz);
-  int32_t best = -1, bperm = 0;
+  int32_t best = -1;
   float bchi = 0.0f;
   for (int iz = zlo; iz <= zhi; iz++) {
-    const int bb = m.bin_base + iz * m.ny;
-    const int e = b.bin_off[bb + yhi + 1];
-    const int p0 = b.bin_off[bb + ylo];
+    const int bb = iz * m.ny;
+    const int e = off[bb + yhi + 1];
+    const int p0 = off[bb + ylo];
     ncand += e - p0;
     for (int p = p0; p < e; p++) {
-      const float2 qc = b.yz[p];
+      const float2 qc = yz[p];
       const float r0 = qc.x - y, r1 = qc.y - z;
       const float ch = chi2_of(q, r0, r1);
       if (!(ch <= pick)) continue;
       if (best < 0 || ch < bchi) {
         best = p;
         bchi = ch;
-        bperm = b.perm[p];
-      } else if (ch == bchi) {
-        const int32_t pp = b.perm[p];
-        if (pp < bperm) {
-          best = p;
-          bperm = pp;
-        }
+      } else if (ch == bchi && b.perm[pos0 + p] < b.perm[pos0 + best]) {
+        best = p;
       }
     }
   }
-  return best;
+  return best < 0 ? -1 : pos0 + best;
 }
 
-// TrackletConstructor (R13-R17) for tracklet t (one lane).
-__device__ __forceinline__ bool tracklet_one(const Consts& k, const TrackBufs& b, const int64_t t)
+// TrackletConstructor (R13-R17), one workgroup per chunk of at most CH
+// tracklets of one instance, one tracklet per thread.  Start hits are in
+// (row, bin) order, so a chunk's start rows form a short range; the
+// workgroup sweeps the rows upward from the lowest start row (phases 1 and
+// 2), each lane walks its state back to its start row (phase 3, no data),
+// and the workgroup sweeps downward from the highest start row.  At every
+// row of a sweep the row's bin boundaries and cluster positions are staged
+// in LDS with coalesced loads, and every lane's search reads them there; a
+// row too large for the LDS buffer is searched in global memory instead
+// (same arithmetic, same result).  Hit slots are [row][tracklet], so the
+// lanes' writes of one row are contiguous.
+//
+// Chunks of one instance are consecutive; workgroup w runs on XCD w % 8
+// (round-robin dispatch), so the chunk index is taken from a per-XCD range
+// and an instance's rows are cached in one L2.
+// LDS bytes for one staged row: 124 per thread, so that with the kernel's
+// register use (5 waves per SIMD) LDS does not limit the resident workgroups
+constexpr int row_lds(int ch) { return ch * 124; }
+
+// first tracklet of every instance (start hits are in instance order)
+__global__ __launch_bounds__(kBlock) void k_tl_first(TrackBufs b)
 {
+  const int64_t S = min(b.counters[CNT_START], b.cap);
+  const int64_t t = gtid();
+  if (t > S) return;
+  const int it = t < S ? b.sseg[b.start[t]] / kRows : b.n_inst;
+  const int ip = t > 0 ? b.sseg[b.start[t - 1]] / kRows : -1;
+  for (int i = ip + 1; i <= it; i++) b.tl_first[i] = t;
+}
+
+// chunk offsets per instance (exclusive scan of ceil(tracklets / CH))
+__global__ __launch_bounds__(kBlock) void k_tl_chunks(TrackBufs b, int ch)
+{
+  int64_t carry = 0;
+  for (int64_t i0 = 0; i0 < b.n_inst; i0 += kBlock) {
+    const int64_t i = i0 + threadIdx.x;
+    const int64_t c = i < b.n_inst ? (b.tl_first[i + 1] - b.tl_first[i] + ch - 1) / ch : 0;
+    int64_t tot;
+    const int64_t ex = block_exclusive_scan(c, &tot);
+    if (i < b.n_inst) b.chunk_off[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    b.chunk_off[b.n_inst] = carry;
+    b.counters[CNT_CHUNKS] = carry;
+  }
+}
+
+template <int CH>
+__global__ __launch_bounds__(CH) void k_tracklets(Consts k, TrackBufs b)
+{
+  constexpr int kRowLds = row_lds(CH);
+  __shared__ __align__(16) unsigned char s_row[kRowLds];
+  __shared__ int s_inst;
+  const int64_t C = b.counters[CNT_CHUNKS];
+  const int64_t per = (C + 7) / 8;
+  const int64_t slot = blockIdx.x / 8;
+  if (slot >= per) return;
+  const int64_t lc = (int64_t)(blockIdx.x % 8) * per + slot;
+  if (lc >= C) return;
+  if (threadIdx.x == 0) s_inst = find_inst(b.chunk_off, b.n_inst, lc);
+  __syncthreads();
+  const int inst = __builtin_amdgcn_readfirstlane(s_inst);
+  const int64_t t0 = b.tl_first[inst] + (lc - b.chunk_off[inst]) * CH;
+  const int64_t t1 = min(t0 + CH, b.tl_first[inst + 1]);
+  const int segb = inst * kRows;
+  const int rlo = b.sseg[b.start[t0]] - segb;
+  const int rhi = b.sseg[b.start[t1 - 1]] - segb;
+  const int64_t t = t0 + threadIdx.x;
+  const bool mine = t < t1;
+  const int64_t cap = b.cap;
+  int32_t* const H = b.tl_hit + t;  // hit slot of row r at H[r * cap]
+  int32_t* const s_off = (int32_t*)s_row;
+
   const float kB = k.kB, vy = k.vy, vz = k.vz, smax = k.snp_max;
   const float edge = k.edge_margin, tanh_ = k.tan_half;
-  int32_t* H = b.tl_hit + t * kRows;  // hit slot of row r at H[r]
-  const int32_t h0 = b.start[t];
-  const int seg0 = b.sseg[h0];
-  const int segbase = seg0 - seg0 % kRows;
-  const int r0 = seg0 % kRows;
-  const int32_t h2 = b.up2[b.up2[h0]];
-  KSt st;
-  {
+  KSt st, keep;
+  float chi2 = 0.0f;
+  int n = 1, r0 = kRows, rmax = 0, rmin = 0, ncand = 0;
+  int32_t hn = -1;  // phase 1: cleaned upward link of the last hit
+  if (mine) {
+    const int32_t h0 = b.start[t];
+    r0 = b.sseg[h0] - segb;
+    const int32_t h1 = b.up2[h0];
+    const int32_t h2 = b.up2[h1];
     const float dxi = k.row_x[r0 + 2] - k.row_x[r0];
     const float2 q0 = b.yz[h0], q2 = b.yz[h2];
     const float dyi = q2.x - q0.x;
@@ -719,120 +792,138 @@ __device__ __forceinline__ bool tracklet_one(const Consts& k, const TrackBufs& b
     st.p[3] = dzi / Li;
     st.p[4] = 0.0f;
     kinit_cov(st, vy, vz);
+    rmax = rmin = r0;
+    H[(int64_t)r0 * cap] = h0;
+    hn = h1;
   }
-  float chi2 = 0.0f;
-  int n = 1, rmax = r0, rmin = r0, stat = 0, ncand = 0;
-  H[r0] = h0;
-  int r = r0;
-  int32_t h = h0;
-  bool ok_up = true;
-  // phase 1: cleaned links, no cut (R14)
-  for (int32_t hn = b.up2[h]; hn >= 0; hn = b.up2[h]) {
-    if (!kprop(st, k.row_x[r], k.row_x[r + 1], kB, smax)) {
-      ok_up = false;
-      break;
+
+  // upward sweep: phase 1 follows the cleaned links without a cut (R14),
+  // phase 2 searches the rows (R15)
+  bool up = mine;
+  int phase = 1, miss = 0;
+  for (int r = rlo + 1; r < kRows; r++) {
+    if (!__syncthreads_or(up)) break;
+    const tpc_row_meta m = b.meta[segb + r];
+    const int nbin = m.ny * m.nz;
+    const int32_t P0 = b.bin_off[m.bin_base];
+    const int cnt = b.bin_off[m.bin_base + nbin] - P0;
+    const int64_t ob = ((int64_t)(nbin + 1) * 4 + 7) & ~(int64_t)7;
+    const bool staged = ob + (int64_t)cnt * 8 <= kRowLds;
+    float2* const s_yz = (float2*)(s_row + (staged ? ob : 0));
+    if (staged) {
+      for (int j = threadIdx.x; j <= nbin; j += CH) s_off[j] = b.bin_off[m.bin_base + j] - P0;
+      for (int j = threadIdx.x; j < cnt; j += CH) s_yz[j] = b.yz[P0 + j];
     }
-    r++;
-    const float2 qn = b.yz[hn];
-    chi2 += kupdate(st, qn.x, qn.y, vy, vz);
-    H[r] = hn;
-    n++;
-    rmax = r;
-    h = hn;
-  }
-  KSt keep = st;
-  // phase 2: upward grid search (R15)
-  if (ok_up) {
-    int miss = 0;
-    while (r < kRows - 1) {
-      if (!kprop(st, k.row_x[r], k.row_x[r + 1], kB, smax)) break;
-      r++;
-      if (!(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) break;
+    __syncthreads();
+    if (!(up && r > r0)) continue;
+    if (phase == 1 && hn < 0) {
+      // links exhausted at row r - 1: the phase-2 restart state is kept
+      phase = 2;
+      keep = st;
+    }
+    if (!kprop(st, k.row_x[r - 1], k.row_x[r], kB, smax)) {
+      up = false;
+    } else if (phase == 1) {
+      const float2 qn = staged ? s_yz[hn - P0] : b.yz[hn];
+      chi2 += kupdate(st, qn.x, qn.y, vy, vz);
+      H[(int64_t)r * cap] = hn;
+      n++;
+      rmax = r;
+      hn = b.up2[hn];
+    } else if (!(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) {
+      up = false;
+    } else {
       const Innov q = innov(st, vy, vz);
-      const int32_t bh = ksearch(k, b, segbase + r, st, q, ncand);
+      const int32_t bh = staged ? ksearch(k, b, m, s_off, s_yz, P0, st, q, ncand)
+                                : ksearch(k, b, m, b.bin_off + m.bin_base, b.yz, 0, st, q, ncand);
       if (bh >= 0) {
-        const float2 qb = b.yz[bh];
+        const float2 qb = staged ? s_yz[bh - P0] : b.yz[bh];
         chi2 += kupdate_q(st, q, qb.x, qb.y);
-        H[r] = bh;
+        H[(int64_t)r * cap] = bh;
         n++;
         rmax = r;
         keep = st;
         miss = 0;
       } else {
-        H[r] = -1;
-        if (++miss >= k.tc_max_miss) break;
+        H[(int64_t)r * cap] = -1;
+        if (++miss >= k.tc_max_miss) up = false;
       }
     }
   }
-  // phase 3: back to the start row, then downward (R16)
-  st = keep;
-  r = rmax;
-  while (r > r0) {
-    if (!kprop(st, k.row_x[r], k.row_x[r - 1], kB, smax)) {
-      stat = 2;
-      break;
+  // a lane that never left phase 1 restarts from its last linked row
+  if (phase == 1) keep = st;
+
+  // phase 3 (R16): back to the start row, then downward
+  int stat = 0;
+  if (mine) {
+    st = keep;
+    for (int r = rmax; r > r0; r--) {
+      if (!kprop(st, k.row_x[r], k.row_x[r - 1], kB, smax)) {
+        stat = 2;
+        break;
+      }
     }
-    r--;
+    keep = st;  // output state (innermost hit)
   }
-  keep = st;  // output state (innermost hit)
-  if (stat == 0) {
-    int miss = 0;
-    while (r > 0) {
-      if (!kprop(st, k.row_x[r], k.row_x[r - 1], kB, smax)) break;
-      r--;
-      if (!(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) break;
+  bool dn = mine && stat == 0;
+  miss = 0;
+  for (int r = rhi - 1; r >= 0; r--) {
+    if (!__syncthreads_or(dn)) break;
+    const tpc_row_meta m = b.meta[segb + r];
+    const int nbin = m.ny * m.nz;
+    const int32_t P0 = b.bin_off[m.bin_base];
+    const int cnt = b.bin_off[m.bin_base + nbin] - P0;
+    const int64_t ob = ((int64_t)(nbin + 1) * 4 + 7) & ~(int64_t)7;
+    const bool staged = ob + (int64_t)cnt * 8 <= kRowLds;
+    float2* const s_yz = (float2*)(s_row + (staged ? ob : 0));
+    if (staged) {
+      for (int j = threadIdx.x; j <= nbin; j += CH) s_off[j] = b.bin_off[m.bin_base + j] - P0;
+      for (int j = threadIdx.x; j < cnt; j += CH) s_yz[j] = b.yz[P0 + j];
+    }
+    __syncthreads();
+    if (!(dn && r < r0)) continue;
+    if (!kprop(st, k.row_x[r + 1], k.row_x[r], kB, smax)) {
+      dn = false;
+    } else if (!(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) {
+      dn = false;
+    } else {
       const Innov q = innov(st, vy, vz);
-      const int32_t bh = ksearch(k, b, segbase + r, st, q, ncand);
+      const int32_t bh = staged ? ksearch(k, b, m, s_off, s_yz, P0, st, q, ncand)
+                                : ksearch(k, b, m, b.bin_off + m.bin_base, b.yz, 0, st, q, ncand);
       if (bh >= 0) {
-        const float2 qb = b.yz[bh];
+        const float2 qb = staged ? s_yz[bh - P0] : b.yz[bh];
         chi2 += kupdate_q(st, q, qb.x, qb.y);
-        H[r] = bh;
+        H[(int64_t)r * cap] = bh;
         n++;
         rmin = r;
         keep = st;
         miss = 0;
       } else {
-        H[r] = -1;
-        if (++miss >= k.tc_max_miss) break;
+        H[(int64_t)r * cap] = -1;
+        if (++miss >= k.tc_max_miss) dn = false;
       }
     }
-    if (n < k.min_tracklet_hits) stat = 1;
-    else if (!(chi2 >= 0.0f && chi2 <= 3.0e38f)) stat = 3;
   }
-  const int64_t cap = b.cap;
+  if (mine) {
+    if (stat == 0) {
+      if (n < k.min_tracklet_hits) stat = 1;
+      else if (!(chi2 >= 0.0f && chi2 <= 3.0e38f)) stat = 3;
+    }
 #pragma unroll
-  for (int j = 0; j < 5; j++) b.tl_par[j * cap + t] = keep.p[j];
+    for (int j = 0; j < 5; j++) b.tl_par[j * cap + t] = keep.p[j];
 #pragma unroll
-  for (int j = 0; j < 15; j++) b.tl_cov[j * cap + t] = keep.c[j];
-  b.tl_chi2[t] = chi2;
-  b.tl_nhit[t] = n;
-  b.tl_rmin[t] = rmin;
-  b.tl_rmax[t] = rmax;
-  b.tl_status[t] = stat;
-  b.tl_ncand[t] = ncand;
-  return stat == 0;
-}
-
-// Persistent tracklet kernel: each wave takes the next 64 start hits from a
-// device queue until the list is exhausted (every wave reaches the exit once
-// the counter passes S), so long and short tracklets balance across CUs.
-__global__ __launch_bounds__(kBlock) void k_tracklets(Consts k, TrackBufs b)
-{
-  const int64_t S = min(b.counters[CNT_START], b.cap);
-  const int lane = threadIdx.x & 63;
-  int kept = 0;
-  for (;;) {
-    int64_t base = 0;
-    if (lane == 0)
-      base = (int64_t)atomicAdd((unsigned long long*)&b.counters[CNT_TLQUEUE], 64ull);
-    base = __shfl(base, 0, 64);
-    if (base >= S) break;
-    const int64_t t = base + lane;
-    if (t < S && tracklet_one(k, b, t)) kept++;
+    for (int j = 0; j < 15; j++) b.tl_cov[j * cap + t] = keep.c[j];
+    b.tl_chi2[t] = chi2;
+    b.tl_nhit[t] = n;
+    b.tl_rmin[t] = rmin;
+    b.tl_rmax[t] = rmax;
+    b.tl_status[t] = stat;
+    b.tl_ncand[t] = ncand;
   }
   // one counter update per wave
-  for (int o = 32; o > 0; o >>= 1) kept += __shfl_xor(kept, o, 64);
-  if (lane == 0 && kept) atomicAdd((unsigned long long*)&b.res->n_tracklets_kept, (unsigned long long)kept);
+  const unsigned long long kept = __ballot(mine && stat == 0);
+  if ((threadIdx.x & 63) == 0 && kept)
+    atomicAdd((unsigned long long*)&b.res->n_tracklets_kept, (unsigned long long)__popcll(kept));
 }
 
 // ------------------------------------------------------------------ a6 selection
@@ -857,24 +948,40 @@ __global__ __launch_bounds__(kBlock) void k_sel_prep(TrackBufs b)
   }
 }
 
-// The selection kernels run one wave per tracklet: the wave reads the
-// tracklet's hit slots (one 608-byte row) with consecutive lanes on
-// consecutive rows.
-constexpr int kWavesPerBlock = kBlock / 64;
-
-__device__ __forceinline__ int64_t wave_tracklet() { return (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); }
+// The selection kernels run one thread per tracklet and walk the union of
+// the wave's row ranges, so that the hit slots of one row ([row][tracklet])
+// are read contiguously by the wave.  Lanes without a tracklet take part in
+// the range reduction with an empty range.
+__device__ __forceinline__ void wave_rows(int lo, int hi, int& wlo, int& whi)
+{
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o, 64));
+    hi = max(hi, __shfl_xor(hi, o, 64));
+  }
+  wlo = lo;
+  whi = hi;
+}
 
 __global__ __launch_bounds__(kBlock) void k_sel_mark(TrackBufs b)
 {
-  const int64_t t = wave_tracklet();
   const int64_t S = min(b.counters[CNT_START], b.cap);
-  if (t >= S || b.tl_status[t] != 0) return;
-  const unsigned long long key = ts_key(b, t);
-  const int lane = threadIdx.x & 63;
-  const int r1 = b.tl_rmax[t];
-  const int32_t* H = b.tl_hit + t * kRows;
-  for (int r = b.tl_rmin[t] + lane; r <= r1; r += 64) {
-    const int32_t h = H[r];
+  const int64_t t = gtid();
+  if (t - (threadIdx.x & 63) >= S) return;  // whole wave past the list
+  const bool act = t < S && b.tl_status[t] == 0;
+  unsigned long long key = 0;
+  int lo = kRows, hi = -1;
+  if (act) {
+    key = ts_key(b, t);
+    lo = b.tl_rmin[t];
+    hi = b.tl_rmax[t];
+  }
+  int wlo, whi;
+  wave_rows(lo, hi, wlo, whi);
+  const int32_t* H = b.tl_hit + t;
+  for (int r = wlo; r <= whi; r++) {
+    if (r < lo || r > hi) continue;
+    const int32_t h = H[(int64_t)r * b.cap];
     // owners only grow: skip the atomic when a larger key is already there
     if (h >= 0 && b.owner[h] < key) atomicMax(&b.owner[h], key);
   }
@@ -882,59 +989,84 @@ __global__ __launch_bounds__(kBlock) void k_sel_mark(TrackBufs b)
 
 __global__ __launch_bounds__(kBlock) void k_sel_count(Consts k, TrackBufs b, int32_t* own_out)
 {
-  const int64_t t = wave_tracklet();
   const int64_t S = min(b.counters[CNT_START], b.cap);
-  if (t >= S) return;
+  const int64_t t = gtid();
   const int lane = threadIdx.x & 63;
+  if (t - lane >= S) return;
+  const bool act = t < S && b.tl_status[t] == 0;
+  unsigned long long key = 0;
+  int lo = kRows, hi = -1;
+  if (act) {
+    key = ts_key(b, t);
+    lo = b.tl_rmin[t];
+    hi = b.tl_rmax[t];
+  }
+  int wlo, whi;
+  wave_rows(lo, hi, wlo, whi);
+  const int32_t* H = b.tl_hit + t;
   int own = 0;
-  if (b.tl_status[t] == 0) {
-    const unsigned long long key = ts_key(b, t);
-    const int r1 = b.tl_rmax[t];
-    const int32_t* H = b.tl_hit + t * kRows;
-    for (int r0 = b.tl_rmin[t]; r0 <= r1; r0 += 64) {
-      const int r = r0 + lane;
-      bool o = false;
-      if (r <= r1) {
-        const int32_t h = H[r];
-        o = h >= 0 && b.owner[h] == key;
-      }
-      own += __popcll(__ballot(o));
-    }
-    if (own < k.min_track_hits) own = 0;
+  for (int r = wlo; r <= whi; r++) {
+    if (r < lo || r > hi) continue;
+    const int32_t h = H[(int64_t)r * b.cap];
+    if (h >= 0 && b.owner[h] == key) own++;
   }
-  if (lane == 0) {
-    own_out[t] = own;
-    const int64_t v = own ? ((int64_t)1 << 32) | own : 0;
+  if (own < k.min_track_hits) own = 0;
+  const int64_t v = own ? ((int64_t)1 << 32) | own : 0;
 #if TPC_DET
+  if (t < S) {
+    own_out[t] = own;
     b.tsv[t] = v;
-#else
-    b.tsv[t] = own ? (int64_t)atomicAdd((unsigned long long*)&b.counters[CNT_TRACKS],
-                                        (unsigned long long)v)
-                   : 0;
-#endif
   }
+#else
+  // one append per wave: inclusive scan of the packed (tracks, hits) pairs
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = shfl_up64(x, o);
+    if (lane >= o) x += y;
+  }
+  const int64_t tot = (int64_t)(uint32_t)__shfl((int)(uint32_t)x, 63, 64) |
+                      ((int64_t)__shfl((int)(x >> 32), 63, 64) << 32);
+  int64_t base = 0;
+  if (lane == 0 && tot)
+    base = (int64_t)atomicAdd((unsigned long long*)&b.counters[CNT_TRACKS], (unsigned long long)tot);
+  base = (int64_t)(uint32_t)__shfl((int)(uint32_t)base, 0, 64) |
+         ((int64_t)__shfl((int)(base >> 32), 0, 64) << 32);
+  if (t < S) {
+    own_out[t] = own;
+    b.tsv[t] = own ? base + (x - v) : 0;
+  }
+#endif
 }
 
 __global__ __launch_bounds__(kBlock) void k_sel_write(Consts k, TrackBufs b, const int32_t* own_in)
 {
-  const int64_t t = wave_tracklet();
   const int64_t S = min(b.counters[CNT_START], b.cap);
-  if (t >= S) return;
-  const int own = own_in[t];
-  if (own == 0) return;
-  const int64_t v = b.tsv[t];
-  const int64_t kk = v >> 32;
-  const int64_t off = v & 0xFFFFFFFFll;
-  if (kk >= b.out.cap_tracks || off + own > b.out.cap_hits) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t cap = b.cap;
-  if (lane < 5) b.out.param[kk * 5 + lane] = b.tl_par[lane * cap + t];
-  if (lane < 15) b.out.cov[kk * 15 + lane] = b.tl_cov[lane * cap + t];
-  const int rmin = b.tl_rmin[t], rmax = b.tl_rmax[t];
-  if (lane == 0) {
+  const int64_t t = gtid();
+  if (t - (threadIdx.x & 63) >= S) return;
+  const int own = t < S ? own_in[t] : 0;
+  int64_t kk = 0, off = 0;
+  bool act = false;
+  if (own) {
+    const int64_t v = b.tsv[t];
+    kk = v >> 32;
+    off = v & 0xFFFFFFFFll;
+    act = kk < b.out.cap_tracks && off + own <= b.out.cap_hits;
+  }
+  int lo = kRows, hi = -1;
+  unsigned long long key = 0;
+  if (act) {
+    const int64_t cap = b.cap;
+    lo = b.tl_rmin[t];
+    hi = b.tl_rmax[t];
+    key = ts_key(b, t);
+#pragma unroll
+    for (int j = 0; j < 5; j++) b.out.param[kk * 5 + j] = b.tl_par[j * cap + t];
+#pragma unroll
+    for (int j = 0; j < 15; j++) b.out.cov[kk * 15 + j] = b.tl_cov[j * cap + t];
     b.out.chi2[kk] = b.tl_chi2[t];
     b.out.ndf[kk] = 2 * b.tl_nhit[t] - 5;
-    b.out.x_ref[kk] = k.row_x[rmin];
+    b.out.x_ref[kk] = k.row_x[lo];
     b.out.hit_off[kk + 1] = (int32_t)(off + own);
     // with enough capacity every track is written and the totals are the
     // counts; only a truncated output needs the largest written index
@@ -944,25 +1076,18 @@ __global__ __launch_bounds__(kBlock) void k_sel_write(Consts k, TrackBufs b, con
       atomicMax((unsigned long long*)&b.res->n_hits, (unsigned long long)(off + own));
     }
   }
-  const unsigned long long key = ts_key(b, t);
-  const int32_t* H = b.tl_hit + t * kRows;
+  int wlo, whi;
+  wave_rows(lo, hi, wlo, whi);
+  const int32_t* H = b.tl_hit + t;
   int64_t j = off;
-  for (int r0 = rmin; r0 <= rmax; r0 += 64) {
-    const int r = r0 + lane;
-    int32_t h = -1;
-    bool o = false;
-    if (r <= rmax) {
-      h = H[r];
-      o = h >= 0 && b.owner[h] == key;
-    }
-    const unsigned long long m = __ballot(o);
-    if (o) {
-      const int64_t slot = j + __popcll(m & ((1ull << lane) - 1ull));
+  for (int r = wlo; r <= whi; r++) {
+    if (r < lo || r > hi) continue;
+    const int32_t h = H[(int64_t)r * b.cap];
+    if (h >= 0 && b.owner[h] == key) {
       const int32_t c = b.perm[h];
-      b.out.hit_clu[slot] = c;
+      b.out.hit_clu[j++] = c;
       b.out.clu2trk[c] = (int32_t)kk;
     }
-    j += __popcll(m);
   }
 }
 
@@ -1020,16 +1145,25 @@ hipError_t sector_track(const Consts& k, const TrackBufs& b, hipStream_t s)
   TPC_LAUNCH("start_finish", 1, 1, s, k_start_finish, b);
   TPC_LAUNCH("sel_prep", blocks_for(b.n > 0 ? b.n : 1), kBlock, s, k_sel_prep, b);
   if (b.cap > 0) {
-    const int64_t tl_blocks = std::min<int64_t>(blocks_for(b.cap), (int64_t)b.n_cu * k.tl_blocks_per_cu);
-    TPC_LAUNCH("tracklets", (unsigned)tl_blocks, kBlock, s, k_tracklets, k, b);
-    const unsigned wblocks = blocks_for(b.cap, kWavesPerBlock);
-    TPC_LAUNCH("sel_mark", wblocks, kBlock, s, k_sel_mark, b);
-    TPC_LAUNCH("sel_count", wblocks, kBlock, s, k_sel_count, k, b, b.tl_own);
+    TPC_LAUNCH("tl_first", blocks_for(b.cap + 1), kBlock, s, k_tl_first, b);
+    TPC_LAUNCH("tl_chunks", 1, kBlock, s, k_tl_chunks, b, k.tl_chunk);
+    // chunks are at most cap / CH + n_inst; whole groups of 8 workgroups
+    const int64_t ub = (b.cap + k.tl_chunk - 1) / k.tl_chunk + b.n_inst;
+    const unsigned tl_blocks = (unsigned)(((ub + 7) / 8) * 8);
+    if (k.tl_chunk == 64)
+      TPC_LAUNCH("tracklets", tl_blocks, 64, s, k_tracklets<64>, k, b);
+    else if (k.tl_chunk == 128)
+      TPC_LAUNCH("tracklets", tl_blocks, 128, s, k_tracklets<128>, k, b);
+    else
+      TPC_LAUNCH("tracklets", tl_blocks, 256, s, k_tracklets<256>, k, b);
+    const unsigned tblocks = blocks_for(b.cap);
+    TPC_LAUNCH("sel_mark", tblocks, kBlock, s, k_sel_mark, b);
+    TPC_LAUNCH("sel_count", tblocks, kBlock, s, k_sel_count, k, b, b.tl_own);
 #if TPC_DET
     scan_exclusive<int64_t>(b.tsv, b.cap, &b.counters[CNT_START], &b.counters[CNT_TRACKS],
                             b.scan_tmp, s);
 #endif
-    TPC_LAUNCH("sel_write", wblocks, kBlock, s, k_sel_write, k, b, b.tl_own);
+    TPC_LAUNCH("sel_write", tblocks, kBlock, s, k_sel_write, k, b, b.tl_own);
   }
   TPC_LAUNCH("sel_finish", 1, 1, s, k_sel_finish, b);
   return hipGetLastError();

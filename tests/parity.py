@@ -15,8 +15,16 @@ NR = 152
 
 
 def bits(a):
+    """Bit patterns of a binary32 array, with every NaN as one canonical
+    pattern: IEEE 754 leaves the sign and payload of the NaN an invalid
+    operation delivers to the implementation (x86 gives a negative quiet
+    NaN, the GPU a positive one), so only NaN-ness is compared."""
     a = np.ascontiguousarray(a)
-    return a.view(np.int32) if a.dtype == np.float32 else a
+    if a.dtype != np.float32:
+        return a
+    b = a.view(np.int32).copy()
+    b[np.isnan(a)] = 0x7FC00000
+    return b
 
 
 def run_gpu(ev_or_arrays, det=True, device="cuda", **kw):
@@ -49,7 +57,7 @@ def gpu_arrays(run: tpc.TrackRun, n: int) -> dict:
         tl_rmin=h(ws.view("tl_rmin", i32, cap))[:S],
         tl_rmax=h(ws.view("tl_rmax", i32, cap))[:S],
         tl_status=h(ws.view("tl_status", i32, cap))[:S],
-        tl_hit=h(ws.view("tl_hit", i32, NR * cap)).reshape(cap, NR)[:S].copy(),
+        tl_hit=h(ws.view("tl_hit", i32, NR * cap)).reshape(NR, cap)[:, :S].T.copy(),
         param=h(run.tracks.param)[:nt], cov=h(run.tracks.cov)[:nt], chi2=h(run.tracks.chi2)[:nt],
         ndf=h(run.tracks.ndf)[:nt], x_ref=h(run.tracks.x_ref)[:nt],
         hit_off=h(run.tracks.hit_off)[:nt + 1], hit_clu=h(run.tracks.hit_clu)[:nh],

@@ -75,7 +75,7 @@ def _args(geom=None, n_inst=1, off=(0, 10)):
 
 
 @pytest.mark.parametrize("case", ["rows", "offset0", "negative", "huge_instance", "min_chain",
-                                  "null_geom", "row_order", "workspace"])
+                                  "null_geom", "row_order", "workspace", "tl_chunk"])
 def test_invalid_arguments_rejected_on_host(case):
     L = tpc.lib()
     g, p, off, cl, gs, dummy = _args()
@@ -96,6 +96,8 @@ def test_invalid_arguments_rejected_on_host(case):
         g.row_x[10] = g.row_x[9]
     elif case == "workspace":
         ws_bytes = 16
+    elif case == "tl_chunk":
+        p.tl_chunk = 96
     gp = None if case == "null_geom" else C.byref(g)
     st = L.tpc_grid_build(gp, C.byref(p), C.c_int32(n_inst), off.ctypes.data_as(C.c_void_p), dummy,
                           cl, C.byref(gs), dummy, dummy, C.c_size_t(ws_bytes), C.c_void_p(0))

@@ -69,7 +69,7 @@ def test_plain_chains_in_one_graph_equal_batched():
 def test_autotune_candidates_keep_output(tmp_path, monkeypatch):
     monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
     ev, b = _batch(10)
-    entry = autotune.tune(G, b, steps=2, candidates=[(0.5, 4), (1.0, 8), (4.0, 16)],
+    entry = autotune.tune(G, b, steps=2, candidates=[(0.5, 64), (1.0, 128), (4.0, 256)],
                           use_cache=False)
     assert all(t["identical"] for t in entry["trials"])
     assert (tmp_path / "tune.json").exists()

@@ -59,6 +59,20 @@ def test_det_config4_small_uneven_instances_bit_exact():
     _det_case(synth.config4(n_inst=24, n_min=200, n_max=3e4))
 
 
+@pytest.mark.parametrize("chunk", [64, 128])
+def test_det_tracklet_chunk_sizes_bit_exact(chunk):
+    _det_case(synth.config4(n_inst=24, n_min=200, n_max=3e4), tl_chunk=chunk)
+
+
+@pytest.mark.parametrize("n_tracks,chunk", [(900, 64), (1500, 64), (3000, 128)])
+def test_det_rows_beyond_lds_bit_exact(n_tracks, chunk):
+    # One dense instance whose rows overflow the LDS row buffer of the
+    # workgroup size (124 bytes per thread): at 900 tracks about 90 of the
+    # 152 rows overflow at 64 threads (staged and global rows in one sweep),
+    # at 1500 and 3000 tracks every row does (global search only).
+    _det_case(synth.config1(n_tracks=n_tracks), tl_chunk=chunk)
+
+
 def test_det_config2_full_bit_exact():
     g, o = _det_case(synth.config2())
     assert len(o.tracks.chi2) > 10000
