@@ -105,10 +105,16 @@ def run(args) -> dict:
 
     out = {}
     # ---- autotuned launch parameters (performance-only; outputs checked identical)
-    tuned = autotune.tune(geom, batch, stream=stream, use_cache=not args.retune, log=log)
+    if args.fixed:
+        occ, chunk = args.fixed.split(",")
+        tuned = {"grid_occupancy": float(occ), "tl_chunk": int(chunk), "ms": None,
+                 "default_ms": None}
+    else:
+        tuned = autotune.tune(geom, batch, stream=stream, use_cache=not args.retune, log=log)
     tp = dict(grid_occupancy=tuned["grid_occupancy"], tl_chunk=tuned["tl_chunk"])
     out["autotune"] = {k: tuned[k] for k in ("grid_occupancy", "tl_chunk", "ms",
                                              "default_ms")}
+    out["autotune"]["fixed"] = bool(args.fixed)
     # ---- batched, deterministic
     det_c = Chain(geom, batch, True, stream, **tp)
     dt_eager = timed(det_c.enqueue, args.steps, args.warmup, "batched det (eager)")
@@ -302,6 +308,9 @@ def main():
     ap.add_argument("--cpu-every", type=int, default=4)
     ap.add_argument("--no-refit", action="store_true")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
+    ap.add_argument("--fixed", default="",
+                    help="OCC,CHUNK: use these launch parameters instead of tuning "
+                         "(profiler runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()

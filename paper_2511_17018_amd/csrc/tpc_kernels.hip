@@ -13,6 +13,7 @@
 // operand order of the algorithm readings (R7-R11, R13-R20) so that, with
 // contraction off, each operation rounds exactly as in the CPU reference.
 #include <algorithm>
+#include <climits>
 
 #include "tpc_internal.h"
 
@@ -468,14 +469,21 @@ __global__ void k_track_init(TrackBufs b)
 }
 
 // NeighboursFinder (R11): best (u on r+1, d on r-1) straight-line pair.
-// The down-row candidates inside the box are staged once per cluster in LDS
-// (thread-major layout, conflict-free); clusters with more than kNfStage of
-// them take the rescan path.  The pair choice is a total order, so the visit
-// order does not change the result.
-constexpr int kNfStage = 12;
+// A workgroup takes 256 consecutive positions and visits the row segments
+// they belong to in turn.  For segment s it stages the z-slab of rows r+1
+// and r-1 that the windows of its clusters can reach -- the z bins from
+// bin_coord(zmin - w) to bin_coord(zmax + w), whole rows of bins, with their
+// positions -- in LDS with coalesced loads (positions are in z-bin-major
+// order, so a workgroup's clusters cover a narrow z range and the slab is a
+// small part of the row).  bin_coord is monotone, so every window of the
+// segment lies inside the slab.  A slab too large for its buffer sends the
+// segment to the same search in global memory.  The pair choice is a total
+// order (score, then the input indices of u and d), so the visit order does
+// not change the result; input indices are read only on an exact tie.
+constexpr int kNfSlab = 8192;  // LDS bytes per staged slab
 
 struct NfBest {
-  int32_t u = -1, d = -1, pu = 0, pd = 0;
+  int32_t u = -1, d = -1;
   float s = 0.0f;
 };
 
@@ -486,102 +494,163 @@ __device__ __forceinline__ void nf_consider(const TrackBufs& b, NfBest& best, fl
     best.u = u;
     best.d = d;
     best.s = sc;
-    best.pu = b.perm[u];
-    best.pd = b.perm[d];
   } else if (sc == best.s) {
     const int32_t pu = b.perm[u], pd = b.perm[d];
-    if (pu < best.pu || (pu == best.pu && pd < best.pd)) {
+    const int32_t bu = b.perm[best.u], bd = b.perm[best.d];
+    if (pu < bu || (pu == bu && pd < bd)) {
       best.u = u;
       best.d = d;
-      best.pu = pu;
-      best.pd = pd;
+    }
+  }
+}
+
+// A slab of one row: bins [iz0 * ny, (iz1 + 1) * ny) with their boundaries
+// relative to the slab's first position P0, then the positions.
+struct Slab {
+  int iz0, iz1;
+  int32_t P0;
+  int ob;  // byte offset of the positions
+  bool ok;
+};
+
+template <int NT>
+__device__ __forceinline__ Slab stage_slab(const TrackBufs& b, const tpc_row_meta& m, float zlo,
+                                           float zhi, unsigned char* buf, int bytes)
+{
+  Slab sl;
+  sl.iz0 = bin_coord(zlo, m.z0, m.iwz, m.nz);
+  sl.iz1 = max(bin_coord(zhi, m.z0, m.iwz, m.nz), sl.iz0);
+  const int j0 = m.bin_base + sl.iz0 * m.ny;
+  const int nb = (sl.iz1 - sl.iz0 + 1) * m.ny;  // bins; nb + 1 boundaries
+  sl.P0 = b.bin_off[j0];
+  const int cnt = b.bin_off[j0 + nb] - sl.P0;
+  const int64_t ob = ((int64_t)(nb + 1) * 4 + 7) & ~(int64_t)7;
+  sl.ok = ob + (int64_t)cnt * 8 <= bytes;
+  sl.ob = (int)(sl.ok ? ob : 0);
+  if (sl.ok) {
+    int32_t* off = (int32_t*)buf;
+    float2* yz = (float2*)(buf + ob);
+    for (int j = threadIdx.x; j <= nb; j += NT) off[j] = b.bin_off[j0 + j] - sl.P0;
+    for (int j = threadIdx.x; j < cnt; j += NT) yz[j] = b.yz[sl.P0 + j];
+  }
+  return sl;
+}
+
+// The pair search of cluster (yh, zh) of row r over the windows of rows
+// r+1 (mu) and r-1 (md).  offu/yzu index bins from z bin izu0 and positions
+// from Pu (the staged slab, or the whole row in global memory with izu0 = 0
+// and Pu = 0); the same for the down row.
+__device__ __forceinline__ void nf_search(const Consts& k, const TrackBufs& b, NfBest& best,
+                                          float yh, float zh, float t, const tpc_row_meta& mu,
+                                          const int32_t* offu, const float2* yzu, int izu0,
+                                          int32_t Pu, const tpc_row_meta& md,
+                                          const int32_t* offd, const float2* yzd, int izd0,
+                                          int32_t Pd)
+{
+  const float wy = k.nf_win_y, wz = k.nf_win_z;
+  const float wym = wy + k.search_margin, wzm = wz + k.search_margin;
+  const float cmax = k.nf_chi2_max, ivy = k.ivy, ivz = k.ivz;
+  const int uylo = bin_coord(yh - wym, mu.y0, mu.iwy, mu.ny);
+  const int uyhi = bin_coord(yh + wym, mu.y0, mu.iwy, mu.ny);
+  const int uzlo = bin_coord(zh - wzm, mu.z0, mu.iwz, mu.nz);
+  const int uzhi = bin_coord(zh + wzm, mu.z0, mu.iwz, mu.nz);
+  const int dylo = bin_coord(yh - wym, md.y0, md.iwy, md.ny);
+  const int dyhi = bin_coord(yh + wym, md.y0, md.iwy, md.ny);
+  const int dzlo = bin_coord(zh - wzm, md.z0, md.iwz, md.nz);
+  const int dzhi = bin_coord(zh + wzm, md.z0, md.iwz, md.nz);
+  for (int izu = uzlo; izu <= uzhi; izu++) {
+    const int ub = (izu - izu0) * mu.ny;
+    const int ue = offu[ub + uyhi + 1];
+    for (int u = offu[ub + uylo]; u < ue; u++) {
+      const float2 qu = yzu[u];
+      const float yu = qu.x, zu = qu.y;
+      if (!(fabsf(yu - yh) <= wy && fabsf(zu - zh) <= wz)) continue;
+      for (int izd = dzlo; izd <= dzhi; izd++) {
+        const int db = (izd - izd0) * md.ny;
+        const int de = offd[db + dyhi + 1];
+        for (int d = offd[db + dylo]; d < de; d++) {
+          const float2 qd = yzd[d];
+          const float yd = qd.x, zd = qd.y;
+          if (!(fabsf(yd - yh) <= wy && fabsf(zd - zh) <= wz)) continue;
+          const float ey = yh - (yd + (yu - yd) * t);
+          const float ez = zh - (zd + (zu - zd) * t);
+          const float sc = (ey * ey) * ivy + (ez * ez) * ivz;
+          if (sc <= cmax) nf_consider(b, best, sc, Pu + u, Pd + d);
+        }
+      }
     }
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_neighbours(Consts k, TrackBufs b)
 {
-  __shared__ float s_y[kNfStage][kBlock];
-  __shared__ float s_z[kNfStage][kBlock];
-  __shared__ int32_t s_i[kNfStage][kBlock];
+  __shared__ __align__(16) unsigned char s_up[kNfSlab];
+  __shared__ __align__(16) unsigned char s_dn[kNfSlab];
+  __shared__ int s_smin, s_smax;
+  // z range of the current segment's clusters, double-buffered by segment
+  // parity (a wave may still read one while the next is reset)
+  __shared__ uint32_t s_zlo[2], s_zhi[2];
   const int64_t h = gtid();
-  if (h >= b.n) return;
   const int tx = threadIdx.x;
-  NfBest best;
-  const int seg = b.sseg[h];
+  int seg = h < b.n ? b.sseg[h] : -1;
   const int r = seg >= 0 ? seg % kRows : 0;
-  if (seg >= 0 && r > 0 && r < kRows - 1) {
+  if (r == 0 || r == kRows - 1) seg = -1;  // no pair on the first and last row
+  float yh = 0.0f, zh = 0.0f;
+  if (seg >= 0) {
     const float2 qh = b.yz[h];
-    const float yh = qh.x, zh = qh.y;
-    const float wy = k.nf_win_y, wz = k.nf_win_z;
-    const float wym = wy + k.search_margin, wzm = wz + k.search_margin;
-    const float cmax = k.nf_chi2_max, ivy = k.ivy, ivz = k.ivz;
-    const float xm = k.row_x[r - 1], x0 = k.row_x[r], xp = k.row_x[r + 1];
-    const float t = (x0 - xm) / (xp - xm);
-    const tpc_row_meta mu = b.meta[seg + 1];
-    const tpc_row_meta md = b.meta[seg - 1];
-    const int uylo = bin_coord(yh - wym, mu.y0, mu.iwy, mu.ny);
-    const int uyhi = bin_coord(yh + wym, mu.y0, mu.iwy, mu.ny);
-    const int uzlo = bin_coord(zh - wzm, mu.z0, mu.iwz, mu.nz);
-    const int uzhi = bin_coord(zh + wzm, mu.z0, mu.iwz, mu.nz);
-    const int dylo = bin_coord(yh - wym, md.y0, md.iwy, md.ny);
-    const int dyhi = bin_coord(yh + wym, md.y0, md.iwy, md.ny);
-    const int dzlo = bin_coord(zh - wzm, md.z0, md.iwz, md.nz);
-    const int dzhi = bin_coord(zh + wzm, md.z0, md.iwz, md.nz);
-    // stage the down candidates
-    int nd = 0;
-    for (int izd = dzlo; izd <= dzhi; izd++) {
-      const int db = md.bin_base + izd * md.ny;
-      const int de = b.bin_off[db + dyhi + 1];
-      for (int d = b.bin_off[db + dylo]; d < de; d++) {
-        const float2 qd = b.yz[d];
-        const float yd = qd.x, zd = qd.y;
-        if (!(fabsf(yd - yh) <= wy && fabsf(zd - zh) <= wz)) continue;
-        if (nd < kNfStage) {
-          s_y[nd][tx] = yd;
-          s_z[nd][tx] = zd;
-          s_i[nd][tx] = d;
-        }
-        nd++;
-      }
-    }
-    if (nd > 0) {
-      for (int izu = uzlo; izu <= uzhi; izu++) {
-        const int ub = mu.bin_base + izu * mu.ny;
-        const int ue = b.bin_off[ub + uyhi + 1];
-        for (int u = b.bin_off[ub + uylo]; u < ue; u++) {
-          const float2 qu = b.yz[u];
-          const float yu = qu.x, zu = qu.y;
-          if (!(fabsf(yu - yh) <= wy && fabsf(zu - zh) <= wz)) continue;
-          if (nd <= kNfStage) {
-            for (int j = 0; j < nd; j++) {
-              const float yd = s_y[j][tx], zd = s_z[j][tx];
-              const float ey = yh - (yd + (yu - yd) * t);
-              const float ez = zh - (zd + (zu - zd) * t);
-              const float sc = (ey * ey) * ivy + (ez * ez) * ivz;
-              if (sc <= cmax) nf_consider(b, best, sc, u, s_i[j][tx]);
-            }
-          } else {
-            for (int izd = dzlo; izd <= dzhi; izd++) {
-              const int db = md.bin_base + izd * md.ny;
-              const int de = b.bin_off[db + dyhi + 1];
-              for (int d = b.bin_off[db + dylo]; d < de; d++) {
-                const float2 qd = b.yz[d];
-        const float yd = qd.x, zd = qd.y;
-                if (!(fabsf(yd - yh) <= wy && fabsf(zd - zh) <= wz)) continue;
-                const float ey = yh - (yd + (yu - yd) * t);
-                const float ez = zh - (zd + (zu - zd) * t);
-                const float sc = (ey * ey) * ivy + (ez * ez) * ivz;
-                if (sc <= cmax) nf_consider(b, best, sc, u, d);
-              }
-            }
-          }
-        }
-      }
-    }
+    yh = qh.x;
+    zh = qh.y;
   }
-  b.up[h] = best.u;
-  b.dn[h] = best.d;
+  if (tx == 0) {
+    s_smin = INT_MAX;
+    s_smax = -1;
+  }
+  __syncthreads();
+  if (seg >= 0) {
+    atomicMin(&s_smin, seg);
+    atomicMax(&s_smax, seg);
+  }
+  __syncthreads();
+  const int smin = s_smin, smax = s_smax;
+  const float wzm = k.nf_win_z + k.search_margin;
+  NfBest best;
+  for (int s = smin; s <= smax; s++) {
+    const int pb = s & 1;
+    if (tx == 0) {
+      s_zlo[pb] = 0xFFFFFFFFu;
+      s_zhi[pb] = 0u;
+    }
+    __syncthreads();  // also: the previous segment's searches are done
+    const bool mine = seg == s;
+    if (mine) {
+      atomicMin(&s_zlo[pb], f2o(zh));
+      atomicMax(&s_zhi[pb], f2o(zh));
+    }
+    __syncthreads();
+    const uint32_t ozlo = s_zlo[pb], ozhi = s_zhi[pb];
+    if (ozlo > ozhi) continue;  // no cluster of this segment here (uniform)
+    const float zlo = o2f(ozlo), zhi = o2f(ozhi);
+    const int rs = s % kRows;
+    const tpc_row_meta mu = b.meta[s + 1];
+    const tpc_row_meta md = b.meta[s - 1];
+    const Slab su = stage_slab<kBlock>(b, mu, zlo - wzm, zhi + wzm, s_up, kNfSlab);
+    const Slab sd = stage_slab<kBlock>(b, md, zlo - wzm, zhi + wzm, s_dn, kNfSlab);
+    __syncthreads();
+    if (!mine) continue;
+    const float xm = k.row_x[rs - 1], x0 = k.row_x[rs], xp = k.row_x[rs + 1];
+    const float t = (x0 - xm) / (xp - xm);
+    if (su.ok && sd.ok)
+      nf_search(k, b, best, yh, zh, t, mu, (const int32_t*)s_up, (const float2*)(s_up + su.ob),
+                su.iz0, su.P0, md, (const int32_t*)s_dn, (const float2*)(s_dn + sd.ob), sd.iz0,
+                sd.P0);
+    else
+      nf_search(k, b, best, yh, zh, t, mu, b.bin_off + mu.bin_base, b.yz, 0, 0, md,
+                b.bin_off + md.bin_base, b.yz, 0, 0);
+  }
+  if (h < b.n) {
+    b.up[h] = best.u;
+    b.dn[h] = best.d;
+  }
 }
 
 // NeighboursCleaner: mutual links only (reads the uncleaned arrays).

@@ -73,6 +73,30 @@ def test_det_rows_beyond_lds_bit_exact(n_tracks, chunk):
     _det_case(synth.config1(n_tracks=n_tracks), tl_chunk=chunk)
 
 
+def test_det_dense_z_band_beyond_lds_bit_exact():
+    # config 1 plus 2000 noise clusters on each of rows 50-52 inside a 5 cm
+    # z band: a workgroup's neighbour-search slab of those rows holds all of
+    # them (more than the LDS slab buffer), so about half of the event's
+    # clusters take the global-memory search, the rest the staged one.  A
+    # blob of 30 clusters in 2 x 2 cm on rows 30-32 gives staged searches
+    # more down-window candidates than the per-thread list holds.
+    rng = np.random.default_rng(11)
+    ev = synth.config1()
+    g = synth.geometry()
+    ys, zs, rs = [ev.y], [ev.z], [ev.row]
+    for r in (50, 51, 52):
+        lim = g["row_x"][r] * g["tan_half"]
+        ys.append(rng.uniform(-lim, lim, 2000).astype(np.float32))
+        zs.append(rng.uniform(0.0, 5.0, 2000).astype(np.float32))
+        rs.append(np.full(2000, r, np.uint16))
+    for r in (30, 31, 32):
+        ys.append(rng.uniform(0.0, 2.0, 30).astype(np.float32))
+        zs.append(rng.uniform(10.0, 12.0, 30).astype(np.float32))
+        rs.append(np.full(30, r, np.uint16))
+    y, z, row = np.concatenate(ys), np.concatenate(zs), np.concatenate(rs)
+    _det_case(_arrays(y, z, row, [0, len(y)]))
+
+
 def test_det_config2_full_bit_exact():
     g, o = _det_case(synth.config2())
     assert len(o.tracks.chi2) > 10000
