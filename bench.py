@@ -30,6 +30,7 @@ import ctypes as C
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -44,6 +45,34 @@ HBM_PEAK_GBS = 8000.0
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "chain_config4_traffic.md")
+KERNEL_SOURCES = ["paper_2511_17018_amd/csrc/tpc_kernels.hip", "paper_2511_17018_amd/csrc/tpc_kalman.h",
+                  "paper_2511_17018_amd/csrc/tpc_internal.h", "include/tpcca.h",
+                  "paper_2511_17018_amd/build.py"]
+
+
+def measured_traffic(kernel: str, occ: float, chunk: int) -> int | None:
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated), or None when the kernel
+    sources or the launch parameters differ from the ones it was taken on."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    m = re.search(r"source_sha256: ([0-9a-f]{64})", text)
+    ml = re.search(r"launch: ([0-9.]+),(\d+)", text)
+    if not m or m.group(1) != h.hexdigest() or not ml:
+        return None
+    if float(ml.group(1)) != float(occ) or int(ml.group(2)) != int(chunk):
+        return None
+    mt = re.search(rf"traffic_bytes {re.escape(kernel)}: (\d+)", text)
+    return int(mt.group(1)) if mt else None
 
 
 def kernel_bytes(name: str, c: dict) -> float | None:
@@ -147,9 +176,11 @@ def run(args) -> dict:
     avg_s = tot_ms / launches / 1e3
     kb = kernel_bytes(name, counts)
     achieved = kb / avg_s / 1e9 if kb else None
+    traffic = measured_traffic(name, tp["grid_occupancy"], tp["tl_chunk"])
     roofline = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                "traffic": None, "avg_launch_ms": avg_s * 1e3,
+                "traffic": traffic, "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT)
+                if traffic else None, "avg_launch_ms": avg_s * 1e3,
                 "alg_bytes_per_launch": kb, "counts": counts}
     out["kernels_ms_per_step"] = {k: round(v[0] / args.steps, 4) for k, v in
                                   sorted(ktimes.items(), key=lambda kv: -kv[1][0])}

@@ -1,0 +1,31 @@
+"""Host-side pieces of bench.py: the traffic figure is taken from the committed
+counter summary only while the kernel sources and launch parameters match."""
+import hashlib
+
+import bench
+
+
+def _write(tmp_path, sha, launch="0.5,64", line="traffic_bytes neighbours: 1234"):
+    p = tmp_path / "traffic.md"
+    p.write_text(f"```\nsource_sha256: {sha}\nlaunch: {launch}\n{line}\n```\n")
+    return str(p)
+
+
+def _sources_sha():
+    h = hashlib.sha256()
+    for f in bench.KERNEL_SOURCES:
+        with open(f"{bench.ROOT}/{f}", "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def test_traffic_only_for_matching_sources_and_launch(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", _write(tmp_path, _sources_sha()))
+    assert bench.measured_traffic("neighbours", 0.5, 64) == 1234
+    assert bench.measured_traffic("tracklets", 0.5, 64) is None
+    assert bench.measured_traffic("neighbours", 1.0, 64) is None
+    assert bench.measured_traffic("neighbours", 0.5, 128) is None
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", _write(tmp_path, "0" * 64))
+    assert bench.measured_traffic("neighbours", 0.5, 64) is None
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
+    assert bench.measured_traffic("neighbours", 0.5, 64) is None
