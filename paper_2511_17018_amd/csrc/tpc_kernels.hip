@@ -582,10 +582,105 @@ __device__ __forceinline__ void nf_search(const Consts& k, const TrackBufs& b, N
   }
 }
 
+// Staged search: each window is scanned once into a per-thread list of slab
+// indices (thread-major in LDS), the down window first so that a cluster
+// without a down candidate skips the up window.  The pairs are then
+// evaluated with the down candidates loaded in batches into registers, so
+// the pair loop carries no dependent LDS loads.  Windows with more than
+// kNfList candidates fall back to nf_search.
+constexpr int kNfList = 32;
+constexpr int kNfBatch = 8;
+
+__device__ __forceinline__ void nf_search_lists(const Consts& k, const TrackBufs& b, NfBest& best,
+                                                float yh, float zh, float t,
+                                                const tpc_row_meta& mu, const int32_t* offu,
+                                                const float2* yzu, int izu0, int32_t Pu,
+                                                const tpc_row_meta& md, const int32_t* offd,
+                                                const float2* yzd, int izd0, int32_t Pd,
+                                                uint16_t (*s_ul)[kBlock], uint16_t (*s_dl)[kBlock])
+{
+  const int tx = threadIdx.x;
+  const float wy = k.nf_win_y, wz = k.nf_win_z;
+  const float wym = wy + k.search_margin, wzm = wz + k.search_margin;
+  const float cmax = k.nf_chi2_max, ivy = k.ivy, ivz = k.ivz;
+  int nd = 0;
+  {
+    const int ylo = bin_coord(yh - wym, md.y0, md.iwy, md.ny);
+    const int yhi = bin_coord(yh + wym, md.y0, md.iwy, md.ny);
+    const int zlo = bin_coord(zh - wzm, md.z0, md.iwz, md.nz);
+    const int zhi = bin_coord(zh + wzm, md.z0, md.iwz, md.nz);
+    for (int iz = zlo; iz <= zhi; iz++) {
+      const int bb = (iz - izd0) * md.ny;
+      const int e = offd[bb + yhi + 1];
+      for (int d = offd[bb + ylo]; d < e; d++) {
+        const float2 q = yzd[d];
+        if (!(fabsf(q.x - yh) <= wy && fabsf(q.y - zh) <= wz)) continue;
+        if (nd < kNfList) s_dl[nd][tx] = (uint16_t)d;
+        nd++;
+      }
+    }
+  }
+  if (nd == 0) return;
+  int nu = 0;
+  {
+    const int ylo = bin_coord(yh - wym, mu.y0, mu.iwy, mu.ny);
+    const int yhi = bin_coord(yh + wym, mu.y0, mu.iwy, mu.ny);
+    const int zlo = bin_coord(zh - wzm, mu.z0, mu.iwz, mu.nz);
+    const int zhi = bin_coord(zh + wzm, mu.z0, mu.iwz, mu.nz);
+    for (int iz = zlo; iz <= zhi; iz++) {
+      const int bb = (iz - izu0) * mu.ny;
+      const int e = offu[bb + yhi + 1];
+      for (int u = offu[bb + ylo]; u < e; u++) {
+        const float2 q = yzu[u];
+        if (!(fabsf(q.x - yh) <= wy && fabsf(q.y - zh) <= wz)) continue;
+        if (nu < kNfList) s_ul[nu][tx] = (uint16_t)u;
+        nu++;
+      }
+    }
+  }
+  if (nu == 0) return;
+  if (nu > kNfList || nd > kNfList) {
+    nf_search(k, b, best, yh, zh, t, mu, offu, yzu, izu0, Pu, md, offd, yzd, izd0, Pd);
+    return;
+  }
+  // down candidates in register batches of kNfBatch (static indices,
+  // unrolled), each up candidate against a whole batch: no LDS load per pair
+  for (int j0 = 0; j0 < nd; j0 += kNfBatch) {
+    float by[kNfBatch], bz[kNfBatch];
+    int bi[kNfBatch];
+#pragma unroll
+    for (int j = 0; j < kNfBatch; j++) {
+      const int d = s_dl[j0 + j < nd ? j0 + j : j0][tx];
+      const float2 q = yzd[d];
+      by[j] = q.x;
+      bz[j] = q.y;
+      bi[j] = d;
+    }
+    const int nb = min(nd - j0, kNfBatch);
+    for (int iu = 0; iu < nu; iu++) {
+      const int u = s_ul[iu][tx];
+      const float2 qu = yzu[u];
+      const float yu = qu.x, zu = qu.y;
+#pragma unroll
+      for (int j = 0; j < kNfBatch; j++) {
+        if (j < nb) {
+          const float yd = by[j], zd = bz[j];
+          const float ey = yh - (yd + (yu - yd) * t);
+          const float ez = zh - (zd + (zu - zd) * t);
+          const float sc = (ey * ey) * ivy + (ez * ez) * ivz;
+          if (sc <= cmax) nf_consider(b, best, sc, Pu + u, Pd + bi[j]);
+        }
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_neighbours(Consts k, TrackBufs b)
 {
   __shared__ __align__(16) unsigned char s_up[kNfSlab];
   __shared__ __align__(16) unsigned char s_dn[kNfSlab];
+  __shared__ uint16_t s_ul[kNfList][kBlock];
+  __shared__ uint16_t s_dl[kNfList][kBlock];
   __shared__ int s_smin, s_smax;
   // z range of the current segment's clusters, double-buffered by segment
   // parity (a wave may still read one while the next is reset)
@@ -640,9 +735,9 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(Consts k, TrackBufs b)
     const float xm = k.row_x[rs - 1], x0 = k.row_x[rs], xp = k.row_x[rs + 1];
     const float t = (x0 - xm) / (xp - xm);
     if (su.ok && sd.ok)
-      nf_search(k, b, best, yh, zh, t, mu, (const int32_t*)s_up, (const float2*)(s_up + su.ob),
-                su.iz0, su.P0, md, (const int32_t*)s_dn, (const float2*)(s_dn + sd.ob), sd.iz0,
-                sd.P0);
+      nf_search_lists(k, b, best, yh, zh, t, mu, (const int32_t*)s_up,
+                      (const float2*)(s_up + su.ob), su.iz0, su.P0, md, (const int32_t*)s_dn,
+                      (const float2*)(s_dn + sd.ob), sd.iz0, sd.P0, s_ul, s_dl);
     else
       nf_search(k, b, best, yh, zh, t, mu, b.bin_off + mu.bin_base, b.yz, 0, 0, md,
                 b.bin_off + md.bin_base, b.yz, 0, 0);

@@ -78,8 +78,8 @@ def test_det_dense_z_band_beyond_lds_bit_exact():
     # z band: a workgroup's neighbour-search slab of those rows holds all of
     # them (more than the LDS slab buffer), so about half of the event's
     # clusters take the global-memory search, the rest the staged one.  A
-    # blob of 30 clusters in 2 x 2 cm on rows 30-32 gives staged searches
-    # more down-window candidates than the per-thread list holds.
+    # blob of 40 clusters in 2 x 2 cm on rows 30-32 gives staged searches
+    # more window candidates than the per-thread lists hold (32).
     rng = np.random.default_rng(11)
     ev = synth.config1()
     g = synth.geometry()
@@ -90,9 +90,9 @@ def test_det_dense_z_band_beyond_lds_bit_exact():
         zs.append(rng.uniform(0.0, 5.0, 2000).astype(np.float32))
         rs.append(np.full(2000, r, np.uint16))
     for r in (30, 31, 32):
-        ys.append(rng.uniform(0.0, 2.0, 30).astype(np.float32))
-        zs.append(rng.uniform(10.0, 12.0, 30).astype(np.float32))
-        rs.append(np.full(30, r, np.uint16))
+        ys.append(rng.uniform(0.0, 2.0, 40).astype(np.float32))
+        zs.append(rng.uniform(10.0, 12.0, 40).astype(np.float32))
+        rs.append(np.full(40, r, np.uint16))
     y, z, row = np.concatenate(ys), np.concatenate(zs), np.concatenate(rs)
     _det_case(_arrays(y, z, row, [0, len(y)]))
 
