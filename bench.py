@@ -12,11 +12,18 @@ batch, with the clusters already resident in HBM.  Reported:
                parameters from the autotuner); batched_eager without the graph
   plain        clusters/s of 256 per-instance launch chains on one stream,
                eager and graph-captured
-  prod         clusters/s of the batched production path, and det/prod ratio
+  prod         clusters/s of the batched production path, the det/prod ratio,
+               its quality and the fraction of clusters it assigns
+               differently from the deterministic path
+  quality      efficiency, fake and clone rates against the MC truth
   roofline     the dominant kernel's algorithmic bytes per launch divided by
                its average launch time (HIP events recorded on the kernel's
-               stream over a timed pass), against the 8 TB/s HBM peak
-  cpu_baseline the single-threaded CPU oracle on a sample of the instances
+               stream over a timed pass), against the 8 TB/s HBM peak;
+               traffic from the committed counter summary when it matches
+  copy_ceiling a 1 GiB device copy in the same run (practical HBM ceiling)
+  h2d          the upload of the inputs (outside the timed region)
+  cpu_baseline the CPU oracle on a sample of the instances, on a pool of
+               host threads (and on one thread)
   refit        the differentiable Kalman refit of 200k found tracks (forward
                and reverse pass) in tracks/s, with its own roofline and CPU
                baseline
@@ -104,6 +111,7 @@ def run(args) -> dict:
     import synth
     from paper_2511_17018_amd import autotune
     from paper_2511_17018_amd.runtime import Chain, GraphChain, plain_chains
+    from synth.quality import track_quality
 
     t0 = time.time()
     ev = synth.config4(scale=args.scale)
@@ -115,7 +123,11 @@ def run(args) -> dict:
     torch.cuda.set_device(0)
     L = tpc.lib()
     geom = synth.geometry()
+    torch.cuda.synchronize()
+    t_h2d = time.perf_counter()
     batch = tpc.upload(ev.x, ev.y, ev.z, ev.row, ev.charge, ev.inst_off, dev)
+    torch.cuda.synchronize()
+    t_h2d = time.perf_counter() - t_h2d
     stream = torch.cuda.Stream(dev)
 
     def timed(fn, steps, warmup, label):
@@ -187,13 +199,32 @@ def run(args) -> dict:
     out["kernels_sum_ms_per_step"] = round(sum(v[0] for v in ktimes.values()) / args.steps, 4)
     out["result"] = {k: int(res[k]) for k in ("n_valid", "n_start", "n_tracklets_kept",
                                               "n_tracks", "n_hits")}
+    det_out = det_c.outputs()
+    out["quality"] = track_quality(ev.label, ev.inst_off, det_out["hit_off"], det_out["hit_clu"])
+    out["h2d"] = {"seconds": t_h2d, "bytes": 16 * N, "GB_per_s": 16 * N / t_h2d / 1e9,
+                  "note": "pageable host arrays -> device SoA, outside the timed region"}
+    out["copy_ceiling"] = copy_bandwidth(torch, stream)
     del graph, det_c
     # ---- batched, production
     if not args.no_prod:
         prod_c = Chain(geom, batch, False, stream, **tp)
         dt_prod = timed(prod_c.enqueue, args.steps, args.warmup, "batched prod (eager)")
+        assert L.tpc_profile_enable(1) == 0
+        with torch.cuda.stream(stream):
+            for _ in range(args.steps):
+                prod_c.enqueue()
+        stream.synchronize()
+        nk = L.tpc_profile_read(rows, 64)
+        L.tpc_profile_enable(0)
+        prod_out = prod_c.outputs()
         out["prod"] = {"value": N / dt_prod, "ms_per_step": dt_prod * 1e3,
-                       "det_eager_over_prod_eager_time": dt_eager / dt_prod}
+                       "det_eager_over_prod_eager_time": dt_eager / dt_prod,
+                       "quality": track_quality(ev.label, ev.inst_off, prod_out["hit_off"],
+                                                prod_out["hit_clu"]),
+                       "differently_assigned_vs_det": differently_assigned(det_out, prod_out, N),
+                       "kernels_ms_per_step": {
+                           rows[i].name.decode(): round(rows[i].total_ms / args.steps, 4)
+                           for i in sorted(range(nk), key=lambda i: -rows[i].total_ms)[:8]}}
         del prod_c
     # ---- plain: one launch chain per instance, eager and graph-captured
     if not args.no_plain:
@@ -304,23 +335,77 @@ def run_refit(args) -> dict:
     return out
 
 
+def copy_bandwidth(torch, stream, reps: int = 5) -> dict:
+    """Device-to-device copy of 1 GiB: a practical HBM ceiling for the same run."""
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    with torch.cuda.stream(stream):
+        b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record(stream)
+    stream.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return {"GB_per_s": 2 * (1 << 30) / (ms / 1e3) / 1e9, "bytes_per_copy": 2 * (1 << 30),
+            "ms": ms}
+
+
+def differently_assigned(a: dict, b: dict, n: int) -> dict:
+    """Fraction of clusters assigned differently by two outputs: unassigned in
+    one of them only, or on a track of `b` that is not the majority partner of
+    its track in `a` (tracks matched by shared clusters)."""
+    ca, cb = a["clu2trk"][:n].astype(np.int64), b["clu2trk"][:n].astype(np.int64)
+    both = (ca >= 0) & (cb >= 0)
+    diff = int(((ca >= 0) != (cb >= 0)).sum())
+    if both.any():
+        pa, pb = ca[both], cb[both]
+        keys, cnt = np.unique(pa * (int(cb.max()) + 1) + pb, return_counts=True)
+        ka, kb = keys // (int(cb.max()) + 1), keys % (int(cb.max()) + 1)
+        order = np.lexsort((-cnt, ka))
+        first = np.ones(len(order), bool)
+        first[1:] = ka[order][1:] != ka[order][:-1]
+        partner = np.full(int(ca.max()) + 1, -1, np.int64)
+        partner[ka[order][first]] = kb[order][first]
+        diff += int((partner[pa] != pb).sum())
+    return {"clusters": diff, "fraction": diff / max(1, n)}
+
+
 def cpu_baseline(ev, every: int) -> dict:
+    """The binary32 oracle (whole chain a1-a6, as it stands) on every
+    `every`-th instance: once on one thread, once with the instances dealt to
+    a pool of threads (the oracle's C calls release the interpreter lock and
+    keep no shared state)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
     import synth
     g = synth.geometry()
     sel = list(range(0, ev.n_inst, every))
-    n_tot, t_tot = 0, 0.0
-    for i in sel:
+
+    def one(i):
         a, b = int(ev.inst_off[i]), int(ev.inst_off[i + 1])
         off = np.array([0, b - a], np.int64)
-        t = time.perf_counter()
         oracle.track(g, oracle.DEFAULT_PARAMS, off, ev.y[a:b], ev.z[a:b], ev.row[a:b])
-        t_tot += time.perf_counter() - t
-        n_tot += b - a
-    log(f"cpu oracle: {n_tot} clusters in {t_tot:.1f}s")
-    return {"value": n_tot / t_tot, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+        return b - a
+
+    t = time.perf_counter()
+    n_tot = sum(one(i) for i in sel)
+    t1 = time.perf_counter() - t
+    workers = max(1, min(16, os.cpu_count() or 1))
+    # largest instances first, so the pool ends together
+    order = sorted(sel, key=lambda i: -(ev.inst_off[i + 1] - ev.inst_off[i]))
+    t = time.perf_counter()
+    with ThreadPoolExecutor(workers) as ex:
+        n_par = sum(ex.map(one, order))
+    tp = time.perf_counter() - t
+    log(f"cpu oracle: {n_tot} clusters in {t1:.1f}s on 1 thread, {tp:.2f}s on {workers}")
+    return {"value": n_par / tp, "unit": "clusters/s", "cores": workers, "kind": "oracle",
             "sample": f"{len(sel)} of {ev.n_inst} instances (every {every}th), {n_tot} clusters, "
-                      "binary32 oracle, whole chain a1-a6, one thread"}
+                      f"binary32 oracle, whole chain a1-a6, instances dealt to {workers} threads",
+            "single_thread": {"value": n_tot / t1, "cores": 1, "seconds": t1}}
 
 
 class tpc_kernel_time(C.Structure):
@@ -380,8 +465,8 @@ def main():
                    "path": "batched+graph", "input_sha256": r["sha"]},
         "roofline": r["roofline"],
     }
-    for k in ("batched_eager", "autotune", "plain", "prod", "result", "kernels_ms_per_step",
-              "kernels_sum_ms_per_step"):
+    for k in ("batched_eager", "autotune", "plain", "prod", "result", "quality", "h2d",
+              "copy_ceiling", "kernels_ms_per_step", "kernels_sum_ms_per_step"):
         if k in r:
             line[k] = r[k]
     if not args.no_cpu:

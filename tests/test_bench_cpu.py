@@ -29,3 +29,13 @@ def test_traffic_only_for_matching_sources_and_launch(tmp_path, monkeypatch):
     assert bench.measured_traffic("neighbours", 0.5, 64) is None
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
     assert bench.measured_traffic("neighbours", 0.5, 64) is None
+
+
+def test_differently_assigned_counts():
+    import numpy as np
+    a = {"clu2trk": np.array([0, 0, 0, 1, 1, -1, 2, 2])}
+    b = {"clu2trk": np.array([5, 5, 4, 3, 3, -1, -1, 7])}
+    # track 0 -> 5 (two of three), so cluster 2 on track 4 differs; cluster 6
+    # is unassigned in b only
+    assert bench.differently_assigned(a, b, 8) == {"clusters": 2, "fraction": 0.25}
+    assert bench.differently_assigned(a, a, 8)["clusters"] == 0
