@@ -162,7 +162,7 @@ typedef struct {
  *   tl_par             f32[5][cap_tracklets]   tl_cov f32[15][cap_tracklets]
  *   tl_chi2            f32[cap_tracklets]      tl_nhit, tl_rmin, tl_rmax, tl_status i32
  *   tl_hit             i32[152][cap_tracklets] (row-major by row: slot of row r of
- *                      tracklet t at r * cap_tracklets + t; valid for rmin <= r <= rmax)
+ *                      tracklet t at r * cap_tracklets + t; -1 outside rmin..rmax)
  *   tl_ncand           i32[cap_tracklets] grid candidates whose chi2 the extension
  *                      searches evaluated (instrumentation for byte counts)
  *   owner              u64[n_clusters]  selection keys per position          */

@@ -76,6 +76,8 @@ struct TrackBufs {
   int32_t* tl_hit;     // [152][cap]: hit slot of row r of tracklet t at r * cap + t
   int32_t* tl_ncand;   // [cap] candidates evaluated by the extension searches
   unsigned long long* owner;  // [n]
+  unsigned long long* tl_key;  // [cap] selection key, 0 for rejected tracklets
+  uint8_t* tl_owned;   // [152][cap] 1 where the tracklet owns its hit on the row
   int32_t* tl_own;     // [cap] owned hits of accepted tracklets, 0 otherwise
   int64_t* tsv;        // [cap] packed (track flag << 32 | owned hits), then its scan
   int64_t* scan_tmp;

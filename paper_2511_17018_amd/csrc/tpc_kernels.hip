@@ -941,6 +941,8 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts k, TrackBufs b)
   int n = 1, r0 = kRows, rmax = 0, rmin = 0, ncand = 0;
   int32_t hn = -1;  // phase 1: cleaned upward link of the last hit
   if (mine) {
+    // every slot outside [rmin, rmax] reads -1 (the selection scans whole rows)
+    for (int r = 0; r < kRows; r++) H[(int64_t)r * cap] = -1;
     const int32_t h0 = b.start[t];
     r0 = b.sseg[h0] - segb;
     const int32_t h1 = b.up2[h0];
@@ -1112,10 +1114,68 @@ __global__ __launch_bounds__(kBlock) void k_sel_prep(TrackBufs b)
   }
 }
 
-// The selection kernels run one thread per tracklet and walk the union of
-// the wave's row ranges, so that the hit slots of one row ([row][tracklet])
-// are read contiguously by the wave.  Lanes without a tracklet take part in
-// the range reduction with an empty range.
+// Per-tracklet selection key (R20), 0 for a rejected tracklet (never owns).
+__global__ __launch_bounds__(kBlock) void k_sel_keys(TrackBufs b)
+{
+  const int64_t S = min(b.counters[CNT_START], b.cap);
+  const int64_t t = gtid();
+  if (t >= S) return;
+  b.tl_key[t] = b.tl_status[t] == 0 ? ts_key(b, t) : 0ull;
+}
+
+// Ownership (R20), one workgroup per (instance, row).  A position of row r of
+// instance i can only be claimed by a tracklet of instance i at row r, so the
+// workgroup owns the row: it max-reduces the keys of all the instance's
+// tracklets with a hit on the row in LDS (coalesced reads of the [row]
+// [tracklet] hit slots and the keys), and after a barrier -- every claim on
+// the row is in -- writes per (row, tracklet) whether the tracklet owns its
+// hit there, and the row's owner keys.  A row of more than kSelRowPos
+// positions is reduced with device atomics on the owner array instead (still
+// claimed only by this workgroup).
+constexpr int kSelRowPos = 4096;
+
+__global__ __launch_bounds__(kBlock) void k_sel_rows(TrackBufs b)
+{
+  __shared__ unsigned long long s_own[kSelRowPos];
+  const int inst = blockIdx.x / kRows, r = blockIdx.x % kRows;
+  const int64_t tf = b.tl_first[inst], tl = b.tl_first[inst + 1];
+  if (tf == tl) return;
+  const int32_t p0 = b.row_off[inst * (kRows + 1) + r];
+  const int cnt = b.row_off[inst * (kRows + 1) + r + 1] - p0;
+  const bool lds = cnt <= kSelRowPos;
+  const int32_t* H = b.tl_hit + (int64_t)r * b.cap;
+  if (lds)
+    for (int j = threadIdx.x; j < cnt; j += kBlock) s_own[j] = 0ull;
+  __syncthreads();
+  for (int64_t t = tf + threadIdx.x; t < tl; t += kBlock) {
+    const int32_t h = H[t];
+    if (h < 0) continue;
+    const unsigned long long k = b.tl_key[t];
+    if (!k) continue;
+    if (lds) atomicMax(&s_own[h - p0], k);
+    else atomicMax(&b.owner[h], k);
+  }
+  __syncthreads();
+  uint8_t* O = b.tl_owned + (int64_t)r * b.cap;
+  for (int64_t t = tf + threadIdx.x; t < tl; t += kBlock) {
+    const int32_t h = H[t];
+    uint8_t o = 0;
+    if (h >= 0) {
+      const unsigned long long k = b.tl_key[t];
+      // the atomic reads the device-coherent value on the global path
+      const unsigned long long w = lds ? s_own[h - p0] : atomicMax(&b.owner[h], 0ull);
+      o = k && w == k;
+    }
+    O[t] = o;
+  }
+  if (lds)
+    for (int j = threadIdx.x; j < cnt; j += kBlock) b.owner[p0 + j] = s_own[j];
+}
+
+// The counting and writing kernels run one thread per tracklet and walk the
+// union of the wave's row ranges, so that the ownership bytes and hit slots
+// of one row ([row][tracklet]) are read contiguously by the wave.  Lanes
+// without a tracklet take part in the range reduction with an empty range.
 __device__ __forceinline__ void wave_rows(int lo, int hi, int& wlo, int& whi)
 {
 #pragma unroll
@@ -1127,30 +1187,6 @@ __device__ __forceinline__ void wave_rows(int lo, int hi, int& wlo, int& whi)
   whi = hi;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sel_mark(TrackBufs b)
-{
-  const int64_t S = min(b.counters[CNT_START], b.cap);
-  const int64_t t = gtid();
-  if (t - (threadIdx.x & 63) >= S) return;  // whole wave past the list
-  const bool act = t < S && b.tl_status[t] == 0;
-  unsigned long long key = 0;
-  int lo = kRows, hi = -1;
-  if (act) {
-    key = ts_key(b, t);
-    lo = b.tl_rmin[t];
-    hi = b.tl_rmax[t];
-  }
-  int wlo, whi;
-  wave_rows(lo, hi, wlo, whi);
-  const int32_t* H = b.tl_hit + t;
-  for (int r = wlo; r <= whi; r++) {
-    if (r < lo || r > hi) continue;
-    const int32_t h = H[(int64_t)r * b.cap];
-    // owners only grow: skip the atomic when a larger key is already there
-    if (h >= 0 && b.owner[h] < key) atomicMax(&b.owner[h], key);
-  }
-}
-
 __global__ __launch_bounds__(kBlock) void k_sel_count(Consts k, TrackBufs b, int32_t* own_out)
 {
   const int64_t S = min(b.counters[CNT_START], b.cap);
@@ -1158,21 +1194,18 @@ __global__ __launch_bounds__(kBlock) void k_sel_count(Consts k, TrackBufs b, int
   const int lane = threadIdx.x & 63;
   if (t - lane >= S) return;
   const bool act = t < S && b.tl_status[t] == 0;
-  unsigned long long key = 0;
   int lo = kRows, hi = -1;
   if (act) {
-    key = ts_key(b, t);
     lo = b.tl_rmin[t];
     hi = b.tl_rmax[t];
   }
   int wlo, whi;
   wave_rows(lo, hi, wlo, whi);
-  const int32_t* H = b.tl_hit + t;
+  const uint8_t* O = b.tl_owned + t;
   int own = 0;
   for (int r = wlo; r <= whi; r++) {
     if (r < lo || r > hi) continue;
-    const int32_t h = H[(int64_t)r * b.cap];
-    if (h >= 0 && b.owner[h] == key) own++;
+    own += O[(int64_t)r * b.cap];
   }
   if (own < k.min_track_hits) own = 0;
   const int64_t v = own ? ((int64_t)1 << 32) | own : 0;
@@ -1218,12 +1251,10 @@ __global__ __launch_bounds__(kBlock) void k_sel_write(Consts k, TrackBufs b, con
     act = kk < b.out.cap_tracks && off + own <= b.out.cap_hits;
   }
   int lo = kRows, hi = -1;
-  unsigned long long key = 0;
   if (act) {
     const int64_t cap = b.cap;
     lo = b.tl_rmin[t];
     hi = b.tl_rmax[t];
-    key = ts_key(b, t);
 #pragma unroll
     for (int j = 0; j < 5; j++) b.out.param[kk * 5 + j] = b.tl_par[j * cap + t];
 #pragma unroll
@@ -1243,15 +1274,14 @@ __global__ __launch_bounds__(kBlock) void k_sel_write(Consts k, TrackBufs b, con
   int wlo, whi;
   wave_rows(lo, hi, wlo, whi);
   const int32_t* H = b.tl_hit + t;
+  const uint8_t* O = b.tl_owned + t;
   int64_t j = off;
   for (int r = wlo; r <= whi; r++) {
     if (r < lo || r > hi) continue;
-    const int32_t h = H[(int64_t)r * b.cap];
-    if (h >= 0 && b.owner[h] == key) {
-      const int32_t c = b.perm[h];
-      b.out.hit_clu[j++] = c;
-      b.out.clu2trk[c] = (int32_t)kk;
-    }
+    if (!O[(int64_t)r * b.cap]) continue;
+    const int32_t c = b.perm[H[(int64_t)r * b.cap]];
+    b.out.hit_clu[j++] = c;
+    b.out.clu2trk[c] = (int32_t)kk;
   }
 }
 
@@ -1321,7 +1351,8 @@ hipError_t sector_track(const Consts& k, const TrackBufs& b, hipStream_t s)
     else
       TPC_LAUNCH("tracklets", tl_blocks, 256, s, k_tracklets<256>, k, b);
     const unsigned tblocks = blocks_for(b.cap);
-    TPC_LAUNCH("sel_mark", tblocks, kBlock, s, k_sel_mark, b);
+    TPC_LAUNCH("sel_keys", tblocks, kBlock, s, k_sel_keys, b);
+    TPC_LAUNCH("sel_rows", (unsigned)((int64_t)b.n_inst * kRows), kBlock, s, k_sel_rows, b);
     TPC_LAUNCH("sel_count", tblocks, kBlock, s, k_sel_count, k, b, b.tl_own);
 #if TPC_DET
     scan_exclusive<int64_t>(b.tsv, b.cap, &b.counters[CNT_START], &b.counters[CNT_TRACKS],

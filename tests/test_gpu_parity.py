@@ -97,6 +97,13 @@ def test_det_dense_z_band_beyond_lds_bit_exact():
     _det_case(_arrays(y, z, row, [0, len(y)]))
 
 
+def test_det_selection_rows_beyond_lds_bit_exact():
+    # one wedge of 4000 tracks: 10 rows hold more than the 4096 positions the
+    # selection reduces in LDS, so they take the device-atomic path in the
+    # same launch as the others
+    _det_case(synth.config1(n_tracks=4000))
+
+
 def test_det_config2_full_bit_exact():
     g, o = _det_case(synth.config2())
     assert len(o.tracks.chi2) > 10000
