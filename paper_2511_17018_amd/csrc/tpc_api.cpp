@@ -32,7 +32,8 @@ struct Carve {
 int64_t default_cap(int32_t n_inst, int64_t n) { return n / 3 + n_inst; }
 
 struct GridWs {
-  int64_t cseg, seg_cnt, seg_mm, inst_bad, nb1, fill, scan_tmp, scan_len, total;
+  int64_t cseg, seg_cnt, seg_mm, inst_bad, nb1, fill, seg_pos, seg_cursor, tmp_perm, tmp_yz;
+  int64_t scan_tmp, scan_len, total;
 };
 
 GridWs grid_ws(const tpc_params* p, int32_t n_inst, int64_t n)
@@ -47,6 +48,10 @@ GridWs grid_ws(const tpc_params* p, int32_t n_inst, int64_t n)
   w.inst_bad = c.take(4 * (int64_t)n_inst);
   w.nb1 = c.take(4 * n_seg);
   w.fill = c.take(4 * bin_cap);
+  w.seg_pos = c.take(4 * n_seg);
+  w.seg_cursor = c.take(4 * n_seg);
+  w.tmp_perm = c.take(4 * n);
+  w.tmp_yz = c.take(8 * n);
   const int64_t big = bin_cap > n_seg ? bin_cap : n_seg;
   w.scan_len = big / kScanTile + 2;
   w.scan_tmp = c.take(8 * w.scan_len);
@@ -259,6 +264,10 @@ tpc_status tpc_grid_build(const tpc_geometry* geom, const tpc_params* params, in
   b.inst_bad = at<int32_t>(ws_dev, w.inst_bad);
   b.nb1 = at<int32_t>(ws_dev, w.nb1);
   b.fill = at<int32_t>(ws_dev, w.fill);
+  b.seg_pos = at<int32_t>(ws_dev, w.seg_pos);
+  b.seg_cursor = at<int32_t>(ws_dev, w.seg_cursor);
+  b.tmp_perm = at<int32_t>(ws_dev, w.tmp_perm);
+  b.tmp_yz = at<float2>(ws_dev, w.tmp_yz);
   b.scan_tmp = at<int64_t>(ws_dev, w.scan_tmp);
   b.scan_tmp_len = w.scan_len;
   const Consts k = make_consts(geom, params);

@@ -49,7 +49,11 @@ struct GridBufs {
   uint32_t* seg_mm;    // [4][n_seg] ordered-float min y, max y, min z, max z
   int32_t* inst_bad;   // [n_inst]
   int32_t* nb1;        // [n_seg] bins + 1 per segment, then their exclusive scan
-  int32_t* fill;       // [bin_cap]
+  int32_t* fill;       // [bin_cap] bin counters of segments with too many bins for LDS
+  int32_t* seg_pos;    // [n_seg] segment lengths, then the segments' first positions
+  int32_t* seg_cursor; // [n_seg] partition cursors
+  int32_t* tmp_perm;   // [n] clusters partitioned by segment: input index
+  float2* tmp_yz;      // [n] and (y, z)
   int64_t* scan_tmp;   // scan partials
   int64_t scan_tmp_len;
 };

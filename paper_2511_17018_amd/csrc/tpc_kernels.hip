@@ -220,6 +220,7 @@ __global__ void k_grid_clear(GridBufs b)
     b.seg_mm[n_seg + s] = 0u;
     b.seg_mm[2 * n_seg + s] = 0xFFFFFFFFu;
     b.seg_mm[3 * n_seg + s] = 0u;
+    b.seg_cursor[s] = 0;
     if (s < b.n_inst) b.inst_bad[s] = 0;
   }
   if (gtid() == 0) {
@@ -344,63 +345,160 @@ __global__ void k_grid_meta(Consts k, GridBufs b)
     atomicAdd((unsigned long long*)&b.res->n_bad, (unsigned long long)b.inst_bad[s]);
 }
 
-__global__ void k_grid_zero(GridBufs b)
-{
-  int64_t tot = b.res->n_bins;
-  if (tot > b.bin_cap) {
-    if (gtid() == 0) b.res->overflow |= 1;
-    return;
-  }
-  for (int64_t j = gtid(); j < tot; j += (int64_t)gridDim.x * blockDim.x) {
-    b.bin_off[j] = 0;
-    b.fill[j] = 0;
-  }
-}
-
+// Bin bases, segment lengths (valid clusters, plus the instance's padding
+// positions after its last row) and the bin-capacity check.
 __global__ void k_grid_meta2(GridBufs b)
 {
-  if (b.res->overflow & 1) return;
   const int64_t n_seg = (int64_t)b.n_inst * kRows;
   const int64_t s = gtid();
+  if (s == 0 && b.res->n_bins > b.bin_cap) b.res->overflow |= 1;
   if (s >= n_seg) return;
-  int base = b.nb1[s];
-  b.meta[s].bin_base = base;
-  if (s % kRows == kRows - 1) {
-    // the last sentinel of an instance counts its padding positions
-    const tpc_row_meta m = b.meta[s];
-    b.bin_off[base + m.ny * m.nz] = b.inst_bad[s / kRows];
+  b.meta[s].bin_base = b.nb1[s];
+  b.seg_pos[s] = b.seg_cnt[s] + (s % kRows == kRows - 1 ? b.inst_bad[s / kRows] : 0);
+}
+
+// Partition by segment: every valid cluster goes to its (instance,row)
+// segment's range of a temporary array (in any order within the segment).
+// A workgroup takes kPartItems consecutive clusters (mostly one instance),
+// counts them per segment in LDS and claims each segment's run with one
+// device atomic, so the scattered writes come in short runs.  A workgroup
+// whose clusters span more than kPartSegs segment ids claims per cluster.
+constexpr int kPartPer = 8;                        // clusters per thread
+constexpr int kPartItems = kBlock * kPartPer;
+constexpr int kPartSegs = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_grid_part(GridBufs b)
+{
+  __shared__ int s_cnt[kPartSegs];
+  __shared__ int s_smin, s_smax;
+  const int tx = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * kPartItems;
+  if (tx == 0) {
+    s_smin = INT_MAX;
+    s_smax = -1;
+  }
+  int seg[kPartPer], rank[kPartPer];
+  int lmin = INT_MAX, lmax = -1;
+#pragma unroll
+  for (int k = 0; k < kPartPer; k++) {
+    const int64_t c = c0 + k * kBlock + tx;
+    seg[k] = c < b.n ? b.cseg[c] : -1;
+    if (seg[k] >= 0) {
+      lmin = min(lmin, seg[k]);
+      lmax = max(lmax, seg[k]);
+    }
+  }
+  __syncthreads();
+  if (lmax >= 0) {
+    atomicMin(&s_smin, lmin);
+    atomicMax(&s_smax, lmax);
+  }
+  __syncthreads();
+  const int smin = s_smin, smax = s_smax;
+  if (smax < 0) return;  // no valid cluster here (uniform)
+  const bool lds = smax - smin < kPartSegs;
+  if (lds)
+    for (int j = tx; j <= smax - smin; j += kBlock) s_cnt[j] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPartPer; k++)
+    if (seg[k] >= 0)
+      rank[k] = lds ? atomicAdd(&s_cnt[seg[k] - smin], 1) : atomicAdd(&b.seg_cursor[seg[k]], 1);
+  __syncthreads();
+  if (lds)
+    for (int j = tx; j <= smax - smin; j += kBlock) {
+      const int n = s_cnt[j];
+      if (n) s_cnt[j] = atomicAdd(&b.seg_cursor[smin + j], n);
+    }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPartPer; k++) {
+    if (seg[k] < 0) continue;
+    const int64_t c = c0 + k * kBlock + tx;
+    const int32_t dst = b.seg_pos[seg[k]] + (lds ? s_cnt[seg[k] - smin] : 0) + rank[k];
+    b.tmp_perm[dst] = (int32_t)c;
+    b.tmp_yz[dst] = make_float2(b.y[c], b.z[c]);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_grid_hist(GridBufs b)
-{
-  if (b.res->overflow & 1) return;
-  const int64_t c = gtid();
-  if (c >= b.n) return;
-  int seg = b.cseg[c];
-  if (seg < 0) return;
-  const tpc_row_meta m = b.meta[seg];
-  int iy = bin_coord(b.y[c], m.y0, m.iwy, m.ny);
-  int iz = bin_coord(b.z[c], m.z0, m.iwz, m.nz);
-  atomicAdd(&b.bin_off[m.bin_base + iz * m.ny + iy], 1);
-}
+// Counting sort of one segment by bin (R10), one workgroup per segment: the
+// workgroup owns the segment's positions and bins, so its bin counters live
+// in LDS (or, for more than kSegBins bins, in the segment's own range of the
+// workspace counters) with no other writer.  Histogram, exclusive scan
+// (written as the bins' first positions, sentinel included), placement with
+// the scanned counters as cursors, and in the deterministic build the
+// ordering of each bin by input index -- an ordering kernel after atomic
+// placement (Sec. 2, run-time part), here inside the workgroup.
+constexpr int kSegBins = 8192;
 
-__global__ __launch_bounds__(kBlock) void k_grid_scatter(GridBufs b)
+__global__ __launch_bounds__(kBlock) void k_grid_seg(GridBufs b)
 {
+  __shared__ int32_t s_c[kSegBins];
   if (b.res->overflow & 1) return;
-  const int64_t c = gtid();
-  if (c >= b.n) return;
-  int seg = b.cseg[c];
-  if (seg < 0) return;
-  const tpc_row_meta m = b.meta[seg];
-  float y = b.y[c], z = b.z[c];
-  int iy = bin_coord(y, m.y0, m.iwy, m.ny);
-  int iz = bin_coord(z, m.z0, m.iwz, m.nz);
-  int j = m.bin_base + iz * m.ny + iy;
-  int pos = b.bin_off[j] + atomicAdd(&b.fill[j], 1);
-  b.sseg[pos] = seg;
-  b.perm[pos] = (int32_t)c;
-  b.yz[pos] = make_float2(y, z);
+  const int64_t s = blockIdx.x;
+  const int tx = threadIdx.x;
+  const tpc_row_meta m = b.meta[s];
+  const int nb = m.ny * m.nz;
+  const int cnt = b.seg_cnt[s];
+  const int32_t P = b.seg_pos[s];
+  const bool lds = nb + 1 <= kSegBins;
+  int32_t* const gc = b.fill + m.bin_base;
+  for (int j = tx; j <= nb; j += kBlock) {
+    if (lds) s_c[j] = 0;
+    else gc[j] = 0;
+  }
+  __syncthreads();
+  for (int j = tx; j < cnt; j += kBlock) {
+    const float2 q = b.tmp_yz[P + j];
+    const int bin = bin_coord(q.y, m.z0, m.iwz, m.nz) * m.ny + bin_coord(q.x, m.y0, m.iwy, m.ny);
+    if (lds) atomicAdd(&s_c[bin], 1);
+    else atomicAdd(&gc[bin], 1);
+  }
+  __syncthreads();
+  int64_t carry = 0;
+  for (int j0 = 0; j0 <= nb; j0 += kBlock) {
+    const int j = j0 + tx;
+    const int v = j <= nb ? (lds ? s_c[j] : atomicAdd(&gc[j], 0)) : 0;
+    int64_t tot;
+    const int64_t ex = block_exclusive_scan(v, &tot);
+    if (j <= nb) {
+      const int off = (int)(carry + ex);
+      b.bin_off[m.bin_base + j] = P + off;
+      if (lds) s_c[j] = off;
+      else atomicExch(&gc[j], off);
+    }
+    carry += tot;
+  }
+  __syncthreads();
+  for (int j = tx; j < cnt; j += kBlock) {
+    const int32_t c = b.tmp_perm[P + j];
+    const float2 q = b.tmp_yz[P + j];
+    const int bin = bin_coord(q.y, m.z0, m.iwz, m.nz) * m.ny + bin_coord(q.x, m.y0, m.iwy, m.ny);
+    const int pos = P + (lds ? atomicAdd(&s_c[bin], 1) : atomicAdd(&gc[bin], 1));
+    b.perm[pos] = c;
+    b.yz[pos] = q;
+    b.sseg[pos] = (int32_t)s;
+  }
+#if TPC_DET
+  __syncthreads();
+  // the cursors now hold each bin's end; bin j starts where bin j-1 ends
+  for (int j = tx; j < nb; j += kBlock) {
+    const int e = lds ? s_c[j] : atomicAdd(&gc[j], 0);
+    const int a = j == 0 ? 0 : (lds ? s_c[j - 1] : atomicAdd(&gc[j - 1], 0));
+    for (int p = P + a + 1; p < P + e; p++) {
+      const int32_t kp = b.perm[p];
+      const float2 kv = b.yz[p];
+      int q = p - 1;
+      while (q >= P + a && b.perm[q] > kp) {
+        b.perm[q + 1] = b.perm[q];
+        b.yz[q + 1] = b.yz[q];
+        q--;
+      }
+      b.perm[q + 1] = kp;
+      b.yz[q + 1] = kv;
+    }
+  }
+#endif
 }
 
 __global__ void k_grid_rowoff(GridBufs b)
@@ -411,42 +509,15 @@ __global__ void k_grid_rowoff(GridBufs b)
   if (s >= n_seg) return;
   const int64_t i = s / kRows;
   const int r = (int)(s % kRows);
-  const tpc_row_meta m = b.meta[s];
-  b.row_off[i * (kRows + 1) + r] = b.bin_off[m.bin_base];
+  b.row_off[i * (kRows + 1) + r] = b.seg_pos[s];
   if (r == kRows - 1) {
-    int end = b.bin_off[m.bin_base + m.ny * m.nz];
+    const int end = b.seg_pos[s] + b.seg_cnt[s];
     b.row_off[i * (kRows + 1) + kRows] = end;
     for (int64_t p = end; p < b.inst_off[i + 1]; p++) {
       b.sseg[p] = -1;
       b.perm[p] = -1;
       b.yz[p] = make_float2(0.0f, 0.0f);
     }
-  }
-}
-
-// Deterministic mode: order each bin by input index (the atomic scatter
-// leaves it in arrival order) -- an ordering kernel after a kernel whose
-// output order depends on concurrency (Sec. 2, run-time part).
-__global__ __launch_bounds__(kBlock) void k_grid_binsort(GridBufs b)
-{
-  if (b.res->overflow & 1) return;
-  const int64_t tot = b.res->n_bins;
-  const int64_t j = gtid();
-  if (j >= tot) return;
-  int a = b.bin_off[j];
-  int e = j + 1 < tot ? b.bin_off[j + 1] : (int)b.n;
-  if (e - a < 2) return;
-  for (int p = a + 1; p < e; p++) {
-    const int kp = b.perm[p];
-    const float2 kv = b.yz[p];
-    int q = p - 1;
-    while (q >= a && b.perm[q] > kp) {
-      b.perm[q + 1] = b.perm[q];
-      b.yz[q + 1] = b.yz[q];
-      q--;
-    }
-    b.perm[q + 1] = kp;
-    b.yz[q + 1] = kv;
   }
 }
 
@@ -1311,15 +1382,11 @@ hipError_t grid_build(const Consts& k, const GridBufs& b, hipStream_t s)
   if (b.n > 0) TPC_LAUNCH("grid_stats", blocks_for(b.n, kStatItems), kBlock, s, k_grid_stats, k, b);
   TPC_LAUNCH("grid_meta", blocks_for(n_seg), kBlock, s, k_grid_meta, k, b);
   scan_exclusive<int32_t>(b.nb1, n_seg, nullptr, &b.res->n_bins, b.scan_tmp, s);
-  TPC_LAUNCH("grid_zero", blocks_for(b.bin_cap), kBlock, s, k_grid_zero, b);
   TPC_LAUNCH("grid_meta2", blocks_for(n_seg), kBlock, s, k_grid_meta2, b);
-  if (b.n > 0) TPC_LAUNCH("grid_hist", blocks_for(b.n), kBlock, s, k_grid_hist, b);
-  scan_exclusive<int32_t>(b.bin_off, b.bin_cap, &b.res->n_bins, nullptr, b.scan_tmp, s);
-  if (b.n > 0) TPC_LAUNCH("grid_scatter", blocks_for(b.n), kBlock, s, k_grid_scatter, b);
+  scan_exclusive<int32_t>(b.seg_pos, n_seg, nullptr, nullptr, b.scan_tmp, s);
+  if (b.n > 0) TPC_LAUNCH("grid_part", blocks_for(b.n, kPartItems), kBlock, s, k_grid_part, b);
+  TPC_LAUNCH("grid_seg", (unsigned)n_seg, kBlock, s, k_grid_seg, b);
   TPC_LAUNCH("grid_rowoff", blocks_for(n_seg), kBlock, s, k_grid_rowoff, b);
-#if TPC_DET
-  TPC_LAUNCH("grid_binsort", blocks_for(b.bin_cap), kBlock, s, k_grid_binsort, b);
-#endif
   return hipGetLastError();
 }
 

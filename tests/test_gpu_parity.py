@@ -30,7 +30,8 @@ def _det_case(ev, **kw):
     _say(f"[det] {getattr(ev, 'name', 'custom')} n={int(ev.inst_off[-1])} inst={len(ev.inst_off) - 1}")
     run = parity.run_gpu(ev, det=True, **kw)
     g = parity.gpu_arrays(run, int(ev.inst_off[-1]))
-    o = oracle.track(G, P, ev.inst_off, ev.y, ev.z, ev.row)
+    po = dict(P, grid_occupancy=kw["grid_occupancy"]) if "grid_occupancy" in kw else P
+    o = oracle.track(G, po, ev.inst_off, ev.y, ev.z, ev.row)
     errs = parity.compare_det(g, o)
     assert not errs, "\n".join(errs)
     return g, o
@@ -102,6 +103,29 @@ def test_det_selection_rows_beyond_lds_bit_exact():
     # selection reduces in LDS, so they take the device-atomic path in the
     # same launch as the others
     _det_case(synth.config1(n_tracks=4000))
+
+
+def test_det_grid_segments_beyond_lds_bit_exact():
+    # grid occupancy 0.25 (four bins per cluster) on a 2200-track wedge: 65
+    # of the 152 rows have more bins than the segment sort holds in LDS and
+    # count in the workspace instead, in the same launch as the smaller rows;
+    # the oracle builds its grid at the same occupancy
+    _det_case(synth.config1(n_tracks=2200), grid_occupancy=0.25)
+
+
+def test_det_many_tiny_instances_bit_exact():
+    # 400 instances of 3-40 clusters: one partition tile of 2048 clusters
+    # spans more segment ids than its LDS counters and claims per cluster
+    rng = np.random.default_rng(3)
+    sizes = rng.integers(3, 40, 400)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    n = int(off[-1])
+    g = synth.geometry()
+    row = rng.integers(0, 152, n).astype(np.uint16)
+    lim = g["row_x"][row] * g["tan_half"]
+    y = (rng.uniform(-1, 1, n) * lim).astype(np.float32)
+    z = rng.uniform(-50, 50, n).astype(np.float32)
+    _det_case(_arrays(y, z, row, off))
 
 
 def test_det_config2_full_bit_exact():
