@@ -575,6 +575,48 @@ __device__ __forceinline__ void nf_consider(const TrackBufs& b, NfBest& best, fl
   }
 }
 
+// Workgroup copies global -> LDS with the loads batched: each thread issues
+// kCopyBatch independent loads before the first store, so a staged row costs
+// one memory latency per kCopyBatch elements per thread instead of one per
+// element.
+constexpr int kCopyBatch = 4;
+
+template <int NT>
+__device__ __forceinline__ void copy_offsets(int32_t* dst, const int32_t* src, int n, int32_t sub)
+{
+  for (int j0 = 0; j0 < n; j0 += NT * kCopyBatch) {
+    int32_t v[kCopyBatch];
+#pragma unroll
+    for (int u = 0; u < kCopyBatch; u++) {
+      const int j = j0 + u * NT + (int)threadIdx.x;
+      v[u] = j < n ? src[j] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyBatch; u++) {
+      const int j = j0 + u * NT + (int)threadIdx.x;
+      if (j < n) dst[j] = v[u] - sub;
+    }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void copy_yz(float2* dst, const float2* src, int n)
+{
+  for (int j0 = 0; j0 < n; j0 += NT * kCopyBatch) {
+    float2 v[kCopyBatch];
+#pragma unroll
+    for (int u = 0; u < kCopyBatch; u++) {
+      const int j = j0 + u * NT + (int)threadIdx.x;
+      v[u] = j < n ? src[j] : make_float2(0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyBatch; u++) {
+      const int j = j0 + u * NT + (int)threadIdx.x;
+      if (j < n) dst[j] = v[u];
+    }
+  }
+}
+
 // A slab of one row: bins [iz0 * ny, (iz1 + 1) * ny) with their boundaries
 // relative to the slab's first position P0, then the positions.
 struct Slab {
@@ -601,8 +643,8 @@ __device__ __forceinline__ Slab stage_slab(const TrackBufs& b, const tpc_row_met
   if (sl.ok) {
     int32_t* off = (int32_t*)buf;
     float2* yz = (float2*)(buf + ob);
-    for (int j = threadIdx.x; j <= nb; j += NT) off[j] = b.bin_off[j0 + j] - sl.P0;
-    for (int j = threadIdx.x; j < cnt; j += NT) yz[j] = b.yz[sl.P0 + j];
+    copy_offsets<NT>(off, b.bin_off + j0, nb + 1, sl.P0);
+    copy_yz<NT>(yz, b.yz + sl.P0, cnt);
   }
   return sl;
 }
@@ -1048,8 +1090,8 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts k, TrackBufs b)
     const bool staged = ob + (int64_t)cnt * 8 <= kRowLds;
     float2* const s_yz = (float2*)(s_row + (staged ? ob : 0));
     if (staged) {
-      for (int j = threadIdx.x; j <= nbin; j += CH) s_off[j] = b.bin_off[m.bin_base + j] - P0;
-      for (int j = threadIdx.x; j < cnt; j += CH) s_yz[j] = b.yz[P0 + j];
+      copy_offsets<CH>(s_off, b.bin_off + m.bin_base, nbin + 1, P0);
+      copy_yz<CH>(s_yz, b.yz + P0, cnt);
     }
     __syncthreads();
     if (!(up && r > r0)) continue;
@@ -1114,8 +1156,8 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts k, TrackBufs b)
     const bool staged = ob + (int64_t)cnt * 8 <= kRowLds;
     float2* const s_yz = (float2*)(s_row + (staged ? ob : 0));
     if (staged) {
-      for (int j = threadIdx.x; j <= nbin; j += CH) s_off[j] = b.bin_off[m.bin_base + j] - P0;
-      for (int j = threadIdx.x; j < cnt; j += CH) s_yz[j] = b.yz[P0 + j];
+      copy_offsets<CH>(s_off, b.bin_off + m.bin_base, nbin + 1, P0);
+      copy_yz<CH>(s_yz, b.yz + P0, cnt);
     }
     __syncthreads();
     if (!(dn && r < r0)) continue;
