@@ -931,6 +931,8 @@ __global__ void k_start_finish(TrackBufs b)
 
 #include "tpc_kalman.h"
 
+constexpr int kSrchZ = 2, kSrchC = 4;
+
 // R15: best cluster of one row for the predicted state.  `off` holds the
 // row's ny*nz+1 bin boundaries and `yz` the cluster positions, both in one
 // index space whose index p is grid position pos0 + p (the LDS copy of a row
@@ -952,21 +954,42 @@ __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b,
   const int zhi = bin_coord(z + wz, m.z0, m.iwz, m.nz);
   int32_t best = -1;
   float bchi = 0.0f;
-  for (int iz = zlo; iz <= zhi; iz++) {
-    const int bb = iz * m.ny;
-    const int e = off[bb + yhi + 1];
-    const int p0 = off[bb + ylo];
-    ncand += e - p0;
-    for (int p = p0; p < e; p++) {
-      const float2 qc = yz[p];
-      const float r0 = qc.x - y, r1 = qc.y - z;
-      const float ch = chi2_of(q, r0, r1);
-      if (!(ch <= pick)) continue;
-      if (best < 0 || ch < bchi) {
-        best = p;
-        bchi = ch;
-      } else if (ch == bchi && b.perm[pos0 + p] < b.perm[pos0 + best]) {
-        best = p;
+  // loads batched: the bin ranges of kSrchZ z rows at once, then up to
+  // kSrchC candidates of a range at once (one memory latency each instead of
+  // one per load on the global path)
+  for (int z0 = zlo; z0 <= zhi; z0 += kSrchZ) {
+    int ra[kSrchZ], re[kSrchZ];
+#pragma unroll
+    for (int u = 0; u < kSrchZ; u++) {
+      ra[u] = re[u] = 0;
+      if (z0 + u <= zhi) {
+        const int bb = (z0 + u) * m.ny;
+        ra[u] = off[bb + ylo];
+        re[u] = off[bb + yhi + 1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSrchZ; u++) {
+      ncand += re[u] - ra[u];
+      for (int p0 = ra[u]; p0 < re[u]; p0 += kSrchC) {
+        float2 qv[kSrchC];
+#pragma unroll
+        for (int c = 0; c < kSrchC; c++)
+          qv[c] = p0 + c < re[u] ? yz[p0 + c] : make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int c = 0; c < kSrchC; c++) {
+          const int p = p0 + c;
+          if (p >= re[u]) continue;
+          const float r0 = qv[c].x - y, r1 = qv[c].y - z;
+          const float ch = chi2_of(q, r0, r1);
+          if (!(ch <= pick)) continue;
+          if (best < 0 || ch < bchi) {
+            best = p;
+            bchi = ch;
+          } else if (ch == bchi && b.perm[pos0 + p] < b.perm[pos0 + best]) {
+            best = p;
+          }
+        }
       }
     }
   }
