@@ -1269,6 +1269,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_keys(TrackBufs b)
 // positions is reduced with device atomics on the owner array instead (still
 // claimed only by this workgroup).
 constexpr int kSelRowPos = 4096;
+constexpr int kSelBatch = 4;
 
 __global__ __launch_bounds__(kBlock) void k_sel_rows(TrackBufs b)
 {
@@ -1283,26 +1284,46 @@ __global__ __launch_bounds__(kBlock) void k_sel_rows(TrackBufs b)
   if (lds)
     for (int j = threadIdx.x; j < cnt; j += kBlock) s_own[j] = 0ull;
   __syncthreads();
-  for (int64_t t = tf + threadIdx.x; t < tl; t += kBlock) {
-    const int32_t h = H[t];
-    if (h < 0) continue;
-    const unsigned long long k = b.tl_key[t];
-    if (!k) continue;
-    if (lds) atomicMax(&s_own[h - p0], k);
-    else atomicMax(&b.owner[h], k);
+  // slots and keys of kSelBatch tracklets per thread are loaded together
+  for (int64_t t0 = tf + threadIdx.x; t0 < tl; t0 += kBlock * kSelBatch) {
+    int32_t hv[kSelBatch];
+    unsigned long long kv[kSelBatch];
+#pragma unroll
+    for (int u = 0; u < kSelBatch; u++) {
+      const int64_t t = t0 + u * kBlock;
+      hv[u] = t < tl ? H[t] : -1;
+      kv[u] = t < tl ? b.tl_key[t] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kSelBatch; u++) {
+      if (hv[u] < 0 || !kv[u]) continue;
+      if (lds) atomicMax(&s_own[hv[u] - p0], kv[u]);
+      else atomicMax(&b.owner[hv[u]], kv[u]);
+    }
   }
   __syncthreads();
   uint8_t* O = b.tl_owned + (int64_t)r * b.cap;
-  for (int64_t t = tf + threadIdx.x; t < tl; t += kBlock) {
-    const int32_t h = H[t];
-    uint8_t o = 0;
-    if (h >= 0) {
-      const unsigned long long k = b.tl_key[t];
-      // the atomic reads the device-coherent value on the global path
-      const unsigned long long w = lds ? s_own[h - p0] : atomicMax(&b.owner[h], 0ull);
-      o = k && w == k;
+  for (int64_t t0 = tf + threadIdx.x; t0 < tl; t0 += kBlock * kSelBatch) {
+    int32_t hv[kSelBatch];
+    unsigned long long kv[kSelBatch];
+#pragma unroll
+    for (int u = 0; u < kSelBatch; u++) {
+      const int64_t t = t0 + u * kBlock;
+      hv[u] = t < tl ? H[t] : -1;
+      kv[u] = t < tl ? b.tl_key[t] : 0ull;
     }
-    O[t] = o;
+#pragma unroll
+    for (int u = 0; u < kSelBatch; u++) {
+      const int64_t t = t0 + u * kBlock;
+      if (t >= tl) continue;
+      uint8_t o = 0;
+      if (hv[u] >= 0 && kv[u]) {
+        // the atomic reads the device-coherent value on the global path
+        const unsigned long long w = lds ? s_own[hv[u] - p0] : atomicMax(&b.owner[hv[u]], 0ull);
+        o = w == kv[u];
+      }
+      O[t] = o;
+    }
   }
   if (lds)
     for (int j = threadIdx.x; j < cnt; j += kBlock) b.owner[p0 + j] = s_own[j];
