@@ -430,6 +430,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_part(GridBufs b)
 // ordering of each bin by input index -- an ordering kernel after atomic
 // placement (Sec. 2, run-time part), here inside the workgroup.
 constexpr int kSegBins = 8192;
+constexpr int kSegBatch = 4;
 
 __global__ __launch_bounds__(kBlock) void k_grid_seg(GridBufs b)
 {
@@ -448,11 +449,20 @@ __global__ __launch_bounds__(kBlock) void k_grid_seg(GridBufs b)
     else gc[j] = 0;
   }
   __syncthreads();
-  for (int j = tx; j < cnt; j += kBlock) {
-    const float2 q = b.tmp_yz[P + j];
-    const int bin = bin_coord(q.y, m.z0, m.iwz, m.nz) * m.ny + bin_coord(q.x, m.y0, m.iwy, m.ny);
-    if (lds) atomicAdd(&s_c[bin], 1);
-    else atomicAdd(&gc[bin], 1);
+  for (int j0 = tx; j0 < cnt; j0 += kBlock * kSegBatch) {
+    float2 qv[kSegBatch];
+#pragma unroll
+    for (int u = 0; u < kSegBatch; u++) {
+      const int j = j0 + u * kBlock;
+      qv[u] = j < cnt ? b.tmp_yz[P + j] : make_float2(0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int u = 0; u < kSegBatch; u++) {
+      if (j0 + u * kBlock >= cnt) continue;
+      const int bin = bin_coord(qv[u].y, m.z0, m.iwz, m.nz) * m.ny + bin_coord(qv[u].x, m.y0, m.iwy, m.ny);
+      if (lds) atomicAdd(&s_c[bin], 1);
+      else atomicAdd(&gc[bin], 1);
+    }
   }
   __syncthreads();
   int64_t carry = 0;
@@ -470,14 +480,25 @@ __global__ __launch_bounds__(kBlock) void k_grid_seg(GridBufs b)
     carry += tot;
   }
   __syncthreads();
-  for (int j = tx; j < cnt; j += kBlock) {
-    const int32_t c = b.tmp_perm[P + j];
-    const float2 q = b.tmp_yz[P + j];
-    const int bin = bin_coord(q.y, m.z0, m.iwz, m.nz) * m.ny + bin_coord(q.x, m.y0, m.iwy, m.ny);
-    const int pos = P + (lds ? atomicAdd(&s_c[bin], 1) : atomicAdd(&gc[bin], 1));
-    b.perm[pos] = c;
-    b.yz[pos] = q;
-    b.sseg[pos] = (int32_t)s;
+  for (int j0 = tx; j0 < cnt; j0 += kBlock * kSegBatch) {
+    int32_t cv[kSegBatch];
+    float2 qv[kSegBatch];
+#pragma unroll
+    for (int u = 0; u < kSegBatch; u++) {
+      const int j = j0 + u * kBlock;
+      cv[u] = j < cnt ? b.tmp_perm[P + j] : 0;
+      qv[u] = j < cnt ? b.tmp_yz[P + j] : make_float2(0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int u = 0; u < kSegBatch; u++) {
+      if (j0 + u * kBlock >= cnt) continue;
+      const float2 q = qv[u];
+      const int bin = bin_coord(q.y, m.z0, m.iwz, m.nz) * m.ny + bin_coord(q.x, m.y0, m.iwy, m.ny);
+      const int pos = P + (lds ? atomicAdd(&s_c[bin], 1) : atomicAdd(&gc[bin], 1));
+      b.perm[pos] = cv[u];
+      b.yz[pos] = q;
+      b.sseg[pos] = (int32_t)s;
+    }
   }
 #if TPC_DET
   __syncthreads();
@@ -1433,12 +1454,25 @@ __global__ __launch_bounds__(kBlock) void k_sel_write(Consts k, TrackBufs b, con
   const int32_t* H = b.tl_hit + t;
   const uint8_t* O = b.tl_owned + t;
   int64_t j = off;
-  for (int r = wlo; r <= whi; r++) {
-    if (r < lo || r > hi) continue;
-    if (!O[(int64_t)r * b.cap]) continue;
-    const int32_t c = b.perm[H[(int64_t)r * b.cap]];
-    b.out.hit_clu[j++] = c;
-    b.out.clu2trk[c] = (int32_t)kk;
+  // four rows at a time: ownership bytes and slots, then the owned hits'
+  // input indices, loaded together
+  for (int r0 = wlo; r0 <= whi; r0 += kSelBatch) {
+    int32_t hv[kSelBatch];
+#pragma unroll
+    for (int u = 0; u < kSelBatch; u++) {
+      const int r = r0 + u;
+      hv[u] = -1;
+      if (r >= lo && r <= hi && O[(int64_t)r * b.cap]) hv[u] = H[(int64_t)r * b.cap];
+    }
+    int32_t cv[kSelBatch];
+#pragma unroll
+    for (int u = 0; u < kSelBatch; u++) cv[u] = hv[u] >= 0 ? b.perm[hv[u]] : -1;
+#pragma unroll
+    for (int u = 0; u < kSelBatch; u++) {
+      if (hv[u] < 0) continue;
+      b.out.hit_clu[j++] = cv[u];
+      b.out.clu2trk[cv[u]] = (int32_t)kk;
+    }
   }
 }
 
