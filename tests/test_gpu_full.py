@@ -1,0 +1,141 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (batched chain, tuned launch parameters), on sampled
+outputs the oracle can compute on its own: sector instances and refit
+tracks are independent, so the oracle tracks a sampled instance (or refits
+a sampled track) alone and the batched GPU output restricted to it must
+match -- bit for bit in the deterministic mode (tracks as hit sets with
+their parameter bits, and the cluster-to-track partition), and to the
+gradient tolerance for the refit's reverse pass.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2511_17018_amd as tpc
+import synth
+from paper_2511_17018_amd.runtime import Chain
+
+pytestmark = pytest.mark.gpu
+
+G = synth.geometry()
+# the launch parameters the benchmark's tuner picks on config 4
+OCC, CHUNK = 1.0, 64
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _batched(ev):
+    batch = tpc.upload(ev.x, ev.y, ev.z, ev.row, ev.charge, ev.inst_off, "cuda")
+    stream = torch.cuda.current_stream()
+    ch = Chain(G, batch, True, stream, grid_occupancy=OCC, tl_chunk=CHUNK)
+    with torch.cuda.stream(stream):
+        ch.enqueue()
+    stream.synchronize()
+    res = ch.result()
+    assert int(res["overflow"]) == 0
+    return ch.outputs(), res
+
+
+def _tracks_of(ho, hc, par, lo, hi):
+    """{hit tuple: parameter bits} of the tracks whose hits lie in [lo, hi)."""
+    out = {}
+    for k in range(len(ho) - 1):
+        h = hc[ho[k]:ho[k + 1]]
+        if len(h) and lo <= h[0] < hi:
+            out[tuple(h.tolist())] = par[k].view(np.int32).tobytes()
+    return out
+
+
+def _check_instance(ev, out, i):
+    a, b = int(ev.inst_off[i]), int(ev.inst_off[i + 1])
+    _say(f"[full] instance {i}: {b - a} clusters")
+    P = dict(oracle.DEFAULT_PARAMS, grid_occupancy=OCC)
+    o = oracle.track(G, P, np.array([0, b - a], np.int64), ev.y[a:b], ev.z[a:b], ev.row[a:b])
+    T = o.tracks
+    ref = _tracks_of(T.hit_off, T.hit_clu + a, T.par, a, b)
+    got = _tracks_of(out["hit_off"], out["hit_clu"], out["param"], a, b)
+    assert len(ref) > 0
+    assert got.keys() == ref.keys(), (len(got), len(ref))
+    assert all(got[k] == ref[k] for k in ref)
+    # the cluster-to-track partition of the instance
+    cg, co = out["clu2trk"][a:b], T.clu2trk
+    assert np.array_equal(cg < 0, co < 0)
+    m = co >= 0
+    pairs = np.unique(np.stack([cg[m], co[m]], 1), axis=0)
+    assert len(pairs) == len(np.unique(cg[m])) == len(np.unique(co[m]))
+
+
+def test_det_config4_full_sampled_instances():
+    ev = synth.config4()
+    _say(f"[full] config 4: {ev.n} clusters, {ev.n_inst} instances")
+    out, res = _batched(ev)
+    sizes = np.diff(ev.inst_off)
+    order = np.argsort(sizes)
+    rng = np.random.default_rng(1)
+    picks = {int(order[0]), int(order[len(order) // 2]), int(order[-1])}
+    picks |= set(int(i) for i in rng.choice(ev.n_inst, 2, replace=False))
+    for i in sorted(picks):
+        _check_instance(ev, out, i)
+
+
+def test_det_config3_full_sampled_sectors():
+    ev = synth.config3()
+    _say(f"[full] config 3: {ev.n} clusters, {ev.n_inst} sectors")
+    out, res = _batched(ev)
+    assert int(res["n_tracks"]) > 100000
+    rng = np.random.default_rng(2)
+    for i in sorted(set(int(j) for j in rng.choice(ev.n_inst, 2, replace=False))):
+        _check_instance(ev, out, i)
+
+
+def test_refit_config5_full_sampled_tracks():
+    ev = synth.config5()
+    ho, hc, seed = ev.extra["hit_off"], ev.extra["hit_clu"], ev.extra["seed_par"]
+    nt = len(ho) - 1
+    _say(f"[full] config 5: {nt} tracks, {ho[-1]} hits")
+    dmap = ev.extra["D_true"]
+    xyz = torch.from_numpy(np.stack([ev.x, ev.y, ev.z]).astype(np.float32)).cuda()
+    row = torch.from_numpy(ev.row.view(np.int16)).cuda()
+    trk = tpc.upload_refit_tracks(ho, hc, ev.sector, seed)
+    m = torch.from_numpy(np.ascontiguousarray(dmap, np.float32)).cuda()
+    rng = np.random.default_rng(5)
+    w = rng.uniform(0.5, 1.5, nt).astype(np.float32)
+    chi2, status, ckpt = tpc.refit(G, xyz, row, trk, m, det=True)
+    gmap, gxyz = tpc.refit_backward(G, xyz, row, trk, m, ckpt, status, torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    chi2, status, ckpt = chi2.cpu().numpy(), status.cpu().numpy(), ckpt.cpu().numpy()
+    gx, gy, gz = gxyz.cpu().numpy()
+    # sampled tracks, refitted by the oracle on their own
+    sel = np.sort(rng.choice(nt, 2000, replace=False))
+    lens = np.diff(ho)[sel]
+    sho = np.concatenate([[0], np.cumsum(lens)])
+    shc = np.concatenate([hc[ho[k]:ho[k + 1]] for k in sel])
+    P = dict(oracle.DEFAULT_PARAMS)
+    c_o, s_o, k_o = oracle.refit(G, P, ev, sho, shc, seed[sel], dmap, prec=32)
+    assert np.array_equal(status[sel], s_o)
+    assert np.array_equal(chi2[sel].view(np.int32), c_o.view(np.int32))
+    hit_rows = np.concatenate([np.arange(ho[k], ho[k + 1]) for k in sel])
+    ok = np.repeat(s_o == 0, lens)
+    assert np.array_equal(ckpt[hit_rows][ok].view(np.int32), k_o[ok].view(np.int32))
+    # gradients of the sampled tracks' clusters: the binary64 adjoint of the
+    # GPU's own binary32 trajectory (element-wise) and the binary64 fit
+    # (norm-wise), as in the small-size refit tests
+    w64 = w[sel].astype(np.float64)
+    _, _, _, rx, ry, rz = oracle.refit_grad(G, P, ev, sho, shc, seed[sel], dmap, w64)
+    _, _, _, sx, sy, sz = oracle.refit_grad(G, P, ev, sho, shc, seed[sel], dmap, w64,
+                                            ckpt=ckpt[hit_rows], status=status[sel])
+    cl = shc[np.repeat(s_o == 0, lens)]
+    for name, g, r, s_ in (("x", gx, rx, sx), ("y", gy, ry, sy), ("z", gz, rz, sz)):
+        a, ref, own = g[cl].astype(np.float64), r[cl], s_[cl]
+        nrm = np.linalg.norm(a - ref) / max(np.linalg.norm(ref), 1e-30)
+        rms = np.sqrt(np.mean(own ** 2))
+        el = float((np.abs(a - own) / np.maximum(np.abs(own), 1e-2 * rms + 1e-30)).max())
+        _say(f"[full] refit grad {name}: norm-wise {nrm:.2e}, element-wise {el:.2e}")
+        assert nrm <= 1e-3 and el <= 1e-6
+    assert np.isfinite(gmap.cpu().numpy()).all()
