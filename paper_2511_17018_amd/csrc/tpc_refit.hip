@@ -47,15 +47,30 @@ __global__ __launch_bounds__(kBlock) void k_refit_fwd(Consts k, RefitBufs b)
   store_ckpt(b.ckpt + a * 20, st);
   float xprev = b.x[c] + b.dmap[(int)b.row[c] * kPhi + b.sector[c] % kPhi];
   float chi2 = 0.0f;
+  // software pipeline over the hits: the cluster index is loaded two hits
+  // ahead and the cluster's data one hit ahead, so that their gathers overlap
+  // the propagation and update of the current hit
+  int32_t cn = a + 1 < e ? b.hit_clu[a + 1] : 0;   // index of hit h
+  int32_t cnn = a + 2 < e ? b.hit_clu[a + 2] : 0;  // index of hit h + 1
+  float xn = b.x[cn], yn = b.y[cn], zn = b.z[cn];
+  int rown = b.row[cn], secn = b.sector[cn];
   for (int64_t h = a + 1; h < e; h++) {
-    c = b.hit_clu[h];
-    const float xk = b.x[c] + b.dmap[(int)b.row[c] * kPhi + b.sector[c] % kPhi];
+    const float xk = xn + b.dmap[rown * kPhi + secn % kPhi];
+    const float yk = yn, zk = zn;
+    if (h + 1 < e) {
+      xn = b.x[cnn];
+      yn = b.y[cnn];
+      zn = b.z[cnn];
+      rown = b.row[cnn];
+      secn = b.sector[cnn];
+      cnn = h + 2 < e ? b.hit_clu[h + 2] : 0;
+    }
     if (!kprop(st, xprev, xk, kB, smax)) {
       b.chi2[t] = 0.0f;
       b.status[t] = 1;
       return;
     }
-    chi2 += kupdate(st, b.y[c], b.z[c], vy, vz);
+    chi2 += kupdate(st, yk, zk, vy, vz);
     store_ckpt(b.ckpt + h * 20, st);
     xprev = xk;
   }
