@@ -161,12 +161,19 @@ __device__ __forceinline__ R prop_backward(const R* p, const PRec& q, R kB, R* p
   return dxb;
 }
 
-// adjoint of the R9 update at predicted state pp, covariance C
-__device__ __forceinline__ void update_backward(const R* pp, const R (&C)[5][5], R my,
-                                                R mz, R vy, R vz, R chib, R* pb,
-                                                R (&Xb)[5][5], R* mb)
+// Symmetric 5x5 matrices are held as their 15 lower-triangle entries
+// (row-major, the checkpoint's covariance order).
+__device__ __forceinline__ constexpr int si(int i, int j)
 {
-  const R S00 = C[0][0] + vy, S01 = C[0][1], S11 = C[1][1] + vz;
+  return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+}
+
+// adjoint of the R9 update at predicted state pp, covariance C (symmetric);
+// X is the symmetric adjoint of the covariance, updated in place
+__device__ __forceinline__ void update_backward(const R* pp, const R* C, R my, R mz, R vy, R vz,
+                                                R chib, R* pb, R* X, R* mb)
+{
+  const R S00 = C[si(0, 0)] + vy, S01 = C[si(0, 1)], S11 = C[si(1, 1)] + vz;
   const R det = S00 * S11 - S01 * S01;
   const R idet = 1.0 / det;
   const R Si[2][2] = {{S11 * idet, -S01 * idet}, {-S01 * idet, S00 * idet}};
@@ -175,7 +182,7 @@ __device__ __forceinline__ void update_backward(const R* pp, const R (&C)[5][5],
 #pragma unroll
   for (int i = 0; i < 5; i++)
 #pragma unroll
-    for (int a = 0; a < 2; a++) K[i][a] = C[i][0] * Si[0][a] + C[i][1] * Si[1][a];
+    for (int a = 0; a < 2; a++) K[i][a] = C[si(i, 0)] * Si[0][a] + C[si(i, 1)] * Si[1][a];
   const R w[2] = {Si[0][0] * r[0] + Si[0][1] * r[1], Si[1][0] * r[0] + Si[1][1] * r[1]};
   R Ub[5][2], Sib[2][2], rb[2] = {0.0, 0.0}, Utp[2] = {0.0, 0.0};
   // C_out = C - U Si U^T  (U = C[:, 0:2], U Si = K)
@@ -185,7 +192,7 @@ __device__ __forceinline__ void update_backward(const R* pp, const R (&C)[5][5],
     for (int a = 0; a < 2; a++) {
       R s = 0.0;
 #pragma unroll
-      for (int j = 0; j < 5; j++) s += Xb[i][j] * K[j][a];
+      for (int j = 0; j < 5; j++) s += X[si(i, j)] * K[j][a];
       Ub[i][a] = -2.0 * s + pb[i] * w[a];  // ... + the p_out = p + U w term
     }
   R XU[5][2];
@@ -195,14 +202,14 @@ __device__ __forceinline__ void update_backward(const R* pp, const R (&C)[5][5],
     for (int a = 0; a < 2; a++) {
       R s = 0.0;
 #pragma unroll
-      for (int j = 0; j < 5; j++) s += Xb[i][j] * C[j][a];
+      for (int j = 0; j < 5; j++) s += X[si(i, j)] * C[si(j, a)];
       XU[i][a] = s;
     }
 #pragma unroll
   for (int i = 0; i < 5; i++)
 #pragma unroll
     for (int a = 0; a < 2; a++) {
-      Utp[a] += C[i][a] * pb[i];
+      Utp[a] += C[si(i, a)] * pb[i];
       rb[a] += K[i][a] * pb[i];
     }
 #pragma unroll
@@ -211,7 +218,7 @@ __device__ __forceinline__ void update_backward(const R* pp, const R (&C)[5][5],
     for (int bq = 0; bq < 2; bq++) {
       R s = 0.0;
 #pragma unroll
-      for (int i = 0; i < 5; i++) s += C[i][a] * XU[i][bq];
+      for (int i = 0; i < 5; i++) s += C[si(i, a)] * XU[i][bq];
       Sib[a][bq] = -s + Utp[a] * r[bq] + chib * r[a] * r[bq];
     }
 #pragma unroll
@@ -226,18 +233,14 @@ __device__ __forceinline__ void update_backward(const R* pp, const R (&C)[5][5],
   for (int a = 0; a < 2; a++)
 #pragma unroll
     for (int bq = 0; bq < 2; bq++) Smb[a][bq] = -(T[a][0] * Si[0][bq] + T[a][1] * Si[1][bq]);
-  Xb[0][0] += Smb[0][0];
-  Xb[1][1] += Smb[1][1];
-  const R s01 = 0.5 * (Smb[0][1] + Smb[1][0]);
-  Xb[0][1] += s01;
-  Xb[1][0] += s01;
+  // symmetric adjoint of S and of U (each off-diagonal pair shares its entry)
+  X[si(0, 0)] += Smb[0][0] + Ub[0][0];
+  X[si(1, 1)] += Smb[1][1] + Ub[1][1];
+  X[si(1, 0)] += 0.5 * (Smb[0][1] + Smb[1][0]) + 0.5 * (Ub[1][0] + Ub[0][1]);
 #pragma unroll
-  for (int i = 0; i < 5; i++)
+  for (int i = 2; i < 5; i++)
 #pragma unroll
-    for (int a = 0; a < 2; a++) {
-      Xb[i][a] += 0.5 * Ub[i][a];
-      Xb[a][i] += 0.5 * Ub[i][a];
-    }
+    for (int a = 0; a < 2; a++) X[si(i, a)] += 0.5 * Ub[i][a];
   mb[0] = rb[0];
   mb[1] = rb[1];
   pb[0] -= rb[0];
@@ -278,11 +281,9 @@ __global__ __launch_bounds__(kBlock) void k_refit_bwd(Consts k, RefitBufs b)
   // binary64 throughout: the checkpoints (binary32) are widened on load
   const R kB = -0.299792458e-2 * (R)k.bz, vy = k.vy, vz = k.vz, w = b.grad_chi2[t];
   R pb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  R Xb[5][5];
+  R X[15];  // symmetric covariance adjoint
 #pragma unroll
-  for (int i = 0; i < 5; i++)
-#pragma unroll
-    for (int j = 0; j < 5; j++) Xb[i][j] = 0.0;
+  for (int i = 0; i < 15; i++) X[i] = 0.0;
   R gXn = 0.0;
   int32_t c = b.hit_clu[e - 1];
   int cell = (int)b.row[c] * kPhi + b.sector[c] % kPhi;
@@ -291,64 +292,65 @@ __global__ __launch_bounds__(kBlock) void k_refit_bwd(Consts k, RefitBufs b)
     const int32_t cp = b.hit_clu[h - 1];
     const int cellp = (int)b.row[cp] * kPhi + b.sector[cp] % kPhi;
     const R X1 = (R)b.x[cp] + (R)b.dmap[cellp];
-    // checkpoint h-1
+    // checkpoint h-1: state and covariance (lower triangle, row-major)
     const float4* q4 = reinterpret_cast<const float4*>(b.ckpt + (h - 1) * 20);
     const float4 v0 = q4[0], v1 = q4[1], v2 = q4[2], v3 = q4[3], v4 = q4[4];
     const R p0[5] = {v0.x, v0.y, v0.z, v0.w, v1.x};
-    const R c15[15] = {v1.y, v1.z, v1.w, v2.x, v2.y, v2.z, v2.w, v3.x,
-                           v3.y, v3.z, v3.w, v4.x, v4.y, v4.z, v4.w};
-    R C0[5][5];
+    const R C0[15] = {v1.y, v1.z, v1.w, v2.x, v2.y, v2.z, v2.w, v3.x,
+                      v3.y, v3.z, v3.w, v4.x, v4.y, v4.z, v4.w};
+    // the Jacobian F = I + E has six off-identity entries: (0,2) a, (0,4) b,
+    // (1,2) d, (1,3) e, (1,4) gq, (2,4) hq
+    R Ea, Eb, Ed, Ee, Egq, Ehq, pp[5];
+    {
+      PRec q;
+      prop_record(p0, X2 - X1, kB, q);
+      Ea = q.a;
+      Eb = q.b;
+      Ed = q.d;
+      Ee = q.e;
+      Egq = q.gq;
+      Ehq = q.hq;
+      pp[0] = p0[0] + q.dy;
+      pp[1] = p0[1] + p0[3] * q.ds;
+      pp[2] = q.s2;
+      pp[3] = p0[3];
+      pp[4] = p0[4];
+    }
+    // predicted covariance F C0 F^T: rows 0-2 of B = F C0, then B F^T
+    R B[3][5];
 #pragma unroll
-    for (int i = 0; i < 5; i++)
+    for (int j = 0; j < 5; j++) {
+      B[0][j] = C0[si(0, j)] + Ea * C0[si(2, j)] + Eb * C0[si(4, j)];
+      B[1][j] = C0[si(1, j)] + Ed * C0[si(2, j)] + Ee * C0[si(3, j)] + Egq * C0[si(4, j)];
+      B[2][j] = C0[si(2, j)] + Ehq * C0[si(4, j)];
+    }
+    R Cp[15];
 #pragma unroll
-      for (int j = 0; j <= i; j++) C0[i][j] = C0[j][i] = c15[i * (i + 1) / 2 + j];
-    PRec q;
-    prop_record(p0, X2 - X1, kB, q);
-    R F[5][5];
+    for (int i = 0; i < 5; i++) {
+      // row i of B (rows 3, 4 are those of C0)
+      R Bi[5];
 #pragma unroll
-    for (int i = 0; i < 5; i++)
-#pragma unroll
-      for (int j = 0; j < 5; j++) F[i][j] = i == j ? 1.0 : 0.0;
-    F[0][2] = q.a;
-    F[0][4] = q.b;
-    F[1][2] = q.d;
-    F[1][3] = q.e;
-    F[1][4] = q.gq;
-    F[2][4] = q.hq;
-    // predicted covariance F C0 F^T and state
-    R FC[5][5], Cp[5][5];
-#pragma unroll
-    for (int i = 0; i < 5; i++)
-#pragma unroll
-      for (int j = 0; j < 5; j++) {
-        R s = 0.0;
-#pragma unroll
-        for (int m = 0; m < 5; m++) s += F[i][m] * C0[m][j];
-        FC[i][j] = s;
-      }
-#pragma unroll
-    for (int i = 0; i < 5; i++)
-#pragma unroll
-      for (int j = 0; j < 5; j++) {
-        R s = 0.0;
-#pragma unroll
-        for (int m = 0; m < 5; m++) s += FC[i][m] * F[j][m];
-        Cp[i][j] = s;
-      }
-    const R pp[5] = {p0[0] + q.dy, p0[1] + p0[3] * q.ds, q.s2, p0[3], p0[4]};
+      for (int m = 0; m < 5; m++) Bi[m] = i < 3 ? B[i < 3 ? i : 0][m] : C0[si(i, m)];
+      Cp[si(i, 0)] = Bi[0] + Ea * Bi[2] + Eb * Bi[4];
+      if (i >= 1) Cp[si(i, 1)] = Bi[1] + Ed * Bi[2] + Ee * Bi[3] + Egq * Bi[4];
+      if (i >= 2) Cp[si(i, 2)] = Bi[2] + Ehq * Bi[4];
+      if (i >= 3) Cp[si(i, 3)] = Bi[3];
+      if (i >= 4) Cp[si(i, 4)] = Bi[4];
+    }
     R mb[2];
-    update_backward(pp, Cp, (R)b.y[c], (R)b.z[c], vy, vz, w, pb, Xb, mb);
-    // covariance part of the propagation: Xn = F^T X F, Fb = 2 (X F C0)
+    update_backward(pp, Cp, (R)b.y[c], (R)b.z[c], vy, vz, w, pb, X, mb);
+    // covariance part of the propagation: XF = X F, Fb = 2 (X F C0) at the
+    // entries of E, X <- F^T X F
     R XF[5][5];
 #pragma unroll
-    for (int i = 0; i < 5; i++)
-#pragma unroll
-      for (int j = 0; j < 5; j++) {
-        R s = 0.0;
-#pragma unroll
-        for (int m = 0; m < 5; m++) s += Xb[i][m] * F[m][j];
-        XF[i][j] = s;
-      }
+    for (int i = 0; i < 5; i++) {
+      const R x0 = X[si(i, 0)], x1 = X[si(i, 1)], x2 = X[si(i, 2)];
+      XF[i][0] = x0;
+      XF[i][1] = x1;
+      XF[i][2] = x2 + Ea * x0 + Ed * x1;
+      XF[i][3] = X[si(i, 3)] + Ee * x1;
+      XF[i][4] = X[si(i, 4)] + Eb * x0 + Egq * x1 + Ehq * x2;
+    }
     R Fb[6];
     {
       const int fi[6] = {0, 0, 1, 1, 1, 2}, fj[6] = {2, 4, 2, 3, 4, 4};
@@ -356,20 +358,31 @@ __global__ __launch_bounds__(kBlock) void k_refit_bwd(Consts k, RefitBufs b)
       for (int u = 0; u < 6; u++) {
         R s = 0.0;
 #pragma unroll
-        for (int m = 0; m < 5; m++) s += XF[fi[u]][m] * C0[m][fj[u]];
+        for (int m = 0; m < 5; m++) s += XF[fi[u]][m] * C0[si(m, fj[u])];
         Fb[u] = 2.0 * s;
       }
     }
+    // F^T XF, lower triangle (row i of F^T XF adds the E entries of column i)
 #pragma unroll
     for (int i = 0; i < 5; i++)
 #pragma unroll
-      for (int j = 0; j < 5; j++) {
-        R s = 0.0;
-#pragma unroll
-        for (int m = 0; m < 5; m++) s += F[m][i] * XF[m][j];
-        Xb[i][j] = s;
+      for (int j = 0; j <= i; j++) {
+        R v = XF[i][j];
+        if (i == 2) v += Ea * XF[0][j] + Ed * XF[1][j];
+        if (i == 3) v += Ee * XF[1][j];
+        if (i == 4) v += Eb * XF[0][j] + Egq * XF[1][j] + Ehq * XF[2][j];
+        X[si(i, j)] = v;
       }
-    const R dxb = prop_backward(p0, q, kB, pb, Fb);
+    // the scalar chain of the propagation (its record rebuilt here, so that
+    // it is not held through the covariance part; the empty asm statements
+    // make the inputs opaque, so the compiler rebuilds instead of keeping the
+    // first record)
+    R dxr = X2 - X1;
+    R pr[5] = {p0[0], p0[1], p0[2], p0[3], p0[4]};
+    asm volatile("" : "+v"(dxr), "+v"(pr[2]), "+v"(pr[3]), "+v"(pr[4]));
+    PRec q;
+    prop_record(pr, dxr, kB, q);
+    const R dxb = prop_backward(pr, q, kB, pb, Fb);
     const R gX = dxb + gXn;
     b.gx[c] = (float)gX;
     b.gy[c] = (float)mb[0];
