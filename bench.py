@@ -86,16 +86,19 @@ def kernel_bytes(name: str, c: dict) -> float | None:
     """Algorithmic bytes one launch of `name` must move (per-unit figures
     times the units of the launch; see the design notes)."""
     N, S, Ht, E = c["N"], c["S"], c["Ht"], c["E"]
+    R = 152
     table = {
         "grid_stats": 14 * N,                 # y, z, row in; segment id out
-        "grid_hist": 12 * N + 8 * N,          # segment id, y, z in; bin counter RMW
-        "grid_scatter": 12 * N + 8 * N + 16 * N,
-        "grid_binsort": 24 * N,
+        "grid_part": 24 * N,                  # segment id, y, z in; index, y, z out
+        "grid_seg": 28 * N + 4 * c.get("bins", 0),  # partitioned in; position data, bins out
         "neighbours": 24 * N + 8 * N,         # own + two neighbour rows' y,z; links out
         "clean": 16 * N + 8 * N,
         "tracklets": 4 * S + 16 * Ht + 8 * E + 88 * S,
-        "sel_mark": 4 * Ht + 16 * Ht,
-        "sel_count": 4 * Ht + 8 * Ht,
+        "sel_keys": 8 * S,
+        # every hit slot of every row, the keys of the hits, ownership bytes
+        # out, the rows' owner keys out
+        "sel_rows": 4 * R * S + 8 * Ht + R * S + 8 * N,
+        "sel_count": Ht,
         # refit, per track-hit: hit index 4, cluster x,y,z 12, row 2, sector 1,
         # checkpoint 80 (written forward, read backward), gradient x,y,z 12
         "refit_fwd": 99 * c.get("Hr", 0),
@@ -182,7 +185,7 @@ def run(args) -> dict:
     i32 = torch.int32
     nhit = ws.view("tl_nhit", i32, cap)[:S].to(torch.int64).sum().item()
     ncand = ws.view("tl_ncand", i32, cap)[:S].to(torch.int64).sum().item()
-    counts = dict(N=N, S=S, Ht=nhit, E=ncand)
+    counts = dict(N=N, S=S, Ht=nhit, E=ncand, bins=int(res["n_bins"]))
     dom = max(ktimes.items(), key=lambda kv: kv[1][0])
     name, (tot_ms, launches) = dom
     avg_s = tot_ms / launches / 1e3
