@@ -165,6 +165,15 @@ def run(args) -> dict:
     res = det_c.result()
     if int(res["overflow"]) or int(res["n_bad"]):
         raise RuntimeError(f"unexpected status {res}")
+    # the same chain with the generic kernels (settings as kernel arguments)
+    # instead of those compiled for the standard configuration
+    gen_c = Chain(geom, batch, True, stream, generic=True, **tp)
+    dt_gen = timed(gen_c.enqueue, args.steps, args.warmup, "batched det, generic kernels")
+    out["standard_kernels"] = {"used": tpc.standard_configuration(geom, det_c.params),
+                               "generic_ms_per_step": dt_gen * 1e3,
+                               "standard_ms_per_step": dt_eager * 1e3,
+                               "generic_over_standard_time": dt_gen / dt_eager}
+    del gen_c
     graph = GraphChain([det_c], stream)
     dt_det = timed(graph.replay, args.steps, args.warmup, "batched det (graph)")
     out["batched_eager"] = {"value": N / dt_eager, "ms_per_step": dt_eager * 1e3}
@@ -468,8 +477,8 @@ def main():
                    "path": "batched+graph", "input_sha256": r["sha"]},
         "roofline": r["roofline"],
     }
-    for k in ("batched_eager", "autotune", "plain", "prod", "result", "quality", "h2d",
-              "copy_ceiling", "kernels_ms_per_step", "kernels_sum_ms_per_step"):
+    for k in ("batched_eager", "autotune", "standard_kernels", "plain", "prod", "result",
+              "quality", "h2d", "copy_ceiling", "kernels_ms_per_step", "kernels_sum_ms_per_step"):
         if k in r:
             line[k] = r[k]
     if not args.no_cpu:

@@ -60,7 +60,9 @@ typedef enum {
 enum {
   TPC_FLAG_DETERMINISTIC = 1u, /* contraction-free code object + ordering kernels (Sec. 2) */
   TPC_FLAG_PERSISTENT = 2u,    /* reserved for work-queue kernels                         */
-  TPC_FLAG_GRAPH = 4u          /* reserved for graph-captured chains                      */
+  TPC_FLAG_GRAPH = 4u,         /* reserved for graph-captured chains                      */
+  TPC_FLAG_GENERIC = 8u        /* never use the kernels compiled for the standard
+                                  configuration (results are the same; for measuring) */
 };
 
 /* Detector description (host, by pointer).  n_rows must be 152; row_x are
@@ -177,6 +179,15 @@ typedef struct {
 
 void tpc_default_params(tpc_params* p);
 const char* tpc_status_string(tpc_status s);
+
+/* 1 if tpc_sector_track would run the kernels compiled for the standard
+ * configuration (the synthetic detector description -- 152 planes at
+ * 85 + r*162/151 cm, B = 0.5 T, tan(10 deg), sigma^2 = 0.01 / 0.0225 cm^2 --
+ * with the default parameters, grid_occupancy and tl_chunk aside, and
+ * TPC_FLAG_GENERIC clear), 0 if it would run the generic ones, TPC_ERR_INVALID
+ * for a null argument.  Both give the same results; the compile-time
+ * constants are the analogue of the paper's run-time compilation (Sec. 5). */
+int32_t tpc_standard_configuration(const tpc_geometry* geom, const tpc_params* params);
 
 /* Size queries (no device work).  cap_tracklets <= 0 selects the proven
  * bound n_clusters/3 + n_inst (every start hit heads a disjoint chain of at

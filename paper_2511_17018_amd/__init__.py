@@ -20,6 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtpcca.so")
 N_ROWS = 152
 FLAG_DETERMINISTIC = 1
+FLAG_GENERIC = 8
 
 _lib = None
 
@@ -39,7 +40,15 @@ def lib() -> C.CDLL:
         _lib.tpc_track_workspace_layout.restype = C.c_int
         _lib.tpc_grid_build.restype = C.c_int
         _lib.tpc_sector_track.restype = C.c_int
+        _lib.tpc_standard_configuration.restype = C.c_int32
     return _lib
+
+
+def standard_configuration(geom: dict, params: Params) -> bool:
+    """Whether sector tracking runs the kernels compiled for the standard
+    configuration (same results as the generic ones)."""
+    g = make_geometry(geom)
+    return lib().tpc_standard_configuration(C.byref(g), C.byref(params)) == 1
 
 
 class Geometry(C.Structure):
@@ -109,12 +118,16 @@ def make_geometry(geom: dict) -> Geometry:
     return g
 
 
-def make_params(det: bool = True, **over) -> Params:
+def make_params(det: bool = True, generic: bool = False, **over) -> Params:
+    """Default parameters with overrides; `generic` keeps the library from
+    using its kernels compiled for the standard configuration."""
     p = Params()
     lib().tpc_default_params(C.byref(p))
     for k, v in over.items():
         setattr(p, k, v)
     p.flags = (p.flags | FLAG_DETERMINISTIC) if det else (p.flags & ~FLAG_DETERMINISTIC)
+    if generic:
+        p.flags |= FLAG_GENERIC
     return p
 
 

@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include "tpc_defaults.h"
 #include "tpc_internal.h"
 
 using namespace tpcca;
@@ -154,6 +155,16 @@ Consts make_consts(const tpc_geometry* g, const tpc_params* p)
   return k;
 }
 
+// A call's constants equal the standard configuration's bit for bit (the
+// performance-only fields aside): the kernels instantiated for it may run.
+bool is_standard(const Consts& k)
+{
+  Consts a = k;
+  a.grid_occupancy = kStdConsts.grid_occupancy;
+  a.tl_chunk = kStdConsts.tl_chunk;
+  return memcmp(&a, &kStdConsts, sizeof(Consts)) == 0;
+}
+
 template <class T>
 T* at(void* base, int64_t off)
 {
@@ -182,6 +193,13 @@ void tpc_default_params(tpc_params* p)
   p->min_track_hits = 10;
   p->flags = 0;
   p->tl_chunk = 0;
+}
+
+int32_t tpc_standard_configuration(const tpc_geometry* geom, const tpc_params* params)
+{
+  if (!geom || !params) return TPC_ERR_INVALID;
+  if (geom->n_rows != kRows) return 0;
+  return !(params->flags & TPC_FLAG_GENERIC) && is_standard(make_consts(geom, params)) ? 1 : 0;
 }
 
 const char* tpc_status_string(tpc_status s)
@@ -338,8 +356,9 @@ tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, 
   b.res = result_dev;
   const Consts k = make_consts(geom, params);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = (params->flags & TPC_FLAG_DETERMINISTIC) ? det::sector_track(k, b, s)
-                                                           : prod::sector_track(k, b, s);
+  const bool std_cfg = !(params->flags & TPC_FLAG_GENERIC) && is_standard(k);
+  hipError_t e = (params->flags & TPC_FLAG_DETERMINISTIC) ? det::sector_track(k, b, std_cfg, s)
+                                                           : prod::sector_track(k, b, std_cfg, s);
   return e == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 

@@ -125,7 +125,8 @@ int64_t scan_partials(int64_t n);
 #define TPCCA_DECLARE_LAUNCHERS(NS)                                                  \
   namespace NS {                                                                     \
   hipError_t grid_build(const Consts& k, const GridBufs& b, hipStream_t s);         \
-  hipError_t sector_track(const Consts& k, const TrackBufs& b, hipStream_t s);      \
+  hipError_t sector_track(const Consts& k, const TrackBufs& b, bool standard,       \
+                          hipStream_t s);                                            \
   hipError_t refit_forward(const Consts& k, const RefitBufs& b, hipStream_t s);     \
   }
 

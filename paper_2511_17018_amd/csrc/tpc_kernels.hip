@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <climits>
 
+#include "tpc_defaults.h"
 #include "tpc_internal.h"
 
 #ifndef TPC_NS
@@ -36,6 +37,15 @@ constexpr int kStatItems = 1024;                // clusters per block in the row
 enum { CNT_START = 0, CNT_TRACKS = 1, CNT_CHUNKS = 2 };
 
 // ------------------------------------------------------------------ helpers
+
+// The constants a kernel reads: its arguments, or -- in the instantiation
+// for the standard configuration -- the compile-time copy.
+template <bool SPEC>
+__device__ __forceinline__ const Consts& kconsts(const Consts& arg)
+{
+  if constexpr (SPEC) return kStdConsts;
+  else return arg;
+}
 
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
@@ -809,8 +819,10 @@ __device__ __forceinline__ void nf_search_lists(const Consts& k, const TrackBufs
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_neighbours(Consts k, TrackBufs b)
+template <bool SPEC>
+__global__ __launch_bounds__(kBlock) void k_neighbours(Consts karg, TrackBufs b)
 {
+  const Consts& k = kconsts<SPEC>(karg);
   __shared__ __align__(16) unsigned char s_up[kNfSlab];
   __shared__ __align__(16) unsigned char s_dn[kNfSlab];
   __shared__ uint16_t s_ul[kNfList][kBlock];
@@ -908,8 +920,10 @@ __device__ __forceinline__ bool is_start(const TrackBufs& b, int min_chain, int6
 }
 
 // StartHitsFinder, deterministic: tile counts, scan, ordered write.
-__global__ __launch_bounds__(kBlock) void k_start_count(Consts k, TrackBufs b, int64_t* part)
+template <bool SPEC>
+__global__ __launch_bounds__(kBlock) void k_start_count(Consts karg, TrackBufs b, int64_t* part)
 {
+  const Consts& k = kconsts<SPEC>(karg);
   int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
   int64_t s = 0;
 #pragma unroll
@@ -919,8 +933,10 @@ __global__ __launch_bounds__(kBlock) void k_start_count(Consts k, TrackBufs b, i
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kBlock) void k_start_write(Consts k, TrackBufs b, const int64_t* part)
+template <bool SPEC>
+__global__ __launch_bounds__(kBlock) void k_start_write(Consts karg, TrackBufs b, const int64_t* part)
 {
+  const Consts& k = kconsts<SPEC>(karg);
   int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
   bool f[kItems];
   int64_t s = 0;
@@ -1065,9 +1081,10 @@ __global__ __launch_bounds__(kBlock) void k_tl_chunks(TrackBufs b, int ch)
   }
 }
 
-template <int CH>
-__global__ __launch_bounds__(CH) void k_tracklets(Consts k, TrackBufs b)
+template <int CH, bool SPEC>
+__global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
 {
+  const Consts& k = kconsts<SPEC>(karg);
   constexpr int kRowLds = row_lds(CH);
   __shared__ __align__(16) unsigned char s_row[kRowLds];
   __shared__ int s_inst;
@@ -1365,8 +1382,10 @@ __device__ __forceinline__ void wave_rows(int lo, int hi, int& wlo, int& whi)
   whi = hi;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sel_count(Consts k, TrackBufs b, int32_t* own_out)
+template <bool SPEC>
+__global__ __launch_bounds__(kBlock) void k_sel_count(Consts karg, TrackBufs b, int32_t* own_out)
 {
+  const Consts& k = kconsts<SPEC>(karg);
   const int64_t S = min(b.counters[CNT_START], b.cap);
   const int64_t t = gtid();
   const int lane = threadIdx.x & 63;
@@ -1414,8 +1433,10 @@ __global__ __launch_bounds__(kBlock) void k_sel_count(Consts k, TrackBufs b, int
 #endif
 }
 
-__global__ __launch_bounds__(kBlock) void k_sel_write(Consts k, TrackBufs b, const int32_t* own_in)
+template <bool SPEC>
+__global__ __launch_bounds__(kBlock) void k_sel_write(Consts karg, TrackBufs b, const int32_t* own_in)
 {
+  const Consts& k = kconsts<SPEC>(karg);
   const int64_t S = min(b.counters[CNT_START], b.cap);
   const int64_t t = gtid();
   if (t - (threadIdx.x & 63) >= S) return;
@@ -1510,18 +1531,19 @@ hipError_t grid_build(const Consts& k, const GridBufs& b, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t sector_track(const Consts& k, const TrackBufs& b, hipStream_t s)
+template <bool SPEC>
+hipError_t sector_track_t(const Consts& k, const TrackBufs& b, hipStream_t s)
 {
   TPC_LAUNCH("track_init", 1, 64, s, k_track_init, b);
   if (b.n > 0) {
-    TPC_LAUNCH("neighbours", blocks_for(b.n), kBlock, s, k_neighbours, k, b);
+    TPC_LAUNCH("neighbours", blocks_for(b.n), kBlock, s, k_neighbours<SPEC>, k, b);
     TPC_LAUNCH("clean", blocks_for(b.n), kBlock, s, k_clean, b);
     // ordered compaction in both modes: start-list order sets the tracklet
     // kernel's memory locality, so the scan is cheaper than atomic append
     const int64_t nb = (b.n + kTile - 1) / kTile;
-    TPC_LAUNCH("start_count", (unsigned)nb, kBlock, s, k_start_count, k, b, b.scan_tmp);
+    TPC_LAUNCH("start_count", (unsigned)nb, kBlock, s, k_start_count<SPEC>, k, b, b.scan_tmp);
     TPC_LAUNCH("scan_partials", 1, 1024, s, k_scan_partials, b.scan_tmp, nb, &b.counters[CNT_START]);
-    TPC_LAUNCH("start_write", (unsigned)nb, kBlock, s, k_start_write, k, b, b.scan_tmp);
+    TPC_LAUNCH("start_write", (unsigned)nb, kBlock, s, k_start_write<SPEC>, k, b, b.scan_tmp);
   }
   TPC_LAUNCH("start_finish", 1, 1, s, k_start_finish, b);
   TPC_LAUNCH("sel_prep", blocks_for(b.n > 0 ? b.n : 1), kBlock, s, k_sel_prep, b);
@@ -1531,24 +1553,32 @@ hipError_t sector_track(const Consts& k, const TrackBufs& b, hipStream_t s)
     // chunks are at most cap / CH + n_inst; whole groups of 8 workgroups
     const int64_t ub = (b.cap + k.tl_chunk - 1) / k.tl_chunk + b.n_inst;
     const unsigned tl_blocks = (unsigned)(((ub + 7) / 8) * 8);
+    const auto kt64 = k_tracklets<64, SPEC>;
+    const auto kt128 = k_tracklets<128, SPEC>;
+    const auto kt256 = k_tracklets<256, SPEC>;
     if (k.tl_chunk == 64)
-      TPC_LAUNCH("tracklets", tl_blocks, 64, s, k_tracklets<64>, k, b);
+      TPC_LAUNCH("tracklets", tl_blocks, 64, s, kt64, k, b);
     else if (k.tl_chunk == 128)
-      TPC_LAUNCH("tracklets", tl_blocks, 128, s, k_tracklets<128>, k, b);
+      TPC_LAUNCH("tracklets", tl_blocks, 128, s, kt128, k, b);
     else
-      TPC_LAUNCH("tracklets", tl_blocks, 256, s, k_tracklets<256>, k, b);
+      TPC_LAUNCH("tracklets", tl_blocks, 256, s, kt256, k, b);
     const unsigned tblocks = blocks_for(b.cap);
     TPC_LAUNCH("sel_keys", tblocks, kBlock, s, k_sel_keys, b);
     TPC_LAUNCH("sel_rows", (unsigned)((int64_t)b.n_inst * kRows), kBlock, s, k_sel_rows, b);
-    TPC_LAUNCH("sel_count", tblocks, kBlock, s, k_sel_count, k, b, b.tl_own);
+    TPC_LAUNCH("sel_count", tblocks, kBlock, s, k_sel_count<SPEC>, k, b, b.tl_own);
 #if TPC_DET
     scan_exclusive<int64_t>(b.tsv, b.cap, &b.counters[CNT_START], &b.counters[CNT_TRACKS],
                             b.scan_tmp, s);
 #endif
-    TPC_LAUNCH("sel_write", tblocks, kBlock, s, k_sel_write, k, b, b.tl_own);
+    TPC_LAUNCH("sel_write", tblocks, kBlock, s, k_sel_write<SPEC>, k, b, b.tl_own);
   }
   TPC_LAUNCH("sel_finish", 1, 1, s, k_sel_finish, b);
   return hipGetLastError();
+}
+
+hipError_t sector_track(const Consts& k, const TrackBufs& b, bool standard, hipStream_t s)
+{
+  return standard ? sector_track_t<true>(k, b, s) : sector_track_t<false>(k, b, s);
 }
 
 }  // namespace TPC_NS

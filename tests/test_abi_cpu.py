@@ -103,3 +103,21 @@ def test_invalid_arguments_rejected_on_host(case):
                           cl, C.byref(gs), dummy, dummy, C.c_size_t(ws_bytes), C.c_void_p(0))
     want = -4 if case == "workspace" else -1
     assert st == want
+
+
+def test_standard_configuration_matches_generator_geometry():
+    # the compile-time constants equal the generator's detector description
+    # and the default parameters bit for bit; any other setting, or the
+    # generic flag, selects the generic kernels
+    g = synth.geometry()
+    assert tpc.standard_configuration(g, tpc.make_params(True))
+    assert tpc.standard_configuration(g, tpc.make_params(False))
+    assert tpc.standard_configuration(g, tpc.make_params(True, grid_occupancy=0.5, tl_chunk=64))
+    assert not tpc.standard_configuration(g, tpc.make_params(True, generic=True))
+    assert not tpc.standard_configuration(g, tpc.make_params(True, tc_max_miss=8))
+    assert not tpc.standard_configuration(g, tpc.make_params(True, nf_win_y=2.5))
+    g2 = dict(g, bz=np.float32(0.2))
+    assert not tpc.standard_configuration(g2, tpc.make_params(True))
+    g3 = dict(g, row_x=g["row_x"].copy())
+    g3["row_x"][100] = np.nextafter(g3["row_x"][100], np.float32(1e9))
+    assert not tpc.standard_configuration(g3, tpc.make_params(True))

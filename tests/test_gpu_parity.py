@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
+import paper_2511_17018_amd as tpc
 import synth
 from tests import parity
 
@@ -30,7 +31,7 @@ def _det_case(ev, **kw):
     _say(f"[det] {getattr(ev, 'name', 'custom')} n={int(ev.inst_off[-1])} inst={len(ev.inst_off) - 1}")
     run = parity.run_gpu(ev, det=True, **kw)
     g = parity.gpu_arrays(run, int(ev.inst_off[-1]))
-    po = dict(P, grid_occupancy=kw["grid_occupancy"]) if "grid_occupancy" in kw else P
+    po = dict(P, **{k: v for k, v in kw.items() if k in P})
     o = oracle.track(G, po, ev.inst_off, ev.y, ev.z, ev.row)
     errs = parity.compare_det(g, o)
     assert not errs, "\n".join(errs)
@@ -126,6 +127,23 @@ def test_det_many_tiny_instances_bit_exact():
     y = (rng.uniform(-1, 1, n) * lim).astype(np.float32)
     z = rng.uniform(-50, 50, n).astype(np.float32)
     _det_case(_arrays(y, z, row, off))
+
+
+def test_det_generic_kernels_bit_exact():
+    # the same call with the kernels compiled for the standard configuration
+    # switched off: the generic instantiations give the oracle's bits too
+    ev = synth.config2(n_tracks=800)
+    assert tpc.standard_configuration(G, tpc.make_params(True))
+    _det_case(ev, generic=True)
+
+
+def test_det_non_default_parameters_bit_exact():
+    # other algorithm settings (generic kernels), oracle at the same settings
+    ev = synth.config4(n_inst=12, n_min=300, n_max=2e4)
+    kw = dict(tc_max_miss=7, nf_win_y=2.5, nf_chi2_max=11.0, min_tracklet_hits=12,
+              min_track_hits=12, tc_chi2_pick=9.0)
+    assert not tpc.standard_configuration(G, tpc.make_params(True, **kw))
+    _det_case(ev, **kw)
 
 
 def test_det_config2_full_bit_exact():
