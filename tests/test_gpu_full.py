@@ -17,6 +17,7 @@ import oracle
 import paper_2511_17018_amd as tpc
 import synth
 from paper_2511_17018_amd.runtime import Chain
+from tests import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -30,16 +31,16 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _batched(ev):
-    batch = tpc.upload(ev.x, ev.y, ev.z, ev.row, ev.charge, ev.inst_off, "cuda")
+def _batched(ev, det=True, batch=None, keep=False):
+    batch = batch or tpc.upload(ev.x, ev.y, ev.z, ev.row, ev.charge, ev.inst_off, "cuda")
     stream = torch.cuda.current_stream()
-    ch = Chain(G, batch, True, stream, grid_occupancy=OCC, tl_chunk=CHUNK)
+    ch = Chain(G, batch, det, stream, grid_occupancy=OCC, tl_chunk=CHUNK)
     with torch.cuda.stream(stream):
         ch.enqueue()
     stream.synchronize()
     res = ch.result()
     assert int(res["overflow"]) == 0
-    return ch.outputs(), res
+    return (ch.outputs(), res, ch) if keep else (ch.outputs(), res)
 
 
 def _tracks_of(ho, hc, par, lo, hi):
@@ -139,3 +140,39 @@ def test_refit_config5_full_sampled_tracks():
         _say(f"[full] refit grad {name}: norm-wise {nrm:.2e}, element-wise {el:.2e}")
         assert nrm <= 1e-3 and el <= 1e-6
     assert np.isfinite(gmap.cpu().numpy()).all()
+
+
+def test_prod_config4_full_within_r30_bounds():
+    # production mode on the full batch: clusters assigned differently from
+    # the deterministic (oracle-exact) output below 1e-5, and the parameters
+    # of sampled kept tracklets within 1e-4 of a binary64 replay of their own
+    # hits at the 99th percentile (R30)
+    ev = synth.config4()
+    batch = tpc.upload(ev.x, ev.y, ev.z, ev.row, ev.charge, ev.inst_off, "cuda")
+    od, _ = _batched(ev, True, batch)
+    op, res, ch = _batched(ev, False, batch, keep=True)
+    frac = parity.match_tracks(op["hit_off"], op["hit_clu"], od["hit_off"], od["hit_clu"], ev.n)
+    _say(f"[full] prod: differently assigned fraction {frac:.3g}")
+    assert frac < 1e-5
+    ws, cap = ch.ws, ch.ws.layout.cap_tracklets
+    S = int(min(res["n_start"], cap))
+    i32, f32 = torch.int32, torch.float32
+    status = ws.view("tl_status", i32, cap)[:S]
+    kept = torch.nonzero(status == 0).flatten()
+    g = torch.Generator(device="cpu").manual_seed(7)
+    idx = kept[torch.randperm(len(kept), generator=g)[:3000].to(kept.device)]
+    rows = torch.arange(152, device=idx.device)
+    sub = dict(
+        tl_status=np.zeros(len(idx), np.int32),
+        start=ws.view("start", i32, cap)[idx].cpu().numpy(),
+        tl_rmin=ws.view("tl_rmin", i32, cap)[idx].cpu().numpy(),
+        tl_rmax=ws.view("tl_rmax", i32, cap)[idx].cpu().numpy(),
+        tl_par=ws.view("tl_par", f32, 5 * cap).view(5, cap)[:, idx].T.cpu().numpy(),
+        tl_hit=ws.view("tl_hit", i32, 152 * cap).view(152, cap)[rows][:, idx].T.cpu().numpy(),
+        sseg=ch.grid.sseg.cpu().numpy(),
+        ys=ch.grid.yz[:, 0].cpu().numpy(), zs=ch.grid.yz[:, 1].cpu().numpy())
+    rel = parity.replay_params(sub).max(axis=1)
+    q99 = float(np.quantile(rel, 0.99))
+    _say(f"[full] prod: parameter rel. error vs binary64 replay, {len(rel)} sampled tracklets: "
+         f"median {np.median(rel):.3g} p99 {q99:.3g} max {rel.max():.3g}")
+    assert q99 <= 1e-4 and rel.max() < 5e-2
