@@ -173,6 +173,23 @@ def test_det_edge_cases_bit_exact():
     assert g["result"]["n_bad"] == 4
 
 
+def test_det_exact_ties_bit_exact():
+    # y and z on a 0.25 cm lattice (exact in binary32: symmetric candidates
+    # give equal scores) and 150 clusters duplicated exactly (equal scores
+    # decided by the input index alone) -- the total-order tie-breaks of the
+    # neighbour finder, the tracklet search and the selection
+    rng = np.random.default_rng(9)
+    ev = synth.config1(n_tracks=200)
+    y = (np.round(ev.y * 4) / 4).astype(np.float32)
+    z = (np.round(ev.z * 4) / 4).astype(np.float32)
+    dup = rng.choice(len(y), 150, replace=False)
+    Y = np.concatenate([y, y[dup]])
+    Z = np.concatenate([z, z[dup]])
+    R = np.concatenate([ev.row, ev.row[dup]])
+    perm = rng.permutation(len(Y))
+    _det_case(_arrays(Y[perm], Z[perm], R[perm], [0, len(Y)]))
+
+
 def test_det_empty_and_tiny_batches():
     _det_case(_arrays([], [], [], [0, 0]))
     _det_case(_arrays([0.5], [1.0], [3], [0, 1]))
