@@ -99,6 +99,9 @@ def kernel_bytes(name: str, c: dict) -> float | None:
         # out, the rows' owner keys out
         "sel_rows": 4 * R * S + 8 * Ht + R * S + 8 * N,
         "sel_count": Ht,
+        # per position: owner, segment, input index; per owned hit of a
+        # track: the track record, hit list entry and cluster->track entry
+        "sel_hits": 12 * N + 40 * c.get("Hs", 0),
         # refit, per track-hit: hit index 4, cluster x,y,z 12, row 2, sector 1,
         # checkpoint 80 (written forward, read backward), gradient x,y,z 12
         "refit_fwd": 99 * c.get("Hr", 0),
@@ -194,7 +197,7 @@ def run(args) -> dict:
     i32 = torch.int32
     nhit = ws.view("tl_nhit", i32, cap)[:S].to(torch.int64).sum().item()
     ncand = ws.view("tl_ncand", i32, cap)[:S].to(torch.int64).sum().item()
-    counts = dict(N=N, S=S, Ht=nhit, E=ncand, bins=int(res["n_bins"]))
+    counts = dict(N=N, S=S, Ht=nhit, E=ncand, bins=int(res["n_bins"]), Hs=int(res["n_hits"]))
     dom = max(ktimes.items(), key=lambda kv: kv[1][0])
     name, (tot_ms, launches) = dom
     avg_s = tot_ms / launches / 1e3

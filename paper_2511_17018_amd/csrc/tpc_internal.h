@@ -82,6 +82,9 @@ struct TrackBufs {
   unsigned long long* owner;  // [n]
   unsigned long long* tl_key;  // [cap] selection key, 0 for rejected tracklets
   uint8_t* tl_owned;   // [152][cap] 1 where the tracklet owns its hit on the row
+  int32_t* own_t;      // [n] tracklet owning each position, -1 if none
+  int4* tl_rec;        // [cap][2] track record: (track, first hit, owned-row mask
+                       // words 0-1), (mask words 2-4, unused); track -1 if none
   int32_t* tl_own;     // [cap] owned hits of accepted tracklets, 0 otherwise
   int64_t* tsv;        // [cap] packed (track flag << 32 | owned hits), then its scan
   int64_t* scan_tmp;

@@ -1284,6 +1284,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_prep(TrackBufs b)
 {
   for (int64_t h = gtid(); h < b.n; h += (int64_t)gridDim.x * blockDim.x) {
     b.owner[h] = 0ull;
+    b.own_t[h] = -1;
     b.out.clu2trk[h] = -1;
   }
 }
@@ -1359,6 +1360,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_rows(TrackBufs b)
         // the atomic reads the device-coherent value on the global path
         const unsigned long long w = lds ? s_own[hv[u] - p0] : atomicMax(&b.owner[hv[u]], 0ull);
         o = w == kv[u];
+        if (o) b.own_t[hv[u]] = (int32_t)t;
       }
       O[t] = o;
     }
@@ -1367,10 +1369,10 @@ __global__ __launch_bounds__(kBlock) void k_sel_rows(TrackBufs b)
     for (int j = threadIdx.x; j < cnt; j += kBlock) b.owner[p0 + j] = s_own[j];
 }
 
-// The counting and writing kernels run one thread per tracklet and walk the
-// union of the wave's row ranges, so that the ownership bytes and hit slots
-// of one row ([row][tracklet]) are read contiguously by the wave.  Lanes
-// without a tracklet take part in the range reduction with an empty range.
+// The counting kernel runs one thread per tracklet and walks the union of
+// the wave's row ranges, so that the ownership bytes of one row ([row]
+// [tracklet]) are read contiguously by the wave.  Lanes without a tracklet
+// take part in the range reduction with an empty range.
 __device__ __forceinline__ void wave_rows(int lo, int hi, int& wlo, int& whi)
 {
 #pragma unroll
@@ -1399,12 +1401,26 @@ __global__ __launch_bounds__(kBlock) void k_sel_count(Consts karg, TrackBufs b, 
   int wlo, whi;
   wave_rows(lo, hi, wlo, whi);
   const uint8_t* O = b.tl_owned + t;
+  // owned rows as a 152-bit mask, 32 rows per word
+  uint32_t m[5];
   int own = 0;
-  for (int r = wlo; r <= whi; r++) {
-    if (r < lo || r > hi) continue;
-    own += O[(int64_t)r * b.cap];
+#pragma unroll
+  for (int w = 0; w < 5; w++) {
+    uint32_t mw = 0;
+    const int ra = max(wlo, 32 * w), rb = min(whi, 32 * w + 31);
+    for (int r = ra; r <= rb; r++) {
+      if (r < lo || r > hi) continue;
+      if (O[(int64_t)r * b.cap]) mw |= 1u << (r - 32 * w);
+    }
+    m[w] = mw;
+    own += __popc(mw);
   }
   if (own < k.min_track_hits) own = 0;
+  if (own) {
+    b.tl_rec[2 * t].z = (int)m[0];
+    b.tl_rec[2 * t].w = (int)m[1];
+    b.tl_rec[2 * t + 1] = make_int4((int)m[2], (int)m[3], (int)m[4], 0);
+  }
   const int64_t v = own ? ((int64_t)1 << 32) | own : 0;
 #if TPC_DET
   if (t < S) {
@@ -1433,68 +1449,69 @@ __global__ __launch_bounds__(kBlock) void k_sel_count(Consts karg, TrackBufs b, 
 #endif
 }
 
+// Track records, one thread per tracklet: an accepted tracklet writes its
+// track's parameters and its (track, first hit) pair into its record.
 template <bool SPEC>
 __global__ __launch_bounds__(kBlock) void k_sel_write(Consts karg, TrackBufs b, const int32_t* own_in)
 {
   const Consts& k = kconsts<SPEC>(karg);
   const int64_t S = min(b.counters[CNT_START], b.cap);
   const int64_t t = gtid();
-  if (t - (threadIdx.x & 63) >= S) return;
-  const int own = t < S ? own_in[t] : 0;
-  int64_t kk = 0, off = 0;
-  bool act = false;
+  if (t >= S) return;
+  const int own = own_in[t];
+  int64_t kk = -1, off = 0;
   if (own) {
     const int64_t v = b.tsv[t];
     kk = v >> 32;
     off = v & 0xFFFFFFFFll;
-    act = kk < b.out.cap_tracks && off + own <= b.out.cap_hits;
+    if (!(kk < b.out.cap_tracks && off + own <= b.out.cap_hits)) kk = -1;
   }
-  int lo = kRows, hi = -1;
-  if (act) {
-    const int64_t cap = b.cap;
-    lo = b.tl_rmin[t];
-    hi = b.tl_rmax[t];
+  b.tl_rec[2 * t].x = (int)kk;
+  if (kk < 0) return;
+  b.tl_rec[2 * t].y = (int)off;
+  const int64_t cap = b.cap;
 #pragma unroll
-    for (int j = 0; j < 5; j++) b.out.param[kk * 5 + j] = b.tl_par[j * cap + t];
+  for (int j = 0; j < 5; j++) b.out.param[kk * 5 + j] = b.tl_par[j * cap + t];
 #pragma unroll
-    for (int j = 0; j < 15; j++) b.out.cov[kk * 15 + j] = b.tl_cov[j * cap + t];
-    b.out.chi2[kk] = b.tl_chi2[t];
-    b.out.ndf[kk] = 2 * b.tl_nhit[t] - 5;
-    b.out.x_ref[kk] = k.row_x[lo];
-    b.out.hit_off[kk + 1] = (int32_t)(off + own);
-    // with enough capacity every track is written and the totals are the
-    // counts; only a truncated output needs the largest written index
-    const int64_t tot = b.counters[CNT_TRACKS];
-    if ((tot >> 32) > b.out.cap_tracks || (tot & 0xFFFFFFFFll) > b.out.cap_hits) {
-      atomicMax((unsigned long long*)&b.res->n_tracks, (unsigned long long)(kk + 1));
-      atomicMax((unsigned long long*)&b.res->n_hits, (unsigned long long)(off + own));
-    }
+  for (int j = 0; j < 15; j++) b.out.cov[kk * 15 + j] = b.tl_cov[j * cap + t];
+  b.out.chi2[kk] = b.tl_chi2[t];
+  b.out.ndf[kk] = 2 * b.tl_nhit[t] - 5;
+  b.out.x_ref[kk] = k.row_x[b.tl_rmin[t]];
+  b.out.hit_off[kk + 1] = (int32_t)(off + own);
+  // with enough capacity every track is written and the totals are the
+  // counts; only a truncated output needs the largest written index
+  const int64_t tot = b.counters[CNT_TRACKS];
+  if ((tot >> 32) > b.out.cap_tracks || (tot & 0xFFFFFFFFll) > b.out.cap_hits) {
+    atomicMax((unsigned long long*)&b.res->n_tracks, (unsigned long long)(kk + 1));
+    atomicMax((unsigned long long*)&b.res->n_hits, (unsigned long long)(off + own));
   }
-  int wlo, whi;
-  wave_rows(lo, hi, wlo, whi);
-  const int32_t* H = b.tl_hit + t;
-  const uint8_t* O = b.tl_owned + t;
-  int64_t j = off;
-  // four rows at a time: ownership bytes and slots, then the owned hits'
-  // input indices, loaded together
-  for (int r0 = wlo; r0 <= whi; r0 += kSelBatch) {
-    int32_t hv[kSelBatch];
+}
+
+// Hit lists and the cluster-to-track map, one thread per position: the
+// position's owner (k_sel_rows) decides, and the hit's place in its track's
+// list is the number of the track's owned rows below the position's row, so
+// every list is in ascending row order whatever the thread order.
+__global__ __launch_bounds__(kBlock) void k_sel_hits(TrackBufs b)
+{
+  const int64_t p = gtid();
+  if (p >= b.n) return;
+  const int32_t t = b.own_t[p];
+  const int32_t seg = b.sseg[p];
+  const int32_t c = b.perm[p];
+  if (t < 0) return;
+  const int4 r0 = b.tl_rec[2 * (int64_t)t];
+  const int4 r1 = b.tl_rec[2 * (int64_t)t + 1];
+  if (r0.x < 0) return;
+  const int r = seg % kRows;
+  const uint32_t m[5] = {(uint32_t)r0.z, (uint32_t)r0.w, (uint32_t)r1.x, (uint32_t)r1.y,
+                         (uint32_t)r1.z};
+  const int w = r >> 5;
+  int rank = __popc(m[0] & (w == 0 ? (1u << (r & 31)) - 1 : ~0u));
 #pragma unroll
-    for (int u = 0; u < kSelBatch; u++) {
-      const int r = r0 + u;
-      hv[u] = -1;
-      if (r >= lo && r <= hi && O[(int64_t)r * b.cap]) hv[u] = H[(int64_t)r * b.cap];
-    }
-    int32_t cv[kSelBatch];
-#pragma unroll
-    for (int u = 0; u < kSelBatch; u++) cv[u] = hv[u] >= 0 ? b.perm[hv[u]] : -1;
-#pragma unroll
-    for (int u = 0; u < kSelBatch; u++) {
-      if (hv[u] < 0) continue;
-      b.out.hit_clu[j++] = cv[u];
-      b.out.clu2trk[cv[u]] = (int32_t)kk;
-    }
-  }
+  for (int j = 1; j < 5; j++)
+    if (j <= w) rank += __popc(m[j] & (j == w ? (1u << (r & 31)) - 1 : ~0u));
+  b.out.hit_clu[(int64_t)r0.y + rank] = c;
+  b.out.clu2trk[c] = r0.x;
 }
 
 __global__ void k_sel_finish(TrackBufs b)
@@ -1571,6 +1588,7 @@ hipError_t sector_track_t(const Consts& k, const TrackBufs& b, hipStream_t s)
                             b.scan_tmp, s);
 #endif
     TPC_LAUNCH("sel_write", tblocks, kBlock, s, k_sel_write<SPEC>, k, b, b.tl_own);
+    if (b.n > 0) TPC_LAUNCH("sel_hits", blocks_for(b.n), kBlock, s, k_sel_hits, b);
   }
   TPC_LAUNCH("sel_finish", 1, 1, s, k_sel_finish, b);
   return hipGetLastError();
