@@ -371,15 +371,22 @@ __global__ void k_grid_meta2(GridBufs b)
 // segment's range of a temporary array (in any order within the segment).
 // A workgroup takes kPartItems consecutive clusters (mostly one instance),
 // counts them per segment in LDS and claims each segment's run with one
-// device atomic, so the scattered writes come in short runs.  A workgroup
-// whose clusters span more than kPartSegs segment ids claims per cluster.
+// device atomic.  The clusters are then ordered by segment in LDS and
+// written out from there, consecutive threads to consecutive slots of a
+// run, so the stores coalesce although the input order is arbitrary.  A
+// workgroup whose clusters span kPartSegs or more segment ids claims per
+// cluster and writes directly.
 constexpr int kPartPer = 8;                        // clusters per thread
 constexpr int kPartItems = kBlock * kPartPer;
 constexpr int kPartSegs = 2048;
 
 __global__ __launch_bounds__(kBlock) void k_grid_part(GridBufs b)
 {
-  __shared__ int s_cnt[kPartSegs];
+  __shared__ int s_cnt[kPartSegs];   // per segment: count, then tile offset
+  __shared__ int s_dst[kPartSegs];   // per segment: destination of tile slot 0
+  __shared__ int32_t s_idx[kPartItems];
+  __shared__ float2 s_q[kPartItems];
+  __shared__ uint16_t s_seg[kPartItems];
   __shared__ int s_smin, s_smax;
   const int tx = threadIdx.x;
   const int64_t c0 = (int64_t)blockIdx.x * kPartItems;
@@ -388,11 +395,13 @@ __global__ __launch_bounds__(kBlock) void k_grid_part(GridBufs b)
     s_smax = -1;
   }
   int seg[kPartPer], rank[kPartPer];
+  float2 q[kPartPer];
   int lmin = INT_MAX, lmax = -1;
 #pragma unroll
   for (int k = 0; k < kPartPer; k++) {
     const int64_t c = c0 + k * kBlock + tx;
     seg[k] = c < b.n ? b.cseg[c] : -1;
+    q[k] = c < b.n ? make_float2(b.y[c], b.z[c]) : make_float2(0.0f, 0.0f);
     if (seg[k] >= 0) {
       lmin = min(lmin, seg[k]);
       lmax = max(lmax, seg[k]);
@@ -406,28 +415,51 @@ __global__ __launch_bounds__(kBlock) void k_grid_part(GridBufs b)
   __syncthreads();
   const int smin = s_smin, smax = s_smax;
   if (smax < 0) return;  // no valid cluster here (uniform)
-  const bool lds = smax - smin < kPartSegs;
-  if (lds)
-    for (int j = tx; j <= smax - smin; j += kBlock) s_cnt[j] = 0;
+  if (smax - smin >= kPartSegs) {
+#pragma unroll
+    for (int k = 0; k < kPartPer; k++) {
+      if (seg[k] < 0) continue;
+      const int32_t dst = b.seg_pos[seg[k]] + atomicAdd(&b.seg_cursor[seg[k]], 1);
+      b.tmp_perm[dst] = (int32_t)(c0 + k * kBlock + tx);
+      b.tmp_yz[dst] = q[k];
+    }
+    return;
+  }
+  const int ns = smax - smin + 1;
+  for (int j = tx; j < ns; j += kBlock) s_cnt[j] = 0;
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPartPer; k++)
-    if (seg[k] >= 0)
-      rank[k] = lds ? atomicAdd(&s_cnt[seg[k] - smin], 1) : atomicAdd(&b.seg_cursor[seg[k]], 1);
+    if (seg[k] >= 0) rank[k] = atomicAdd(&s_cnt[seg[k] - smin], 1);
   __syncthreads();
-  if (lds)
-    for (int j = tx; j <= smax - smin; j += kBlock) {
-      const int n = s_cnt[j];
-      if (n) s_cnt[j] = atomicAdd(&b.seg_cursor[smin + j], n);
+  // tile offsets (exclusive scan of the counts) and each run's claim
+  int64_t carry = 0;
+  for (int j0 = 0; j0 < ns; j0 += kBlock) {
+    const int j = j0 + tx;
+    const int n = j < ns ? s_cnt[j] : 0;
+    int64_t tot;
+    const int off = (int)(carry + block_exclusive_scan(n, &tot));
+    if (j < ns) {
+      s_cnt[j] = off;
+      if (n) s_dst[j] = b.seg_pos[smin + j] + atomicAdd(&b.seg_cursor[smin + j], n) - off;
     }
+    carry += tot;
+  }
+  const int nv = (int)carry;
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPartPer; k++) {
     if (seg[k] < 0) continue;
-    const int64_t c = c0 + k * kBlock + tx;
-    const int32_t dst = b.seg_pos[seg[k]] + (lds ? s_cnt[seg[k] - smin] : 0) + rank[k];
-    b.tmp_perm[dst] = (int32_t)c;
-    b.tmp_yz[dst] = make_float2(b.y[c], b.z[c]);
+    const int slot = s_cnt[seg[k] - smin] + rank[k];
+    s_idx[slot] = (int32_t)(c0 + k * kBlock + tx);
+    s_q[slot] = q[k];
+    s_seg[slot] = (uint16_t)(seg[k] - smin);
+  }
+  __syncthreads();
+  for (int i = tx; i < nv; i += kBlock) {
+    const int32_t dst = s_dst[s_seg[i]] + i;
+    b.tmp_perm[dst] = s_idx[i];
+    b.tmp_yz[dst] = s_q[i];
   }
 }
 
@@ -441,6 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_part(GridBufs b)
 // placement (Sec. 2, run-time part), here inside the workgroup.
 constexpr int kSegBins = 8192;
 constexpr int kSegBatch = 4;
+constexpr int kSortReg = 8;
 
 __global__ __launch_bounds__(kBlock) void k_grid_seg(GridBufs b)
 {
@@ -512,10 +545,46 @@ __global__ __launch_bounds__(kBlock) void k_grid_seg(GridBufs b)
   }
 #if TPC_DET
   __syncthreads();
-  // the cursors now hold each bin's end; bin j starts where bin j-1 ends
+  // the cursors now hold each bin's end; bin j starts where bin j-1 ends.
+  // A bin of at most kSortReg entries is loaded into registers at once and
+  // sorted there (odd-even transposition network); longer bins are sorted
+  // in place.  Input indices are distinct, so the order is unique.
   for (int j = tx; j < nb; j += kBlock) {
     const int e = lds ? s_c[j] : atomicAdd(&gc[j], 0);
     const int a = j == 0 ? 0 : (lds ? s_c[j - 1] : atomicAdd(&gc[j - 1], 0));
+    const int len = e - a;
+    if (len < 2) continue;
+    if (len <= kSortReg) {
+      int32_t kp[kSortReg];
+      float2 kv[kSortReg];
+#pragma unroll
+      for (int u = 0; u < kSortReg; u++) {
+        kp[u] = u < len ? b.perm[P + a + u] : INT_MAX;
+        kv[u] = u < len ? b.yz[P + a + u] : make_float2(0.0f, 0.0f);
+      }
+#pragma unroll
+      for (int pass = 0; pass < kSortReg; pass++) {
+#pragma unroll
+        for (int u = pass & 1; u + 1 < kSortReg; u += 2) {
+          if (kp[u] > kp[u + 1]) {
+            const int32_t ti = kp[u];
+            kp[u] = kp[u + 1];
+            kp[u + 1] = ti;
+            const float2 tq = kv[u];
+            kv[u] = kv[u + 1];
+            kv[u + 1] = tq;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kSortReg; u++) {
+        if (u < len) {
+          b.perm[P + a + u] = kp[u];
+          b.yz[P + a + u] = kv[u];
+        }
+      }
+      continue;
+    }
     for (int p = P + a + 1; p < P + e; p++) {
       const int32_t kp = b.perm[p];
       const float2 kv = b.yz[p];
