@@ -1117,8 +1117,8 @@ __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b,
 // Chunks of one instance are consecutive; workgroup w runs on XCD w % 8
 // (round-robin dispatch), so the chunk index is taken from a per-XCD range
 // and an instance's rows are cached in one L2.
-// LDS bytes for one staged row: 124 per thread, so that with the kernel's
-// register use (5 waves per SIMD) LDS does not limit the resident workgroups
+// LDS bytes for one staged row: 124 per thread, so that LDS does not limit
+// the resident workgroups up to 5 waves per SIMD (20 x 64 x 124 B < 160 KB)
 constexpr int row_lds(int ch) { return ch * 124; }
 
 // first tracklet of every instance (start hits are in instance order)
@@ -1377,7 +1377,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_keys(TrackBufs b)
 // positions is reduced with device atomics on the owner array instead (still
 // claimed only by this workgroup).
 constexpr int kSelRowPos = 4096;
-constexpr int kSelBatch = 4;
+constexpr int kSelBatch = 8;
 
 __global__ __launch_bounds__(kBlock) void k_sel_rows(TrackBufs b)
 {
