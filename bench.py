@@ -73,13 +73,16 @@ def measured_traffic(kernel: str, occ: float, chunk: int) -> int | None:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     m = re.search(r"source_sha256: ([0-9a-f]{64})", text)
-    ml = re.search(r"launch: ([0-9.]+),(\d+)", text)
-    if not m or m.group(1) != h.hexdigest() or not ml:
+    if not m or m.group(1) != h.hexdigest():
         return None
-    if float(ml.group(1)) != float(occ) or int(ml.group(2)) != int(chunk):
-        return None
-    mt = re.search(rf"traffic_bytes {re.escape(kernel)}: (\d+)", text)
-    return int(mt.group(1)) if mt else None
+    # one block of traffic_bytes lines per profiled launch configuration
+    for block in re.split(r"^launch: ", text, flags=re.M)[1:]:
+        ml = re.match(r"([0-9.]+),(\d+)", block)
+        if not ml or float(ml.group(1)) != float(occ) or int(ml.group(2)) != int(chunk):
+            continue
+        mt = re.search(rf"^traffic_bytes {re.escape(kernel)}: (\d+)", block, flags=re.M)
+        return int(mt.group(1)) if mt else None
+    return None
 
 
 def kernel_bytes(name: str, c: dict) -> float | None:

@@ -31,6 +31,20 @@ def test_traffic_only_for_matching_sources_and_launch(tmp_path, monkeypatch):
     assert bench.measured_traffic("neighbours", 0.5, 64) is None
 
 
+def test_traffic_block_of_the_matching_launch(tmp_path, monkeypatch):
+    p = tmp_path / "traffic.md"
+    p.write_text(f"```\nsource_sha256: {_sources_sha()}\n"
+                 "launch: 1.0,64\ntraffic_bytes neighbours: 11\ntraffic_bytes tracklets: 12\n"
+                 "launch: 0.5,64\ntraffic_bytes neighbours: 21\n```\n")
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(p))
+    assert bench.measured_traffic("neighbours", 1.0, 64) == 11
+    assert bench.measured_traffic("tracklets", 1.0, 64) == 12
+    assert bench.measured_traffic("neighbours", 0.5, 64) == 21
+    # a kernel missing from its own block is not taken from another block
+    assert bench.measured_traffic("tracklets", 0.5, 64) is None
+    assert bench.measured_traffic("neighbours", 2.0, 64) is None
+
+
 def test_differently_assigned_counts():
     import numpy as np
     a = {"clu2trk": np.array([0, 0, 0, 1, 1, -1, 2, 2])}
