@@ -874,15 +874,33 @@ __device__ __forceinline__ void nf_search_lists(const Consts& k, const TrackBufs
       const int u = s_ul[iu][tx];
       const float2 qu = yzu[u];
       const float yu = qu.x, zu = qu.y;
+      // the batch's scores, then one candidate per batch: its smallest
+      // score (slots beyond the list score +inf); the rare exact tie of two
+      // down candidates goes through the pair order one by one
+      float sc[kNfBatch];
+      float m = INFINITY;
 #pragma unroll
       for (int j = 0; j < kNfBatch; j++) {
-        if (j < nb) {
-          const float yd = by[j], zd = bz[j];
-          const float ey = yh - (yd + (yu - yd) * t);
-          const float ez = zh - (zd + (zu - zd) * t);
-          const float sc = (ey * ey) * ivy + (ez * ez) * ivz;
-          if (sc <= cmax) nf_consider(b, best, sc, Pu + u, Pd + bi[j]);
-        }
+        const float yd = by[j], zd = bz[j];
+        const float ey = yh - (yd + (yu - yd) * t);
+        const float ez = zh - (zd + (zu - zd) * t);
+        sc[j] = j < nb ? (ey * ey) * ivy + (ez * ez) * ivz : INFINITY;
+        m = fminf(m, sc[j]);
+      }
+      if (!(m <= cmax)) continue;
+      int db = 0, ne = 0;
+#pragma unroll
+      for (int j = kNfBatch - 1; j >= 0; j--) {
+        const bool e = sc[j] == m;
+        db = e ? bi[j] : db;
+        ne += e ? 1 : 0;
+      }
+      if (ne == 1) {
+        nf_consider(b, best, m, Pu + u, Pd + db);
+      } else {
+#pragma unroll
+        for (int j = 0; j < kNfBatch; j++)
+          if (sc[j] == m) nf_consider(b, best, m, Pu + u, Pd + bi[j]);
       }
     }
   }
