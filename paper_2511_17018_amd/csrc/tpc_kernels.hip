@@ -887,7 +887,8 @@ __device__ __forceinline__ void nf_search_lists(const Consts& k, const TrackBufs
         sc[j] = j < nb ? (ey * ey) * ivy + (ez * ez) * ivz : INFINITY;
         m = fminf(m, sc[j]);
       }
-      if (!(m <= cmax)) continue;
+      // nothing here can beat the running best (scores only decrease)
+      if (!(m <= cmax) || (best.u >= 0 && m > best.s)) continue;
       int db = 0, ne = 0;
 #pragma unroll
       for (int j = kNfBatch - 1; j >= 0; j--) {
