@@ -639,20 +639,14 @@ __global__ void k_track_init(TrackBufs b)
   }
 }
 
-// NeighboursFinder (R11): best (u on r+1, d on r-1) straight-line pair.
-// A workgroup takes 256 consecutive positions and visits the row segments
-// they belong to in turn.  For segment s it stages the z-slab of rows r+1
-// and r-1 that the windows of its clusters can reach -- the z bins from
-// bin_coord(zmin - w) to bin_coord(zmax + w), whole rows of bins, with their
-// positions -- in LDS with coalesced loads (positions are in z-bin-major
-// order, so a workgroup's clusters cover a narrow z range and the slab is a
-// small part of the row).  bin_coord is monotone, so every window of the
-// segment lies inside the slab.  A slab too large for its buffer sends the
-// segment to the same search in global memory.  The pair choice is a total
-// order (score, then the input indices of u and d), so the visit order does
-// not change the result; input indices are read only on an exact tie.
-constexpr int kNfSlab = 8192;  // LDS bytes per staged slab
-
+// NeighboursFinder (R11): best (u on r+1, d on r-1) straight-line pair, one
+// thread per position.  Positions are in (segment, z bin, y bin) order, so
+// the threads of a wave search neighbouring windows of the same two rows
+// and read them from the cache; staging the rows' reachable slabs in LDS
+// first (with a workgroup loop over its segments) measured slower.  The
+// pair choice is a total order (score, then the input indices of u and d),
+// so the visit order does not change the result; input indices are read
+// only on an exact tie.
 struct NfBest {
   int32_t u = -1, d = -1;
   float s = 0.0f;
@@ -675,90 +669,13 @@ __device__ __forceinline__ void nf_consider(const TrackBufs& b, NfBest& best, fl
   }
 }
 
-// Workgroup copies global -> LDS with the loads batched: each thread issues
-// kCopyBatch independent loads before the first store, so a staged row costs
-// one memory latency per kCopyBatch elements per thread instead of one per
-// element.
-constexpr int kCopyBatch = 4;
-
-template <int NT>
-__device__ __forceinline__ void copy_offsets(int32_t* dst, const int32_t* src, int n, int32_t sub)
-{
-  for (int j0 = 0; j0 < n; j0 += NT * kCopyBatch) {
-    int32_t v[kCopyBatch];
-#pragma unroll
-    for (int u = 0; u < kCopyBatch; u++) {
-      const int j = j0 + u * NT + (int)threadIdx.x;
-      v[u] = j < n ? src[j] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < kCopyBatch; u++) {
-      const int j = j0 + u * NT + (int)threadIdx.x;
-      if (j < n) dst[j] = v[u] - sub;
-    }
-  }
-}
-
-template <int NT>
-__device__ __forceinline__ void copy_yz(float2* dst, const float2* src, int n)
-{
-  for (int j0 = 0; j0 < n; j0 += NT * kCopyBatch) {
-    float2 v[kCopyBatch];
-#pragma unroll
-    for (int u = 0; u < kCopyBatch; u++) {
-      const int j = j0 + u * NT + (int)threadIdx.x;
-      v[u] = j < n ? src[j] : make_float2(0.0f, 0.0f);
-    }
-#pragma unroll
-    for (int u = 0; u < kCopyBatch; u++) {
-      const int j = j0 + u * NT + (int)threadIdx.x;
-      if (j < n) dst[j] = v[u];
-    }
-  }
-}
-
-// A slab of one row: bins [iz0 * ny, (iz1 + 1) * ny) with their boundaries
-// relative to the slab's first position P0, then the positions.
-struct Slab {
-  int iz0, iz1;
-  int32_t P0;
-  int ob;  // byte offset of the positions
-  bool ok;
-};
-
-template <int NT>
-__device__ __forceinline__ Slab stage_slab(const TrackBufs& b, const tpc_row_meta& m, float zlo,
-                                           float zhi, unsigned char* buf, int bytes)
-{
-  Slab sl;
-  sl.iz0 = bin_coord(zlo, m.z0, m.iwz, m.nz);
-  sl.iz1 = max(bin_coord(zhi, m.z0, m.iwz, m.nz), sl.iz0);
-  const int j0 = m.bin_base + sl.iz0 * m.ny;
-  const int nb = (sl.iz1 - sl.iz0 + 1) * m.ny;  // bins; nb + 1 boundaries
-  sl.P0 = b.bin_off[j0];
-  const int cnt = b.bin_off[j0 + nb] - sl.P0;
-  const int64_t ob = ((int64_t)(nb + 1) * 4 + 7) & ~(int64_t)7;
-  sl.ok = ob + (int64_t)cnt * 8 <= bytes;
-  sl.ob = (int)(sl.ok ? ob : 0);
-  if (sl.ok) {
-    int32_t* off = (int32_t*)buf;
-    float2* yz = (float2*)(buf + ob);
-    copy_offsets<NT>(off, b.bin_off + j0, nb + 1, sl.P0);
-    copy_yz<NT>(yz, b.yz + sl.P0, cnt);
-  }
-  return sl;
-}
-
 // The pair search of cluster (yh, zh) of row r over the windows of rows
-// r+1 (mu) and r-1 (md).  offu/yzu index bins from z bin izu0 and positions
-// from Pu (the staged slab, or the whole row in global memory with izu0 = 0
-// and Pu = 0); the same for the down row.
+// r+1 (mu, bin boundaries offu) and r-1 (md, offd), nested loops over the
+// two windows (the fallback for windows longer than the lists below).
 __device__ __forceinline__ void nf_search(const Consts& k, const TrackBufs& b, NfBest& best,
                                           float yh, float zh, float t, const tpc_row_meta& mu,
-                                          const int32_t* offu, const float2* yzu, int izu0,
-                                          int32_t Pu, const tpc_row_meta& md,
-                                          const int32_t* offd, const float2* yzd, int izd0,
-                                          int32_t Pd)
+                                          const int32_t* offu, const tpc_row_meta& md,
+                                          const int32_t* offd)
 {
   const float wy = k.nf_win_y, wz = k.nf_win_z;
   const float wym = wy + k.search_margin, wzm = wz + k.search_margin;
@@ -772,47 +689,49 @@ __device__ __forceinline__ void nf_search(const Consts& k, const TrackBufs& b, N
   const int dzlo = bin_coord(zh - wzm, md.z0, md.iwz, md.nz);
   const int dzhi = bin_coord(zh + wzm, md.z0, md.iwz, md.nz);
   for (int izu = uzlo; izu <= uzhi; izu++) {
-    const int ub = (izu - izu0) * mu.ny;
+    const int ub = izu * mu.ny;
     const int ue = offu[ub + uyhi + 1];
     for (int u = offu[ub + uylo]; u < ue; u++) {
-      const float2 qu = yzu[u];
+      const float2 qu = b.yz[u];
       const float yu = qu.x, zu = qu.y;
       if (!(fabsf(yu - yh) <= wy && fabsf(zu - zh) <= wz)) continue;
       for (int izd = dzlo; izd <= dzhi; izd++) {
-        const int db = (izd - izd0) * md.ny;
+        const int db = izd * md.ny;
         const int de = offd[db + dyhi + 1];
         for (int d = offd[db + dylo]; d < de; d++) {
-          const float2 qd = yzd[d];
+          const float2 qd = b.yz[d];
           const float yd = qd.x, zd = qd.y;
           if (!(fabsf(yd - yh) <= wy && fabsf(zd - zh) <= wz)) continue;
           const float ey = yh - (yd + (yu - yd) * t);
           const float ez = zh - (zd + (zu - zd) * t);
           const float sc = (ey * ey) * ivy + (ez * ez) * ivz;
-          if (sc <= cmax) nf_consider(b, best, sc, Pu + u, Pd + d);
+          if (sc <= cmax) nf_consider(b, best, sc, u, d);
         }
       }
     }
   }
 }
 
-// Staged search: each window is scanned once into a per-thread list of slab
-// indices (thread-major in LDS), the down window first so that a cluster
-// without a down candidate skips the up window.  The pairs are then
-// evaluated with the down candidates loaded in batches into registers, so
-// the pair loop carries no dependent LDS loads.  Windows with more than
-// kNfList candidates fall back to nf_search.
+// List search: each window is scanned once into a per-thread list of
+// row-relative indices (thread-major in LDS; rows of fewer than 65536
+// positions), the down window first so that a cluster without a down
+// candidate skips the up window.  The pairs are then evaluated with the
+// down candidates loaded in batches into registers.  Windows with more than
+// kNfList candidates fall back to nf_search.  yzu = yz + Pu and yzd = yz + Pd
+// are the two rows' positions.
 constexpr int kNfList = 32;
 constexpr int kNfBatch = 8;
 
 __device__ __forceinline__ void nf_search_lists(const Consts& k, const TrackBufs& b, NfBest& best,
                                                 float yh, float zh, float t,
                                                 const tpc_row_meta& mu, const int32_t* offu,
-                                                const float2* yzu, int izu0, int32_t Pu,
-                                                const tpc_row_meta& md, const int32_t* offd,
-                                                const float2* yzd, int izd0, int32_t Pd,
+                                                int32_t Pu, const tpc_row_meta& md,
+                                                const int32_t* offd, int32_t Pd,
                                                 uint16_t (*s_ul)[kBlock], uint16_t (*s_dl)[kBlock])
 {
   const int tx = threadIdx.x;
+  const float2* const yzu = b.yz + Pu;
+  const float2* const yzd = b.yz + Pd;
   const float wy = k.nf_win_y, wz = k.nf_win_z;
   const float wym = wy + k.search_margin, wzm = wz + k.search_margin;
   const float cmax = k.nf_chi2_max, ivy = k.ivy, ivz = k.ivz;
@@ -823,9 +742,9 @@ __device__ __forceinline__ void nf_search_lists(const Consts& k, const TrackBufs
     const int zlo = bin_coord(zh - wzm, md.z0, md.iwz, md.nz);
     const int zhi = bin_coord(zh + wzm, md.z0, md.iwz, md.nz);
     for (int iz = zlo; iz <= zhi; iz++) {
-      const int bb = (iz - izd0) * md.ny;
-      const int e = offd[bb + yhi + 1];
-      for (int d = offd[bb + ylo]; d < e; d++) {
+      const int bb = iz * md.ny;
+      const int e = offd[bb + yhi + 1] - Pd;
+      for (int d = offd[bb + ylo] - Pd; d < e; d++) {
         const float2 q = yzd[d];
         if (!(fabsf(q.x - yh) <= wy && fabsf(q.y - zh) <= wz)) continue;
         if (nd < kNfList) s_dl[nd][tx] = (uint16_t)d;
@@ -841,9 +760,9 @@ __device__ __forceinline__ void nf_search_lists(const Consts& k, const TrackBufs
     const int zlo = bin_coord(zh - wzm, mu.z0, mu.iwz, mu.nz);
     const int zhi = bin_coord(zh + wzm, mu.z0, mu.iwz, mu.nz);
     for (int iz = zlo; iz <= zhi; iz++) {
-      const int bb = (iz - izu0) * mu.ny;
-      const int e = offu[bb + yhi + 1];
-      for (int u = offu[bb + ylo]; u < e; u++) {
+      const int bb = iz * mu.ny;
+      const int e = offu[bb + yhi + 1] - Pu;
+      for (int u = offu[bb + ylo] - Pu; u < e; u++) {
         const float2 q = yzu[u];
         if (!(fabsf(q.x - yh) <= wy && fabsf(q.y - zh) <= wz)) continue;
         if (nu < kNfList) s_ul[nu][tx] = (uint16_t)u;
@@ -853,7 +772,7 @@ __device__ __forceinline__ void nf_search_lists(const Consts& k, const TrackBufs
   }
   if (nu == 0) return;
   if (nu > kNfList || nd > kNfList) {
-    nf_search(k, b, best, yh, zh, t, mu, offu, yzu, izu0, Pu, md, offd, yzd, izd0, Pd);
+    nf_search(k, b, best, yh, zh, t, mu, offu, md, offd);
     return;
   }
   // down candidates in register batches of kNfBatch (static indices,
@@ -911,75 +830,30 @@ template <bool SPEC>
 __global__ __launch_bounds__(kBlock) void k_neighbours(Consts karg, TrackBufs b)
 {
   const Consts& k = kconsts<SPEC>(karg);
-  __shared__ __align__(16) unsigned char s_up[kNfSlab];
-  __shared__ __align__(16) unsigned char s_dn[kNfSlab];
   __shared__ uint16_t s_ul[kNfList][kBlock];
   __shared__ uint16_t s_dl[kNfList][kBlock];
-  __shared__ int s_smin, s_smax;
-  // z range of the current segment's clusters, double-buffered by segment
-  // parity (a wave may still read one while the next is reset)
-  __shared__ uint32_t s_zlo[2], s_zhi[2];
   const int64_t h = gtid();
-  const int tx = threadIdx.x;
-  int seg = h < b.n ? b.sseg[h] : -1;
+  if (h >= b.n) return;
+  const int seg = b.sseg[h];
   const int r = seg >= 0 ? seg % kRows : 0;
-  if (r == 0 || r == kRows - 1) seg = -1;  // no pair on the first and last row
-  float yh = 0.0f, zh = 0.0f;
-  if (seg >= 0) {
-    const float2 qh = b.yz[h];
-    yh = qh.x;
-    zh = qh.y;
-  }
-  if (tx == 0) {
-    s_smin = INT_MAX;
-    s_smax = -1;
-  }
-  __syncthreads();
-  if (seg >= 0) {
-    atomicMin(&s_smin, seg);
-    atomicMax(&s_smax, seg);
-  }
-  __syncthreads();
-  const int smin = s_smin, smax = s_smax;
-  const float wzm = k.nf_win_z + k.search_margin;
   NfBest best;
-  for (int s = smin; s <= smax; s++) {
-    const int pb = s & 1;
-    if (tx == 0) {
-      s_zlo[pb] = 0xFFFFFFFFu;
-      s_zhi[pb] = 0u;
-    }
-    __syncthreads();  // also: the previous segment's searches are done
-    const bool mine = seg == s;
-    if (mine) {
-      atomicMin(&s_zlo[pb], f2o(zh));
-      atomicMax(&s_zhi[pb], f2o(zh));
-    }
-    __syncthreads();
-    const uint32_t ozlo = s_zlo[pb], ozhi = s_zhi[pb];
-    if (ozlo > ozhi) continue;  // no cluster of this segment here (uniform)
-    const float zlo = o2f(ozlo), zhi = o2f(ozhi);
-    const int rs = s % kRows;
-    const tpc_row_meta mu = b.meta[s + 1];
-    const tpc_row_meta md = b.meta[s - 1];
-    const Slab su = stage_slab<kBlock>(b, mu, zlo - wzm, zhi + wzm, s_up, kNfSlab);
-    const Slab sd = stage_slab<kBlock>(b, md, zlo - wzm, zhi + wzm, s_dn, kNfSlab);
-    __syncthreads();
-    if (!mine) continue;
-    const float xm = k.row_x[rs - 1], x0 = k.row_x[rs], xp = k.row_x[rs + 1];
+  // no pair on the first and last row
+  if (seg >= 0 && r > 0 && r < kRows - 1) {
+    const float2 qh = b.yz[h];
+    const tpc_row_meta mu = b.meta[seg + 1];
+    const tpc_row_meta md = b.meta[seg - 1];
+    const float xm = k.row_x[r - 1], x0 = k.row_x[r], xp = k.row_x[r + 1];
     const float t = (x0 - xm) / (xp - xm);
-    if (su.ok && sd.ok)
-      nf_search_lists(k, b, best, yh, zh, t, mu, (const int32_t*)s_up,
-                      (const float2*)(s_up + su.ob), su.iz0, su.P0, md, (const int32_t*)s_dn,
-                      (const float2*)(s_dn + sd.ob), sd.iz0, sd.P0, s_ul, s_dl);
+    const int32_t* const offu = b.bin_off + mu.bin_base;
+    const int32_t* const offd = b.bin_off + md.bin_base;
+    const int32_t Pu = offu[0], Pd = offd[0];
+    if (offu[mu.ny * mu.nz] - Pu < 65536 && offd[md.ny * md.nz] - Pd < 65536)
+      nf_search_lists(k, b, best, qh.x, qh.y, t, mu, offu, Pu, md, offd, Pd, s_ul, s_dl);
     else
-      nf_search(k, b, best, yh, zh, t, mu, b.bin_off + mu.bin_base, b.yz, 0, 0, md,
-                b.bin_off + md.bin_base, b.yz, 0, 0);
+      nf_search(k, b, best, qh.x, qh.y, t, mu, offu, md, offd);
   }
-  if (h < b.n) {
-    b.up[h] = best.u;
-    b.dn[h] = best.d;
-  }
+  b.up[h] = best.u;
+  b.dn[h] = best.d;
 }
 
 // NeighboursCleaner: mutual links only (reads the uncleaned arrays).
@@ -1126,19 +1000,16 @@ __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b,
 // (row, bin) order, so a chunk's start rows form a short range; the
 // workgroup sweeps the rows upward from the lowest start row (phases 1 and
 // 2), each lane walks its state back to its start row (phase 3, no data),
-// and the workgroup sweeps downward from the highest start row.  At every
-// row of a sweep the row's bin boundaries and cluster positions are staged
-// in LDS with coalesced loads, and every lane's search reads them there; a
-// row too large for the LDS buffer is searched in global memory instead
-// (same arithmetic, same result).  Hit slots are [row][tracklet], so the
-// lanes' writes of one row are contiguous.
+// and the workgroup sweeps downward from the highest start row.  The lanes
+// of a sweep search the same row at the same time, so the row's bin
+// boundaries and cluster positions are read from the cache; the kernel is
+// bound by instruction issue, and staging each row in LDS first cost more
+// instructions than it saved.  Hit slots are [row][tracklet], so the lanes'
+// writes of one row are contiguous.
 //
 // Chunks of one instance are consecutive; workgroup w runs on XCD w % 8
 // (round-robin dispatch), so the chunk index is taken from a per-XCD range
 // and an instance's rows are cached in one L2.
-// LDS bytes for one staged row: 124 per thread, so that LDS does not limit
-// the resident workgroups up to 5 waves per SIMD (20 x 64 x 124 B < 160 KB)
-constexpr int row_lds(int ch) { return ch * 124; }
 
 // first tracklet of every instance (start hits are in instance order)
 __global__ __launch_bounds__(kBlock) void k_tl_first(TrackBufs b)
@@ -1173,8 +1044,6 @@ template <int CH, bool SPEC>
 __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
 {
   const Consts& k = kconsts<SPEC>(karg);
-  constexpr int kRowLds = row_lds(CH);
-  __shared__ __align__(16) unsigned char s_row[kRowLds];
   __shared__ int s_inst;
   const int64_t C = b.counters[CNT_CHUNKS];
   const int64_t per = (C + 7) / 8;
@@ -1194,7 +1063,6 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
   const bool mine = t < t1;
   const int64_t cap = b.cap;
   int32_t* const H = b.tl_hit + t;  // hit slot of row r at H[r * cap]
-  int32_t* const s_off = (int32_t*)s_row;
 
   const float kB = k.kB, vy = k.vy, vz = k.vz, smax = k.snp_max;
   const float edge = k.edge_margin, tanh_ = k.tan_half;
@@ -1232,17 +1100,6 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
   for (int r = rlo + 1; r < kRows; r++) {
     if (!__syncthreads_or(up)) break;
     const tpc_row_meta m = b.meta[segb + r];
-    const int nbin = m.ny * m.nz;
-    const int32_t P0 = b.bin_off[m.bin_base];
-    const int cnt = b.bin_off[m.bin_base + nbin] - P0;
-    const int64_t ob = ((int64_t)(nbin + 1) * 4 + 7) & ~(int64_t)7;
-    const bool staged = ob + (int64_t)cnt * 8 <= kRowLds;
-    float2* const s_yz = (float2*)(s_row + (staged ? ob : 0));
-    if (staged) {
-      copy_offsets<CH>(s_off, b.bin_off + m.bin_base, nbin + 1, P0);
-      copy_yz<CH>(s_yz, b.yz + P0, cnt);
-    }
-    __syncthreads();
     if (!(up && r > r0)) continue;
     if (phase == 1 && hn < 0) {
       // links exhausted at row r - 1: the phase-2 restart state is kept
@@ -1252,7 +1109,7 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
     if (!kprop(st, k.row_x[r - 1], k.row_x[r], kB, smax)) {
       up = false;
     } else if (phase == 1) {
-      const float2 qn = staged ? s_yz[hn - P0] : b.yz[hn];
+      const float2 qn = b.yz[hn];
       chi2 += kupdate(st, qn.x, qn.y, vy, vz);
       H[(int64_t)r * cap] = hn;
       n++;
@@ -1262,10 +1119,9 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
       up = false;
     } else {
       const Innov q = innov(st, vy, vz);
-      const int32_t bh = staged ? ksearch(k, b, m, s_off, s_yz, P0, st, q, ncand)
-                                : ksearch(k, b, m, b.bin_off + m.bin_base, b.yz, 0, st, q, ncand);
+      const int32_t bh = ksearch(k, b, m, b.bin_off + m.bin_base, b.yz, 0, st, q, ncand);
       if (bh >= 0) {
-        const float2 qb = staged ? s_yz[bh - P0] : b.yz[bh];
+        const float2 qb = b.yz[bh];
         chi2 += kupdate_q(st, q, qb.x, qb.y);
         H[(int64_t)r * cap] = bh;
         n++;
@@ -1298,17 +1154,6 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
   for (int r = rhi - 1; r >= 0; r--) {
     if (!__syncthreads_or(dn)) break;
     const tpc_row_meta m = b.meta[segb + r];
-    const int nbin = m.ny * m.nz;
-    const int32_t P0 = b.bin_off[m.bin_base];
-    const int cnt = b.bin_off[m.bin_base + nbin] - P0;
-    const int64_t ob = ((int64_t)(nbin + 1) * 4 + 7) & ~(int64_t)7;
-    const bool staged = ob + (int64_t)cnt * 8 <= kRowLds;
-    float2* const s_yz = (float2*)(s_row + (staged ? ob : 0));
-    if (staged) {
-      copy_offsets<CH>(s_off, b.bin_off + m.bin_base, nbin + 1, P0);
-      copy_yz<CH>(s_yz, b.yz + P0, cnt);
-    }
-    __syncthreads();
     if (!(dn && r < r0)) continue;
     if (!kprop(st, k.row_x[r + 1], k.row_x[r], kB, smax)) {
       dn = false;
@@ -1316,10 +1161,9 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
       dn = false;
     } else {
       const Innov q = innov(st, vy, vz);
-      const int32_t bh = staged ? ksearch(k, b, m, s_off, s_yz, P0, st, q, ncand)
-                                : ksearch(k, b, m, b.bin_off + m.bin_base, b.yz, 0, st, q, ncand);
+      const int32_t bh = ksearch(k, b, m, b.bin_off + m.bin_base, b.yz, 0, st, q, ncand);
       if (bh >= 0) {
-        const float2 qb = staged ? s_yz[bh - P0] : b.yz[bh];
+        const float2 qb = b.yz[bh];
         chi2 += kupdate_q(st, q, qb.x, qb.y);
         H[(int64_t)r * cap] = bh;
         n++;
