@@ -1098,7 +1098,11 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
   bool up = mine;
   int phase = 1, miss = 0;
   for (int r = rlo + 1; r < kRows; r++) {
-    if (!__syncthreads_or(up)) break;
+    if constexpr (CH == 64) {
+      if (!__ballot(up)) break;  // one wave: a vote, no barrier
+    } else {
+      if (!__syncthreads_or(up)) break;
+    }
     const tpc_row_meta m = b.meta[segb + r];
     if (!(up && r > r0)) continue;
     if (phase == 1 && hn < 0) {
@@ -1152,7 +1156,11 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
   bool dn = mine && stat == 0;
   miss = 0;
   for (int r = rhi - 1; r >= 0; r--) {
-    if (!__syncthreads_or(dn)) break;
+    if constexpr (CH == 64) {
+      if (!__ballot(dn)) break;  // one wave: a vote, no barrier
+    } else {
+      if (!__syncthreads_or(dn)) break;
+    }
     const tpc_row_meta m = b.meta[segb + r];
     if (!(dn && r < r0)) continue;
     if (!kprop(st, k.row_x[r + 1], k.row_x[r], kB, smax)) {
