@@ -722,6 +722,54 @@ __device__ __forceinline__ void nf_search(const Consts& k, const TrackBufs& b, N
 constexpr int kNfList = 32;
 constexpr int kNfBatch = 8;
 
+// One window scan into a per-thread list: the bin ranges of kNfZ z rows are
+// loaded at once, then kNfC candidates at once, so a window costs a few
+// memory latencies instead of one per z row and candidate.
+constexpr int kNfZ = 2, kNfC = 4;
+
+__device__ __forceinline__ int nf_window(const tpc_row_meta& m, const int32_t* off,
+                                         const float2* yz, int32_t P, float yh, float zh,
+                                         float wy, float wz, float wym, float wzm,
+                                         uint16_t (*list)[kBlock])
+{
+  const int tx = threadIdx.x;
+  const int ylo = bin_coord(yh - wym, m.y0, m.iwy, m.ny);
+  const int yhi = bin_coord(yh + wym, m.y0, m.iwy, m.ny);
+  const int zlo = bin_coord(zh - wzm, m.z0, m.iwz, m.nz);
+  const int zhi = bin_coord(zh + wzm, m.z0, m.iwz, m.nz);
+  int n = 0;
+  for (int z0 = zlo; z0 <= zhi; z0 += kNfZ) {
+    int ra[kNfZ], re[kNfZ];
+#pragma unroll
+    for (int u = 0; u < kNfZ; u++) {
+      ra[u] = re[u] = 0;
+      if (z0 + u <= zhi) {
+        const int bb = (z0 + u) * m.ny;
+        ra[u] = off[bb + ylo] - P;
+        re[u] = off[bb + yhi + 1] - P;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kNfZ; u++) {
+      for (int p0 = ra[u]; p0 < re[u]; p0 += kNfC) {
+        float2 qv[kNfC];
+#pragma unroll
+        for (int c = 0; c < kNfC; c++)
+          qv[c] = p0 + c < re[u] ? yz[p0 + c] : make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int c = 0; c < kNfC; c++) {
+          if (p0 + c >= re[u]) continue;
+          if (!(fabsf(qv[c].x - yh) <= wy && fabsf(qv[c].y - zh) <= wz)) continue;
+          if (n < kNfList) list[n][tx] = (uint16_t)(p0 + c);
+          n++;
+        }
+      }
+    }
+  }
+  return n;
+}
+
+// The list search of cluster (yh, zh) of row r (see above).
 __device__ __forceinline__ void nf_search_lists(const Consts& k, const TrackBufs& b, NfBest& best,
                                                 float yh, float zh, float t,
                                                 const tpc_row_meta& mu, const int32_t* offu,
@@ -735,41 +783,9 @@ __device__ __forceinline__ void nf_search_lists(const Consts& k, const TrackBufs
   const float wy = k.nf_win_y, wz = k.nf_win_z;
   const float wym = wy + k.search_margin, wzm = wz + k.search_margin;
   const float cmax = k.nf_chi2_max, ivy = k.ivy, ivz = k.ivz;
-  int nd = 0;
-  {
-    const int ylo = bin_coord(yh - wym, md.y0, md.iwy, md.ny);
-    const int yhi = bin_coord(yh + wym, md.y0, md.iwy, md.ny);
-    const int zlo = bin_coord(zh - wzm, md.z0, md.iwz, md.nz);
-    const int zhi = bin_coord(zh + wzm, md.z0, md.iwz, md.nz);
-    for (int iz = zlo; iz <= zhi; iz++) {
-      const int bb = iz * md.ny;
-      const int e = offd[bb + yhi + 1] - Pd;
-      for (int d = offd[bb + ylo] - Pd; d < e; d++) {
-        const float2 q = yzd[d];
-        if (!(fabsf(q.x - yh) <= wy && fabsf(q.y - zh) <= wz)) continue;
-        if (nd < kNfList) s_dl[nd][tx] = (uint16_t)d;
-        nd++;
-      }
-    }
-  }
+  const int nd = nf_window(md, offd, yzd, Pd, yh, zh, wy, wz, wym, wzm, s_dl);
   if (nd == 0) return;
-  int nu = 0;
-  {
-    const int ylo = bin_coord(yh - wym, mu.y0, mu.iwy, mu.ny);
-    const int yhi = bin_coord(yh + wym, mu.y0, mu.iwy, mu.ny);
-    const int zlo = bin_coord(zh - wzm, mu.z0, mu.iwz, mu.nz);
-    const int zhi = bin_coord(zh + wzm, mu.z0, mu.iwz, mu.nz);
-    for (int iz = zlo; iz <= zhi; iz++) {
-      const int bb = iz * mu.ny;
-      const int e = offu[bb + yhi + 1] - Pu;
-      for (int u = offu[bb + ylo] - Pu; u < e; u++) {
-        const float2 q = yzu[u];
-        if (!(fabsf(q.x - yh) <= wy && fabsf(q.y - zh) <= wz)) continue;
-        if (nu < kNfList) s_ul[nu][tx] = (uint16_t)u;
-        nu++;
-      }
-    }
-  }
+  const int nu = nf_window(mu, offu, yzu, Pu, yh, zh, wy, wz, wym, wzm, s_ul);
   if (nu == 0) return;
   if (nu > kNfList || nd > kNfList) {
     nf_search(k, b, best, yh, zh, t, mu, offu, md, offd);
