@@ -805,10 +805,16 @@ __device__ __forceinline__ void nf_search_lists(const Consts& k, const TrackBufs
       bi[j] = d;
     }
     const int nb = min(nd - j0, kNfBatch);
+    // the next up candidate is loaded while the current one is scored
+    int un = s_ul[0][tx];
+    float2 qn = yzu[un];
     for (int iu = 0; iu < nu; iu++) {
-      const int u = s_ul[iu][tx];
-      const float2 qu = yzu[u];
-      const float yu = qu.x, zu = qu.y;
+      const int u = un;
+      const float yu = qn.x, zu = qn.y;
+      if (iu + 1 < nu) {
+        un = s_ul[iu + 1][tx];
+        qn = yzu[un];
+      }
       // the batch's scores, then one candidate per batch: its smallest
       // score (slots beyond the list score +inf); the rare exact tie of two
       // down candidates goes through the pair order one by one
