@@ -247,14 +247,16 @@ __device__ __forceinline__ void update_backward(const R* pp, const R* C, R my, R
   pb[1] -= rb[1];
 }
 
-__device__ __forceinline__ void acc_add(const RefitBufs& b, int cell, double g)
+// adds to the workgroup's partial sums in LDS (flushed once per workgroup)
+__device__ __forceinline__ void acc_add(const RefitBufs& b, unsigned long long* acc, int cell,
+                                        double g)
 {
   double v = rint(g * kFix);
   if (!(fabs(v) <= kFixMax)) {
     v = g < 0.0 ? -kFixMax : kFixMax;
     atomicOr(b.flags, 1);
   }
-  atomicAdd(reinterpret_cast<unsigned long long*>(&b.acc[cell]), (unsigned long long)(long long)v);
+  atomicAdd(&acc[cell], (unsigned long long)(long long)v);
 }
 
 __global__ __launch_bounds__(kBlock) void k_refit_bwd_zero(RefitBufs b)
@@ -272,10 +274,9 @@ __global__ __launch_bounds__(kBlock) void k_refit_bwd_zero(RefitBufs b)
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_refit_bwd(Consts k, RefitBufs b)
+__device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, int64_t t,
+                                          unsigned long long* acc)
 {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= b.n_tracks) return;
   const int64_t a = b.hit_off[t], e = b.hit_off[t + 1];
   if (e - a < 1 || b.status[t] != 0) return;
   // binary64 throughout: the checkpoints (binary32) are widened on load
@@ -387,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_refit_bwd(Consts k, RefitBufs b)
     b.gx[c] = (float)gX;
     b.gy[c] = (float)mb[0];
     b.gz[c] = (float)mb[1];
-    acc_add(b, cell, gX);
+    acc_add(b, acc, cell, gX);
     gXn = -dxb;
     c = cp;
     cell = cellp;
@@ -396,7 +397,23 @@ __global__ __launch_bounds__(kBlock) void k_refit_bwd(Consts k, RefitBufs b)
   b.gx[c] = (float)gXn;
   b.gy[c] = (float)pb[0];
   b.gz[c] = (float)pb[1];
-  acc_add(b, cell, gXn);
+  acc_add(b, acc, cell, gXn);
+}
+
+// One lane per track; the map sums of the workgroup's tracks are gathered
+// in LDS and added to the device accumulators once per cell.
+__global__ __launch_bounds__(kBlock) void k_refit_bwd(Consts k, RefitBufs b)
+{
+  __shared__ unsigned long long s_acc[kRows * kPhi];
+  for (int i = threadIdx.x; i < kRows * kPhi; i += kBlock) s_acc[i] = 0ull;
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < b.n_tracks) bwd_track(k, b, t, s_acc);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kRows * kPhi; i += kBlock) {
+    const unsigned long long v = s_acc[i];
+    if (v) atomicAdd(reinterpret_cast<unsigned long long*>(&b.acc[i]), v);
+  }
 }
 
 __global__ void k_refit_bwd_map(RefitBufs b)
