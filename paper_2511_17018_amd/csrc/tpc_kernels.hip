@@ -954,17 +954,16 @@ __global__ void k_start_finish(TrackBufs b)
 
 constexpr int kSrchZ = 2, kSrchC = 4;
 
-// R15: best cluster of one row for the predicted state.  `off` holds the
-// row's ny*nz+1 bin boundaries and `yz` the cluster positions, both in one
-// index space whose index p is grid position pos0 + p (the LDS copy of a row
-// starts at its first position; the global arrays at zero).  The pick is a
-// total order -- smallest chi2, then smallest input index -- so the scan
-// order does not matter; the input index is read only on an exact tie.
+// R15: best grid position of row segment m for the predicted state, or -1.
+// The pick is a total order -- smallest chi2, then smallest input index --
+// so the scan order does not matter; the input index is read only on an
+// exact tie.
 __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b,
-                                           const tpc_row_meta& m, const int32_t* off,
-                                           const float2* yz, int32_t pos0, const KSt& st,
+                                           const tpc_row_meta& m, const KSt& st,
                                            const Innov& q, int& ncand)
 {
+  const int32_t* const off = b.bin_off + m.bin_base;  // the segment's bin boundaries
+  const float2* const yz = b.yz;
   const float y = st.p[0], z = st.p[1];
   const float pick = k.tc_chi2_pick;
   const float wy = sqrtf(pick * q.S00) + k.search_margin;
@@ -977,7 +976,7 @@ __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b,
   float bchi = 0.0f;
   // loads batched: the bin ranges of kSrchZ z rows at once, then up to
   // kSrchC candidates of a range at once (one memory latency each instead of
-  // one per load on the global path)
+  // one per load)
   for (int z0 = zlo; z0 <= zhi; z0 += kSrchZ) {
     int ra[kSrchZ], re[kSrchZ];
 #pragma unroll
@@ -1007,14 +1006,14 @@ __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b,
           if (best < 0 || ch < bchi) {
             best = p;
             bchi = ch;
-          } else if (ch == bchi && b.perm[pos0 + p] < b.perm[pos0 + best]) {
+          } else if (ch == bchi && b.perm[p] < b.perm[best]) {
             best = p;
           }
         }
       }
     }
   }
-  return best < 0 ? -1 : pos0 + best;
+  return best;
 }
 
 // TrackletConstructor (R13-R17), one workgroup per chunk of at most CH
@@ -1145,7 +1144,7 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
       up = false;
     } else {
       const Innov q = innov(st, vy, vz);
-      const int32_t bh = ksearch(k, b, m, b.bin_off + m.bin_base, b.yz, 0, st, q, ncand);
+      const int32_t bh = ksearch(k, b, m, st, q, ncand);
       if (bh >= 0) {
         const float2 qb = b.yz[bh];
         chi2 += kupdate_q(st, q, qb.x, qb.y);
@@ -1191,7 +1190,7 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
       dn = false;
     } else {
       const Innov q = innov(st, vy, vz);
-      const int32_t bh = ksearch(k, b, m, b.bin_off + m.bin_base, b.yz, 0, st, q, ncand);
+      const int32_t bh = ksearch(k, b, m, st, q, ncand);
       if (bh >= 0) {
         const float2 qb = b.yz[bh];
         chi2 += kupdate_q(st, q, qb.x, qb.y);
