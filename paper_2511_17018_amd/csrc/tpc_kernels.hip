@@ -1087,7 +1087,24 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
 
   const float kB = k.kB, vy = k.vy, vz = k.vz, smax = k.snp_max;
   const float edge = k.edge_margin, tanh_ = k.tan_half;
-  KSt st, keep;
+  KSt st;
+  // the state after the last update (restart and output state), per thread
+  // in LDS ([element][lane]): in registers it took 20 more VGPRs, four waves
+  // per SIMD instead of seven
+  __shared__ float s_keep[20][CH];
+  const int tx = threadIdx.x;
+  auto put_keep = [&](const KSt& x) {
+#pragma unroll
+    for (int j = 0; j < 5; j++) s_keep[j][tx] = x.p[j];
+#pragma unroll
+    for (int j = 0; j < 15; j++) s_keep[5 + j][tx] = x.c[j];
+  };
+  auto get_keep = [&](KSt& x) {
+#pragma unroll
+    for (int j = 0; j < 5; j++) x.p[j] = s_keep[j][tx];
+#pragma unroll
+    for (int j = 0; j < 15; j++) x.c[j] = s_keep[5 + j][tx];
+  };
   float chi2 = 0.0f;
   int n = 1, r0 = kRows, rmax = 0, rmin = 0, ncand = 0;
   int32_t hn = -1;  // phase 1: cleaned upward link of the last hit
@@ -1129,30 +1146,29 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
     if (phase == 1 && hn < 0) {
       // links exhausted at row r - 1: the phase-2 restart state is kept
       phase = 2;
-      keep = st;
+      put_keep(st);
     }
     if (!kprop(st, k.row_x[r - 1], k.row_x[r], kB, smax)) {
       up = false;
-    } else if (phase == 1) {
-      const float2 qn = b.yz[hn];
-      chi2 += kupdate(st, qn.x, qn.y, vy, vz);
-      H[(int64_t)r * cap] = hn;
-      n++;
-      rmax = r;
-      hn = b.up2[hn];
-    } else if (!(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) {
+    } else if (phase == 2 && !(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) {
       up = false;
     } else {
+      // one filter update for both phases: the link's hit (phase 1, no cut)
+      // or the row's best cluster (phase 2)
       const Innov q = innov(st, vy, vz);
-      const int32_t bh = ksearch(k, b, m, st, q, ncand);
+      const int32_t bh = phase == 1 ? hn : ksearch(k, b, m, st, q, ncand);
       if (bh >= 0) {
         const float2 qb = b.yz[bh];
         chi2 += kupdate_q(st, q, qb.x, qb.y);
         H[(int64_t)r * cap] = bh;
         n++;
         rmax = r;
-        keep = st;
-        miss = 0;
+        if (phase == 1) {
+          hn = b.up2[hn];
+        } else {
+          put_keep(st);
+          miss = 0;
+        }
       } else {
         H[(int64_t)r * cap] = -1;
         if (++miss >= k.tc_max_miss) up = false;
@@ -1160,19 +1176,19 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
     }
   }
   // a lane that never left phase 1 restarts from its last linked row
-  if (phase == 1) keep = st;
+  if (phase == 1) put_keep(st);
 
   // phase 3 (R16): back to the start row, then downward
   int stat = 0;
   if (mine) {
-    st = keep;
+    get_keep(st);
     for (int r = rmax; r > r0; r--) {
       if (!kprop(st, k.row_x[r], k.row_x[r - 1], kB, smax)) {
         stat = 2;
         break;
       }
     }
-    keep = st;  // output state (innermost hit)
+    put_keep(st);  // output state (innermost hit)
   }
   bool dn = mine && stat == 0;
   miss = 0;
@@ -1197,7 +1213,7 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
         H[(int64_t)r * cap] = bh;
         n++;
         rmin = r;
-        keep = st;
+        put_keep(st);
         miss = 0;
       } else {
         H[(int64_t)r * cap] = -1;
@@ -1211,9 +1227,9 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
       else if (!(chi2 >= 0.0f && chi2 <= 3.0e38f)) stat = 3;
     }
 #pragma unroll
-    for (int j = 0; j < 5; j++) b.tl_par[j * cap + t] = keep.p[j];
+    for (int j = 0; j < 5; j++) b.tl_par[j * cap + t] = s_keep[j][tx];
 #pragma unroll
-    for (int j = 0; j < 15; j++) b.tl_cov[j * cap + t] = keep.c[j];
+    for (int j = 0; j < 15; j++) b.tl_cov[j * cap + t] = s_keep[5 + j][tx];
     b.tl_chi2[t] = chi2;
     b.tl_nhit[t] = n;
     b.tl_rmin[t] = rmin;
