@@ -725,7 +725,7 @@ constexpr int kNfBatch = 8;
 // One window scan into a per-thread list: the bin ranges of kNfZ z rows are
 // loaded at once, then kNfC candidates at once, so a window costs a few
 // memory latencies instead of one per z row and candidate.
-constexpr int kNfZ = 2, kNfC = 4;
+constexpr int kNfZ = 2, kNfC = 8;
 
 __device__ __forceinline__ int nf_window(const tpc_row_meta& m, const int32_t* off,
                                          const float2* yz, int32_t P, float yh, float zh,
@@ -952,7 +952,7 @@ __global__ void k_start_finish(TrackBufs b)
 
 #include "tpc_kalman.h"
 
-constexpr int kSrchZ = 2, kSrchC = 4;
+constexpr int kSrchZ = 4, kSrchC = 4;
 
 // R15: best grid position of row segment m for the predicted state, or -1.
 // The pick is a total order -- smallest chi2, then smallest input index --
