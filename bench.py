@@ -97,7 +97,6 @@ def kernel_bytes(name: str, c: dict) -> float | None:
         "neighbours": 24 * N + 8 * N,         # own + two neighbour rows' y,z; links out
         "clean": 16 * N + 8 * N,
         "tracklets": 4 * S + 16 * Ht + 8 * E + 88 * S,
-        "sel_keys": 8 * S,
         # every hit slot of every row, the keys of the hits, ownership bytes
         # out, the rows' owner keys out
         "sel_rows": 4 * R * S + 8 * Ht + R * S + 8 * N,

@@ -62,8 +62,8 @@ GridWs grid_ws(const tpc_params* p, int32_t n_inst, int64_t n)
 
 struct TrackWs {
   tpc_track_ws_layout pub;
-  int64_t tl_own, tsv, tl_first, chunk_off, tl_key, tl_owned, own_t, tl_rec, counters,
-      scan_len;
+  int64_t tl_own, tsv, tl_first, chunk_off, tl_key, tl_owned, own_t, tl_rec, start_flag,
+      counters, scan_len;
 };
 
 TrackWs track_ws(int32_t n_inst, int64_t n, int64_t cap)
@@ -94,6 +94,7 @@ TrackWs track_ws(int32_t n_inst, int64_t n, int64_t cap)
   w.tl_owned = c.take((int64_t)kRows * cap);
   w.own_t = c.take(4 * n);
   w.tl_rec = c.take(32 * cap);
+  w.start_flag = c.take((n + kScanTile - 1) / kScanTile * kScanTile);
   w.counters = c.take(8 * 8);
   const int64_t big = n > cap ? n : cap;
   w.scan_len = big / kScanTile + 2;
@@ -354,6 +355,7 @@ tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, 
   b.tl_owned = at<uint8_t>(ws_dev, w.tl_owned);
   b.own_t = at<int32_t>(ws_dev, w.own_t);
   b.tl_rec = at<int4>(ws_dev, w.tl_rec);
+  b.start_flag = at<unsigned long long>(ws_dev, w.start_flag);
   b.counters = at<int64_t>(ws_dev, w.counters);
   b.scan_tmp = at<int64_t>(ws_dev, w.pub.scratch);
   b.scan_tmp_len = w.scan_len;

@@ -72,6 +72,7 @@ struct TrackBufs {
   // workspace
   int32_t *up, *dn, *up2, *dn2;
   int32_t* start;
+  unsigned long long* start_flag;  // [scan tiles * kBlock] start flags, one byte each
   int64_t cap;         // tracklet capacity
   float* tl_par;       // [5][cap]
   float* tl_cov;       // [15][cap]

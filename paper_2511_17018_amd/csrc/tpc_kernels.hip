@@ -903,37 +903,40 @@ __device__ __forceinline__ bool is_start(const TrackBufs& b, int min_chain, int6
   return true;
 }
 
-// StartHitsFinder, deterministic: tile counts, scan, ordered write.
+// StartHitsFinder, deterministic: tile counts, scan, ordered write.  The
+// count pass keeps each thread's eight flags (one byte each) for the write
+// pass, so the chains are walked once.
 template <bool SPEC>
 __global__ __launch_bounds__(kBlock) void k_start_count(Consts karg, TrackBufs b, int64_t* part)
 {
   const Consts& k = kconsts<SPEC>(karg);
-  int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t base = tid * kItems;
   int64_t s = 0;
+  unsigned long long fl = 0ull;
 #pragma unroll
-  for (int j = 0; j < kItems; j++) s += is_start(b, k.min_chain, base + j) ? 1 : 0;
+  for (int j = 0; j < kItems; j++) {
+    const bool f = is_start(b, k.min_chain, base + j);
+    s += f ? 1 : 0;
+    fl |= (unsigned long long)(f ? 1u : 0u) << (8 * j);
+  }
+  b.start_flag[tid] = fl;
   int64_t tot;
   block_exclusive_scan(s, &tot);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-template <bool SPEC>
-__global__ __launch_bounds__(kBlock) void k_start_write(Consts karg, TrackBufs b, const int64_t* part)
+__global__ __launch_bounds__(kBlock) void k_start_write(TrackBufs b, const int64_t* part)
 {
-  const Consts& k = kconsts<SPEC>(karg);
-  int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
-  bool f[kItems];
-  int64_t s = 0;
-#pragma unroll
-  for (int j = 0; j < kItems; j++) {
-    f[j] = is_start(b, k.min_chain, base + j);
-    s += f[j] ? 1 : 0;
-  }
+  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t base = tid * kItems;
+  const unsigned long long fl = b.start_flag[tid];
+  const int64_t s = __popcll(fl);
   int64_t tot;
   int64_t o = block_exclusive_scan(s, &tot) + part[blockIdx.x];
 #pragma unroll
   for (int j = 0; j < kItems; j++) {
-    if (f[j]) {
+    if ((fl >> (8 * j)) & 1ull) {
       if (o < b.cap) b.start[o] = (int32_t)(base + j);
       o++;
     }
@@ -1014,6 +1017,17 @@ __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b,
     }
   }
   return best;
+}
+
+// Selection key of a kept tracklet (R20): hits (8 bits), then ~bits(chi2)
+// (31 bits), then 2^25 - 1 minus the start hit's instance-local input index
+// (25 bits), which does not depend on the grid.
+__device__ __forceinline__ unsigned long long sel_key(int nhit, float chi2, int64_t lid)
+{
+  const uint32_t bits = __float_as_uint(chi2);
+  return ((unsigned long long)(uint32_t)nhit << 56) |
+         ((unsigned long long)(~bits & 0x7FFFFFFFu) << 25) |
+         (unsigned long long)(0x1FFFFFFull - (unsigned long long)lid);
 }
 
 // TrackletConstructor (R13-R17), one workgroup per chunk of at most CH
@@ -1236,6 +1250,9 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
     b.tl_rmax[t] = rmax;
     b.tl_status[t] = stat;
     b.tl_ncand[t] = ncand;
+    // selection key, 0 for a rejected tracklet (it never owns a hit)
+    const int64_t lid = (int64_t)b.perm[b.start[t]] - b.inst_off[inst];
+    b.tl_key[t] = stat == 0 ? sel_key(n, chi2, lid) : 0ull;
   }
   // one counter update per wave
   const unsigned long long kept = __ballot(mine && stat == 0);
@@ -1245,18 +1262,6 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
 
 // ------------------------------------------------------------------ a6 selection
 
-__device__ __forceinline__ unsigned long long ts_key(const TrackBufs& b, int64_t t)
-{
-  const int32_t h0 = b.start[t];
-  const int seg0 = b.sseg[h0];
-  // instance-local input index of the start hit (independent of the grid)
-  const int64_t lid = (int64_t)b.perm[h0] - b.inst_off[seg0 / kRows];
-  const uint32_t bits = __float_as_uint(b.tl_chi2[t]);
-  return ((unsigned long long)(uint32_t)b.tl_nhit[t] << 56) |
-         ((unsigned long long)(~bits & 0x7FFFFFFFu) << 25) |
-         (unsigned long long)(0x1FFFFFFull - (unsigned long long)lid);
-}
-
 __global__ __launch_bounds__(kBlock) void k_sel_prep(TrackBufs b)
 {
   for (int64_t h = gtid(); h < b.n; h += (int64_t)gridDim.x * blockDim.x) {
@@ -1264,15 +1269,6 @@ __global__ __launch_bounds__(kBlock) void k_sel_prep(TrackBufs b)
     b.own_t[h] = -1;
     b.out.clu2trk[h] = -1;
   }
-}
-
-// Per-tracklet selection key (R20), 0 for a rejected tracklet (never owns).
-__global__ __launch_bounds__(kBlock) void k_sel_keys(TrackBufs b)
-{
-  const int64_t S = min(b.counters[CNT_START], b.cap);
-  const int64_t t = gtid();
-  if (t >= S) return;
-  b.tl_key[t] = b.tl_status[t] == 0 ? ts_key(b, t) : 0ull;
 }
 
 // Ownership (R20), one workgroup per (instance, row).  A position of row r of
@@ -1537,7 +1533,7 @@ hipError_t sector_track_t(const Consts& k, const TrackBufs& b, hipStream_t s)
     const int64_t nb = (b.n + kTile - 1) / kTile;
     TPC_LAUNCH("start_count", (unsigned)nb, kBlock, s, k_start_count<SPEC>, k, b, b.scan_tmp);
     TPC_LAUNCH("scan_partials", 1, 1024, s, k_scan_partials, b.scan_tmp, nb, &b.counters[CNT_START]);
-    TPC_LAUNCH("start_write", (unsigned)nb, kBlock, s, k_start_write<SPEC>, k, b, b.scan_tmp);
+    TPC_LAUNCH("start_write", (unsigned)nb, kBlock, s, k_start_write, b, b.scan_tmp);
   }
   TPC_LAUNCH("start_finish", 1, 1, s, k_start_finish, b);
   TPC_LAUNCH("sel_prep", blocks_for(b.n > 0 ? b.n : 1), kBlock, s, k_sel_prep, b);
@@ -1557,7 +1553,6 @@ hipError_t sector_track_t(const Consts& k, const TrackBufs& b, hipStream_t s)
     else
       TPC_LAUNCH("tracklets", tl_blocks, 256, s, kt256, k, b);
     const unsigned tblocks = blocks_for(b.cap);
-    TPC_LAUNCH("sel_keys", tblocks, kBlock, s, k_sel_keys, b);
     TPC_LAUNCH("sel_rows", (unsigned)((int64_t)b.n_inst * kRows), kBlock, s, k_sel_rows, b);
     TPC_LAUNCH("sel_count", tblocks, kBlock, s, k_sel_count<SPEC>, k, b, b.tl_own);
 #if TPC_DET

@@ -173,6 +173,23 @@ def test_det_edge_cases_bit_exact():
     assert g["result"]["n_bad"] == 4
 
 
+def test_det_row_beyond_list_index_range_bit_exact():
+    # config 1 plus 70 000 noise clusters on row 50: clusters of rows 49 and
+    # 51 search a neighbour row of more than 65535 positions, which the
+    # per-thread candidate lists (16-bit row-relative indices) cannot index,
+    # so they take the nested search over the global arrays; the row also
+    # has more grid bins than the segment sort holds in LDS
+    rng = np.random.default_rng(13)
+    ev = synth.config1()
+    n_noise = 70000
+    lim = G["row_x"][50] * G["tan_half"]
+    Y = np.concatenate([ev.y, rng.uniform(-lim, lim, n_noise).astype(np.float32)])
+    Z = np.concatenate([ev.z, rng.uniform(-250.0, 250.0, n_noise).astype(np.float32)])
+    R = np.concatenate([ev.row, np.full(n_noise, 50, np.uint16)])
+    perm = rng.permutation(len(Y))
+    _det_case(_arrays(Y[perm], Z[perm], R[perm], [0, len(Y)]))
+
+
 def test_det_exact_ties_bit_exact():
     # y and z on a 0.25 cm lattice (exact in binary32: symmetric candidates
     # give equal scores) and 150 clusters duplicated exactly (equal scores
