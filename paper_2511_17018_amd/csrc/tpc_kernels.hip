@@ -471,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_part(GridBufs b)
 // the scanned counters as cursors, and in the deterministic build the
 // ordering of each bin by input index -- an ordering kernel after atomic
 // placement (Sec. 2, run-time part), here inside the workgroup.
-constexpr int kSegBins = 8192;
+constexpr int kSegBins = 4096;
 constexpr int kSegBatch = 4;
 constexpr int kSortReg = 8;
 

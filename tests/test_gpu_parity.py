@@ -107,11 +107,11 @@ def test_det_selection_rows_beyond_lds_bit_exact():
 
 
 def test_det_grid_segments_beyond_lds_bit_exact():
-    # grid occupancy 0.25 (four bins per cluster) on a 2200-track wedge: 65
-    # of the 152 rows have more bins than the segment sort holds in LDS and
-    # count in the workspace instead, in the same launch as the smaller rows;
-    # the oracle builds its grid at the same occupancy
-    _det_case(synth.config1(n_tracks=2200), grid_occupancy=0.25)
+    # grid occupancy 0.25 (four bins per cluster) on an 1100-track wedge: 74
+    # of the 152 rows have more bins (4095) than the segment sort holds in
+    # LDS and count in the workspace instead, in the same launch as the
+    # smaller rows; the oracle builds its grid at the same occupancy
+    _det_case(synth.config1(n_tracks=1100), grid_occupancy=0.25)
 
 
 def test_det_many_tiny_instances_bit_exact():
