@@ -49,6 +49,18 @@ __device__ __forceinline__ const Consts& kconsts(const Consts& arg)
 
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
+// Workgroup w runs on XCD w % 8 (round-robin dispatch).  A launch of
+// xcd_grid(nblk) workgroups that takes its block index from xcd_block gives
+// each XCD one contiguous eighth of the nblk logical blocks, so that blocks
+// working on neighbouring data share one L2; -1 for the padding workgroups
+// (whole workgroups, so it is safe before a barrier).
+__device__ __forceinline__ int64_t xcd_block(int64_t nblk)
+{
+  const int64_t per = (nblk + 7) / 8;
+  const int64_t blk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  return blk < nblk ? blk : -1;
+}
+
 __device__ __forceinline__ int find_inst(const int64_t* off, int n_inst, int64_t c)
 {
   int lo = 0, hi = n_inst;  // off[lo] <= c < off[hi]
@@ -198,6 +210,8 @@ unsigned blocks_for(int64_t n, int per = kBlock)
   int64_t b = (n + per - 1) / per;
   return (unsigned)(b > 0 ? b : 1);
 }
+
+unsigned xcd_grid(int64_t nblk) { return (unsigned)(((nblk + 7) / 8) * 8); }
 
 // Launch with optional event timing (tpc_profile_enable).
 #define TPC_LAUNCH(name, grid, block, stream, kern, ...)   \
@@ -854,7 +868,10 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(Consts karg, TrackBufs b)
   const Consts& k = kconsts<SPEC>(karg);
   __shared__ uint16_t s_ul[kNfList][kBlock];
   __shared__ uint16_t s_dl[kNfList][kBlock];
-  const int64_t h = gtid();
+  // contiguous eighths per XCD: neighbouring positions search the same rows
+  const int64_t blk = xcd_block((b.n + kBlock - 1) / kBlock);
+  if (blk < 0) return;
+  const int64_t h = blk * kBlock + threadIdx.x;
   if (h >= b.n) return;
   const int seg = b.sseg[h];
   const int r = seg >= 0 ? seg % kRows : 0;
@@ -881,7 +898,9 @@ __global__ __launch_bounds__(kBlock) void k_neighbours(Consts karg, TrackBufs b)
 // NeighboursCleaner: mutual links only (reads the uncleaned arrays).
 __global__ __launch_bounds__(kBlock) void k_clean(TrackBufs b)
 {
-  const int64_t h = gtid();
+  const int64_t blk = xcd_block((b.n + kBlock - 1) / kBlock);
+  if (blk < 0) return;
+  const int64_t h = blk * kBlock + threadIdx.x;
   if (h >= b.n) return;
   int32_t u = b.up[h], d = b.dn[h];
   b.up2[h] = (u >= 0 && b.dn[u] == (int32_t)h) ? u : -1;
@@ -910,7 +929,9 @@ template <bool SPEC>
 __global__ __launch_bounds__(kBlock) void k_start_count(Consts karg, TrackBufs b, int64_t* part)
 {
   const Consts& k = kconsts<SPEC>(karg);
-  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t blk = xcd_block((b.n + kTile - 1) / kTile);
+  if (blk < 0) return;
+  const int64_t tid = blk * kBlock + threadIdx.x;
   const int64_t base = tid * kItems;
   int64_t s = 0;
   unsigned long long fl = 0ull;
@@ -923,17 +944,19 @@ __global__ __launch_bounds__(kBlock) void k_start_count(Consts karg, TrackBufs b
   b.start_flag[tid] = fl;
   int64_t tot;
   block_exclusive_scan(s, &tot);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+  if (threadIdx.x == 0) part[blk] = tot;
 }
 
 __global__ __launch_bounds__(kBlock) void k_start_write(TrackBufs b, const int64_t* part)
 {
-  const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t blk = xcd_block((b.n + kTile - 1) / kTile);
+  if (blk < 0) return;
+  const int64_t tid = blk * kBlock + threadIdx.x;
   const int64_t base = tid * kItems;
   const unsigned long long fl = b.start_flag[tid];
   const int64_t s = __popcll(fl);
   int64_t tot;
-  int64_t o = block_exclusive_scan(s, &tot) + part[blockIdx.x];
+  int64_t o = block_exclusive_scan(s, &tot) + part[blk];
 #pragma unroll
   for (int j = 0; j < kItems; j++) {
     if ((fl >> (8 * j)) & 1ull) {
@@ -1466,7 +1489,11 @@ __global__ __launch_bounds__(kBlock) void k_sel_write(Consts karg, TrackBufs b, 
 // every list is in ascending row order whatever the thread order.
 __global__ __launch_bounds__(kBlock) void k_sel_hits(TrackBufs b)
 {
-  const int64_t p = gtid();
+  // contiguous eighths per XCD: the scattered writes of one instance's
+  // clusters and tracks meet in one L2
+  const int64_t blk = xcd_block((b.n + kBlock - 1) / kBlock);
+  if (blk < 0) return;
+  const int64_t p = blk * kBlock + threadIdx.x;
   if (p >= b.n) return;
   const int32_t t = b.own_t[p];
   const int32_t seg = b.sseg[p];
@@ -1526,14 +1553,14 @@ hipError_t sector_track_t(const Consts& k, const TrackBufs& b, hipStream_t s)
 {
   TPC_LAUNCH("track_init", 1, 64, s, k_track_init, b);
   if (b.n > 0) {
-    TPC_LAUNCH("neighbours", blocks_for(b.n), kBlock, s, k_neighbours<SPEC>, k, b);
-    TPC_LAUNCH("clean", blocks_for(b.n), kBlock, s, k_clean, b);
+    TPC_LAUNCH("neighbours", xcd_grid(blocks_for(b.n)), kBlock, s, k_neighbours<SPEC>, k, b);
+    TPC_LAUNCH("clean", xcd_grid(blocks_for(b.n)), kBlock, s, k_clean, b);
     // ordered compaction in both modes: start-list order sets the tracklet
     // kernel's memory locality, so the scan is cheaper than atomic append
     const int64_t nb = (b.n + kTile - 1) / kTile;
-    TPC_LAUNCH("start_count", (unsigned)nb, kBlock, s, k_start_count<SPEC>, k, b, b.scan_tmp);
+    TPC_LAUNCH("start_count", xcd_grid(nb), kBlock, s, k_start_count<SPEC>, k, b, b.scan_tmp);
     TPC_LAUNCH("scan_partials", 1, 1024, s, k_scan_partials, b.scan_tmp, nb, &b.counters[CNT_START]);
-    TPC_LAUNCH("start_write", (unsigned)nb, kBlock, s, k_start_write, b, b.scan_tmp);
+    TPC_LAUNCH("start_write", xcd_grid(nb), kBlock, s, k_start_write, b, b.scan_tmp);
   }
   TPC_LAUNCH("start_finish", 1, 1, s, k_start_finish, b);
   TPC_LAUNCH("sel_prep", blocks_for(b.n > 0 ? b.n : 1), kBlock, s, k_sel_prep, b);
@@ -1560,7 +1587,7 @@ hipError_t sector_track_t(const Consts& k, const TrackBufs& b, hipStream_t s)
                             b.scan_tmp, s);
 #endif
     TPC_LAUNCH("sel_write", tblocks, kBlock, s, k_sel_write<SPEC>, k, b, b.tl_own);
-    if (b.n > 0) TPC_LAUNCH("sel_hits", blocks_for(b.n), kBlock, s, k_sel_hits, b);
+    if (b.n > 0) TPC_LAUNCH("sel_hits", xcd_grid(blocks_for(b.n)), kBlock, s, k_sel_hits, b);
   }
   TPC_LAUNCH("sel_finish", 1, 1, s, k_sel_finish, b);
   return hipGetLastError();
