@@ -403,7 +403,10 @@ __global__ __launch_bounds__(kBlock) void k_grid_part(GridBufs b)
   __shared__ uint16_t s_seg[kPartItems];
   __shared__ int s_smin, s_smax;
   const int tx = threadIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.x * kPartItems;
+  // contiguous eighths per XCD: an instance's segment runs fill in one L2
+  const int64_t blk = xcd_block((b.n + kPartItems - 1) / kPartItems);
+  if (blk < 0) return;
+  const int64_t c0 = blk * kPartItems;
   if (tx == 0) {
     s_smin = INT_MAX;
     s_smax = -1;
@@ -1542,7 +1545,8 @@ hipError_t grid_build(const Consts& k, const GridBufs& b, hipStream_t s)
   scan_exclusive<int32_t>(b.nb1, n_seg, nullptr, &b.res->n_bins, b.scan_tmp, s);
   TPC_LAUNCH("grid_meta2", blocks_for(n_seg), kBlock, s, k_grid_meta2, b);
   scan_exclusive<int32_t>(b.seg_pos, n_seg, nullptr, nullptr, b.scan_tmp, s);
-  if (b.n > 0) TPC_LAUNCH("grid_part", blocks_for(b.n, kPartItems), kBlock, s, k_grid_part, b);
+  if (b.n > 0)
+    TPC_LAUNCH("grid_part", xcd_grid(blocks_for(b.n, kPartItems)), kBlock, s, k_grid_part, b);
   TPC_LAUNCH("grid_seg", (unsigned)n_seg, kBlock, s, k_grid_seg, b);
   TPC_LAUNCH("grid_rowoff", blocks_for(n_seg), kBlock, s, k_grid_rowoff, b);
   return hipGetLastError();
