@@ -279,12 +279,24 @@ __global__ __launch_bounds__(kBlock) void k_grid_stats(Consts k, GridBufs b)
   __syncthreads();
   const int i0 = s_inst;
   const int64_t end0 = b.inst_off[i0 + 1];
-  for (int j = threadIdx.x; j < kStatItems; j += blockDim.x) {
-    int64_t c = c0 + j;
+  // the rows and coordinates of this thread's clusters are loaded at once
+  constexpr int kPer = kStatItems / kBlock;
+  int rv[kPer];
+  float yv[kPer], zv[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; u++) {
+    const int64_t c = c0 + u * kBlock + threadIdx.x;
+    rv[u] = c < b.n ? (int)b.row[c] : 0;
+    yv[u] = c < b.n ? b.y[c] : 0.0f;
+    zv[u] = c < b.n ? b.z[c] : 0.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; u++) {
+    const int64_t c = c0 + u * kBlock + threadIdx.x;
     if (c >= b.n) break;
     int i = c < end0 ? i0 : find_inst(b.inst_off, b.n_inst, c);
-    int row = b.row[c];
-    float y = b.y[c], z = b.z[c];
+    int row = rv[u];
+    float y = yv[u], z = zv[u];
     bool ok = row < kRows;
     if (ok) {
       float lim = k.row_x[row] * k.tan_half + k.y_valid_margin;
