@@ -1161,8 +1161,6 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
   int n = 1, r0 = kRows, rmax = 0, rmin = 0, ncand = 0;
   int32_t hn = -1;  // phase 1: cleaned upward link of the last hit
   if (mine) {
-    // every slot outside [rmin, rmax] reads -1 (the selection scans whole rows)
-    for (int r = 0; r < kRows; r++) H[(int64_t)r * cap] = -1;
     const int32_t h0 = b.start[t];
     r0 = b.sseg[h0] - segb;
     const int32_t h1 = b.up2[h0];
@@ -1288,6 +1286,10 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
     b.tl_rmax[t] = rmax;
     b.tl_status[t] = stat;
     b.tl_ncand[t] = ncand;
+    // the sweeps wrote every row of [rmin, rmax] (a hit or -1); the other
+    // rows read -1 too, since the selection scans whole rows
+    for (int r = 0; r < rmin; r++) H[(int64_t)r * cap] = -1;
+    for (int r = rmax + 1; r < kRows; r++) H[(int64_t)r * cap] = -1;
     // selection key, 0 for a rejected tracklet (it never owns a hit)
     const int64_t lid = (int64_t)b.perm[b.start[t]] - b.inst_off[inst];
     b.tl_key[t] = stat == 0 ? sel_key(n, chi2, lid) : 0ull;
