@@ -59,8 +59,10 @@ typedef enum {
 
 enum {
   TPC_FLAG_DETERMINISTIC = 1u, /* contraction-free code object + ordering kernels (Sec. 2) */
-  TPC_FLAG_PERSISTENT = 2u,    /* reserved for work-queue kernels                         */
-  TPC_FLAG_GRAPH = 4u,         /* reserved for graph-captured chains                      */
+  TPC_FLAG_PERSISTENT = 2u,    /* accepted, no effect: the tracklet kernel always takes
+                                  static chunks of one instance per workgroup */
+  TPC_FLAG_GRAPH = 4u,         /* accepted, no effect: every call only enqueues work on
+                                  its stream, so any call can be graph-captured as is */
   TPC_FLAG_GENERIC = 8u        /* never use the kernels compiled for the standard
                                   configuration (results are the same; for measuring) */
 };
