@@ -3,8 +3,8 @@
 Candidates are (grid_occupancy, tl_chunk): the clusters per grid bin,
 which trades bins scanned against clusters examined in every window
 search, and the tracklets per workgroup of the row-sweeping tracklet
-kernel, which trades rows staged per tracklet against lanes idle in a
-sweep.  Results do not depend on either (the window queries are widened to
+kernel, which trades row visits shared by a workgroup's lanes against
+lanes idle in a sweep.  Results do not depend on either (the window queries are widened to
 whole bins and filtered geometrically, and tracklet outputs go to fixed
 slots), and the tuner checks that: every candidate's
 deterministic output must equal the default's bit for bit, or it is

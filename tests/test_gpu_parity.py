@@ -67,21 +67,20 @@ def test_det_tracklet_chunk_sizes_bit_exact(chunk):
 
 
 @pytest.mark.parametrize("n_tracks,chunk", [(900, 64), (1500, 64), (3000, 128)])
-def test_det_rows_beyond_lds_bit_exact(n_tracks, chunk):
-    # One dense instance whose rows overflow the LDS row buffer of the
-    # workgroup size (124 bytes per thread): at 900 tracks about 90 of the
-    # 152 rows overflow at 64 threads (staged and global rows in one sweep),
-    # at 1500 and 3000 tracks every row does (global search only).
+def test_det_dense_rows_bit_exact(n_tracks, chunk):
+    # One dense instance (900 to 3000 tracks in one wedge): rows of
+    # thousands of positions, many start hits per row (chunks of one start
+    # row) and wide tracklet search windows, at 64 and 128 tracklets per
+    # workgroup.
     _det_case(synth.config1(n_tracks=n_tracks), tl_chunk=chunk)
 
 
-def test_det_dense_z_band_beyond_lds_bit_exact():
+def test_det_dense_z_band_bit_exact():
     # config 1 plus 2000 noise clusters on each of rows 50-52 inside a 5 cm
-    # z band: a workgroup's neighbour-search slab of those rows holds all of
-    # them (more than the LDS slab buffer), so about half of the event's
-    # clusters take the global-memory search, the rest the staged one.  A
-    # blob of 40 clusters in 2 x 2 cm on rows 30-32 gives staged searches
-    # more window candidates than the per-thread lists hold (32).
+    # z band: the neighbour windows of those rows hold far more candidates
+    # than the per-thread lists (32), so their clusters take the nested
+    # search, beside clusters on the list path in the same waves.  A blob of
+    # 40 clusters in 2 x 2 cm on rows 30-32 does the same in a small region.
     rng = np.random.default_rng(11)
     ev = synth.config1()
     g = synth.geometry()
