@@ -24,6 +24,8 @@ __device__ __forceinline__ void store_ckpt(float* ck, const KSt& st)
   q[4] = make_float4(st.c[11], st.c[12], st.c[13], st.c[14]);
 }
 
+constexpr int kFwdBlk = 8;  // hits per load block of the forward pass
+
 // R21-R24: one lane per track; planes X_k = x_k + D[row_k][sector_k mod 18].
 __global__ __launch_bounds__(kBlock) void k_refit_fwd(Consts k, RefitBufs b)
 {
@@ -47,32 +49,36 @@ __global__ __launch_bounds__(kBlock) void k_refit_fwd(Consts k, RefitBufs b)
   store_ckpt(b.ckpt + a * 20, st);
   float xprev = b.x[c] + b.dmap[(int)b.row[c] * kPhi + b.sector[c] % kPhi];
   float chi2 = 0.0f;
-  // software pipeline over the hits: the cluster index is loaded two hits
-  // ahead and the cluster's data one hit ahead, so that their gathers overlap
-  // the propagation and update of the current hit
-  int32_t cn = a + 1 < e ? b.hit_clu[a + 1] : 0;   // index of hit h
-  int32_t cnn = a + 2 < e ? b.hit_clu[a + 2] : 0;  // index of hit h + 1
-  float xn = b.x[cn], yn = b.y[cn], zn = b.z[cn];
-  int rown = b.row[cn], secn = b.sector[cn];
-  for (int64_t h = a + 1; h < e; h++) {
-    const float xk = xn + b.dmap[rown * kPhi + secn % kPhi];
-    const float yk = yn, zk = zn;
-    if (h + 1 < e) {
-      xn = b.x[cnn];
-      yn = b.y[cnn];
-      zn = b.z[cnn];
-      rown = b.row[cnn];
-      secn = b.sector[cnn];
-      cnn = h + 2 < e ? b.hit_clu[h + 2] : 0;
+  // the hits go in blocks of kFwdBlk: the block's cluster indices, then
+  // its clusters' data and plane offsets are loaded at once, then its hits
+  // are filtered and checkpointed.  A load issued after a store is only
+  // waited for together with that store (one in-order counter), so the
+  // stores cost one wait per block instead of one per hit.
+  const int64_t last = e - 1;
+  for (int64_t h0 = a + 1; h0 < e; h0 += kFwdBlk) {
+    int32_t ci[kFwdBlk];
+#pragma unroll
+    for (int u = 0; u < kFwdBlk; u++) ci[u] = b.hit_clu[h0 + u < last ? h0 + u : last];
+    float xs[kFwdBlk], ys[kFwdBlk], zs[kFwdBlk];
+#pragma unroll
+    for (int u = 0; u < kFwdBlk; u++) {
+      xs[u] = b.x[ci[u]] + b.dmap[(int)b.row[ci[u]] * kPhi + b.sector[ci[u]] % kPhi];
+      ys[u] = b.y[ci[u]];
+      zs[u] = b.z[ci[u]];
     }
-    if (!kprop(st, xprev, xk, kB, smax)) {
-      b.chi2[t] = 0.0f;
-      b.status[t] = 1;
-      return;
+#pragma unroll
+    for (int u = 0; u < kFwdBlk; u++) {
+      const int64_t h = h0 + u;
+      if (h >= e) break;
+      if (!kprop(st, xprev, xs[u], kB, smax)) {
+        b.chi2[t] = 0.0f;
+        b.status[t] = 1;
+        return;
+      }
+      chi2 += kupdate(st, ys[u], zs[u], vy, vz);
+      store_ckpt(b.ckpt + h * 20, st);
+      xprev = xs[u];
     }
-    chi2 += kupdate(st, yk, zk, vy, vz);
-    store_ckpt(b.ckpt + h * 20, st);
-    xprev = xk;
   }
   b.chi2[t] = chi2;
   b.status[t] = 0;
