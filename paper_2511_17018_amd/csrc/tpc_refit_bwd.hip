@@ -247,16 +247,47 @@ __device__ __forceinline__ void update_backward(const R* pp, const R* C, R my, R
   pb[1] -= rb[1];
 }
 
-// adds to the workgroup's partial sums in LDS (flushed once per workgroup)
-__device__ __forceinline__ void acc_add(const RefitBufs& b, unsigned long long* acc, int cell,
-                                        double g)
+// adds to the workgroup's partial sums in LDS (flushed once per workgroup);
+// true if the term was clamped (the caller raises the overflow flag once)
+__device__ __forceinline__ bool acc_add(unsigned long long* acc, int cell, double g)
 {
   double v = rint(g * kFix);
-  if (!(fabs(v) <= kFixMax)) {
-    v = g < 0.0 ? -kFixMax : kFixMax;
-    atomicOr(b.flags, 1);
-  }
+  const bool ovf = !(fabs(v) <= kFixMax);
+  if (ovf) v = g < 0.0 ? -kFixMax : kFixMax;
   atomicAdd(&acc[cell], (unsigned long long)(long long)v);
+  return ovf;
+}
+
+// Per-thread LDS buffer of the cluster gradients of kBwdOut hits, written
+// to global memory every kBwdOut hits: a load issued after a store is
+// waited for together with that store (the counter retires them in order),
+// so storing each hit's gradient at once would stall every step's loads.
+constexpr int kBwdOut = 8;
+
+struct BwdOut {
+  float (*g)[3][kBlock];  // [kBwdOut][x, y, z][thread]
+  int32_t (*c)[kBlock];   // [kBwdOut][thread] cluster index
+};
+
+__device__ __forceinline__ void out_put(const BwdOut& o, int j, int32_t c, float gx, float gy,
+                                        float gz)
+{
+  const int tx = threadIdx.x;
+  o.g[j][0][tx] = gx;
+  o.g[j][1][tx] = gy;
+  o.g[j][2][tx] = gz;
+  o.c[j][tx] = c;
+}
+
+__device__ __forceinline__ void out_flush(const RefitBufs& b, const BwdOut& o, int n)
+{
+  const int tx = threadIdx.x;
+  for (int j = 0; j < n; j++) {
+    const int32_t c = o.c[j][tx];
+    b.gx[c] = o.g[j][0][tx];
+    b.gy[c] = o.g[j][1][tx];
+    b.gz[c] = o.g[j][2][tx];
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_refit_bwd_zero(RefitBufs b)
@@ -275,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_refit_bwd_zero(RefitBufs b)
 }
 
 __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, int64_t t,
-                                          unsigned long long* acc)
+                                          unsigned long long* acc, const BwdOut& o)
 {
   const int64_t a = b.hit_off[t], e = b.hit_off[t + 1];
   if (e - a < 1 || b.status[t] != 0) return;
@@ -289,6 +320,8 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
   int32_t c = b.hit_clu[e - 1];
   int cell = (int)b.row[c] * kPhi + b.sector[c] % kPhi;
   R X2 = (R)b.x[c] + (R)b.dmap[cell];
+  bool ovf = false;
+  int j = 0;  // gradients buffered in o
   for (int64_t h = e - 1; h >= a + 1; h--) {
     const int32_t cp = b.hit_clu[h - 1];
     const int cellp = (int)b.row[cp] * kPhi + b.sector[cp] % kPhi;
@@ -385,19 +418,21 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
     prop_record(pr, dxr, kB, q);
     const R dxb = prop_backward(pr, q, kB, pb, Fb);
     const R gX = dxb + gXn;
-    b.gx[c] = (float)gX;
-    b.gy[c] = (float)mb[0];
-    b.gz[c] = (float)mb[1];
-    acc_add(b, acc, cell, gX);
+    out_put(o, j, c, (float)gX, (float)mb[0], (float)mb[1]);
+    if (++j == kBwdOut) {
+      out_flush(b, o, j);
+      j = 0;
+    }
+    ovf |= acc_add(acc, cell, gX);
     gXn = -dxb;
     c = cp;
     cell = cellp;
     X2 = X1;
   }
-  b.gx[c] = (float)gXn;
-  b.gy[c] = (float)pb[0];
-  b.gz[c] = (float)pb[1];
-  acc_add(b, acc, cell, gXn);
+  out_put(o, j, c, (float)gXn, (float)pb[0], (float)pb[1]);
+  out_flush(b, o, j + 1);
+  ovf |= acc_add(acc, cell, gXn);
+  if (ovf) atomicOr(b.flags, 1);
 }
 
 // One lane per track; the map sums of the workgroup's tracks are gathered
@@ -405,10 +440,12 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
 __global__ __launch_bounds__(kBlock) void k_refit_bwd(Consts k, RefitBufs b)
 {
   __shared__ unsigned long long s_acc[kRows * kPhi];
+  __shared__ float s_og[kBwdOut][3][kBlock];
+  __shared__ int32_t s_oc[kBwdOut][kBlock];
   for (int i = threadIdx.x; i < kRows * kPhi; i += kBlock) s_acc[i] = 0ull;
   __syncthreads();
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < b.n_tracks) bwd_track(k, b, t, s_acc);
+  if (t < b.n_tracks) bwd_track(k, b, t, s_acc, BwdOut{s_og, s_oc});
   __syncthreads();
   for (int i = threadIdx.x; i < kRows * kPhi; i += kBlock) {
     const unsigned long long v = s_acc[i];
