@@ -320,12 +320,41 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
   int32_t c = b.hit_clu[e - 1];
   int cell = (int)b.row[c] * kPhi + b.sector[c] % kPhi;
   R X2 = (R)b.x[c] + (R)b.dmap[cell];
+  float yc = b.y[c], zc = b.z[c];
+  // the hits ahead (downwards) are loaded across steps, with no store in
+  // most steps: the cluster index three hits ahead, the cluster's data two
+  // ahead and its plane offset one ahead (indices below the first hit are
+  // clamped to it; their data is loaded but unused)
+  auto idx = [&](int64_t hh) { return b.hit_clu[hh > a ? hh : a]; };
+  int32_t cp1 = idx(e - 2);
+  float x1 = b.x[cp1], y1 = b.y[cp1], z1 = b.z[cp1];
+  int cell1 = (int)b.row[cp1] * kPhi + b.sector[cp1] % kPhi;
+  float dm1 = b.dmap[cell1];
+  int32_t cp2 = idx(e - 3);
+  float x2 = b.x[cp2], y2 = b.y[cp2], z2 = b.z[cp2];
+  int row2 = b.row[cp2], sec2 = b.sector[cp2];
+  int32_t i3 = idx(e - 4);
   bool ovf = false;
   int j = 0;  // gradients buffered in o
   for (int64_t h = e - 1; h >= a + 1; h--) {
-    const int32_t cp = b.hit_clu[h - 1];
-    const int cellp = (int)b.row[cp] * kPhi + b.sector[cp] % kPhi;
-    const R X1 = (R)b.x[cp] + (R)b.dmap[cellp];
+    const int32_t cp = cp1;
+    const int cellp = cell1;
+    const R X1 = (R)x1 + (R)dm1;
+    const float ycp = y1, zcp = z1;
+    // advance the pipeline by one hit
+    cp1 = cp2;
+    cell1 = row2 * kPhi + sec2 % kPhi;
+    dm1 = b.dmap[cell1];
+    x1 = x2;
+    y1 = y2;
+    z1 = z2;
+    cp2 = i3;
+    x2 = b.x[i3];
+    y2 = b.y[i3];
+    z2 = b.z[i3];
+    row2 = b.row[i3];
+    sec2 = b.sector[i3];
+    i3 = idx(h - 4);
     // checkpoint h-1: state and covariance (lower triangle, row-major)
     const float4* q4 = reinterpret_cast<const float4*>(b.ckpt + (h - 1) * 20);
     const float4 v0 = q4[0], v1 = q4[1], v2 = q4[2], v3 = q4[3], v4 = q4[4];
@@ -372,7 +401,7 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
       if (i >= 4) Cp[si(i, 4)] = Bi[4];
     }
     R mb[2];
-    update_backward(pp, Cp, (R)b.y[c], (R)b.z[c], vy, vz, w, pb, X, mb);
+    update_backward(pp, Cp, (R)yc, (R)zc, vy, vz, w, pb, X, mb);
     // covariance part of the propagation: XF = X F, Fb = 2 (X F C0) at the
     // entries of E, X <- F^T X F
     R XF[5][5];
@@ -428,6 +457,8 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
     c = cp;
     cell = cellp;
     X2 = X1;
+    yc = ycp;
+    zc = zcp;
   }
   out_put(o, j, c, (float)gXn, (float)pb[0], (float)pb[1]);
   out_flush(b, o, j + 1);
