@@ -47,9 +47,14 @@ extern "C" {
 tpc_status tpc_profile_enable(int32_t on)
 {
   if (on && !g_on) {
-    g_ev.resize(2 * kPool);
-    for (auto& e : g_ev)
-      if (hipEventCreate(&e) != hipSuccess) return TPC_ERR_HIP;
+    g_ev.assign(2 * kPool, nullptr);
+    for (size_t i = 0; i < g_ev.size(); i++)
+      if (hipEventCreate(&g_ev[i]) != hipSuccess) {
+        // leave the timer off, holding no events
+        for (size_t j = 0; j < i; j++) (void)hipEventDestroy(g_ev[j]);
+        g_ev.clear();
+        return TPC_ERR_HIP;
+      }
     g_rec.clear();
     g_next = 0;
     g_on = true;
