@@ -319,6 +319,11 @@ def test_grid_invariants():
         for k in range(ny * nz):
             seg = pp[bo[k] - ro[r]:bo[k + 1] - ro[r]]
             assert np.all(np.diff(seg) > 0)
+        # the data box spans the bins: the row's smallest coordinate lands in
+        # column 0 and its largest in the last column
+        for ax_i, ax_v, n_ax in ((iy, yy, ny), (iz, zz, nz)):
+            if len(ax_v):
+                assert ax_i[np.argmin(ax_v)] == 0 and ax_i[np.argmax(ax_v)] == n_ax - 1
         # monotone binning: higher bin column => not smaller coordinate
         for ax_i, ax_v, n_ax in ((iy, yy, ny), (iz, zz, nz)):
             for k in range(n_ax - 1):
@@ -567,6 +572,37 @@ def test_selection_merges_broken_chain_clone():
     assert len(r.start) >= 2
     assert len(r.tracks.chi2) == 1
     assert r.tracks.hit_off[1] == len(y)
+
+
+@pytest.mark.parametrize("lower_first", [True, False])
+def test_selection_exact_key_tie_goes_to_lower_start_index(lower_first):
+    # R20: two tracklets with the same hit count and bit-identical chi2 share
+    # the hits of rows 40..59; each also holds a hit of its own on row 39,
+    # which is its start hit.  The tie goes to the start hit with the lower
+    # input index, whatever the tracklets' order in the list: that tracklet
+    # owns 21 hits and becomes the one track, the other owns one.
+    ev = synth.config1()
+    gr = oracle.grid_build(G, P, ev.inst_off, ev.y, ev.z, ev.row)
+    ro = gr.row_off
+    assert np.all(np.diff(ro[39:61]) >= 1) and ro[40] - ro[39] >= 2
+    a, b = int(ro[39]), int(ro[39]) + 1
+    lo, hi = (a, b) if gr.perm[a] < gr.perm[b] else (b, a)
+    starts = [lo, hi] if lower_first else [hi, lo]
+    nr = G["n_rows"]
+    hit = np.full((2, nr), -1, np.int32)
+    for t, s0 in enumerate(starts):
+        hit[t, 39] = s0
+        hit[t, 40:60] = ro[40:60]
+    cov = np.zeros((2, 15), np.float32)
+    cov[:, [0, 2, 5, 9, 14]] = 1.0
+    tl = oracle.Tracklets(np.zeros((2, 5), np.float32), cov,
+                          np.full(2, 3.25, np.float32), np.full(2, 21, np.int32),
+                          np.full(2, 39, np.int32), np.full(2, 59, np.int32), hit,
+                          np.zeros(2, np.int32))
+    T = oracle.select(G, P, ev.inst_off, gr, np.array(starts, np.int32), tl)
+    assert len(T.chi2) == 1 and T.hit_off[1] == 21
+    assert gr.perm[lo] in T.hit_clu and gr.perm[hi] not in T.hit_clu
+    assert T.clu2trk[gr.perm[lo]] == 0 and T.clu2trk[gr.perm[hi]] == -1
 
 
 def test_selection_capacity_truncates_in_order():
