@@ -526,6 +526,134 @@ def test_tracklet_stops_at_sector_edge():
     assert tl.rmax[k] == rows[-1]
 
 
+def _first_chain_tracklet(y, z, row):
+    """Chain result and the tracklet of the lowest start hit (single instance)."""
+    r = oracle.track(G, P, np.array([0, len(y)], np.int64), y, z, row)
+    t = int(np.argmin(r.grid.sseg[r.start]))
+    return r, t
+
+
+def test_tracklet_search_stops_after_consecutive_misses_only():
+    # R15: the upward search ends at the tc_max_miss-th consecutive row without
+    # a hit; a found hit starts the count again.  The links end at row 38
+    # (rows 40.. are missing), so rows from 39 up are reached by the search.
+    rng = np.random.default_rng(24)
+    st = np.array([1.0, 5.0, 0.05, 0.4, 0.8])
+    rows = np.arange(152)
+    y, z, row, _ = _single_track_event(st, rows, False, rng)
+    m = P["tc_max_miss"]
+    for gap, top in ((m - 1, 151), (m, 39)):
+        keep = (rows < 40) | (rows >= 40 + gap)
+        r, t = _first_chain_tracklet(y[keep], z[keep], row[keep])
+        assert r.tracklets.rmax[t] == top
+    # 2m scattered misses (every other row of 60..100), never m in a row
+    keep = ~((rows >= 60) & (rows <= 100) & (rows % 2 == 0))
+    assert (~keep).sum() >= 2 * m
+    r, t = _first_chain_tracklet(y[keep], z[keep], row[keep])
+    assert r.tracklets.rmax[t] == 151 and r.tracklets.nhit[t] == keep.sum()
+
+
+def test_tracklet_kept_from_min_tracklet_hits():
+    # R17: a tracklet is kept iff it has at least min_tracklet_hits hits.  A
+    # noise-free track on rows 50..50+k-1 only gives one tracklet of k hits.
+    rng = np.random.default_rng(25)
+    st = np.array([-3.0, 20.0, -0.05, 0.3, 0.5])
+    k = P["min_tracklet_hits"]
+    for nrow, status in ((k - 1, 1), (k, 0)):
+        rows = np.arange(50, 50 + nrow)
+        y, z, row, _ = _single_track_event(st, rows, False, rng)
+        r, t = _first_chain_tracklet(y, z, row)
+        assert r.tracklets.nhit[t] == nrow and r.tracklets.status[t] == status
+
+
+def test_tracklet_search_tie_goes_to_lower_input_index():
+    # R15: two clusters at the same (y, z) of row 100 give the search an exact
+    # chi2 tie, which the lower input index wins.  Row 70 is missing, so the
+    # first chain's tracklet reaches row 100 by searching, not by links.
+    rng = np.random.default_rng(26)
+    st = np.array([0.5, -8.0, 0.08, -0.35, -0.6])
+    rows = np.arange(152)
+    y, z, row, _ = _single_track_event(st, rows, False, rng)
+    keep = rows != 70
+    y, z, row = y[keep], z[keep], row[keep]
+    i100 = int(np.nonzero(row == 100)[0][0])
+    for dup_first in (True, False):
+        # the copy of the row-100 cluster goes before or after all others
+        if dup_first:
+            yy, zz, rr = (np.concatenate([[y[i100]], y]), np.concatenate([[z[i100]], z]),
+                          np.concatenate([[row[i100]], row]))
+            lo = 0
+        else:
+            yy, zz, rr = (np.append(y, y[i100]), np.append(z, z[i100]),
+                          np.append(row, row[i100]))
+            lo = i100
+        r, t = _first_chain_tracklet(yy.astype(np.float32), zz.astype(np.float32),
+                                     rr.astype(np.uint16))
+        assert r.grid.sseg[r.start[t]] % 152 < 70
+        assert r.grid.perm[r.tracklets.hit[t, 100]] == lo
+
+
+def test_tracklet_search_window_follows_each_axis_variance():
+    # R15: the search window is sqrt(pick * S) + margin per axis, with S00 for
+    # y and S11 for z.  The row-100 hit of a noise-free track is moved 0.5 cm
+    # in z: chi2 ~ 0.25 / S11 ~ 11 <= 13.8, beyond the y-sized half-width
+    # (~0.4 cm) but inside the z-sized one (~0.58 cm).  A 40 x 40 cm lattice of
+    # other clusters on that row (kept 2 cm away from the track) makes 1 cm
+    # bins with an edge 0.44 cm above the true z, so a z window of the y size
+    # never reaches the moved hit's bin.  Row 70 is missing: the first chain's
+    # tracklet reaches row 100 by searching.
+    rng = np.random.default_rng(27)
+    st = np.array([0.5, -8.0, 0.08, -0.35, -0.6])
+    rows = np.arange(152)
+    y, z, row, _ = _single_track_event(st, rows, False, rng)
+    yt, zt = float(y[100]), float(z[100])
+    z = z.copy()
+    z[100] = np.float32(zt + 0.5)
+    keep = rows != 70
+    y, z, row = y[keep], z[keep], row[keep]
+    moved = int(np.nonzero(row == 100)[0][0])
+    y0, z0 = np.float32(yt - 20.3), np.float32(zt + 0.44 - 20)
+    ly, lz = np.meshgrid(y0 + np.float32(40) * np.arange(40, dtype=np.float32) / 39,
+                         z0 + np.float32(40) * np.arange(40, dtype=np.float32) / 39)
+    ly, lz = ly.ravel().astype(np.float32), lz.ravel().astype(np.float32)
+    far = np.hypot(ly - yt, lz - zt) > 2.0
+    ly, lz = ly[far], lz[far]
+    extra = 1601 - 1 - len(ly)                          # at least 1600 clusters on the row
+    ly = np.append(ly, np.full(extra, y0 + 0.5, np.float32))
+    lz = np.append(lz, z0 + 0.5 + 0.01 * np.arange(extra, dtype=np.float32))
+    yy = np.concatenate([y, ly]).astype(np.float32)
+    zz = np.concatenate([z, lz]).astype(np.float32)
+    rr = np.concatenate([row, np.full(len(ly), 100, np.uint16)])
+    p = dict(P, grid_occupancy=1.0)
+    r = oracle.track(G, p, np.array([0, len(yy)], np.int64), yy, zz, rr)
+    ny, nz = r.grid.meta_i[100][:2]
+    assert (ny, nz) == (40, 40) and r.grid.meta_f[100][1] == z0 and r.grid.meta_f[100][3] == 1
+    t = int(np.argmin(r.grid.sseg[r.start]))
+    assert r.grid.sseg[r.start[t]] % 152 < 70
+    assert r.grid.perm[r.tracklets.hit[t, 100]] == moved
+
+
+def test_tracklets_independent_of_the_grid():
+    # R15's window holds every cluster with chi2 <= tc_chi2_pick (the bounding
+    # box of that ellipse plus a margin), and ties go by input index, so the
+    # tracklets do not depend on the bin size; one bin per row is a full scan.
+    ev = synth.config2(n_tracks=300)
+    ref = None
+    for occ in (0.5, 2.0, 1e9):
+        r = oracle.track(G, dict(P, grid_occupancy=occ), ev.inst_off, ev.y, ev.z, ev.row)
+        tl, perm = r.tracklets, r.grid.perm
+        got = {}
+        for t in range(len(r.start)):
+            hits = tuple(int(perm[h]) if h >= 0 else -1
+                         for h in tl.hit[t, tl.rmin[t]:tl.rmax[t] + 1])
+            got[int(perm[r.start[t]])] = (tl.status[t], tl.nhit[t], tl.rmin[t], hits,
+                                          tl.chi2[t].tobytes(), tl.par[t].tobytes())
+        if ref is None:
+            ref = got
+        else:
+            assert got == ref
+
+
 # --------------------------------------------------------------- P9 selection
 def test_selection_matches_brute_force_ownership():
     ev = synth.config2(n_tracks=600)
