@@ -564,6 +564,11 @@ def test_tracklet_kept_from_min_tracklet_hits():
         y, z, row, _ = _single_track_event(st, rows, False, rng)
         r, t = _first_chain_tracklet(y, z, row)
         assert r.tracklets.nhit[t] == nrow and r.tracklets.status[t] == status
+    # the kept one is the track: two measurements per hit less five
+    # parameters, state given at the innermost hit's plane (R17)
+    T = r.tracks
+    assert len(T.chi2) == 1 and T.hit_off[1] == k
+    assert T.ndf[0] == 2 * k - 5 and T.x_ref[0] == np.float32(G["row_x"][50])
 
 
 def test_tracklet_search_tie_goes_to_lower_input_index():
