@@ -26,19 +26,21 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-W
           "-Wno-unused-function"]
 
 
-def build(force: bool = True, src: str | None = None, out: str | None = None) -> str:
-    """Compile liboracle.so with gcc (binary32 and binary64 objects)."""
+def build(force: bool = True, out: str | None = None, srcdir: str | None = None) -> str:
+    """Compile liboracle.so with gcc (binary32 and binary64 objects; the
+    refit also as complex binary64) from the C sources in `srcdir`."""
     out = out or LIB
     if not force and os.path.exists(out):
         return out
-    src = src or os.path.join(HERE, "tpc_oracle.c")
-    refit = os.path.join(HERE, "tpc_refit.c")
+    srcdir = srcdir or HERE
     objs = []
-    for name, tags in ((src, (("f32", []), ("f64", ["-DORC_F64"]))),
-                       (refit, (("rf32", []), ("rf64", ["-DORC_F64"]), ("rc128", ["-DORC_C128"])))):
+    for name, tags in (("tpc_oracle.c", (("f32", []), ("f64", ["-DORC_F64"]))),
+                       ("tpc_refit.c", (("rf32", []), ("rf64", ["-DORC_F64"]),
+                                        ("rc128", ["-DORC_C128"])))):
         for tag, defs in tags:
             obj = out + f".{tag}.o"
-            subprocess.run(["gcc", *CFLAGS, *defs, "-I", HERE, "-c", name, "-o", obj], check=True)
+            subprocess.run(["gcc", *CFLAGS, *defs, "-I", srcdir, "-c",
+                            os.path.join(srcdir, name), "-o", obj], check=True)
             objs.append(obj)
     tmp = out + ".tmp"
     subprocess.run(["gcc", "-shared", "-o", tmp, *objs, "-lm"], check=True)
