@@ -55,17 +55,20 @@ def log(*a):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "chain_config4_traffic.md")
+VALU_PROFILE = os.path.join(ROOT, "profiles", "chain_config4_valu_counters.md")
+N_CU = 256
+CLOCK_HZ = 2.4e9
 KERNEL_SOURCES = ["paper_2511_17018_amd/csrc/tpc_kernels.hip", "paper_2511_17018_amd/csrc/tpc_kalman.h",
                   "paper_2511_17018_amd/csrc/tpc_internal.h", "include/tpcca.h",
                   "paper_2511_17018_amd/build.py"]
 
 
-def measured_traffic(kernel: str, occ: float, chunk: int) -> int | None:
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, calibrated), or None when the kernel
-    sources or the launch parameters differ from the ones it was taken on."""
+def _profiled(path: str, field: str, kernel: str, occ: float, chunk: int) -> int | None:
+    """Per-launch figure `field` of `kernel` from a committed rocprofv3
+    summary, or None when the kernel sources or the launch parameters differ
+    from the ones it was taken on."""
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(path).read()
     except OSError:
         return None
     h = hashlib.sha256()
@@ -75,14 +78,36 @@ def measured_traffic(kernel: str, occ: float, chunk: int) -> int | None:
     m = re.search(r"source_sha256: ([0-9a-f]{64})", text)
     if not m or m.group(1) != h.hexdigest():
         return None
-    # one block of traffic_bytes lines per profiled launch configuration
+    # one block of figures per profiled launch configuration
     for block in re.split(r"^launch: ", text, flags=re.M)[1:]:
         ml = re.match(r"([0-9.]+),(\d+)", block)
         if not ml or float(ml.group(1)) != float(occ) or int(ml.group(2)) != int(chunk):
             continue
-        mt = re.search(rf"^traffic_bytes {re.escape(kernel)}: (\d+)", block, flags=re.M)
+        mt = re.search(rf"^{re.escape(field)} {re.escape(kernel)}: (\d+)", block, flags=re.M)
         return int(mt.group(1)) if mt else None
     return None
+
+
+def measured_traffic(kernel: str, occ: float, chunk: int) -> int | None:
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated)."""
+    return _profiled(TRAFFIC_PROFILE, "traffic_bytes", kernel, occ, chunk)
+
+
+def measured_valu(kernel: str, occ: float, chunk: int) -> int | None:
+    """VALU wave64 instructions per launch of `kernel` (SQ_INSTS_VALU)."""
+    return _profiled(VALU_PROFILE, "valu_insts", kernel, occ, chunk)
+
+
+def valu_issue(kernel: str, occ: float, chunk: int, avg_s: float) -> dict | None:
+    """The kernel's VALU issue rate in wave64 instructions per CU-cycle (256
+    CUs at the 2.4 GHz peak clock over the live launch duration), beside the
+    issue model's limit without packed FP32: one per CU-cycle (four 16-lane
+    SIMDs, four cycles per wave64 instruction)."""
+    n = measured_valu(kernel, occ, chunk)
+    if n is None:
+        return None
+    return {"insts_per_launch": n, "per_cu_cycle": n / (N_CU * CLOCK_HZ * avg_s),
+            "model_limit_per_cu_cycle": 1.0, "source": os.path.relpath(VALU_PROFILE, ROOT)}
 
 
 def kernel_bytes(name: str, c: dict) -> float | None:
@@ -210,7 +235,8 @@ def run(args) -> dict:
                 "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                 "traffic": traffic, "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT)
                 if traffic else None, "avg_launch_ms": avg_s * 1e3,
-                "alg_bytes_per_launch": kb, "counts": counts}
+                "alg_bytes_per_launch": kb, "counts": counts,
+                "valu_issue": valu_issue(name, tp["grid_occupancy"], tp["tl_chunk"], avg_s)}
     out["kernels_ms_per_step"] = {k: round(v[0] / args.steps, 4) for k, v in
                                   sorted(ktimes.items(), key=lambda kv: -kv[1][0])}
     out["kernels_sum_ms_per_step"] = round(sum(v[0] for v in ktimes.values()) / args.steps, 4)
