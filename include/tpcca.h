@@ -57,12 +57,11 @@ typedef enum {
   TPC_ERR_WORKSPACE = -4    /* workspace smaller than the size query said */
 } tpc_status;
 
+/* params->flags: any other bit set is rejected with TPC_ERR_INVALID.  (Every
+ * call only enqueues work on its stream, so any call can be captured into a
+ * HIP graph as it is; no flag asks for that.) */
 enum {
   TPC_FLAG_DETERMINISTIC = 1u, /* contraction-free code object + ordering kernels (Sec. 2) */
-  TPC_FLAG_PERSISTENT = 2u,    /* accepted, no effect: the tracklet kernel always takes
-                                  static chunks of one instance per workgroup */
-  TPC_FLAG_GRAPH = 4u,         /* accepted, no effect: every call only enqueues work on
-                                  its stream, so any call can be graph-captured as is */
   TPC_FLAG_GENERIC = 8u        /* never use the kernels compiled for the standard
                                   configuration (results are the same; for measuring) */
 };
@@ -200,23 +199,41 @@ size_t tpc_track_workspace_bytes(int32_t n_inst, int64_t n_clusters, int64_t cap
 tpc_status tpc_track_workspace_layout(int32_t n_inst, int64_t n_clusters, int64_t cap_tracklets,
                                       tpc_track_ws_layout* out);
 
-/* a1: build the per (instance,row) grid of the valid clusters (R10 of the
- * design notes; total-order sort of Sec. 2).  Invalid clusters (row >= 152,
+/* a1: build the per (instance,row) grid of the valid clusters, ordered by
+ * (row, bin, input index): the total-order sort that Sec. 2 requires of the
+ * deterministic mode.  The grid is a search structure of the tracker only
+ * (the paper does not describe the tracker's data structures): results of
+ * tpc_sector_track do not depend on its bin size.  Invalid clusters (row >= 152,
  * |y| beyond the sector plus margin, |z| > 1e5, NaN) are counted in
  * result->n_bad and left out.  Writes result fields n_valid, n_bad, n_bins
  * (overflow bit 1 if bin_cap is too small; the grid is then unusable).
  * inst_off_host and inst_off_dev hold the same n_inst+1 offsets.
  * Errors: TPC_ERR_INVALID (null pointer, n_rows != 152, bad offsets,
- * instance >= 2^24 clusters), TPC_ERR_WORKSPACE, TPC_ERR_HIP. */
+ * instance >= 2^24 clusters, a bin table that tpc_grid_bin_capacity sizes
+ * above 2^31 - 1 entries -- bin offsets are 32-bit --, unknown flags),
+ * TPC_ERR_WORKSPACE, TPC_ERR_HIP. */
 tpc_status tpc_grid_build(const tpc_geometry* geom, const tpc_params* params, int32_t n_inst,
                           const int64_t* inst_off_host, const int64_t* inst_off_dev,
                           tpc_clusters in, const tpc_grid* grid, tpc_result* result_dev,
                           void* ws_dev, size_t ws_bytes, void* stream);
 
-/* a2..a6: neighbours, cleaner, start hits, tracklets, selection on a grid
- * built by tpc_grid_build with the same arguments.  Writes the tracks and the
- * remaining result fields.  TPC_FLAG_DETERMINISTIC in params->flags selects
- * the deterministic code object and ordering kernels. */
+/* a2..a6: TPC sector tracking -- finding the tracks in the clusters of
+ * each instance (one TPC sector of one collision or time frame) and
+ * assigning clusters to tracks, the online step whose cluster-to-track
+ * association Sec. 2 compares between CPU and GPU -- on a grid built by
+ * tpc_grid_build with the same arguments: neighbour finding and cleaning,
+ * start hits, tracklet construction with a Kalman helix fit in the solenoid
+ * field (the track propagation of Sec. 4), tracklet selection.  Writes the
+ * tracks (tpc_tracks) and the remaining result fields.
+ * TPC_FLAG_DETERMINISTIC in params->flags selects the deterministic code
+ * object and ordering kernels, whose output equals the binary32 CPU
+ * reference bit for bit (Sec. 2: deterministic processing mode); without it
+ * clusters may be assigned differently in rare ties of rounding (Sec. 2
+ * quotes far below 0.001 % of clusters).  cap_tracklets <= 0 selects the
+ * default capacity (tpc_track_workspace_bytes); more start hits than the
+ * capacity set overflow bit 2 and the tracklets beyond it are dropped.
+ * Errors: TPC_ERR_INVALID (as tpc_grid_build; also null output arrays,
+ * capacities >= 2^31), TPC_ERR_WORKSPACE, TPC_ERR_HIP. */
 tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, int32_t n_inst,
                             const int64_t* inst_off_host, const int64_t* inst_off_dev,
                             tpc_clusters in, const tpc_grid* grid, const tpc_tracks* out,
@@ -250,15 +267,29 @@ typedef struct {
  * and ckpt equal the binary32 CPU reference bit for bit.  This refit is the
  * differentiable extension of the tracking step; the paper's shared track
  * propagation with field and material maps (Sec. 4) is its context.
- * Errors: TPC_ERR_INVALID (null pointers, n_tracks < 0, n_rows != 152). */
+ * A hit must name a cluster in [0, n_clusters) whose row is below 152 (the
+ * map has no plane for other rows): a track with any other hit is not
+ * refitted (status 2, chi2 0; 2 takes precedence over 1).  Checkpoints of
+ * tracks with status != 0 are unspecified.
+ * Errors: TPC_ERR_INVALID (null pointers, n_tracks < 0, n_clusters >= 2^31,
+ * n_rows != 152, unknown flags). */
 tpc_status tpc_refit(const tpc_geometry* geom, const tpc_params* params, int64_t n_clusters,
                      tpc_clusters in, tpc_refit_tracks trk, const float* dist_map_dev,
                      float* chi2_dev, int32_t* status_dev, float* ckpt_dev, void* stream);
 
 /* a9: gradient of L = sum_t grad_chi2[t] * chi2[t] with respect to the map
  * (grad_map[152][18]) and the cluster coordinates (grad_x, grad_y, grad_z,
- * [n_clusters]; clusters on no refitted track get 0).  All outputs are
- * overwritten.  Uses the forward call's ckpt and status (same inputs).
+ * [n_clusters]; clusters on no refitted track get 0).  The paper names the
+ * offline-only TPC distortion corrections (Sec. 6) and the shared track
+ * propagation (Sec. 4) but no gradient: this reverse-mode derivative of the
+ * refit's chi2 is the differentiable extension, for fitting such a
+ * correction map.  All outputs are overwritten.  Uses the forward call's
+ * ckpt and status (same inputs); tracks with status != 0 contribute nothing.
+ * Precondition: each cluster is a hit of at most one refitted track (as in
+ * the tracker's output, where clu2trk names one track per cluster).  The
+ * cluster gradients are stored, not added, so a cluster on several tracks
+ * gets the gradient of one of its hits, which one is unspecified; the map
+ * gradient stays the full sum over all hits.
  * Every step is rebuilt from the previous checkpoint and differentiated in
  * reverse.  The map sums are exact 64-bit fixed-point sums (scale 2^24), so
  * the gradient is identical from run to run.  ws_dev must hold

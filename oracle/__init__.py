@@ -365,7 +365,8 @@ def _refit_args(geom, params, ev_like, hit_off, hit_clu, seed, dmap):
 
 
 def refit(geom, params, ev_like, hit_off, hit_clu, seed, dmap, prec=32):
-    """Forward refit: (chi2[n], status[n], ckpt[n_hits, 20])."""
+    """Forward refit: (chi2[n], status[n], ckpt[n_hits, 20]).  status 1: the
+    propagation failed; 2: a hit names no cluster or a row beyond the map."""
     g, P, a = _refit_args(geom, params, ev_like, hit_off, hit_clu, seed, dmap)
     n = len(a["hit_off"]) - 1
     nh = int(a["hit_off"][-1])
@@ -376,8 +377,8 @@ def refit(geom, params, ev_like, hit_off, hit_clu, seed, dmap, prec=32):
     f = _fn("orc_refit", prec)
     f.restype = None
     f(C.byref(g), C.byref(P), C.c_int64(n), _p(a["hit_off"]), _p(a["hit_clu"]), _p(a["sector"]),
-      _p(a["x"]), _p(a["y"]), _p(a["z"]), _p(a["row"]), _p(a["seed"]), _p(a["dmap"]), _p(chi2),
-      _p(status), _p(ckpt))
+      _p(a["x"]), _p(a["y"]), _p(a["z"]), _p(a["row"]), C.c_int64(len(a["x"])), _p(a["seed"]),
+      _p(a["dmap"]), _p(chi2), _p(status), _p(ckpt))
     return chi2[:n], status[:n], ckpt[:nh]
 
 
@@ -394,8 +395,8 @@ def refit_loss(geom, params, ev_like, hit_off, hit_clu, seed, dmap, w, which=Non
     f = getattr(lib(), f"orc_refit_loss_{mode}")
     f.restype = C.c_double
     return f(C.byref(g), C.byref(P), C.c_int64(n), _p(a["hit_off"]), _p(a["hit_clu"]),
-             _p(a["sector"]), _p(a["x"]), _p(a["y"]), _p(a["z"]), _p(a["row"]), _p(a["seed"]),
-             _p(a["dmap"]), _p(w), C.c_int(-1 if which is None else REFIT_WHICH[which]),
+             _p(a["sector"]), _p(a["x"]), _p(a["y"]), _p(a["z"]), _p(a["row"]),
+             C.c_int64(len(a["x"])), _p(a["seed"]), _p(a["dmap"]), _p(w), C.c_int(-1 if which is None else REFIT_WHICH[which]),
              C.c_int64(idx), C.c_double(h))
 
 

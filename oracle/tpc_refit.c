@@ -89,17 +89,35 @@ static int refit_one(const orc_geom* g, const orc_params* P, int64_t a, int64_t 
   return 1;
 }
 
+/* A track is refitted only if every hit names a cluster in [0, n_clusters)
+ * on one of the map's rows (the plane offset D[row][.] exists); otherwise it
+ * is rejected as a whole: status 2, chi2 0, no checkpoints, zero gradient. */
+static int hits_valid(const orc_geom* g, int64_t a, int64_t b, const int32_t* hit_clu,
+                      const uint16_t* row, int64_t n_clusters)
+{
+  for (int64_t k = a; k < b; k++) {
+    const int64_t c = hit_clu[k];
+    if (c < 0 || c >= n_clusters || row[c] >= g->n_rows) return 0;
+  }
+  return 1;
+}
+
 /* a8 -- forward refit of n_tracks tracks (CSR hit lists, cluster indices). */
 void SFX(orc_refit)(const orc_geom* g, const orc_params* P, int64_t n_tracks, const int32_t* hit_off,
                     const int32_t* hit_clu, const uint8_t* sector, const float* x, const float* y,
-                    const float* z, const uint16_t* row, const float* seed, const float* dmap,
-                    real* chi2, int32_t* status, real* ckpt)
+                    const float* z, const uint16_t* row, int64_t n_clusters, const float* seed,
+                    const float* dmap, real* chi2, int32_t* status, real* ckpt)
 {
   for (int64_t t = 0; t < n_tracks; t++) {
     const int64_t a = hit_off[t], b = hit_off[t + 1];
     if (b <= a) {
       chi2[t] = 0;
       status[t] = 0;
+      continue;
+    }
+    if (!hits_valid(g, a, b, hit_clu, row, n_clusters)) {
+      chi2[t] = 0;
+      status[t] = 2;
       continue;
     }
     status[t] = refit_one(g, P, a, b, hit_clu, sector, x, y, z, row, seed + 5 * t, dmap, &chi2[t],
@@ -114,13 +132,13 @@ void SFX(orc_refit)(const orc_geom* g, const orc_params* P, int64_t n_tracks, co
 double SFX(orc_refit_loss)(const orc_geom* g, const orc_params* P, int64_t n_tracks,
                            const int32_t* hit_off, const int32_t* hit_clu, const uint8_t* sector,
                            const float* x, const float* y, const float* z, const uint16_t* row,
-                           const float* seed, const float* dmap, const double* w, int which,
-                           int64_t idx, double h)
+                           int64_t n_clusters, const float* seed, const float* dmap,
+                           const double* w, int which, int64_t idx, double h)
 {
   real tot = 0;
   for (int64_t t = 0; t < n_tracks; t++) {
     const int64_t a = hit_off[t], b = hit_off[t + 1];
-    if (b <= a) continue;
+    if (b <= a || !hits_valid(g, a, b, hit_clu, row, n_clusters)) continue;
     real c2 = 0;
     if (refit_one(g, P, a, b, hit_clu, sector, x, y, z, row, seed + 5 * t, dmap, &c2, NULL, which,
                   idx, (real)PERT(h)))
@@ -400,7 +418,7 @@ void orc_refit_grad_f64(const orc_geom* g, const orc_params* P, int64_t n_tracks
   for (int64_t c = 0; c < n_clusters; c++) gx[c] = gy[c] = gz[c] = 0;
   for (int64_t t = 0; t < n_tracks; t++) {
     const int64_t a = hit_off[t], b = hit_off[t + 1];
-    if (b - a < 1 || status[t] != 0) continue;
+    if (b - a < 1 || status[t] != 0 || !hits_valid(g, a, b, hit_clu, row, n_clusters)) continue;
     double pb[5] = {0, 0, 0, 0, 0};
     double Xb[5][5] = {{0}};
     double gX_next = 0; /* adjoint of X_k from step k+1 */

@@ -17,6 +17,7 @@ namespace {
 constexpr int64_t kAlign = 256;
 constexpr int64_t kScanTile = 2048;  // items per block of the scan kernels
 constexpr int64_t kMaxInstClusters = (int64_t)1 << 24;
+constexpr uint32_t kKnownFlags = TPC_FLAG_DETERMINISTIC | TPC_FLAG_GENERIC;
 
 int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -121,6 +122,10 @@ tpc_status check_common(const tpc_geometry* g, const tpc_params* p, int32_t n_in
   const int64_t n = off_h[n_inst];
   if (n >= ((int64_t)1 << 31) - 1) return TPC_ERR_INVALID;
   if (n > 0 && (!in.y || !in.z || !in.row)) return TPC_ERR_INVALID;
+  if (p->flags & ~kKnownFlags) return TPC_ERR_INVALID;
+  // bin bases and offsets are 32-bit: the table the size query asks for
+  // must fit
+  if (tpc_grid_bin_capacity(p, n_inst, n) > (int64_t)INT32_MAX) return TPC_ERR_INVALID;
   if (p->min_chain < 3 || p->tc_max_miss < 1 || p->min_track_hits < 1 ||
       p->min_tracklet_hits < 0 || !(p->grid_occupancy > 0) || !(p->snp_max > 0) ||
       !(p->snp_max < 1) || !(p->search_margin >= 0) ||
@@ -377,6 +382,8 @@ static tpc_status refit_check(const tpc_geometry* g, const tpc_params* p, int64_
 {
   if (!g || !p || g->n_rows != kRows || n_clusters < 0 || trk.n_tracks < 0 || trk.n_hits < 0)
     return TPC_ERR_INVALID;
+  // cluster indices are 32-bit
+  if (n_clusters >= ((int64_t)1 << 31) || (p->flags & ~kKnownFlags)) return TPC_ERR_INVALID;
   if (!dmap || !(p->snp_max > 0) || !(p->snp_max < 1)) return TPC_ERR_INVALID;
   if (trk.n_tracks > 0 && (!trk.hit_off || !trk.seed)) return TPC_ERR_INVALID;
   if (trk.n_hits > 0 && (!trk.hit_clu || !trk.sector || !in.x || !in.y || !in.z || !in.row))

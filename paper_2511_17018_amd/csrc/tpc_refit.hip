@@ -26,6 +26,16 @@ __device__ __forceinline__ void store_ckpt(float* ck, const KSt& st)
 
 constexpr int kFwdBlk = 8;  // hits per load block of the forward pass
 
+// every hit of [h, e) names a cluster below ncl on a row of the map
+__device__ __noinline__ bool hits_valid(const RefitBufs& b, int64_t h, int64_t e, uint32_t ncl)
+{
+  for (; h < e; h++) {
+    const int32_t c = b.hit_clu[h];
+    if ((uint32_t)c >= ncl || b.row[c] >= kRows) return false;
+  }
+  return true;
+}
+
 // R21-R24: one lane per track; planes X_k = x_k + D[row_k][sector_k mod 18].
 __global__ __launch_bounds__(kBlock) void k_refit_fwd(Consts k, RefitBufs b)
 {
@@ -38,7 +48,16 @@ __global__ __launch_bounds__(kBlock) void k_refit_fwd(Consts k, RefitBufs b)
     return;
   }
   const float kB = k.kB, vy = k.vy, vz = k.vz, smax = k.snp_max;
+  // a hit must name a cluster on one of the map's rows; a track with any
+  // other hit is rejected as a whole (status 2), and the loads below use
+  // in-range indices whatever the hit list holds
+  const uint32_t ncl = (uint32_t)b.n_clusters;
   int32_t c = b.hit_clu[a];
+  if ((uint32_t)c >= ncl || b.row[c] >= kRows) {
+    b.chi2[t] = 0.0f;
+    b.status[t] = 2;
+    return;
+  }
   KSt st;
   st.p[0] = b.y[c];
   st.p[1] = b.z[c];
@@ -57,22 +76,40 @@ __global__ __launch_bounds__(kBlock) void k_refit_fwd(Consts k, RefitBufs b)
   const int64_t last = e - 1;
   for (int64_t h0 = a + 1; h0 < e; h0 += kFwdBlk) {
     int32_t ci[kFwdBlk];
+    bool bad = false;
 #pragma unroll
-    for (int u = 0; u < kFwdBlk; u++) ci[u] = b.hit_clu[h0 + u < last ? h0 + u : last];
+    for (int u = 0; u < kFwdBlk; u++) {
+      ci[u] = b.hit_clu[h0 + u < last ? h0 + u : last];
+      bad |= (uint32_t)ci[u] >= ncl;
+      ci[u] = (uint32_t)ci[u] < ncl ? ci[u] : 0;
+    }
+    int rw[kFwdBlk];
+#pragma unroll
+    for (int u = 0; u < kFwdBlk; u++) {
+      rw[u] = b.row[ci[u]];
+      bad |= rw[u] >= kRows;
+      rw[u] = rw[u] < kRows ? rw[u] : 0;
+    }
     float xs[kFwdBlk], ys[kFwdBlk], zs[kFwdBlk];
 #pragma unroll
     for (int u = 0; u < kFwdBlk; u++) {
-      xs[u] = b.x[ci[u]] + b.dmap[(int)b.row[ci[u]] * kPhi + b.sector[ci[u]] % kPhi];
+      xs[u] = b.x[ci[u]] + b.dmap[rw[u] * kPhi + b.sector[ci[u]] % kPhi];
       ys[u] = b.y[ci[u]];
       zs[u] = b.z[ci[u]];
+    }
+    if (bad) {
+      b.chi2[t] = 0.0f;
+      b.status[t] = 2;
+      return;
     }
 #pragma unroll
     for (int u = 0; u < kFwdBlk; u++) {
       const int64_t h = h0 + u;
       if (h >= e) break;
       if (!kprop(st, xprev, xs[u], kB, smax)) {
+        // an invalid hit further on still makes the track status 2
         b.chi2[t] = 0.0f;
-        b.status[t] = 1;
+        b.status[t] = hits_valid(b, h0 + kFwdBlk, e, ncl) ? 1 : 2;
         return;
       }
       chi2 += kupdate(st, ys[u], zs[u], vy, vz);

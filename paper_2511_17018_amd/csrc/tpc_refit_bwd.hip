@@ -317,23 +317,34 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
 #pragma unroll
   for (int i = 0; i < 15; i++) X[i] = 0.0;
   R gXn = 0.0;
-  int32_t c = b.hit_clu[e - 1];
-  int cell = (int)b.row[c] * kPhi + b.sector[c] % kPhi;
+  // the forward pass gives status 2 to a track with a hit outside the
+  // clusters or the map's rows; the clamps below only keep every access in
+  // bounds if the status passed in does not belong to these inputs
+  const uint32_t ncl = (uint32_t)b.n_clusters;
+  auto clu = [&](int64_t hh) {
+    const int32_t v = b.hit_clu[hh > a ? hh : a];
+    return (uint32_t)v < ncl ? v : 0;
+  };
+  auto rowc = [&](int32_t cc) {
+    const int r = b.row[cc];
+    return r < kRows ? r : kRows - 1;
+  };
+  int32_t c = clu(e - 1);
+  int cell = rowc(c) * kPhi + b.sector[c] % kPhi;
   R X2 = (R)b.x[c] + (R)b.dmap[cell];
   float yc = b.y[c], zc = b.z[c];
   // the hits ahead (downwards) are loaded across steps, with no store in
   // most steps: the cluster index three hits ahead, the cluster's data two
   // ahead and its plane offset one ahead (indices below the first hit are
   // clamped to it; their data is loaded but unused)
-  auto idx = [&](int64_t hh) { return b.hit_clu[hh > a ? hh : a]; };
-  int32_t cp1 = idx(e - 2);
+  int32_t cp1 = clu(e - 2);
   float x1 = b.x[cp1], y1 = b.y[cp1], z1 = b.z[cp1];
-  int cell1 = (int)b.row[cp1] * kPhi + b.sector[cp1] % kPhi;
+  int cell1 = rowc(cp1) * kPhi + b.sector[cp1] % kPhi;
   float dm1 = b.dmap[cell1];
-  int32_t cp2 = idx(e - 3);
+  int32_t cp2 = clu(e - 3);
   float x2 = b.x[cp2], y2 = b.y[cp2], z2 = b.z[cp2];
-  int row2 = b.row[cp2], sec2 = b.sector[cp2];
-  int32_t i3 = idx(e - 4);
+  int row2 = rowc(cp2), sec2 = b.sector[cp2];
+  int32_t i3 = clu(e - 4);
   bool ovf = false;
   int j = 0;  // gradients buffered in o
   for (int64_t h = e - 1; h >= a + 1; h--) {
@@ -352,9 +363,9 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
     x2 = b.x[i3];
     y2 = b.y[i3];
     z2 = b.z[i3];
-    row2 = b.row[i3];
+    row2 = rowc(i3);
     sec2 = b.sector[i3];
-    i3 = idx(h - 4);
+    i3 = clu(h - 4);
     // checkpoint h-1: state and covariance (lower triangle, row-major)
     const float4* q4 = reinterpret_cast<const float4*>(b.ckpt + (h - 1) * 20);
     const float4 v0 = q4[0], v1 = q4[1], v2 = q4[2], v3 = q4[3], v4 = q4[4];

@@ -121,3 +121,56 @@ def test_standard_configuration_matches_generator_geometry():
     g3 = dict(g, row_x=g["row_x"].copy())
     g3["row_x"][100] = np.nextafter(g3["row_x"][100], np.float32(1e9))
     assert not tpc.standard_configuration(g3, tpc.make_params(True))
+
+
+@pytest.mark.parametrize("case", ["unknown_flag", "bin_table_over_int32"])
+def test_grid_and_track_reject_unknown_flags_and_oversized_bin_tables(case):
+    L = tpc.lib()
+    g, p, off, cl, gs, dummy = _args()
+    n_inst = 1
+    if case == "unknown_flag":
+        p.flags |= 2          # no such flag
+    else:
+        # 2^27 clusters in 16 instances at occupancy 0.25: the bin table the
+        # size query asks for exceeds the 32-bit bin offsets
+        n_inst = 16
+        off = np.arange(17, dtype=np.int64) * ((1 << 24) - 1)
+        p.grid_occupancy = 0.25
+        assert L.tpc_grid_bin_capacity(C.byref(p), C.c_int32(n_inst), C.c_int64(int(off[-1]))) > 2**31 - 1
+    st = L.tpc_grid_build(C.byref(g), C.byref(p), C.c_int32(n_inst), off.ctypes.data_as(C.c_void_p),
+                          dummy, cl, C.byref(gs), dummy, dummy, C.c_size_t(1 << 50), C.c_void_p(0))
+    assert st == -1
+    tr = tpc.TracksStruct(dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 10, 10)
+    st = L.tpc_sector_track(C.byref(g), C.byref(p), C.c_int32(n_inst),
+                            off.ctypes.data_as(C.c_void_p), dummy, cl, C.byref(gs), C.byref(tr),
+                            dummy, dummy, C.c_size_t(1 << 50), C.c_int64(0), C.c_void_p(0))
+    assert st == -1
+
+
+@pytest.mark.parametrize("case", ["unknown_flag", "clusters_over_int32", "null_map", "rows"])
+def test_refit_rejects_bad_arguments_on_host(case):
+    L = tpc.lib()
+    g = tpc.make_geometry(synth.geometry())
+    p = tpc.make_params(True)
+    dummy = C.c_void_p(0x1000)   # never dereferenced: validation fails first
+    cl = tpc.Clusters(dummy, dummy, dummy, dummy, dummy)
+    trk = tpc.RefitTracksStruct(dummy, dummy, dummy, dummy, 4, 40)
+    nc = 1000
+    dmap = dummy
+    if case == "unknown_flag":
+        p.flags |= 4
+    elif case == "clusters_over_int32":
+        nc = 1 << 31
+    elif case == "null_map":
+        dmap = C.c_void_p(0)
+    elif case == "rows":
+        g.n_rows = 150
+    L.tpc_refit.restype = C.c_int
+    L.tpc_refit_backward.restype = C.c_int
+    st = L.tpc_refit(C.byref(g), C.byref(p), C.c_int64(nc), cl, trk, dmap, dummy, dummy,
+                     C.c_void_p(0x2000), C.c_void_p(0))
+    assert st == -1
+    st = L.tpc_refit_backward(C.byref(g), C.byref(p), C.c_int64(nc), cl, trk, dmap,
+                              C.c_void_p(0x2000), dummy, dummy, dummy, dummy, dummy, dummy,
+                              C.c_void_p(0x3000), C.c_size_t(1 << 20), C.c_void_p(0))
+    assert st == -1

@@ -154,3 +154,41 @@ def test_refit_prod_close_to_binary64():
     c = chi2.cpu().numpy()
     ok = (status.cpu().numpy() == 0) & (s64 == 0)
     assert np.all(np.abs(c[ok] - c64[ok]) <= 1e-3 * np.maximum(c64[ok], 1.0))
+
+
+def test_refit_rejects_tracks_with_invalid_hits_like_the_oracle():
+    """Hits past the last cluster, negative, or on a row beyond the map:
+    status 2 (also when a propagation failure comes first), chi2 0, no
+    gradient, and every other track bit-exact with the oracle."""
+    ev = synth.config5(n_found=300)
+    ho, hc, seed = _args(ev)
+    hc = hc.copy()
+    row = ev.row.copy()
+    hc[ho[3] + 2] = ev.n
+    hc[ho[5]] = -7
+    row[hc[ho[7] + 4]] = 152
+    hc[ho[11 + 1] - 1] = ev.n + 100           # last hit of track 11
+    seed = seed.copy()
+    seed[11, 2], seed[11, 4] = 0.9895, -5.0   # its first propagation fails too
+    import copy
+    ev2 = copy.copy(ev)
+    ev2.row = row
+    ev2.extra = dict(ev.extra, hit_clu=hc, seed_par=seed)
+    dmap = ev.extra["D_true"]
+    _say(f"[refit invalid hits] tracks={len(ho) - 1}")
+    c_o, s_o, k_o = oracle.refit(G, P, ev2, ho, hc, seed, dmap, prec=32)
+    assert np.all(s_o[[3, 5, 7, 11]] == 2)
+    xyz, rw, trk, m = _gpu(ev2, dmap)
+    chi2, status, ckpt = tpc.refit(G, xyz, rw, trk, m, det=True)
+    gmap, gxyz = tpc.refit_backward(G, xyz, rw, trk, m, ckpt, status, torch.ones_like(chi2))
+    torch.cuda.synchronize()
+    assert np.array_equal(status.cpu().numpy(), s_o)
+    assert np.array_equal(chi2.cpu().numpy().view(np.int32), c_o.view(np.int32))
+    ok = np.repeat(s_o == 0, np.diff(ho))
+    assert np.array_equal(ckpt.cpu().numpy()[ok].view(np.int32), k_o[ok].view(np.int32))
+    g = gxyz.cpu().numpy()
+    for t in (3, 5, 7, 11):
+        cl = hc[ho[t]:ho[t + 1]]
+        cl = cl[(cl >= 0) & (cl < ev.n)]
+        assert np.all(g[:, cl] == 0)
+    assert np.isfinite(gmap.cpu().numpy()).all()

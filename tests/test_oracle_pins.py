@@ -860,3 +860,72 @@ def test_replay_straight_line_three_hits_exact():
     assert par[3] == pytest.approx(dzi / L, rel=1e-12, abs=1e-12)
     assert par[2] == pytest.approx(dyi / L, rel=1e-12, abs=1e-12)
     assert chi2 < 1e-10
+
+
+def test_tracklet_straight_line_start_state_exact():
+    """R13 through the tracker itself: clusters exactly on a straight line
+    (no field bending, qpt = 0) with both slopes nonzero.  The start state
+    takes snp and tgl from the chord of the first and third hit, so it is
+    the line's own direction: every update has zero residual, the fit's
+    chi2 vanishes, and the output keeps snp = dy/L and tgl = dz/L with
+    L the transverse chord.  A start tgl of dz/dx instead of dz/L would be
+    off by the factor 1/cos(phi) and leave residuals at the next hits."""
+    geo = dict(G, bz=0.0)
+    rows = np.arange(152)
+    x = G["row_x"].astype(np.float32)
+    # binary32-exact points: multiplying by powers of two rounds nothing
+    y = (np.float32(0.125) * x).astype(np.float32)
+    z = (np.float32(-0.5) * x).astype(np.float32)
+    o = np.random.default_rng(31).permutation(152)
+    io = np.array([0, 152], np.int64)
+    r = oracle.track(geo, P, io, y[o], z[o], rows.astype(np.uint16)[o], prec=64)
+    tl = r.tracklets
+    kept = np.nonzero(tl.status == 0)[0]
+    assert len(kept) >= 1
+    slope_y, slope_z = 0.125, -0.5
+    snp = slope_y / np.hypot(1.0, slope_y)
+    tgl = slope_z / np.hypot(1.0, slope_y)
+    for t in kept:
+        assert tl.chi2[t] <= 1e-10
+        assert abs(tl.par[t, 2] - snp) <= 1e-12 and abs(tl.par[t, 3] - tgl) <= 1e-12
+        assert abs(tl.par[t, 4]) <= 1e-10
+        r0 = tl.rmin[t]
+        assert abs(tl.par[t, 0] - float(y[r0])) <= 1e-10
+        assert abs(tl.par[t, 1] - float(z[r0])) <= 1e-10
+    assert len(r.tracks.chi2) == 1 and r.tracks.hit_off[1] == 152
+
+
+@pytest.mark.parametrize("occ", [0.5, 1.0, 2.0])
+def test_grid_bins_hold_the_requested_occupancy(occ):
+    """R10 as a property: a row of n clusters asks for nb = floor(n / occ)
+    square bins over its data box.  Where the area term sets the width
+    (w^2 = dy dz / nb above both of its floors), ceil on each axis gives at
+    least nb bins, and one rounding step per axis stays within a small
+    factor of nb; over all rows the mean number of clusters per bin then
+    lies between occ / 2.5 and occ.  A width taken without the square root
+    would leave one or two bins per row."""
+    evs = (synth.config1(), synth.config2(n_tracks=2000))
+    for ev in evs:
+        Pk = dict(P, grid_occupancy=occ)
+        gr = oracle.grid_build(G, Pk, ev.inst_off, ev.y, ev.z, ev.row, prec=32)
+        tot_c = tot_b = 0
+        n_area = 0
+        for i in range(len(ev.inst_off) - 1):
+            a, b = int(ev.inst_off[i]), int(ev.inst_off[i + 1])
+            ys, zs, rs = ev.y[a:b].astype(np.float64), ev.z[a:b].astype(np.float64), ev.row[a:b]
+            for r in range(152):
+                ny, nz, _, cnt = gr.meta_i[i * 152 + r]
+                if cnt == 0:
+                    continue
+                sel = rs == r
+                dy = ys[sel].max() - ys[sel].min()
+                dz = zs[sel].max() - zs[sel].min()
+                nb = max(1, int(np.floor(cnt / occ)))
+                assert ny * nz <= 5 * nb + 4
+                if np.sqrt(dy * dz / nb) > max(1.0, max(dy, dz) / nb) * 1.001:
+                    n_area += 1
+                    assert nb <= ny * nz <= 2 * nb + 4, (i, r, ny, nz, nb)
+                tot_c += cnt
+                tot_b += ny * nz
+        assert n_area > 100
+        assert occ / 2.5 <= tot_c / tot_b <= occ

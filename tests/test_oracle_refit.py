@@ -129,3 +129,34 @@ def test_map_gradient_quadratic_relation_and_zero_at_truth(smear):
     assert abs(lhs / rhs - 1) < 0.03, (lhs, rhs)
     if not smear:
         assert np.linalg.norm(gt) < 1e-3 * np.linalg.norm(g0)
+
+
+def test_refit_rejects_tracks_with_invalid_hits():
+    """A hit naming no cluster, or a cluster on a row beyond the map, has no
+    measurement plane: its track is rejected as a whole (status 2, chi2 0,
+    zero gradient) and the other tracks are untouched."""
+    ev = _ev(12)
+    ho, hc, seed, D = _args(ev)
+    ref_chi2, ref_st, _ = oracle.refit(G, P, ev, ho, hc, seed, D, prec=64)
+    hc = hc.copy()
+    row = ev.row.copy()
+    hc[ho[3] + 2] = ev.n            # index past the last cluster
+    hc[ho[5]] = -1                  # negative index
+    row[hc[ho[7] + 4]] = 152        # row beyond the map
+    import copy
+    ev2 = copy.copy(ev)
+    ev2.row = row
+    for prec in (32, 64):
+        chi2, st, _ = oracle.refit(G, P, ev2, ho, hc, seed, D, prec=prec)
+        bad = [3, 5, 7]
+        assert np.all(st[bad] == 2) and np.all(chi2[bad] == 0)
+        good = np.setdiff1d(np.arange(len(st)), bad)
+        if prec == 64:
+            assert np.array_equal(chi2[good], ref_chi2[good]) and np.array_equal(st[good], ref_st[good])
+    _, st, gm, gx, gy, gz = oracle.refit_grad(G, P, ev2, ho, hc, seed, D)
+    for t in (3, 5, 7):
+        cl = hc[ho[t]:ho[t + 1]]
+        cl = cl[(cl >= 0) & (cl < ev.n)]
+        assert np.all(gx[cl] == 0) and np.all(gy[cl] == 0) and np.all(gz[cl] == 0)
+    loss = oracle.refit_loss(G, P, ev2, ho, hc, seed, D, np.ones(len(st)))
+    assert loss == pytest.approx(ref_chi2[st == 0].sum(), rel=1e-12)
