@@ -303,6 +303,25 @@ tpc_status tpc_refit_backward(const tpc_geometry* geom, const tpc_params* params
                               float* grad_map_dev, float* grad_x_dev, float* grad_y_dev,
                               float* grad_z_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Allocation-free variant of tpc_refit_backward, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid hipMalloc): the same kernels, with
+ * the map-gradient accumulators and the overflow flag (the workspace of
+ * tpc_refit_backward, tpc_refit_workspace_bytes() bytes) in a static array
+ * of the library that each GPU holds once, for the whole process.  Its size
+ * does not depend on the inputs, so no input is too large for it.  Every
+ * call on a GPU shares that GPU's array, which each call clears itself
+ * before use (with a kernel, no memset): calls that overlap on one GPU race
+ * and must not be issued on concurrent streams.  Arguments, outputs and
+ * errors as tpc_refit_backward; nothing is allocated, not even on the first
+ * call on a device (which looks the array's address up once). */
+tpc_status tpc_refit_backward_noalloc(const tpc_geometry* geom, const tpc_params* params,
+                                      int64_t n_clusters, tpc_clusters in, tpc_refit_tracks trk,
+                                      const float* dist_map_dev, const float* ckpt_dev,
+                                      const int32_t* status_dev, const float* grad_chi2_dev,
+                                      float* grad_map_dev, float* grad_x_dev, float* grad_y_dev,
+                                      float* grad_z_dev, void* stream);
+
 /* Optional per-kernel timing for benchmarks.  tpc_profile_enable(1) creates
  * a pool of HIP events (host call, once); afterwards every kernel the library
  * enqueues is bracketed by two events recorded on the stream it is launched

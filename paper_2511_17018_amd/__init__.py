@@ -386,6 +386,27 @@ def refit_backward(geom: dict, xyz: torch.Tensor, row: torch.Tensor, trk: RefitT
     return gmap, gxyz[:, :nc]
 
 
+def refit_backward_noalloc(geom: dict, xyz: torch.Tensor, row: torch.Tensor, trk: RefitTracks,
+                           dist_map: torch.Tensor, ckpt: torch.Tensor, status: torch.Tensor,
+                           grad_chi2: torch.Tensor, gmap: torch.Tensor, gxyz: torch.Tensor):
+    """tpc_refit_backward_noalloc into caller-given outputs grad_map[152, 18]
+    and grad_xyz[3, >= n_clusters] (the library allocates nothing)."""
+    nc = xyz.shape[1]
+    assert gmap.is_contiguous() and gmap.numel() == N_ROWS * N_PHI
+    assert gxyz.is_contiguous() and gxyz.shape[0] == 3 and gxyz.shape[1] >= max(nc, 1)
+    L = lib()
+    L.tpc_refit_backward_noalloc.restype = C.c_int
+    g = make_geometry(geom)
+    p = make_params(True)
+    ckpt_p = _ptr(ckpt) if trk.n_hits else C.c_void_p(0)
+    _check(L.tpc_refit_backward_noalloc(
+        C.byref(g), C.byref(p), C.c_int64(nc), _xyz_struct(xyz, row), trk.struct(),
+        _ptr(dist_map.contiguous()), ckpt_p, _ptr(status), _ptr(grad_chi2.contiguous()),
+        _ptr(gmap), _ptr(gxyz[0]), _ptr(gxyz[1]), _ptr(gxyz[2]), _stream()),
+        "tpc_refit_backward_noalloc")
+    return gmap, gxyz[:, :nc]
+
+
 class TpcRefit(torch.autograd.Function):
     """chi2[t] of every found track under the distortion map, differentiable
     with respect to the cluster coordinates xyz[3, N] and the map [152, 18].

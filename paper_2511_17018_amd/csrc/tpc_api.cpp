@@ -374,7 +374,7 @@ tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, 
   return e == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 
-size_t tpc_refit_workspace_bytes(void) { return (size_t)(8 * kRows * kPhi + 256); }
+size_t tpc_refit_workspace_bytes(void) { return bwd::refit_scratch_bytes(); }
 
 static tpc_status refit_check(const tpc_geometry* g, const tpc_params* p, int64_t n_clusters,
                               const tpc_clusters& in, const tpc_refit_tracks& trk,
@@ -430,6 +430,48 @@ tpc_status tpc_refit(const tpc_geometry* geom, const tpc_params* params, int64_t
   return e == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 
+static tpc_status refit_backward_check(const tpc_geometry* geom, const tpc_params* params,
+                                       int64_t n_clusters, const tpc_clusters& in,
+                                       const tpc_refit_tracks& trk, const float* dist_map_dev,
+                                       const float* ckpt_dev, const int32_t* status_dev,
+                                       const float* grad_chi2_dev, const float* grad_map_dev,
+                                       const float* grad_x_dev, const float* grad_y_dev,
+                                       const float* grad_z_dev)
+{
+  tpc_status st = refit_check(geom, params, n_clusters, in, trk, dist_map_dev);
+  if (st != TPC_OK) return st;
+  if (!grad_map_dev) return TPC_ERR_INVALID;
+  if (trk.n_tracks > 0 && (!status_dev || !grad_chi2_dev)) return TPC_ERR_INVALID;
+  if (trk.n_hits > 0 && (!ckpt_dev || reinterpret_cast<uintptr_t>(ckpt_dev) % 16))
+    return TPC_ERR_INVALID;
+  if (n_clusters > 0 && (!grad_x_dev || !grad_y_dev || !grad_z_dev)) return TPC_ERR_INVALID;
+  return TPC_OK;
+}
+
+tpc_status tpc_refit_backward_noalloc(const tpc_geometry* geom, const tpc_params* params,
+                                      int64_t n_clusters, tpc_clusters in, tpc_refit_tracks trk,
+                                      const float* dist_map_dev, const float* ckpt_dev,
+                                      const int32_t* status_dev, const float* grad_chi2_dev,
+                                      float* grad_map_dev, float* grad_x_dev, float* grad_y_dev,
+                                      float* grad_z_dev, void* stream)
+{
+  tpc_status st = refit_backward_check(geom, params, n_clusters, in, trk, dist_map_dev, ckpt_dev,
+                                       status_dev, grad_chi2_dev, grad_map_dev, grad_x_dev,
+                                       grad_y_dev, grad_z_dev);
+  if (st != TPC_OK) return st;
+  RefitBufs b = refit_bufs(n_clusters, in, trk, dist_map_dev);
+  b.ckpt = const_cast<float*>(ckpt_dev);
+  b.status = const_cast<int32_t*>(status_dev);
+  b.grad_chi2 = grad_chi2_dev;
+  b.grad_map = grad_map_dev;
+  b.gx = grad_x_dev;
+  b.gy = grad_y_dev;
+  b.gz = grad_z_dev;
+  const Consts k = make_consts(geom, params);
+  hipError_t e = bwd::refit_backward_noalloc(k, b, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+}
+
 tpc_status tpc_refit_backward(const tpc_geometry* geom, const tpc_params* params,
                               int64_t n_clusters, tpc_clusters in, tpc_refit_tracks trk,
                               const float* dist_map_dev, const float* ckpt_dev,
@@ -437,13 +479,11 @@ tpc_status tpc_refit_backward(const tpc_geometry* geom, const tpc_params* params
                               float* grad_map_dev, float* grad_x_dev, float* grad_y_dev,
                               float* grad_z_dev, void* ws_dev, size_t ws_bytes, void* stream)
 {
-  tpc_status st = refit_check(geom, params, n_clusters, in, trk, dist_map_dev);
+  tpc_status st = refit_backward_check(geom, params, n_clusters, in, trk, dist_map_dev, ckpt_dev,
+                                       status_dev, grad_chi2_dev, grad_map_dev, grad_x_dev,
+                                       grad_y_dev, grad_z_dev);
   if (st != TPC_OK) return st;
-  if (!grad_map_dev || !ws_dev) return TPC_ERR_INVALID;
-  if (trk.n_tracks > 0 && (!status_dev || !grad_chi2_dev)) return TPC_ERR_INVALID;
-  if (trk.n_hits > 0 && (!ckpt_dev || reinterpret_cast<uintptr_t>(ckpt_dev) % 16))
-    return TPC_ERR_INVALID;
-  if (n_clusters > 0 && (!grad_x_dev || !grad_y_dev || !grad_z_dev)) return TPC_ERR_INVALID;
+  if (!ws_dev) return TPC_ERR_INVALID;
   if (ws_bytes < tpc_refit_workspace_bytes()) return TPC_ERR_WORKSPACE;
   if (reinterpret_cast<uintptr_t>(ws_dev) % 8) return TPC_ERR_INVALID;
   RefitBufs b = refit_bufs(n_clusters, in, trk, dist_map_dev);

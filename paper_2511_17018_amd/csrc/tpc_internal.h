@@ -136,6 +136,9 @@ int64_t scan_partials(int64_t n);
 
 namespace bwd {
 hipError_t refit_backward(const Consts& k, const RefitBufs& b, hipStream_t s);
+// the same on the library's static per-device scratch (b.acc, b.flags unused)
+hipError_t refit_backward_noalloc(const Consts& k, RefitBufs b, hipStream_t s);
+size_t refit_scratch_bytes();
 }
 
 TPCCA_DECLARE_LAUNCHERS(det)

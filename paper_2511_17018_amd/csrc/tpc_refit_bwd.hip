@@ -20,6 +20,8 @@
 // The gradient is compared with the binary64 reference within a tolerance,
 // not bit for bit, so this file is built once, with fast math (no contraction
 // constraints).
+#include <mutex>
+
 #include "tpc_internal.h"
 
 namespace tpcca {
@@ -502,6 +504,53 @@ __global__ void k_refit_bwd_map(RefitBufs b)
 }
 
 }  // namespace
+
+// Device memory of the allocation-free entry point: the reverse pass's map
+// accumulators and overflow flag (the same layout as its workspace).  Each
+// GPU holds its own copy until the process ends; every allocation-free call
+// on a GPU shares it.  Host code never uses the array's name as an address:
+// kernels get the device address that hipGetSymbolAddress returns.
+constexpr size_t kScratchBytes = 8 * kRows * kPhi + 256;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// the current device's address of `scratch`, looked up once per device
+hipError_t scratch_address(void** out)
+{
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+size_t refit_scratch_bytes() { return kScratchBytes; }
+
+hipError_t refit_backward_noalloc(const Consts& k, RefitBufs b, hipStream_t s)
+{
+  void* p = nullptr;
+  const hipError_t e = scratch_address(&p);
+  if (e != hipSuccess) return e;
+  b.acc = static_cast<long long*>(p);
+  b.flags = reinterpret_cast<int*>(static_cast<char*>(p) + 8 * kRows * kPhi);
+  return refit_backward(k, b, s);
+}
 
 hipError_t refit_backward(const Consts& k, const RefitBufs& b, hipStream_t s)
 {

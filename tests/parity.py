@@ -152,11 +152,72 @@ def match_tracks(hit_off_a, hit_clu_a, hit_off_b, hit_clu_b, n):
     return float(diff.mean()) if n else 0.0
 
 
-def replay_params(g: dict, prec=64):
-    """binary64 replay of every kept GPU tracklet on its own hit list."""
+def check_structure(g: dict, row: np.ndarray, min_track_hits: int = 10) -> list:
+    """Validity of a tracking output whatever its order (production mode):
+    hit_off ascending from 0; every track holds at least min_track_hits
+    clusters in strictly ascending row; no cluster on two tracks; clu2trk
+    names exactly the track of every listed cluster and -1 elsewhere; the
+    counts agree with the result word and nothing overflowed."""
+    e = []
+    res = g["result"]
+    ho, hc, c2t = g["hit_off"], g["hit_clu"], g["clu2trk"]
+    nt = len(ho) - 1
+    if int(res["overflow"]) != 0:
+        e.append(f"overflow {res['overflow']}")
+    if nt != int(res["n_tracks"]) or nt != int(res["need_tracks"]):
+        e.append(f"tracks {nt} vs n_tracks {res['n_tracks']} need {res['need_tracks']}")
+    if len(hc) != int(res["n_hits"]) or len(hc) != int(res["need_hits"]) or ho[-1] != len(hc):
+        e.append(f"hits {len(hc)} vs n_hits {res['n_hits']} need {res['need_hits']} end {ho[-1]}")
+        return e
+    if ho[0] != 0 or np.any(np.diff(ho) < min_track_hits):
+        e.append("hit_off not ascending by at least min_track_hits")
+        return e
+    if len(hc) and (hc.min() < 0 or hc.max() >= len(c2t)):
+        e.append("hit list names a cluster out of range")
+        return e
+    if len(np.unique(hc)) != len(hc):
+        e.append(f"{len(hc) - len(np.unique(hc))} clusters on more than one track")
+    trk = np.repeat(np.arange(nt), np.diff(ho))
+    if not np.array_equal(c2t[hc], trk):
+        e.append("clu2trk disagrees with the hit lists")
+    listed = np.zeros(len(c2t), bool)
+    listed[hc] = True
+    if np.any(c2t[~listed] != -1):
+        e.append("clu2trk names a track for an unlisted cluster")
+    r = row[hc].astype(np.int64)
+    same = trk[1:] == trk[:-1]
+    if np.any(r[1:][same] <= r[:-1][same]):
+        e.append("rows not strictly ascending within a track")
+    return e
+
+
+K_PROD = 10.0   # production error allowed per component, relative to binary32's
+
+
+def prod_param_errors(g: dict, kept=None):
+    """Per kept tracklet and parameter: the production error and the
+    deterministic binary32 filter's error on the same hit list, both against
+    the binary64 replay of that list, relative to max(|p64|, floor)."""
+    e_prod = replay_params(g, kept=kept)
+    e_32 = replay_params(g, kept=kept, against=32)
+    return e_prod, e_32
+
+
+def prod_bound_violations(e_prod, e_32, k=K_PROD, base=1e-4):
+    """Tracklets whose production error exceeds max(base, k * binary32 error)
+    in some parameter."""
+    bound = np.maximum(base, k * e_32)
+    return np.nonzero(np.any(e_prod > bound, axis=1))[0]
+
+
+def replay_params(g: dict, prec=64, kept=None, against=None):
+    """binary64 replay of every kept GPU tracklet on its own hit list:
+    relative errors of the GPU parameters (or, with against=32, of the
+    binary32 replay of the same list) with respect to it."""
     floor = np.array([1, 1, 0.01, 0.01, 0.01])
     rel = []
-    for t in np.nonzero(g["tl_status"] == 0)[0]:
+    ts = np.nonzero(g["tl_status"] == 0)[0] if kept is None else kept
+    for t in ts:
         h0 = g["start"][t]
         r0 = int(g["sseg"][h0] % NR)
         rmin, rmax = int(g["tl_rmin"][t]), int(g["tl_rmax"][t])
@@ -170,6 +231,13 @@ def replay_params(g: dict, prec=64):
         hz[rows[m]] = g["zs"][hh[m]]
         has[rows[m]] = 1
         ok, par, cov, chi2 = oracle.replay(G, P, r0, rmin, rmax, hy, hz, has, prec=prec)
-        if ok:
-            rel.append(np.abs(g["tl_par"][t] - par) / np.maximum(np.abs(par), floor))
+        if not ok:
+            rel.append(np.full(5, np.nan))
+            continue
+        if against == 32:
+            ok32, p32, _, _ = oracle.replay(G, P, r0, rmin, rmax, hy, hz, has, prec=32)
+            cand = p32.astype(np.float64) if ok32 else np.full(5, np.inf)
+        else:
+            cand = g["tl_par"][t]
+        rel.append(np.abs(cand - par) / np.maximum(np.abs(par), floor))
     return np.array(rel).reshape(-1, 5)
