@@ -26,9 +26,11 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-W
           "-Wno-unused-function"]
 
 
-def build(force: bool = True, out: str | None = None, srcdir: str | None = None) -> str:
+def build(force: bool = True, out: str | None = None, srcdir: str | None = None,
+          extra: tuple = ()) -> str:
     """Compile liboracle.so with gcc (binary32 and binary64 objects; the
-    refit also as complex binary64) from the C sources in `srcdir`."""
+    refit also as complex binary64) from the C sources in `srcdir`; `extra`
+    flags go to every compile and the link (e.g. sanitizers)."""
     out = out or LIB
     if not force and os.path.exists(out):
         return out
@@ -39,11 +41,11 @@ def build(force: bool = True, out: str | None = None, srcdir: str | None = None)
                                         ("rc128", ["-DORC_C128"])))):
         for tag, defs in tags:
             obj = out + f".{tag}.o"
-            subprocess.run(["gcc", *CFLAGS, *defs, "-I", srcdir, "-c",
+            subprocess.run(["gcc", *CFLAGS, *extra, *defs, "-I", srcdir, "-c",
                             os.path.join(srcdir, name), "-o", obj], check=True)
             objs.append(obj)
     tmp = out + ".tmp"
-    subprocess.run(["gcc", "-shared", "-o", tmp, *objs, "-lm"], check=True)
+    subprocess.run(["gcc", "-shared", *extra, "-o", tmp, *objs, "-lm"], check=True)
     os.replace(tmp, out)
     for o in objs:
         os.remove(o)
@@ -345,6 +347,14 @@ def update(geom, p, c, my, mz, prec=64):
     f.restype = sc
     ch = f(C.byref(g), _p(p), _p(c), sc(my), sc(mz))
     return float(ch), p, c
+
+
+def underflow_raised(clear: bool = True) -> bool:
+    """The IEEE underflow flag of this thread (R29: no operation of the
+    binary32 reference may deliver a subnormal); clear resets it."""
+    f = lib().orc_underflow_raised
+    f.restype = C.c_int
+    return bool(f(C.c_int(1 if clear else 0)))
 
 
 # ----------------------------------------------------------------------------

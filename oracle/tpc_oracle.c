@@ -620,3 +620,16 @@ real SFX(orc_update)(const orc_geom* g, real* p, real* c, real my, real mz)
   memcpy(c, s.c, sizeof(s.c));
   return chi2;
 }
+
+#if !defined(ORC_F64)
+#include <fenv.h>
+/* R29 check: whether an operation since the last clear delivered a tiny
+ * (subnormal or flushed) inexact result -- the IEEE underflow flag of the
+ * calling thread.  clear != 0 resets the flag after reading it. */
+int orc_underflow_raised(int clear)
+{
+  const int r = fetestexcept(FE_UNDERFLOW) != 0;
+  if (clear) feclearexcept(FE_UNDERFLOW);
+  return r;
+}
+#endif
