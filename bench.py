@@ -223,7 +223,16 @@ def run(args) -> dict:
     S = int(min(res["n_start"], cap))
     i32 = torch.int32
     nhit = ws.view("tl_nhit", i32, cap)[:S].to(torch.int64).sum().item()
-    ncand = ws.view("tl_ncand", i32, cap)[:S].to(torch.int64).sum().item()
+    # E: clusters inside the extension searches' window boxes, counted by the
+    # instrumented tracklet kernel in an untimed run (same results)
+    cnt_c = Chain(geom, batch, True, stream, count=True, **tp)
+    with torch.cuda.stream(stream):
+        cnt_c.enqueue()
+    stream.synchronize()
+    if int(cnt_c.result()["n_tracks"]) != int(res["n_tracks"]):
+        raise RuntimeError("instrumented run differs")
+    ncand = cnt_c.ws.view("tl_ncand", i32, cap)[:S].to(torch.int64).sum().item()
+    del cnt_c
     counts = dict(N=N, S=S, Ht=nhit, E=ncand, bins=int(res["n_bins"]), Hs=int(res["n_hits"]))
     dom = max(ktimes.items(), key=lambda kv: kv[1][0])
     name, (tot_ms, launches) = dom

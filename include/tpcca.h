@@ -62,8 +62,12 @@ typedef enum {
  * HIP graph as it is; no flag asks for that.) */
 enum {
   TPC_FLAG_DETERMINISTIC = 1u, /* contraction-free code object + ordering kernels (Sec. 2) */
-  TPC_FLAG_GENERIC = 8u        /* never use the kernels compiled for the standard
+  TPC_FLAG_GENERIC = 8u,       /* never use the kernels compiled for the standard
                                   configuration (results are the same; for measuring) */
+  TPC_FLAG_COUNT_CANDIDATES = 16u /* tpc_sector_track: an instrumented tracklet kernel
+                                  counts, per tracklet, the clusters inside its search
+                                  windows into the workspace's tl_ncand (results are the
+                                  same; slower; for byte counts) */
 };
 
 /* Detector description (host, by pointer).  n_rows must be 152; row_x are
@@ -166,8 +170,10 @@ typedef struct {
  *   tl_chi2            f32[cap_tracklets]      tl_nhit, tl_rmin, tl_rmax, tl_status i32
  *   tl_hit             i32[152][cap_tracklets] (row-major by row: slot of row r of
  *                      tracklet t at r * cap_tracklets + t; -1 outside rmin..rmax)
- *   tl_ncand           i32[cap_tracklets] grid candidates whose chi2 the extension
- *                      searches evaluated (instrumentation for byte counts)
+ *   tl_ncand           i32[cap_tracklets] with TPC_FLAG_COUNT_CANDIDATES: clusters
+ *                      inside the extension searches' window boxes (the candidates
+ *                      any search must examine, whatever the bin size); otherwise
+ *                      not written
  *   owner              u64[n_clusters]  selection keys per position          */
 typedef struct {
   int64_t up, dn, up2, dn2, start;

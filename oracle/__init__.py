@@ -38,7 +38,8 @@ def build(force: bool = True, out: str | None = None, srcdir: str | None = None,
     objs = []
     for name, tags in (("tpc_oracle.c", (("f32", []), ("f64", ["-DORC_F64"]))),
                        ("tpc_refit.c", (("rf32", []), ("rf64", ["-DORC_F64"]),
-                                        ("rc128", ["-DORC_C128"])))):
+                                        ("rc128", ["-DORC_C128"]))),
+                       ("tpc_transform.c", (("tf32", []), ("tf64", ["-DORC_F64"])))):
         for tag, defs in tags:
             obj = out + f".{tag}.o"
             subprocess.run(["gcc", *CFLAGS, *extra, *defs, "-I", srcdir, "-c",
@@ -434,3 +435,52 @@ def refit_grad(geom, params, ev_like, hit_off, hit_clu, seed, dmap, w=None, ckpt
       _p(np.ascontiguousarray(status, np.int32)), _p(w), C.c_int64(nc), _p(gmap), _p(gx), _p(gy),
       _p(gz))
     return chi2, status, gmap.reshape(g.n_rows, 18), gx[:nc], gy[:nc], gz[:nc]
+
+
+# ----------------------------------------------------------------------------
+# cluster coordinate transformation (f3)
+
+class TGeom(C.Structure):
+    _fields_ = [("row_x", C.c_float * N_ROWS_MAX), ("pad_w", C.c_float * N_ROWS_MAX),
+                ("pad_c", C.c_float * N_ROWS_MAX), ("tbin", C.c_float), ("vdrift", C.c_float),
+                ("zlen", C.c_float), ("t0", C.c_float), ("nu", C.c_int32), ("nv", C.c_int32),
+                ("nw", C.c_int32), ("u0", C.c_float), ("iu", C.c_float), ("v0", C.c_float),
+                ("iv", C.c_float), ("w0", C.c_float), ("iw", C.c_float)]
+
+
+def make_tgeom(tg: dict) -> TGeom:
+    t = TGeom()
+    for name in ("row_x", "pad_w", "pad_c"):
+        arr = np.asarray(tg[name], np.float32)
+        for r in range(N_ROWS_MAX):
+            getattr(t, name)[r] = float(arr[r])
+    for name in ("tbin", "vdrift", "zlen", "t0", "u0", "iu", "v0", "iv", "w0", "iw"):
+        setattr(t, name, float(np.float32(tg[name])))
+    for name in ("nu", "nv", "nw"):
+        setattr(t, name, int(tg[name]))
+    return t
+
+
+def transform(tg: dict, sector, row, pad, time, dmap=None, rmap=None, prec=32):
+    """R31-R34: raw clusters (sector, row, pad, time) to tracker inputs
+    (x, y, z, row); dmap [152, 18] radial offsets, rmap [36, nu, nv, nw, 4]
+    residual corrections (None: not applied)."""
+    T = make_tgeom(tg)
+    n = len(row)
+    dt = _dt(prec)
+    sector = np.ascontiguousarray(sector, np.uint8)
+    row = np.ascontiguousarray(row, np.uint16)
+    pad = np.ascontiguousarray(pad, np.float32)
+    time = np.ascontiguousarray(time, np.float32)
+    dm = None if dmap is None else np.ascontiguousarray(dmap, np.float32)
+    rm = None if rmap is None else np.ascontiguousarray(rmap, np.float32)
+    x = np.empty(max(n, 1), dt)
+    y = np.empty(max(n, 1), dt)
+    z = np.empty(max(n, 1), dt)
+    ro = np.empty(max(n, 1), np.uint16)
+    f = getattr(lib(), f"orc_transform_f{prec}")
+    f.restype = None
+    f(C.byref(T), C.c_int64(n), _p(sector), _p(row), _p(pad), _p(time),
+      _p(dm) if dm is not None else None, _p(rm) if rm is not None else None,
+      _p(x), _p(y), _p(z), _p(ro))
+    return x[:n], y[:n], z[:n], ro[:n]

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libtpcca.so")
 N_ROWS = 152
 FLAG_DETERMINISTIC = 1
 FLAG_GENERIC = 8
+FLAG_COUNT_CANDIDATES = 16
 
 _lib = None
 
@@ -118,9 +119,10 @@ def make_geometry(geom: dict) -> Geometry:
     return g
 
 
-def make_params(det: bool = True, generic: bool = False, **over) -> Params:
+def make_params(det: bool = True, generic: bool = False, count: bool = False, **over) -> Params:
     """Default parameters with overrides; `generic` keeps the library from
-    using its kernels compiled for the standard configuration."""
+    using its kernels compiled for the standard configuration; `count` runs
+    the instrumented tracklet kernel (window candidates in tl_ncand)."""
     p = Params()
     lib().tpc_default_params(C.byref(p))
     for k, v in over.items():
@@ -128,6 +130,8 @@ def make_params(det: bool = True, generic: bool = False, **over) -> Params:
     p.flags = (p.flags | FLAG_DETERMINISTIC) if det else (p.flags & ~FLAG_DETERMINISTIC)
     if generic:
         p.flags |= FLAG_GENERIC
+    if count:
+        p.flags |= FLAG_COUNT_CANDIDATES
     return p
 
 

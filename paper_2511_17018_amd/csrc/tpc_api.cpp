@@ -17,7 +17,8 @@ namespace {
 constexpr int64_t kAlign = 256;
 constexpr int64_t kScanTile = 2048;  // items per block of the scan kernels
 constexpr int64_t kMaxInstClusters = (int64_t)1 << 24;
-constexpr uint32_t kKnownFlags = TPC_FLAG_DETERMINISTIC | TPC_FLAG_GENERIC;
+constexpr uint32_t kKnownFlags =
+    TPC_FLAG_DETERMINISTIC | TPC_FLAG_GENERIC | TPC_FLAG_COUNT_CANDIDATES;
 
 int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -364,6 +365,7 @@ tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, 
   b.counters = at<int64_t>(ws_dev, w.counters);
   b.scan_tmp = at<int64_t>(ws_dev, w.pub.scratch);
   b.scan_tmp_len = w.scan_len;
+  b.count_candidates = (params->flags & TPC_FLAG_COUNT_CANDIDATES) != 0;
   b.out = *out;
   b.res = result_dev;
   const Consts k = make_consts(geom, params);

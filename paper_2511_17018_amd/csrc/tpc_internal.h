@@ -93,6 +93,7 @@ struct TrackBufs {
   int64_t* tl_first;   // [n_inst + 1] first tracklet of each instance
   int64_t* chunk_off;  // [n_inst + 1] first tracklet chunk of each instance
   int64_t* counters;   // [8] device counters
+  bool count_candidates;  // instrumented tracklet kernel (tl_ncand)
   // outputs
   tpc_tracks out;
   tpc_result* res;

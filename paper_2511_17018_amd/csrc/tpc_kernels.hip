@@ -999,6 +999,7 @@ constexpr int kSrchZ = 4, kSrchC = 4;
 // The pick is a total order -- smallest chi2, then smallest input index --
 // so the scan order does not matter; the input index is read only on an
 // exact tie.
+template <bool COUNT>
 __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b,
                                            const tpc_row_meta& m, const KSt& st,
                                            const Innov& q, int& ncand)
@@ -1031,7 +1032,6 @@ __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b,
     }
 #pragma unroll
     for (int u = 0; u < kSrchZ; u++) {
-      ncand += re[u] - ra[u];
       for (int p0 = ra[u]; p0 < re[u]; p0 += kSrchC) {
         float2 qv[kSrchC];
 #pragma unroll
@@ -1042,6 +1042,9 @@ __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b,
           const int p = p0 + c;
           if (p >= re[u]) continue;
           const float r0 = qv[c].x - y, r1 = qv[c].y - z;
+          // instrumentation only: the candidates inside the window box, the
+          // ones any implementation of the search has to examine
+          if constexpr (COUNT) ncand += (fabsf(r0) <= wy) & (fabsf(r1) <= wz);
           const float ch = chi2_of(q, r0, r1);
           if (!(ch <= pick)) continue;
           if (best < 0 || ch < bchi) {
@@ -1113,7 +1116,7 @@ __global__ __launch_bounds__(kBlock) void k_tl_chunks(TrackBufs b, int ch)
   }
 }
 
-template <int CH, bool SPEC>
+template <int CH, bool SPEC, bool COUNT>
 __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
 {
   const Consts& k = kconsts<SPEC>(karg);
@@ -1206,7 +1209,7 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
       // one filter update for both phases: the link's hit (phase 1, no cut)
       // or the row's best cluster (phase 2)
       const Innov q = innov(st, vy, vz);
-      const int32_t bh = phase == 1 ? hn : ksearch(k, b, m, st, q, ncand);
+      const int32_t bh = phase == 1 ? hn : ksearch<COUNT>(k, b, m, st, q, ncand);
       if (bh >= 0) {
         const float2 qb = b.yz[bh];
         chi2 += kupdate_q(st, q, qb.x, qb.y);
@@ -1256,7 +1259,7 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
       dn = false;
     } else {
       const Innov q = innov(st, vy, vz);
-      const int32_t bh = ksearch(k, b, m, st, q, ncand);
+      const int32_t bh = ksearch<COUNT>(k, b, m, st, q, ncand);
       if (bh >= 0) {
         const float2 qb = b.yz[bh];
         chi2 += kupdate_q(st, q, qb.x, qb.y);
@@ -1285,11 +1288,15 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
     b.tl_rmin[t] = rmin;
     b.tl_rmax[t] = rmax;
     b.tl_status[t] = stat;
-    b.tl_ncand[t] = ncand;
-    // the sweeps wrote every row of [rmin, rmax] (a hit or -1); the other
-    // rows read -1 too, since the selection scans whole rows
-    for (int r = 0; r < rmin; r++) H[(int64_t)r * cap] = -1;
-    for (int r = rmax + 1; r < kRows; r++) H[(int64_t)r * cap] = -1;
+    if constexpr (COUNT) b.tl_ncand[t] = ncand;
+  }
+  // the sweeps wrote every row of [rmin, rmax] (a hit or -1); the other rows
+  // read -1 too, since the selection scans whole rows.  The rows go in the
+  // same order in every lane, so a wave's stores of one row are contiguous
+  // (lane-own row ranges scattered them over 64 cache lines).
+  for (int r = 0; r < kRows; r++)
+    if (mine && (r < rmin || r > rmax)) H[(int64_t)r * cap] = -1;
+  if (mine) {
     // selection key, 0 for a rejected tracklet (it never owns a hit)
     const int64_t lid = (int64_t)b.perm[b.start[t]] - b.inst_off[inst];
     b.tl_key[t] = stat == 0 ? sel_key(n, chi2, lid) : 0ull;
@@ -1588,9 +1595,10 @@ hipError_t sector_track_t(const Consts& k, const TrackBufs& b, hipStream_t s)
     // chunks are at most cap / CH + n_inst; whole groups of 8 workgroups
     const int64_t ub = (b.cap + k.tl_chunk - 1) / k.tl_chunk + b.n_inst;
     const unsigned tl_blocks = (unsigned)(((ub + 7) / 8) * 8);
-    const auto kt64 = k_tracklets<64, SPEC>;
-    const auto kt128 = k_tracklets<128, SPEC>;
-    const auto kt256 = k_tracklets<256, SPEC>;
+    const bool cnt = b.count_candidates;
+    const auto kt64 = cnt ? k_tracklets<64, SPEC, true> : k_tracklets<64, SPEC, false>;
+    const auto kt128 = cnt ? k_tracklets<128, SPEC, true> : k_tracklets<128, SPEC, false>;
+    const auto kt256 = cnt ? k_tracklets<256, SPEC, true> : k_tracklets<256, SPEC, false>;
     if (k.tl_chunk == 64)
       TPC_LAUNCH("tracklets", tl_blocks, 64, s, kt64, k, b);
     else if (k.tl_chunk == 128)

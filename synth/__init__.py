@@ -446,3 +446,117 @@ def config5(rep=0, n_found=200_000, min_hits=10, smear=True, amp=1.0) -> Event:
 
 def make(config: int, **kw) -> Event:
     return {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}[config](**kw)
+
+
+# ---------------------------------------------------------------------------
+# readout encoding for the cluster coordinate transformation (f3)
+
+T_BIN_US = 0.2                    # time-bin length (5 MHz sampling)
+PAD_W_INNER, PAD_W_OUTER = 0.42, 0.60   # pad widths [cm], rows < 63 and >= 63
+N_ROWS_INNER = 63
+
+
+def transform_geometry(nu=16, nv=9, nw=26, t0_us=0.0) -> dict:
+    """Readout description of the pad rows and the drift (detector data for
+    both implementations): pad width and centre pad per row, time-bin
+    length, drift velocity and length, the call's time offset, and the
+    residual-correction grid (nu nodes over the rows, nv over y/x beyond the
+    sector edges, nw over the drift distance)."""
+    g = geometry()
+    r = np.arange(N_ROWS)
+    pad_w = np.where(r < N_ROWS_INNER, PAD_W_INNER, PAD_W_OUTER)
+    tan_half = np.tan(np.radians(SECTOR_DEG / 2))
+    n_pads = 2 * np.ceil((g["row_x"].astype(np.float64) * tan_half + 2.0) / pad_w)
+    vmax = 1.05 * tan_half
+    return dict(row_x=g["row_x"], pad_w=pad_w.astype(np.float32),
+                pad_c=((n_pads - 1) / 2).astype(np.float32), n_pads=n_pads.astype(np.int32),
+                tbin=np.float32(T_BIN_US), vdrift=np.float32(V_DRIFT), zlen=np.float32(Z_MAX),
+                t0=np.float32(t0_us), nu=nu, nv=nv, nw=nw,
+                u0=np.float32(0.0), iu=np.float32((nu - 1) / (N_ROWS - 1)),
+                v0=np.float32(-vmax), iv=np.float32((nv - 1) / (2 * vmax)),
+                w0=np.float32(0.0), iw=np.float32((nw - 1) / Z_MAX))
+
+
+def cluster_sides(ev: Event) -> np.ndarray:
+    """Readout side of every cluster (1 = C, negative z): the instance's side
+    where instances are (sector, side) pairs, else the sign of z."""
+    if ev.n_inst == 2 * N_PHI and ev.name in ("config2", "config3"):
+        inst = np.repeat(np.arange(ev.n_inst), np.diff(ev.inst_off))
+        return (inst >= N_PHI).astype(np.uint8)
+    return (ev.z < 0).astype(np.uint8)
+
+
+class Distortion:
+    """A smooth space-point distortion per sector instance (36): each
+    transverse component (y, z) is a sum of three products of cosines in the
+    row fraction, y/x and the drift distance, with seeded amplitudes and
+    phases, at most `amp` cm.  Physics of the generator, not of the
+    method: measured position = true position + d(true position)."""
+
+    def __init__(self, amp=0.5, seed=SEED_BASE + 0x31):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        self.amp = amp
+        self.k = rng.integers(1, 4, (36, 3, 3, 3)).astype(np.float64)
+        self.ph = rng.uniform(0, 2 * np.pi, (36, 3, 3, 3))
+        self.a = rng.uniform(-1, 1, (36, 3, 3)) * amp / 3
+        # no radial component: a cluster is read on its pad row's plane
+        # (radial plane displacements are the refit's map D)
+        self.a[:, 0, :] = 0.0
+
+    def __call__(self, s, x, y, z):
+        """d(x, y, z) of sector instances s (arrays): [3, n] in cm."""
+        s = np.asarray(s, np.int64)
+        u = (np.asarray(x, np.float64) - X_INNER) / (X_OUTER - X_INNER)
+        v = np.asarray(y, np.float64) / np.asarray(x, np.float64) / np.tan(np.radians(10)) / 2
+        w = (Z_MAX - np.abs(np.asarray(z, np.float64))) / Z_MAX
+        out = np.zeros((3, len(s)))
+        for q in range(3):
+            for m in range(3):
+                k, ph = self.k[s, q, m], self.ph[s, q, m]
+                out[q] += self.a[s, q, m] * (np.cos(np.pi * k[:, 0] * u + ph[:, 0])
+                                             * np.cos(np.pi * k[:, 1] * v + ph[:, 1])
+                                             * np.cos(np.pi * k[:, 2] * w + ph[:, 2]))
+        return out
+
+
+def calibration_map(tg: dict, dist: Distortion) -> np.ndarray:
+    """The residual-correction map that undoes `dist` to first order: minus
+    the distortion at the grid nodes, float32 [36, nu, nv, nw, 4]."""
+    nu, nv, nw = tg["nu"], tg["nv"], tg["nw"]
+    u = np.float64(tg["u0"]) + np.arange(nu) / np.float64(tg["iu"])
+    v = np.float64(tg["v0"]) + np.arange(nv) / np.float64(tg["iv"])
+    w = np.float64(tg["w0"]) + np.arange(nw) / np.float64(tg["iw"])
+    U, V, W = np.meshgrid(u, v, w, indexing="ij")
+    x = X_INNER + U * (X_OUTER - X_INNER) / (N_ROWS - 1)
+    y = V * x
+    out = np.zeros((36, nu, nv, nw, 4), np.float32)
+    for s in range(36):
+        zs = (Z_MAX - W) * (-1.0 if s >= N_PHI else 1.0)
+        d = dist(np.full(x.size, s), x.ravel(), y.ravel(), zs.ravel())
+        for q in range(3):
+            out[s, ..., q] = (-d[q]).reshape(U.shape)
+    return out
+
+
+def encode_raw(ev: Event, tg: dict, dist: Distortion | None = None,
+               dmap: np.ndarray | None = None) -> dict:
+    """Readout coordinates of the event's clusters (binary64, rounded to
+    binary32 at the end): sector instance k + 18 side, row, pad, time.  With
+    `dist` the clusters are first displaced by the distortion (their
+    measured position); with `dmap` their plane is taken at x_r + D[r][k]
+    (a radial displacement the transformation's radial offset undoes)."""
+    side = cluster_sides(ev)
+    s = ev.sector.astype(np.int64) + N_PHI * side.astype(np.int64)
+    x = tg["row_x"][ev.row].astype(np.float64)
+    y = ev.y.astype(np.float64)
+    z = ev.z.astype(np.float64)
+    if dist is not None:
+        d = dist(s, x, y, z)
+        y = y + d[1]
+        z = z + d[2]
+    pad = y / tg["pad_w"][ev.row].astype(np.float64) + tg["pad_c"][ev.row].astype(np.float64)
+    sgn = np.where(side == 1, -1.0, 1.0)
+    drift = np.float64(tg["zlen"]) - sgn * z
+    time = (drift / np.float64(tg["vdrift"]) + np.float64(tg["t0"])) / np.float64(tg["tbin"])
+    return dict(sector=s.astype(np.uint8), row=ev.row.copy(), pad=pad.astype(np.float32),
+                time=time.astype(np.float32))

@@ -25,6 +25,7 @@ TRACK = ["tests/test_oracle_pins.py"]
 NOT_PINS = ["--deselect", "tests/test_oracle_pins.py::test_oracle_matches_stored_golden_summary"]
 REFIT = ["tests/test_oracle_refit.py"]
 BOTH = TRACK + REFIT
+TRANSFORM = ["tests/test_oracle_transform.py"]
 
 # (source file, pin files, what is planted, original text, planted text)
 MUTATIONS = [
@@ -77,6 +78,15 @@ MUTATIONS = [
     ("tpc_refit.c", REFIT, "refit drops last hit", "for (int64_t k = a + 1; k < b; k++) {\n    const int64_t c = hit_clu[k];\n    const real xk", "for (int64_t k = a + 1; k < b - 1; k++) {\n    const int64_t c = hit_clu[k];\n    const real xk"),
     ("tpc_refit.c", REFIT, "refit seed snp from tgl", "st.p[2] = (real)seed5[2];", "st.p[2] = (real)seed5[3];"),
     ("tpc_refit.c", REFIT, "refit x not advanced", "    xprev = xk;\n", "    (void)xk;\n"),
+    ("tpc_transform.c", TRANSFORM, "lerp reversed", "return a + (b - a) * t;", "return b + (a - b) * t;"),
+    ("tpc_transform.c", TRANSFORM, "cell fraction not clamped", "  if (t > 1) t = 1;\n", "\n"),
+    ("tpc_transform.c", TRANSFORM, "map v from the nominal plane", "cell(yc / xc,", "cell(yc / (real)T->row_x[r],"),
+    ("tpc_transform.c", TRANSFORM, "side sign", "real zc = side ? -za : za;", "real zc = side ? za : -za;"),
+    ("tpc_transform.c", TRANSFORM, "pad centre sign", "((real)pad[c] - (real)T->pad_c[r])", "((real)pad[c] + (real)T->pad_c[r])"),
+    ("tpc_transform.c", TRANSFORM, "time offset sign", "(real)T->tbin - (real)T->t0)", "(real)T->tbin + (real)T->t0)"),
+    ("tpc_transform.c", TRANSFORM, "map w from z", "cell(d, (real)T->w0,", "cell(za, (real)T->w0,"),
+    ("tpc_transform.c", TRANSFORM, "dz correction sign", "zc = zc + corr[2];", "zc = zc - corr[2];"),
+    ("tpc_transform.c", TRANSFORM, "map u and w lerp swapped", "corr[q] = lerp(f0, f1, au);", "corr[q] = lerp(f0, f1, aw);"),
 ]
 
 
