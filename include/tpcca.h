@@ -328,6 +328,56 @@ tpc_status tpc_refit_backward_noalloc(const tpc_geometry* geom, const tpc_params
                                       float* grad_map_dev, float* grad_x_dev, float* grad_y_dev,
                                       float* grad_z_dev, void* stream);
 
+/* f3: cluster coordinate transformation with corrections -- the step before
+ * tpc_grid_build.  Online TPC processing transforms the clusters' readout
+ * coordinates into space points, and the paper's offline-only corrections
+ * amend that transformation (Sec. 6: they cost about 20 % of the online
+ * time by making the code more complicated); the formulas are this
+ * library's (readings R31-R34 of the design notes):
+ *   raw cluster  sector s (0..35 = phi-sector k + 18 side, side 1 = C at
+ *                negative z), row r, pad and time (continuous pad and
+ *                time-bin coordinates);
+ *   nominal      x = row_x[r], y = (pad - pad_c[r]) * pad_w[r],
+ *                drift d = (time * tbin_us - t0_us) * vdrift,
+ *                z = zlen - d on side A, -(zlen - d) on side C;
+ *   corrections  x += dist_map[r][k] (the radial map that tpc_refit fits;
+ *                NULL: none), then a residual correction (dx, dy, dz)
+ *                added to (x, y, z), interpolated trilinearly in
+ *                (u = r, v = y / x, w = d) on a regular grid per sector s
+ *                (corr_map [36][nu][nv][nw] nodes of four floats dx, dy, dz,
+ *                unused; NULL: none): node i of an axis sits at
+ *                q0 + i / iq, the cell is clamp(floor((q - q0) iq), 0, n - 2)
+ *                and the fraction is clamped to [0, 1] (boundary values
+ *                continue outside the grid); three rounds of
+ *                lerp(a, b, t) = a + (b - a) t, along w, then v, then u.
+ * A raw cluster with s >= 36 or r >= 152 gets row_out 0xFFFF (and x = y =
+ * z = 0); non-finite pad or time give non-finite y or z.  tpc_grid_build
+ * counts both as invalid.  The outputs are the tracker's x, y, z, row
+ * arrays in the input order.  With TPC_FLAG_DETERMINISTIC the outputs equal
+ * the binary32 CPU reference bit for bit.
+ * Errors: TPC_ERR_INVALID (null pointers, n < 0, a grid axis with fewer
+ * than 2 nodes, unknown flags), TPC_ERR_HIP. */
+typedef struct {
+  float row_x[TPC_N_ROWS];  /* pad-row planes [cm] */
+  float pad_w[TPC_N_ROWS];  /* pad width [cm] */
+  float pad_c[TPC_N_ROWS];  /* centre pad coordinate of the row */
+  float tbin_us, vdrift_cm_us, zlen_cm, t0_us;
+  int32_t nu, nv, nw;       /* residual-map nodes per axis */
+  float u0, iu, v0, iv, w0, iw;  /* first node and inverse spacing per axis */
+} tpc_transform_geometry;
+
+typedef struct {
+  const uint8_t* sector;
+  const uint16_t* row;
+  const float *pad, *time;
+} tpc_raw_clusters;
+
+tpc_status tpc_cluster_transform(const tpc_transform_geometry* tg, uint32_t flags,
+                                 int64_t n_clusters, tpc_raw_clusters in,
+                                 const float* dist_map_dev, const float* corr_map_dev,
+                                 float* x_dev, float* y_dev, float* z_dev, uint16_t* row_dev,
+                                 void* stream);
+
 /* Optional per-kernel timing for benchmarks.  tpc_profile_enable(1) creates
  * a pool of HIP events (host call, once); afterwards every kernel the library
  * enqueues is bracketed by two events recorded on the stream it is launched

@@ -180,6 +180,16 @@ def upload(x, y, z, row, charge, inst_off, device="cuda") -> Batch:
                  t(charge, np.int16), off, torch.from_numpy(off).to(device))
 
 
+def upload_device(x: torch.Tensor, y: torch.Tensor, z: torch.Tensor, row: torch.Tensor,
+                  inst_off, charge: torch.Tensor | None = None) -> Batch:
+    """A batch from clusters already on the device (e.g. the output of
+    cluster_transform); inst_off is host data."""
+    off = np.ascontiguousarray(inst_off, np.int64)
+    if charge is None:
+        charge = torch.zeros_like(row)
+    return Batch(x, y, z, row, charge, off, torch.from_numpy(off).to(row.device))
+
+
 @dataclass
 class Grid:
     sseg: torch.Tensor
@@ -434,3 +444,59 @@ class TpcRefit(torch.autograd.Function):
         gmap, gxyz = refit_backward(ctx.geom, xyz_c, ctx.row, ctx.tracks, map_c, ckpt, status,
                                     grad_chi2.float().contiguous())
         return gxyz, gmap, None, None, None, None
+
+
+# ----------------------------------------------------------------------------
+# cluster coordinate transformation (tpc_cluster_transform)
+
+class TransformGeometry(C.Structure):
+    _fields_ = [("row_x", C.c_float * N_ROWS), ("pad_w", C.c_float * N_ROWS),
+                ("pad_c", C.c_float * N_ROWS), ("tbin_us", C.c_float), ("vdrift_cm_us", C.c_float),
+                ("zlen_cm", C.c_float), ("t0_us", C.c_float), ("nu", C.c_int32), ("nv", C.c_int32),
+                ("nw", C.c_int32), ("u0", C.c_float), ("iu", C.c_float), ("v0", C.c_float),
+                ("iv", C.c_float), ("w0", C.c_float), ("iw", C.c_float)]
+
+
+class RawClusters(C.Structure):
+    _fields_ = [("sector", C.c_void_p), ("row", C.c_void_p), ("pad", C.c_void_p),
+                ("time", C.c_void_p)]
+
+
+def make_transform_geometry(tg: dict) -> TransformGeometry:
+    t = TransformGeometry()
+    for name in ("row_x", "pad_w", "pad_c"):
+        arr = np.asarray(tg[name], np.float32)
+        for r in range(N_ROWS):
+            getattr(t, name)[r] = float(arr[r])
+    t.tbin_us, t.vdrift_cm_us = float(tg["tbin"]), float(tg["vdrift"])
+    t.zlen_cm, t.t0_us = float(tg["zlen"]), float(tg["t0"])
+    t.nu, t.nv, t.nw = int(tg["nu"]), int(tg["nv"]), int(tg["nw"])
+    for name in ("u0", "iu", "v0", "iv", "w0", "iw"):
+        setattr(t, name, float(np.float32(tg[name])))
+    return t
+
+
+def cluster_transform(tg: dict, sector: torch.Tensor, row: torch.Tensor, pad: torch.Tensor,
+                      time: torch.Tensor, dist_map=None, corr_map=None, det: bool = True,
+                      out=None):
+    """tpc_cluster_transform on the current stream: (x, y, z, row) tensors
+    (row int16-typed, holding the uint16 row or 0xFFFF).  `out` may give the
+    four output tensors."""
+    n = row.numel()
+    dev = row.device
+    if out is None:
+        out = (torch.empty(max(n, 1), dtype=torch.float32, device=dev),
+               torch.empty(max(n, 1), dtype=torch.float32, device=dev),
+               torch.empty(max(n, 1), dtype=torch.float32, device=dev),
+               torch.empty(max(n, 1), dtype=torch.int16, device=dev))
+    x, y, z, ro = out
+    t = make_transform_geometry(tg)
+    L = lib()
+    L.tpc_cluster_transform.restype = C.c_int
+    raw = RawClusters(_ptr(sector), _ptr(row), _ptr(pad), _ptr(time))
+    dm = _ptr(dist_map) if dist_map is not None else C.c_void_p(0)
+    cm = _ptr(corr_map) if corr_map is not None else C.c_void_p(0)
+    _check(L.tpc_cluster_transform(C.byref(t), C.c_uint32(FLAG_DETERMINISTIC if det else 0),
+                                   C.c_int64(n), raw, dm, cm, _ptr(x), _ptr(y), _ptr(z), _ptr(ro),
+                                   _stream()), "tpc_cluster_transform")
+    return x[:n], y[:n], z[:n], ro[:n]

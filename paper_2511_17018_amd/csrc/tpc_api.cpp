@@ -503,4 +503,54 @@ tpc_status tpc_refit_backward(const tpc_geometry* geom, const tpc_params* params
   return e == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 
+tpc_status tpc_cluster_transform(const tpc_transform_geometry* tg, uint32_t flags,
+                                 int64_t n_clusters, tpc_raw_clusters in,
+                                 const float* dist_map_dev, const float* corr_map_dev,
+                                 float* x_dev, float* y_dev, float* z_dev, uint16_t* row_dev,
+                                 void* stream)
+{
+  if (!tg || n_clusters < 0 || (flags & ~kKnownFlags)) return TPC_ERR_INVALID;
+  if (corr_map_dev && (tg->nu < 2 || tg->nv < 2 || tg->nw < 2)) return TPC_ERR_INVALID;
+  if (n_clusters > 0 && (!in.sector || !in.row || !in.pad || !in.time || !x_dev || !y_dev ||
+                         !z_dev || !row_dev))
+    return TPC_ERR_INVALID;
+  if (corr_map_dev && reinterpret_cast<uintptr_t>(corr_map_dev) % 16) return TPC_ERR_INVALID;
+  TransformConsts k;
+  memcpy(k.row_x, tg->row_x, sizeof(k.row_x));
+  memcpy(k.pad_w, tg->pad_w, sizeof(k.pad_w));
+  memcpy(k.pad_c, tg->pad_c, sizeof(k.pad_c));
+  k.tbin = tg->tbin_us;
+  k.vdrift = tg->vdrift_cm_us;
+  k.zlen = tg->zlen_cm;
+  k.t0 = tg->t0_us;
+  k.nu = tg->nu;
+  k.nv = tg->nv;
+  k.nw = tg->nw;
+  k.u0 = tg->u0;
+  k.iu = tg->iu;
+  k.v0 = tg->v0;
+  k.iv = tg->iv;
+  k.w0 = tg->w0;
+  k.iw = tg->iw;
+  TransformBufs b;
+  b.sector = in.sector;
+  b.row = in.row;
+  b.pad = in.pad;
+  b.time = in.time;
+  b.dmap = dist_map_dev;
+  b.rmap = reinterpret_cast<const float4*>(corr_map_dev);
+  b.x = x_dev;
+  b.y = y_dev;
+  b.z = z_dev;
+  b.row_out = row_dev;
+  b.n = n_clusters;
+  auto al = [](const void* p, uintptr_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; };
+  b.aligned = al(in.sector, 4) && al(in.row, 8) && al(in.pad, 16) && al(in.time, 16) &&
+              al(x_dev, 16) && al(y_dev, 16) && al(z_dev, 16) && al(row_dev, 8);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = (flags & TPC_FLAG_DETERMINISTIC) ? det::cluster_transform(k, b, s)
+                                                   : prod::cluster_transform(k, b, s);
+  return e == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+}
+
 }  // extern "C"

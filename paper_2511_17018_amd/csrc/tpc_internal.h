@@ -120,6 +120,27 @@ struct RefitBufs {
 
 constexpr int kPhi = 18;
 
+// Constants of the cluster transformation (f3), by value in the kernel
+// arguments.
+struct TransformConsts {
+  float row_x[kRows], pad_w[kRows], pad_c[kRows];
+  float tbin, vdrift, zlen, t0;
+  int32_t nu, nv, nw;
+  float u0, iu, v0, iv, w0, iw;
+};
+
+struct TransformBufs {
+  const uint8_t* sector;
+  const uint16_t* row;
+  const float *pad, *time;
+  const float* dmap;    // [152][18] or null
+  const float4* rmap;   // [36][nu][nv][nw] nodes (dx, dy, dz, unused) or null
+  float *x, *y, *z;
+  uint16_t* row_out;
+  int64_t n;
+  bool aligned;         // every array allows the four-cluster vector accesses
+};
+
 // Kernel timing hooks (tpc_profile_*): no-ops unless profiling is enabled.
 int prof_begin(hipStream_t s, const char* name);
 void prof_end(hipStream_t s, int slot);
@@ -133,6 +154,8 @@ int64_t scan_partials(int64_t n);
   hipError_t sector_track(const Consts& k, const TrackBufs& b, bool standard,       \
                           hipStream_t s);                                            \
   hipError_t refit_forward(const Consts& k, const RefitBufs& b, hipStream_t s);     \
+  hipError_t cluster_transform(const TransformConsts& k, const TransformBufs& b,    \
+                               hipStream_t s);                                       \
   }
 
 namespace bwd {

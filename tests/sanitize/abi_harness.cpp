@@ -152,6 +152,30 @@ static void invalid_calls()
                                     nullptr) == TPC_ERR_INVALID);
   EXPECT(tpc_refit_backward_noalloc(&g, &p, 1000, in, trk, dmap, f, st, f, nullptr, f, f, f,
                                     nullptr) == TPC_ERR_INVALID);
+  // cluster transformation
+  tpc_transform_geometry tg;
+  memset(&tg, 0, sizeof(tg));
+  tg.nu = tg.nv = tg.nw = 2;
+  tpc_raw_clusters raw = {(const uint8_t*)fake(0x9000), (const uint16_t*)fake(0x9000),
+                          (const float*)fake(0x9000), (const float*)fake(0x9000)};
+  const float* cm = (const float*)fake(0xA000);
+  uint16_t* ro = (uint16_t*)fake(0xB000);
+  EXPECT(tpc_cluster_transform(&tg, 1u, 1000, raw, dmap, cm, f, f, f, ro, nullptr) == TPC_OK);
+  EXPECT(tpc_cluster_transform(&tg, 1u, 0, raw, nullptr, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, nullptr) == TPC_OK);
+  EXPECT(tpc_cluster_transform(nullptr, 1u, 1000, raw, dmap, cm, f, f, f, ro, nullptr) ==
+         TPC_ERR_INVALID);
+  EXPECT(tpc_cluster_transform(&tg, 2u, 1000, raw, dmap, cm, f, f, f, ro, nullptr) ==
+         TPC_ERR_INVALID);
+  EXPECT(tpc_cluster_transform(&tg, 1u, -1, raw, dmap, cm, f, f, f, ro, nullptr) ==
+         TPC_ERR_INVALID);
+  EXPECT(tpc_cluster_transform(&tg, 1u, 1000, raw, dmap, cm, f, nullptr, f, ro, nullptr) ==
+         TPC_ERR_INVALID);
+  EXPECT(tpc_cluster_transform(&tg, 1u, 1000, raw, dmap, (const float*)fake(0xA004), f, f, f, ro,
+                               nullptr) == TPC_ERR_INVALID);
+  tg.nw = 1;
+  EXPECT(tpc_cluster_transform(&tg, 1u, 1000, raw, dmap, cm, f, f, f, ro, nullptr) ==
+         TPC_ERR_INVALID);
   for (int s = 1; s >= -5; s--) EXPECT(tpc_status_string((tpc_status)s) != nullptr);
   EXPECT(tpc_standard_configuration(&g, &p) == 1);
   EXPECT(tpc_standard_configuration(nullptr, &p) == TPC_ERR_INVALID);

@@ -104,6 +104,13 @@ static hipError_t refit_stub(const RefitBufs& b)
   {                                                                                  \
     return refit_stub(b);                                                            \
   }                                                                                  \
+  hipError_t cluster_transform(const TransformConsts& k, const TransformBufs& b,    \
+                               hipStream_t)                                          \
+  {                                                                                  \
+    if (b.n < 0 || (b.rmap && (k.nu < 2 || k.nv < 2 || k.nw < 2))) abort();          \
+    stub::g_calls++;                                                                 \
+    return hipSuccess;                                                               \
+  }                                                                                  \
   }
 STUB_NS(det)
 STUB_NS(prod)
