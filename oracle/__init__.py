@@ -39,7 +39,8 @@ def build(force: bool = True, out: str | None = None, srcdir: str | None = None,
     for name, tags in (("tpc_oracle.c", (("f32", []), ("f64", ["-DORC_F64"]))),
                        ("tpc_refit.c", (("rf32", []), ("rf64", ["-DORC_F64"]),
                                         ("rc128", ["-DORC_C128"]))),
-                       ("tpc_transform.c", (("tf32", []), ("tf64", ["-DORC_F64"])))):
+                       ("tpc_transform.c", (("tf32", []), ("tf64", ["-DORC_F64"]))),
+                       ("tpc_merge.c", (("mf32", []), ("mf64", ["-DORC_F64"])))):
         for tag, defs in tags:
             obj = out + f".{tag}.o"
             subprocess.run(["gcc", *CFLAGS, *extra, *defs, "-I", srcdir, "-c",
@@ -484,3 +485,117 @@ def transform(tg: dict, sector, row, pad, time, dmap=None, rmap=None, prec=32):
       _p(dm) if dm is not None else None, _p(rm) if rm is not None else None,
       _p(x), _p(y), _p(z), _p(ro))
     return x[:n], y[:n], z[:n], ro[:n]
+
+
+# ----------------------------------------------------------------------------
+# sector-track merging and the global refit (f1)
+
+class MParams(C.Structure):
+    _fields_ = [("max_dz", C.c_float), ("max_dist", C.c_float), ("chi2_max", C.c_float),
+                ("cos_a", C.c_float * 18), ("sin_a", C.c_float * 18), ("cos_d", C.c_float),
+                ("sin_d", C.c_float)]
+
+
+DEFAULT_MERGE = dict(max_dz=20.0, max_dist=40.0, chi2_max=30.0)
+
+
+def make_mparams(**over) -> MParams:
+    d = dict(DEFAULT_MERGE)
+    d.update(over)
+    m = MParams()
+    m.max_dz, m.max_dist, m.chi2_max = d["max_dz"], d["max_dist"], d["chi2_max"]
+    for k in range(18):
+        a = np.radians(20.0 * (k + 0.5))
+        m.cos_a[k] = float(np.float32(np.cos(a)))
+        m.sin_a[k] = float(np.float32(np.sin(a)))
+    m.cos_d = float(np.float32(np.cos(np.radians(20.0))))
+    m.sin_d = float(np.float32(np.sin(np.radians(20.0))))
+    return m
+
+
+@dataclass
+class Merged:
+    out_ok: np.ndarray
+    out_p: np.ndarray
+    out_c: np.ndarray
+    out_x: np.ndarray
+    succ: np.ndarray
+    pred: np.ndarray
+    succ_chi2: np.ndarray
+    pred_chi2: np.ndarray
+    next: np.ndarray
+    chain_off: np.ndarray
+    chain_seg: np.ndarray
+    hit_off: np.ndarray
+    hit_clu: np.ndarray
+    par: np.ndarray
+    cov: np.ndarray
+    chi2: np.ndarray
+    ndf: np.ndarray
+    status: np.ndarray
+    k: np.ndarray
+    x_ref: np.ndarray
+
+
+def merge(geom, inst_off, y, z, row, tracks, prec=32, **mover) -> Merged:
+    """R35-R41 on the sector tracker's tracks (an oracle.Tracks, or any
+    object with par, cov, x_ref, hit_off, hit_clu) of the 36 sector
+    instances."""
+    g = make_geom(geom)
+    M = make_mparams(**mover)
+    dt = _dt(prec)
+    n = len(tracks.hit_off) - 1
+    na = max(n, 1)
+    par = np.ascontiguousarray(tracks.par, dt).reshape(-1)
+    cov = np.ascontiguousarray(tracks.cov, dt).reshape(-1)
+    xr = np.ascontiguousarray(tracks.x_ref, np.float32)
+    ho = np.ascontiguousarray(tracks.hit_off, np.int32)
+    hc = np.ascontiguousarray(tracks.hit_clu, np.int32)
+    nh = int(ho[-1])
+    r = Merged(np.zeros(na, np.int32), np.zeros((na, 5), dt), np.zeros((na, 15), dt),
+               np.zeros(na, dt), np.zeros(na, np.int32), np.zeros(na, np.int32), np.zeros(na, dt),
+               np.zeros(na, dt), np.zeros(na, np.int32), np.zeros(na + 1, np.int32),
+               np.zeros(na, np.int32), np.zeros(na + 1, np.int32), np.zeros(max(nh, 1), np.int32),
+               np.zeros((na, 5), dt), np.zeros((na, 15), dt), np.zeros(na, dt),
+               np.zeros(na, np.int32), np.zeros(na, np.int32), np.zeros(na, np.int32),
+               np.zeros(na, np.float32))
+    f = _fn("orc_merge", prec)
+    f.restype = C.c_int64
+    nc = f(C.byref(g), C.byref(M), C.c_int64(n), _p(par if n else np.zeros(5, dt)),
+           _p(cov if n else np.zeros(15, dt)), _p(xr if n else np.zeros(1, np.float32)), _p(ho),
+           _p(hc if nh else np.zeros(1, np.int32)), _p(np.ascontiguousarray(inst_off, np.int64)),
+           _p(np.ascontiguousarray(row, np.uint16)), _p(np.ascontiguousarray(y, np.float32)),
+           _p(np.ascontiguousarray(z, np.float32)), _p(r.out_ok), _p(r.out_p), _p(r.out_c),
+           _p(r.out_x), _p(r.succ), _p(r.pred), _p(r.succ_chi2), _p(r.pred_chi2), _p(r.next),
+           _p(r.chain_off), _p(r.chain_seg), _p(r.hit_off), _p(r.hit_clu), _p(r.par), _p(r.cov),
+           _p(r.chi2), _p(r.ndf), _p(r.status), _p(r.k), _p(r.x_ref))
+    cut = lambda a, m: a[:m]  # noqa: E731
+    return Merged(cut(r.out_ok, n), cut(r.out_p, n), cut(r.out_c, n), cut(r.out_x, n),
+                  cut(r.succ, n), cut(r.pred, n), cut(r.succ_chi2, n), cut(r.pred_chi2, n),
+                  cut(r.next, n), r.chain_off[:nc + 1], cut(r.chain_seg, n), r.hit_off[:nc + 1],
+                  r.hit_clu[:nh], cut(r.par, nc), cut(r.cov, nc), cut(r.chi2, nc), cut(r.ndf, nc),
+                  cut(r.status, nc), cut(r.k, nc), cut(r.x_ref, nc))
+
+
+def rotate(geom, p, c, x, up, prec=64):
+    """R36 on one state: rotation into the next (up) or previous phi
+    sector's frame; returns (ok, p, c, x_new)."""
+    g = make_geom(geom)
+    M = make_mparams()
+    dt = _dt(prec)
+    p = np.array(p, dt)
+    c = np.array(c, dt)
+    xn = np.zeros(1, dt)
+    f = _fn("orc_rotate", prec)
+    f.restype = C.c_int
+    sc = C.c_double if prec == 64 else C.c_float
+    ok = f(C.byref(g), C.byref(M), _p(p), _p(c), sc(x), C.c_int(1 if up else 0), _p(xn))
+    return bool(ok), p, c, float(xn[0])
+
+
+def chi2_5(S15, d, prec=64):
+    """R37's chi2 d^T S^-1 d (S as a lower triangle in the tracker's order)."""
+    dt = _dt(prec)
+    f = _fn("orc_chi2_5", prec)
+    f.restype = C.c_double if prec == 64 else C.c_float
+    return float(f(_p(np.ascontiguousarray(S15, dt)), _p(np.ascontiguousarray(d, dt))))

@@ -26,6 +26,7 @@ NOT_PINS = ["--deselect", "tests/test_oracle_pins.py::test_oracle_matches_stored
 REFIT = ["tests/test_oracle_refit.py"]
 BOTH = TRACK + REFIT
 TRANSFORM = ["tests/test_oracle_transform.py"]
+MERGE = ["tests/test_oracle_merge.py"]
 
 # (source file, pin files, what is planted, original text, planted text)
 MUTATIONS = [
@@ -87,6 +88,16 @@ MUTATIONS = [
     ("tpc_transform.c", TRANSFORM, "map w from z", "cell(d, (real)T->w0,", "cell(za, (real)T->w0,"),
     ("tpc_transform.c", TRANSFORM, "dz correction sign", "zc = zc + corr[2];", "zc = zc - corr[2];"),
     ("tpc_transform.c", TRANSFORM, "map u and w lerp swapped", "corr[q] = lerp(f0, f1, au);", "corr[q] = lerp(f0, f1, aw);"),
+    ("tpc_merge.c", MERGE, "rotated y sign", "s->p[0] = y * ca - x * sa;", "s->p[0] = y * ca + x * sa;"),
+    ("tpc_merge.c", MERGE, "rotation jacobian j00 sign", "const real j00 = ca - sa * (snn / csn);", "const real j00 = ca + sa * (snn / csn);"),
+    ("tpc_merge.c", MERGE, "rotation jacobian curvature term dropped", "const real j20 = -(kB * s->p[4]) * sa;", "const real j20 = 0;"),
+    ("tpc_merge.c", MERGE, "rotation jacobian j22 inverted", "const real j22 = csn / csp;", "const real j22 = csp / csn;"),
+    ("tpc_merge.c", MERGE, "ldl forward substitution sign", "v = v - L[i][k] * w[k];", "v = v + L[i][k] * w[k];"),
+    ("tpc_merge.c", MERGE, "links not mutual", "if (succ[A] >= 0 && pred[succ[A]] == A) {", "if (succ[A] >= 0) {"),
+    ("tpc_merge.c", MERGE, "inward covariance not inflated", "s.c[j] = s.c[j] * (real)INWARD_SCALE;", "(void)0;"),
+    ("tpc_merge.c", MERGE, "chains start anywhere", "(pass == 0 && has_pred[t])", "(pass == 0 && 0)"),
+    ("tpc_merge.c", MERGE, "outer state without the segment's hits", "&s, &x, &k, hit_clu, a + 1, b - a - 1, 1,", "&s, &x, &k, hit_clu, a + 1, 0, 1,"),
+    ("tpc_merge.c", MERGE, "global refit seed from the last segment", "m_seed(g, &s, y, z, m_hit_clu[a], par + t0 * 5);", "m_seed(g, &s, y, z, m_hit_clu[a], par + chain_seg[chain_off[m + 1] - 1] * 5);"),
 ]
 
 
