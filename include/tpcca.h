@@ -378,6 +378,80 @@ tpc_status tpc_cluster_transform(const tpc_transform_geometry* tg, uint32_t flag
                                  float* x_dev, float* y_dev, float* z_dev, uint16_t* row_dev,
                                  void* stream);
 
+/* f1: sector-track merging and global refit.  The paper counts track
+ * propagation in the magnetic field among the components TPC tracking
+ * shares (Sec. 4) and judges the output by the cluster-to-track association
+ * (Sec. 2); how the segments that one particle leaves in several sectors are
+ * joined is this library's reading (R35-R41 of the design notes):
+ *   - the instances are the 36 TPC sectors, i = k + 18 side (n_inst = 36);
+ *     the segments are the tracks of tpc_sector_track;
+ *   - each segment's outer state comes from an outward Kalman filter over
+ *     its own hits (seeded at its first hit with its snp, tgl, q/pt);
+ *   - segment A's outer state is compared with the inner state (the
+ *     tracker's parameters at x_ref) of every segment B of sector k +- 1 on
+ *     the same side or of sector k on the other side whose first hit lies
+ *     within max_dz in z and max_dist in the transverse plane of A's last
+ *     hit: A's state is rotated into B's frame (cos_d, sin_d: one sector's
+ *     angle) and propagated to B's reference plane, and the chi2 of the
+ *     five-parameter difference under the summed covariance (an LDL^T
+ *     solve) must be <= chi2_max;
+ *   - a link A -> B is kept iff B is A's best successor and A is B's best
+ *     predecessor (minimum of (chi2, segment index)); chains follow the links
+ *     from the segments without a predecessor, in the order of their first
+ *     segment (then, for link cycles, from their lowest segment);
+ *   - each chain is one merged track: its segments' hits in chain order,
+ *     refitted by an outward filter (rotating at every change of sector)
+ *     and an inward filter started from the outward end state with its
+ *     covariance inflated a hundredfold; the inward state at the first hit
+ *     is the output (frame of the first segment's sector), with the inward
+ *     chi2 and ndf = 2 hits - 5; status 1 if a propagation or rotation
+ *     failed (|snp| reaching 0.99, or the track turning back).
+ * Every segment belongs to exactly one merged track.  The segment count and
+ * hit count are read from seg_result_dev (n_tracks, n_hits), so the call can
+ * follow tpc_sector_track on the same stream without a host round trip;
+ * seg->cap_tracks and cap_hits bound them.  With TPC_FLAG_DETERMINISTIC the
+ * outputs equal the binary32 CPU reference bit for bit.
+ * Errors: TPC_ERR_INVALID (null pointers, n_inst != 36, capacities below
+ * the segment arrays', unknown flags), TPC_ERR_WORKSPACE, TPC_ERR_HIP. */
+typedef struct {
+  float max_dz, max_dist, chi2_max;
+  float cos_a[TPC_N_PHI], sin_a[TPC_N_PHI];  /* sector axis k at (k + 1/2) 20 deg */
+  float cos_d, sin_d;                        /* the 20 deg between two sectors */
+} tpc_merge_params;
+
+/* Merged tracks (device arrays, caller-allocated, cap_tracks >= the
+ * segment capacity, cap_hits >= the segments' hit capacity):
+ *   param [cap][5], cov [cap][15], chi2, ndf, status, sector (phi sector of
+ *   the output frame), x_ref (plane of the first hit);
+ *   hit_off [cap + 1], hit_clu [cap_hits]   merged hit lists (input indices)
+ *   seg_off [cap + 1], seg [cap]            the segments of each track
+ *   next [cap]                              each segment's kept link (-1 none)
+ *   counts [2] (int64)                      merged tracks, merged hits      */
+typedef struct {
+  float* param;
+  float* cov;
+  float* chi2;
+  int32_t* ndf;
+  int32_t* status;
+  int32_t* sector;
+  float* x_ref;
+  int32_t* hit_off;
+  int32_t* hit_clu;
+  int32_t* seg_off;
+  int32_t* seg;
+  int32_t* next;
+  int64_t* counts;
+  int64_t cap_tracks, cap_hits;
+} tpc_merged;
+
+void tpc_default_merge_params(tpc_merge_params* m);
+size_t tpc_merge_workspace_bytes(int64_t cap_segments);
+tpc_status tpc_merge_tracks(const tpc_geometry* geom, const tpc_params* params,
+                            const tpc_merge_params* mp, int32_t n_inst,
+                            const int64_t* inst_off_dev, tpc_clusters in,
+                            const tpc_tracks* seg, const tpc_result* seg_result_dev,
+                            const tpc_merged* out, void* ws_dev, size_t ws_bytes, void* stream);
+
 /* Optional per-kernel timing for benchmarks.  tpc_profile_enable(1) creates
  * a pool of HIP events (host call, once); afterwards every kernel the library
  * enqueues is bracketed by two events recorded on the stream it is launched

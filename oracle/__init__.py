@@ -36,7 +36,9 @@ def build(force: bool = True, out: str | None = None, srcdir: str | None = None,
         return out
     srcdir = srcdir or HERE
     objs = []
-    for name, tags in (("tpc_oracle.c", (("f32", []), ("f64", ["-DORC_F64"]))),
+    for name, tags in (("tpc_oracle.c", (("f32", []), ("f64", ["-DORC_F64"]),
+                                         ("f32c", ["-DORC_F32C", "-mfma",
+                                                   "-ffp-contract=fast"]))),
                        ("tpc_refit.c", (("rf32", []), ("rf64", ["-DORC_F64"]),
                                         ("rc128", ["-DORC_C128"]))),
                        ("tpc_transform.c", (("tf32", []), ("tf64", ["-DORC_F64"]))),
@@ -113,10 +115,11 @@ def _p(a):
 
 
 def _dt(prec):
-    return np.float32 if prec == 32 else np.float64
+    return np.float64 if prec == 64 else np.float32
 
 
 def _fn(name, prec):
+    # prec 32, 64, or "32c" (binary32 with fused multiply-add)
     return getattr(lib(), f"{name}_f{prec}")
 
 

@@ -38,7 +38,13 @@ typedef float real;
 #define RE(x) (x)
 #define FLOOR floorf
 #define CEIL ceilf
+#if defined(ORC_F32C)
+/* binary32 built with contraction (fused multiply-add): a second rounding
+ * realisation of the same formulas, for the production-mode bounds */
+#define SFX(n) n##_f32c
+#else
 #define SFX(n) n##_f32
+#endif
 /* 1/6, 3/40 and 3/20 rounded to binary32 (exact hex literals) */
 #define K_SIXTH 0x1.555556p-3f
 #define K_3_40 0x1.333334p-4f

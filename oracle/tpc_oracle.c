@@ -621,7 +621,7 @@ real SFX(orc_update)(const orc_geom* g, real* p, real* c, real my, real mz)
   return chi2;
 }
 
-#if !defined(ORC_F64)
+#if !defined(ORC_F64) && !defined(ORC_F32C)
 #include <fenv.h>
 /* R29 check: whether an operation since the last clear delivered a tiny
  * (subnormal or flushed) inexact result -- the IEEE underflow flag of the

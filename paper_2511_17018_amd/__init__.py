@@ -500,3 +500,95 @@ def cluster_transform(tg: dict, sector: torch.Tensor, row: torch.Tensor, pad: to
                                    C.c_int64(n), raw, dm, cm, _ptr(x), _ptr(y), _ptr(z), _ptr(ro),
                                    _stream()), "tpc_cluster_transform")
     return x[:n], y[:n], z[:n], ro[:n]
+
+
+# ----------------------------------------------------------------------------
+# sector-track merging and global refit (tpc_merge_tracks)
+
+class MergeParams(C.Structure):
+    _fields_ = [("max_dz", C.c_float), ("max_dist", C.c_float), ("chi2_max", C.c_float),
+                ("cos_a", C.c_float * N_PHI), ("sin_a", C.c_float * N_PHI), ("cos_d", C.c_float),
+                ("sin_d", C.c_float)]
+
+
+class MergedStruct(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in ("param", "cov", "chi2", "ndf", "status", "sector",
+                                          "x_ref", "hit_off", "hit_clu", "seg_off", "seg", "next",
+                                          "counts")] + [("cap_tracks", C.c_int64),
+                                                        ("cap_hits", C.c_int64)]
+
+
+def default_merge_params(**over) -> MergeParams:
+    m = MergeParams()
+    lib().tpc_default_merge_params(C.byref(m))
+    for k, v in over.items():
+        setattr(m, k, v)
+    return m
+
+
+@dataclass
+class Merged:
+    param: torch.Tensor
+    cov: torch.Tensor
+    chi2: torch.Tensor
+    ndf: torch.Tensor
+    status: torch.Tensor
+    sector: torch.Tensor
+    x_ref: torch.Tensor
+    hit_off: torch.Tensor
+    hit_clu: torch.Tensor
+    seg_off: torch.Tensor
+    seg: torch.Tensor
+    next: torch.Tensor
+    counts: torch.Tensor
+    ws: torch.Tensor
+
+    def struct(self) -> MergedStruct:
+        return MergedStruct(*[_ptr(getattr(self, f)) for f in (
+            "param", "cov", "chi2", "ndf", "status", "sector", "x_ref", "hit_off", "hit_clu",
+            "seg_off", "seg", "next", "counts")], self.param.shape[0], self.hit_clu.numel())
+
+    def host(self) -> dict:
+        nc, nh = (int(v) for v in self.counts.cpu().tolist())
+        h = lambda t: t.cpu().numpy()  # noqa: E731
+        return dict(n=nc, param=h(self.param[:nc]), cov=h(self.cov[:nc]), chi2=h(self.chi2[:nc]),
+                    ndf=h(self.ndf[:nc]), status=h(self.status[:nc]), sector=h(self.sector[:nc]),
+                    x_ref=h(self.x_ref[:nc]), hit_off=h(self.hit_off[:nc + 1]),
+                    hit_clu=h(self.hit_clu[:nh]), seg_off=h(self.seg_off[:nc + 1]),
+                    seg=h(self.seg[:int(self.seg_off[nc].item())]), next=h(self.next))
+
+
+def alloc_merged(cap_tracks: int, cap_hits: int, device="cuda") -> Merged:
+    f32 = dict(dtype=torch.float32, device=device)
+    i32 = dict(dtype=torch.int32, device=device)
+    ct = max(cap_tracks, 1)
+    wsb = int(lib().tpc_merge_workspace_bytes(C.c_int64(cap_tracks)))
+    return Merged(torch.empty((ct, 5), **f32), torch.empty((ct, 15), **f32), torch.empty(ct, **f32),
+                  torch.empty(ct, **i32), torch.empty(ct, **i32), torch.empty(ct, **i32),
+                  torch.empty(ct, **f32), torch.empty(ct + 1, **i32),
+                  torch.empty(max(cap_hits, 1), **i32), torch.empty(ct + 1, **i32),
+                  torch.empty(ct, **i32), torch.empty(ct, **i32),
+                  torch.zeros(2, dtype=torch.int64, device=device),
+                  torch.empty(max(wsb, 256), dtype=torch.uint8, device=device))
+
+
+def merge_tracks(geom: dict, batch: Batch, tracks: Tracks, result: torch.Tensor, det: bool = True,
+                 out: Merged | None = None, mp: MergeParams | None = None) -> Merged:
+    """tpc_merge_tracks on the current stream (asynchronous): the sector
+    tracker's tracks of a 36-sector batch merged across sector edges and the
+    central membrane, and refitted.  `result` is the tracker's device result
+    word (Workspace.result)."""
+    g = make_geometry(geom)
+    p = make_params(det)
+    mp = mp if mp is not None else default_merge_params()
+    out = out if out is not None else alloc_merged(tracks.param.shape[0], tracks.hit_clu.numel(),
+                                                   batch.x.device)
+    ts = tracks.struct()
+    ms = out.struct()
+    L = lib()
+    L.tpc_merge_tracks.restype = C.c_int
+    _check(L.tpc_merge_tracks(C.byref(g), C.byref(p), C.byref(mp), C.c_int32(batch.n_inst),
+                              _ptr(batch.inst_off), batch.struct(), C.byref(ts), _ptr(result),
+                              C.byref(ms), _ptr(out.ws), C.c_size_t(out.ws.numel()), _stream()),
+           "tpc_merge_tracks")
+    return out

@@ -52,6 +52,10 @@ def build(verbose: bool = False) -> str:
           "-o", os.path.join(BUILD, "tpc_transform_det.o")], "tpc_transform_det.o"),
         ([_hipcc(), *COMMON, *PROD, "-c", os.path.join(CSRC, "tpc_transform.hip"),
           "-o", os.path.join(BUILD, "tpc_transform_prod.o")], "tpc_transform_prod.o"),
+        ([_hipcc(), *COMMON, *DET, "-c", os.path.join(CSRC, "tpc_merge.hip"),
+          "-o", os.path.join(BUILD, "tpc_merge_det.o")], "tpc_merge_det.o"),
+        ([_hipcc(), *COMMON, *PROD, "-c", os.path.join(CSRC, "tpc_merge.hip"),
+          "-o", os.path.join(BUILD, "tpc_merge_prod.o")], "tpc_merge_prod.o"),
         ([_hipcc(), *COMMON, *BWD, "-c", os.path.join(CSRC, "tpc_refit_bwd.hip"),
           "-o", os.path.join(BUILD, "tpc_refit_bwd.o")], "tpc_refit_bwd.o"),
     ]

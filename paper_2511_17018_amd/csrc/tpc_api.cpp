@@ -503,6 +503,120 @@ tpc_status tpc_refit_backward(const tpc_geometry* geom, const tpc_params* params
   return e == hipSuccess ? TPC_OK : TPC_ERR_HIP;
 }
 
+void tpc_default_merge_params(tpc_merge_params* m)
+{
+  if (!m) return;
+  m->max_dz = 20.0f;
+  m->max_dist = 40.0f;
+  m->chi2_max = 30.0f;
+  const double deg = 3.14159265358979323846 / 180.0;
+  for (int k = 0; k < kPhi; k++) {
+    const double a = (20.0 * (k + 0.5)) * deg;
+    m->cos_a[k] = (float)cos(a);
+    m->sin_a[k] = (float)sin(a);
+  }
+  m->cos_d = (float)cos(20.0 * deg);
+  m->sin_d = (float)sin(20.0 * deg);
+}
+
+namespace {
+struct MergeWs {
+  int64_t n_seg, seg_inst, seg_pos, out_ok, out_p, out_c, out_x, sort_cnt, inst_seg_off,
+      seg_order, succ, pred, succ_chi2, pred_chi2, has_pred, chain_head, total, sort_blocks;
+};
+
+MergeWs merge_ws(int64_t cap)
+{
+  MergeWs w;
+  Carve c;
+  w.sort_blocks = (cap + kBlock - 1) / kBlock;
+  if (w.sort_blocks < 1) w.sort_blocks = 1;
+  w.n_seg = c.take(8);
+  w.seg_inst = c.take(4 * cap);
+  w.seg_pos = c.take(24 * cap);
+  w.out_ok = c.take(4 * cap);
+  w.out_p = c.take(20 * cap);
+  w.out_c = c.take(60 * cap);
+  w.out_x = c.take(4 * cap);
+  w.sort_cnt = c.take(4 * 2 * kPhi * w.sort_blocks);
+  w.inst_seg_off = c.take(4 * (2 * kPhi + 1));
+  w.seg_order = c.take(4 * cap);
+  w.succ = c.take(4 * cap);
+  w.pred = c.take(4 * cap);
+  w.succ_chi2 = c.take(4 * cap);
+  w.pred_chi2 = c.take(4 * cap);
+  w.has_pred = c.take(4 * cap);
+  w.chain_head = c.take(4 * cap);
+  w.total = c.off;
+  return w;
+}
+}  // namespace
+
+size_t tpc_merge_workspace_bytes(int64_t cap_segments)
+{
+  if (cap_segments < 0) return 0;
+  return (size_t)merge_ws(cap_segments).total;
+}
+
+tpc_status tpc_merge_tracks(const tpc_geometry* geom, const tpc_params* params,
+                            const tpc_merge_params* mp, int32_t n_inst,
+                            const int64_t* inst_off_dev, tpc_clusters in,
+                            const tpc_tracks* seg, const tpc_result* seg_result_dev,
+                            const tpc_merged* out, void* ws_dev, size_t ws_bytes, void* stream)
+{
+  if (!geom || !params || !mp || !seg || !out || !inst_off_dev || !seg_result_dev || !ws_dev)
+    return TPC_ERR_INVALID;
+  if (geom->n_rows != kRows || n_inst != 2 * kPhi || (params->flags & ~kKnownFlags))
+    return TPC_ERR_INVALID;
+  if (!(geom->sigma_y2 > 0) || !(geom->sigma_z2 > 0)) return TPC_ERR_INVALID;
+  const int64_t cap = seg->cap_tracks;
+  if (cap < 0 || cap >= ((int64_t)1 << 31) || seg->cap_hits < 0 ||
+      seg->cap_hits >= ((int64_t)1 << 31))
+    return TPC_ERR_INVALID;
+  if (cap > 0 && (!seg->param || !seg->cov || !seg->x_ref || !seg->hit_off || !seg->hit_clu ||
+                  !in.y || !in.z || !in.row))
+    return TPC_ERR_INVALID;
+  if (out->cap_tracks < cap || out->cap_hits < seg->cap_hits) return TPC_ERR_INVALID;
+  if (cap > 0 && (!out->param || !out->cov || !out->chi2 || !out->ndf || !out->status ||
+                  !out->sector || !out->x_ref || !out->hit_off || !out->hit_clu ||
+                  !out->seg_off || !out->seg || !out->next || !out->counts))
+    return TPC_ERR_INVALID;
+  const MergeWs w = merge_ws(cap);
+  if ((int64_t)ws_bytes < w.total) return TPC_ERR_WORKSPACE;
+  MergeBufs b;
+  b.y = in.y;
+  b.z = in.z;
+  b.row = in.row;
+  b.inst_off = inst_off_dev;
+  b.seg = *seg;
+  b.res = seg_result_dev;
+  b.cap_seg = cap;
+  b.mp = *mp;
+  b.out = *out;
+  b.n_seg = at<int64_t>(ws_dev, w.n_seg);
+  b.seg_inst = at<int32_t>(ws_dev, w.seg_inst);
+  b.seg_pos = at<float>(ws_dev, w.seg_pos);
+  b.out_ok = at<int32_t>(ws_dev, w.out_ok);
+  b.out_p = at<float>(ws_dev, w.out_p);
+  b.out_c = at<float>(ws_dev, w.out_c);
+  b.out_x = at<float>(ws_dev, w.out_x);
+  b.sort_cnt = at<int32_t>(ws_dev, w.sort_cnt);
+  b.sort_blocks = w.sort_blocks;
+  b.inst_seg_off = at<int32_t>(ws_dev, w.inst_seg_off);
+  b.seg_order = at<int32_t>(ws_dev, w.seg_order);
+  b.succ = at<int32_t>(ws_dev, w.succ);
+  b.pred = at<int32_t>(ws_dev, w.pred);
+  b.succ_chi2 = at<float>(ws_dev, w.succ_chi2);
+  b.pred_chi2 = at<float>(ws_dev, w.pred_chi2);
+  b.has_pred = at<int32_t>(ws_dev, w.has_pred);
+  b.chain_head = at<int32_t>(ws_dev, w.chain_head);
+  const Consts k = make_consts(geom, params);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = (params->flags & TPC_FLAG_DETERMINISTIC) ? det::merge_tracks(k, b, s)
+                                                           : prod::merge_tracks(k, b, s);
+  return e == hipSuccess ? TPC_OK : TPC_ERR_HIP;
+}
+
 tpc_status tpc_cluster_transform(const tpc_transform_geometry* tg, uint32_t flags,
                                  int64_t n_clusters, tpc_raw_clusters in,
                                  const float* dist_map_dev, const float* corr_map_dev,

@@ -141,6 +141,32 @@ struct TransformBufs {
   bool aligned;         // every array allows the four-cluster vector accesses
 };
 
+// Buffers of sector-track merging and the global refit (f1).
+struct MergeBufs {
+  const float *y, *z;
+  const uint16_t* row;
+  const int64_t* inst_off;   // [37]
+  tpc_tracks seg;            // the tracker's tracks (param, cov, x_ref, hit lists)
+  const tpc_result* res;     // their counts
+  int64_t cap_seg;
+  tpc_merge_params mp;
+  tpc_merged out;
+  // workspace
+  int64_t* n_seg;            // [1] segments of this call
+  int32_t* seg_inst;         // [cap] instance of each segment
+  float* seg_pos;            // [cap][6] global x, y, z of the first and the last hit
+  int32_t* out_ok;           // [cap] outer state valid
+  float *out_p, *out_c, *out_x;  // [cap][5], [cap][15], [cap]
+  int32_t* sort_cnt;         // [36][sort_blocks] per-block instance counts, then offsets
+  int64_t sort_blocks;
+  int32_t* inst_seg_off;     // [37] first sorted segment of each instance
+  int32_t* seg_order;        // [cap] segments in (instance, index) order
+  int32_t *succ, *pred;      // [cap] best successor / predecessor
+  float *succ_chi2, *pred_chi2;
+  int32_t* has_pred;         // [cap] a kept link ends here
+  int32_t* chain_head;       // [cap] first segment of each chain
+};
+
 // Kernel timing hooks (tpc_profile_*): no-ops unless profiling is enabled.
 int prof_begin(hipStream_t s, const char* name);
 void prof_end(hipStream_t s, int slot);
@@ -156,6 +182,7 @@ int64_t scan_partials(int64_t n);
   hipError_t refit_forward(const Consts& k, const RefitBufs& b, hipStream_t s);     \
   hipError_t cluster_transform(const TransformConsts& k, const TransformBufs& b,    \
                                hipStream_t s);                                       \
+  hipError_t merge_tracks(const Consts& k, const MergeBufs& b, hipStream_t s);      \
   }
 
 namespace bwd {

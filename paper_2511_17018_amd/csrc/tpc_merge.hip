@@ -1,0 +1,596 @@
+// Sector-track merging and global refit (f1), gfx950.  Compiled into the
+// deterministic build (no contraction, correctly rounded division and
+// square root: the outputs equal the binary32 CPU reference bit for bit) and
+// the production build.
+//
+// Steps (one kernel each; counts come from the tracker's device result, so
+// no host round trip):
+//   seg_info     one lane per segment: its sector, the global positions of
+//                its first and last hit, its outer state (outward filter over
+//                its own hits)
+//   seg_sort     the segments ordered by (instance, index): per-block
+//                instance counts, one-block offsets, stable per-block ranks
+//   succ / pred  one lane per segment, segments taken in instance order so
+//                that a wave's lanes loop over the same candidate lists (one
+//                cache line serves the wave): best successor and best
+//                predecessor over the three neighbouring instances
+//   link, chain  mutual links; chain heads compacted by scans in index order
+//                (link cycles after them, from their lowest segment); chain
+//                lengths and hit counts scanned into offsets
+//   chain_hits   one lane per chain: segment list and merged hit list
+//   refit        one lane per chain: outward and inward filter with
+//                rotations between the sector frames
+#include "tpc_internal.h"
+
+#ifndef TPC_NS
+#error "TPC_NS must name the build (det or prod)"
+#endif
+
+namespace tpcca {
+namespace TPC_NS {
+namespace {
+
+#include "tpc_kalman.h"
+
+constexpr int kInst = 2 * kPhi;
+constexpr float kSmax = 0.99f;
+constexpr float kInwardScale = 100.0f;
+
+__device__ __forceinline__ int64_t gid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+
+// instance of input index c (inst_off has kInst + 1 entries)
+__device__ __forceinline__ int inst_of(const int64_t* off, int64_t c)
+{
+  int lo = 0, hi = kInst;
+  while (hi - lo > 1) {
+    const int m = (lo + hi) / 2;
+    if (off[m] <= c) lo = m;
+    else hi = m;
+  }
+  return lo;
+}
+
+// R36: rotation by (ca, sa) at the state's point x; new plane in xn
+__device__ __forceinline__ bool mrot(KSt& s, float x, float ca, float sa, float kB, float& xn)
+{
+  const float one = 1.0f;
+  const float snp = s.p[2];
+  if (!(fabsf(snp) < kSmax)) return false;
+  const float csp = sqrtf((one - snp) * (one + snp));
+  const float csn = csp * ca + snp * sa;
+  const float snn = snp * ca - csp * sa;
+  if (!(csn > 0.0f) || !(fabsf(snn) < kSmax)) return false;
+  const float y = s.p[0];
+  xn = x * ca + y * sa;
+  s.p[0] = y * ca - x * sa;
+  s.p[2] = snn;
+  const float j00 = ca - sa * (snn / csn);
+  const float j10 = -(s.p[3] * (sa / csn));
+  const float j20 = -(kB * s.p[4]) * sa;
+  const float j22 = csn / csp;
+  float c[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; i++)
+#pragma unroll
+    for (int j = 0; j < 5; j++) c[i][j] = s.c[ci(i, j)];
+  float t[5][5];
+#pragma unroll
+  for (int j = 0; j < 5; j++) {
+    t[0][j] = j00 * c[0][j];
+    t[1][j] = c[1][j] + j10 * c[0][j];
+    t[2][j] = j20 * c[0][j] + j22 * c[2][j];
+    t[3][j] = c[3][j];
+    t[4][j] = c[4][j];
+  }
+#pragma unroll
+  for (int i = 0; i < 5; i++) {
+    const float r[5] = {j00 * t[i][0], t[i][1] + j10 * t[i][0], j20 * t[i][0] + j22 * t[i][2],
+                        t[i][3], t[i][4]};
+#pragma unroll
+    for (int j = 0; j <= i; j++) s.c[ci(i, j)] = r[j];
+  }
+  return true;
+}
+
+__device__ __forceinline__ bool mmove(KSt& s, float x1, float x2, float kB)
+{
+  if (x1 == x2) return true;
+  return kprop(s, x1, x2, kB, kSmax);
+}
+
+// R36: into the rotated frame and onto plane xh (target point (xh, yh));
+// rotation at the state's point, else at the target point
+__device__ __forceinline__ bool mtransport(KSt& s, float& x, float ca, float sa, float xh, float yh,
+                                        float kB)
+{
+  KSt t = s;
+  float xr;
+  if (mrot(t, x, ca, sa, kB, xr) && mmove(t, xr, xh, kB)) {
+    s = t;
+    x = xh;
+    return true;
+  }
+  t = s;
+  const float xc = xh * ca - yh * sa;
+  if (mmove(t, x, xc, kB) && mrot(t, xc, ca, sa, kB, xr) && mmove(t, xr, xh, kB)) {
+    s = t;
+    x = xh;
+    return true;
+  }
+  return false;
+}
+
+// R37: d^T S^-1 d by LDL^T (negative if S is not positive definite)
+__device__ __forceinline__ float mchi2(const float* S, const float* d)
+{
+  float L[5][5], D[5];
+#pragma unroll
+  for (int i = 0; i < 5; i++) {
+#pragma unroll
+    for (int j = 0; j < i; j++) {
+      float v = S[ci(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; k++) v = v - L[i][k] * (L[j][k] * D[k]);
+      L[i][j] = v / D[j];
+    }
+    float v = S[ci(i, i)];
+#pragma unroll
+    for (int k = 0; k < i; k++) v = v - L[i][k] * (L[i][k] * D[k]);
+    if (!(v > 0.0f)) return -1.0f;
+    D[i] = v;
+  }
+  float w[5], chi2 = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 5; i++) {
+    float v = d[i];
+#pragma unroll
+    for (int k = 0; k < i; k++) v = v - L[i][k] * w[k];
+    w[i] = v;
+    chi2 = chi2 + (v * v) / D[i];
+  }
+  return chi2;
+}
+
+// R40: filter pass over hits[first + dir q], q < count, from state s at
+// plane x in frame k; chi2 accumulates
+__device__ __forceinline__ bool mpass(const Consts& k, const MergeBufs& b, const int64_t* s_off,
+                                   KSt& s, float& x, int& kf, const int32_t* hits, int64_t first,
+                                   int64_t count, int dir, float& chi2)
+{
+  const float kB = k.kB, vy = k.vy, vz = k.vz;
+  for (int64_t q = 0; q < count; q++) {
+    const int64_t c = hits[first + dir * q];
+    const int kk = inst_of(s_off, c) % kPhi;
+    const float xh = k.row_x[b.row[c]];
+    if (kk != kf) {
+      const bool up = (kk - kf + kPhi) % kPhi == 1;
+      const float sa = up ? b.mp.sin_d : -b.mp.sin_d;
+      if (!mtransport(s, x, b.mp.cos_d, sa, xh, b.y[c], kB)) return false;
+      kf = kk;
+    } else {
+      if (!mmove(s, x, xh, kB)) return false;
+      x = xh;
+    }
+    chi2 = chi2 + kupdate(s, b.y[c], b.z[c], vy, vz);
+  }
+  return true;
+}
+
+__device__ __forceinline__ void mseed(const Consts& k, KSt& s, const MergeBufs& b, int64_t c,
+                                      const float* p5)
+{
+  s.p[0] = b.y[c];
+  s.p[1] = b.z[c];
+  s.p[2] = p5[2];
+  s.p[3] = p5[3];
+  s.p[4] = p5[4];
+  kinit_cov(s, k.vy, k.vz);
+}
+
+__device__ __forceinline__ void load_off(const MergeBufs& b, int64_t* s_off)
+{
+  for (int i = threadIdx.x; i <= kInst; i += blockDim.x) s_off[i] = b.inst_off[i];
+  __syncthreads();
+}
+
+// --------------------------------------------------------------- seg_info
+__global__ __launch_bounds__(kBlock) void k_seg_info(Consts k, MergeBufs b)
+{
+  __shared__ int64_t s_off[kInst + 1];
+  load_off(b, s_off);
+  const int64_t n = *b.n_seg;
+  const int64_t t = gid();
+  if (t >= n) return;
+  const int64_t a = b.seg.hit_off[t], e = b.seg.hit_off[t + 1];
+  const int64_t c0 = b.seg.hit_clu[a], c1 = b.seg.hit_clu[e - 1];
+  const int inst = inst_of(s_off, c0);
+  const int kk = inst % kPhi;
+  b.seg_inst[t] = inst;
+  // global positions of the first and last hit (pair pre-filter)
+  const float x0 = k.row_x[b.row[c0]], x1 = k.row_x[b.row[c1]];
+  const float ca = b.mp.cos_a[kk], sa = b.mp.sin_a[kk];
+  b.seg_pos[t * 6 + 0] = x0 * ca - b.y[c0] * sa;
+  b.seg_pos[t * 6 + 1] = x0 * sa + b.y[c0] * ca;
+  b.seg_pos[t * 6 + 2] = b.z[c0];
+  b.seg_pos[t * 6 + 3] = x1 * ca - b.y[c1] * sa;
+  b.seg_pos[t * 6 + 4] = x1 * sa + b.y[c1] * ca;
+  b.seg_pos[t * 6 + 5] = b.z[c1];
+  // outer state: outward filter over the segment's own hits
+  float p5[5];
+#pragma unroll
+  for (int j = 0; j < 5; j++) p5[j] = b.seg.param[t * 5 + j];
+  KSt s;
+  mseed(k, s, b, c0, p5);
+  float x = x0, chi2 = 0.0f;
+  int kf = kk;
+  const bool ok = mpass(k, b, s_off, s, x, kf, b.seg.hit_clu, a + 1, e - a - 1, 1, chi2);
+  b.out_ok[t] = ok ? 1 : 0;
+#pragma unroll
+  for (int j = 0; j < 5; j++) b.out_p[t * 5 + j] = ok ? s.p[j] : 0.0f;
+#pragma unroll
+  for (int j = 0; j < 15; j++) b.out_c[t * 15 + j] = ok ? s.c[j] : 0.0f;
+  b.out_x[t] = ok ? x : 0.0f;
+}
+
+// --------------------------------------------------------------- seg_sort
+// segments in (instance, index) order: per-block instance counts ...
+__global__ __launch_bounds__(kBlock) void k_sort_count(MergeBufs b)
+{
+  __shared__ int s_cnt[kInst];
+  if (threadIdx.x < kInst) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t n = *b.n_seg;
+  const int64_t t = gid();
+  if (t < n) atomicAdd(&s_cnt[b.seg_inst[t]], 1);
+  __syncthreads();
+  if (threadIdx.x < kInst) b.sort_cnt[(int64_t)threadIdx.x * b.sort_blocks + blockIdx.x] =
+      s_cnt[threadIdx.x];
+}
+
+// ... an exclusive scan of the (instance-major) counts in one block ...
+__global__ __launch_bounds__(1024) void k_sort_scan(MergeBufs b)
+{
+  __shared__ int s_w[16];
+  const int64_t total = (int64_t)kInst * b.sort_blocks;
+  int carry = 0;
+  for (int64_t i0 = 0; i0 < total; i0 += 1024) {
+    const int64_t i = i0 + threadIdx.x;
+    const int v = i < total ? b.sort_cnt[i] : 0;
+    int x = v;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[wid] = x;
+    __syncthreads();
+    int wofs = 0, tot = 0;
+    for (int w = 0; w < 16; w++) {
+      if (w < wid) wofs += s_w[w];
+      tot += s_w[w];
+    }
+    if (i < total) b.sort_cnt[i] = carry + wofs + x - v;
+    // the first block's offset of instance i starts instance i
+    if (i < total && i % b.sort_blocks == 0) b.inst_seg_off[i / b.sort_blocks] = carry + wofs + x - v;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) b.inst_seg_off[kInst] = carry;
+}
+
+// ... and stable ranks within the block
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(MergeBufs b)
+{
+  __shared__ int s_inst[kBlock];
+  const int64_t n = *b.n_seg;
+  const int64_t t = gid();
+  s_inst[threadIdx.x] = t < n ? b.seg_inst[t] : -1;
+  __syncthreads();
+  if (t >= n) return;
+  const int me = s_inst[threadIdx.x];
+  int rank = 0;
+  for (int j = 0; j < (int)threadIdx.x; j++) rank += s_inst[j] == me ? 1 : 0;
+  b.seg_order[b.sort_cnt[(int64_t)me * b.sort_blocks + blockIdx.x] + rank] = (int32_t)t;
+}
+
+// --------------------------------------------------------------- pairs
+// R37: chi2 of A's outer state against B's inner state, -1 if no candidate
+__device__ __forceinline__ float mpair(const Consts& k, const MergeBufs& b, int64_t A, int64_t B)
+{
+  const float kB = k.kB;
+  if (!b.out_ok[A]) return -1.0f;
+  const int ia = b.seg_inst[A], ib = b.seg_inst[B];
+  const int ka = ia % kPhi, kb = ib % kPhi;
+  const int nb = (kb - ka + kPhi) % kPhi;
+  const bool same_side = ia / kPhi == ib / kPhi;
+  if (!((same_side && (nb == 1 || nb == kPhi - 1)) || (!same_side && nb == 0))) return -1.0f;
+  const float d0 = b.seg_pos[A * 6 + 3] - b.seg_pos[B * 6 + 0];
+  const float d1 = b.seg_pos[A * 6 + 4] - b.seg_pos[B * 6 + 1];
+  if (!(fabsf(b.seg_pos[A * 6 + 5] - b.seg_pos[B * 6 + 2]) <= b.mp.max_dz)) return -1.0f;
+  if (!(d0 * d0 + d1 * d1 <= b.mp.max_dist * b.mp.max_dist)) return -1.0f;
+  KSt s;
+#pragma unroll
+  for (int j = 0; j < 5; j++) s.p[j] = b.out_p[A * 5 + j];
+#pragma unroll
+  for (int j = 0; j < 15; j++) s.c[j] = b.out_c[A * 15 + j];
+  float x = b.out_x[A];
+  const float xb = b.seg.x_ref[B];
+  if (nb != 0) {
+    const float sa = nb == 1 ? b.mp.sin_d : -b.mp.sin_d;
+    if (!mtransport(s, x, b.mp.cos_d, sa, xb, b.seg.param[B * 5 + 0], kB)) return -1.0f;
+  } else if (!mmove(s, x, xb, kB)) {
+    return -1.0f;
+  }
+  float d[5], S[15];
+#pragma unroll
+  for (int j = 0; j < 5; j++) d[j] = s.p[j] - b.seg.param[B * 5 + j];
+#pragma unroll
+  for (int j = 0; j < 15; j++) S[j] = s.c[j] + b.seg.cov[B * 15 + j];
+  const float chi2 = mchi2(S, d);
+  if (!(chi2 >= 0.0f) || !(chi2 <= b.mp.chi2_max)) return -1.0f;
+  return chi2;
+}
+
+// the three instances a segment of instance i pairs with: k - 1, k + 1 on
+// its side, k on the other side
+__device__ __forceinline__ int nbr_inst(int i, int which)
+{
+  const int kk = i % kPhi, side = i / kPhi;
+  if (which == 0) return (kk + kPhi - 1) % kPhi + kPhi * side;
+  if (which == 1) return (kk + 1) % kPhi + kPhi * side;
+  return kk + kPhi * (1 - side);
+}
+
+// best successor (PRED = false: the lane's segment is A) or best
+// predecessor (PRED = true: the lane's segment is B); candidates of the three
+// neighbouring instances in increasing index (the order of the sort), so
+// the first minimum is the one of lowest index
+template <bool PRED>
+__global__ __launch_bounds__(kBlock) void k_best(Consts k, MergeBufs b)
+{
+  const int64_t n = *b.n_seg;
+  const int64_t q = gid();
+  if (q >= n) return;
+  const int64_t me = b.seg_order[q];
+  const int im = b.seg_inst[me];
+  int32_t best = -1;
+  float bchi = 0.0f;
+  // candidates of the three instances merged in index order
+  int64_t pos[3], end[3];
+#pragma unroll
+  for (int w = 0; w < 3; w++) {
+    const int j = nbr_inst(im, w);
+    pos[w] = b.inst_seg_off[j];
+    end[w] = b.inst_seg_off[j + 1];
+  }
+  for (;;) {
+    int64_t cand = INT64_MAX;
+    int wsel = -1;
+#pragma unroll
+    for (int w = 0; w < 3; w++) {
+      if (pos[w] < end[w]) {
+        const int64_t c = b.seg_order[pos[w]];
+        if (c < cand) {
+          cand = c;
+          wsel = w;
+        }
+      }
+    }
+    if (wsel < 0) break;
+    pos[wsel]++;
+    const float c2 = PRED ? mpair(k, b, cand, me) : mpair(k, b, me, cand);
+    if (c2 < 0.0f) continue;
+    if (best < 0 || c2 < bchi) {
+      best = (int32_t)cand;
+      bchi = c2;
+    }
+  }
+  if (PRED) {
+    b.pred[me] = best;
+    b.pred_chi2[me] = bchi;
+  } else {
+    b.succ[me] = best;
+    b.succ_chi2[me] = bchi;
+  }
+}
+
+// --------------------------------------------------------------- links, chains
+__global__ __launch_bounds__(kBlock) void k_link(MergeBufs b)
+{
+  const int64_t n = *b.n_seg;
+  const int64_t a = gid();
+  if (a >= n) return;
+  const int32_t s = b.succ[a];
+  const bool keep = s >= 0 && b.pred[s] == a;
+  b.out.next[a] = keep ? s : -1;
+  if (keep) b.has_pred[s] = 1;
+}
+
+// one block: chain starts (heads in index order, then the lowest segment of
+// every link cycle), their lengths and hit counts, and the offsets
+__global__ __launch_bounds__(1024) void k_chains(MergeBufs b)
+{
+  __shared__ int64_t s_w[16];
+  __shared__ int64_t s_carry[3];
+  const int64_t n = *b.n_seg;
+  if (threadIdx.x < 3) s_carry[threadIdx.x] = 0;
+  __syncthreads();
+  for (int pass = 0; pass < 2; pass++) {
+    for (int64_t i0 = 0; i0 < n; i0 += 1024) {
+      const int64_t t = i0 + threadIdx.x;
+      bool start = false;
+      int64_t nseg = 0, nhit = 0;
+      if (t < n) {
+        if (pass == 0) {
+          start = b.has_pred[t] == 0;
+        } else if (b.has_pred[t]) {
+          // every segment has at most one predecessor, so a segment with one
+          // is either on a head's chain (its successors end at -1) or on a
+          // link cycle (they come back to it); the cycle's lowest segment
+          // starts its chain
+          int64_t lowest = t, u = b.out.next[t];
+          for (int64_t step = 0; step < n && u >= 0 && u != t; step++) {
+            if (u < lowest) lowest = u;
+            u = b.out.next[u];
+          }
+          start = u == t && lowest == t;
+        }
+        if (start) {
+          int64_t u = t;
+          do {
+            nseg++;
+            nhit += b.seg.hit_off[u + 1] - b.seg.hit_off[u];
+            u = b.out.next[u];
+          } while (u >= 0 && u != t);
+        }
+      }
+      // three exclusive scans in one: starts, segments, hits
+      int64_t v[3] = {start ? 1 : 0, nseg, nhit}, ex[3], tot[3];
+      const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        int64_t x = v[q];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int64_t y = __shfl_up(x, o, 64);
+          if (lane >= o) x += y;
+        }
+        if (lane == 63) s_w[wid] = x;
+        __syncthreads();
+        int64_t wofs = 0, tt = 0;
+        for (int w = 0; w < 16; w++) {
+          if (w < wid) wofs += s_w[w];
+          tt += s_w[w];
+        }
+        ex[q] = x - v[q] + wofs;
+        tot[q] = tt;
+        __syncthreads();
+      }
+      if (start) {
+        const int64_t m = s_carry[0] + ex[0];
+        b.chain_head[m] = (int32_t)t;
+        b.out.seg_off[m] = (int32_t)(s_carry[1] + ex[1]);
+        b.out.hit_off[m] = (int32_t)(s_carry[2] + ex[2]);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        s_carry[0] += tot[0];
+        s_carry[1] += tot[1];
+        s_carry[2] += tot[2];
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    const int64_t m = s_carry[0];
+    b.out.seg_off[m] = (int32_t)s_carry[1];
+    b.out.hit_off[m] = (int32_t)s_carry[2];
+    b.out.counts[0] = m;
+    b.out.counts[1] = s_carry[2];
+  }
+}
+
+// one lane per chain: its segment list and merged hit list
+__global__ __launch_bounds__(kBlock) void k_chain_hits(MergeBufs b)
+{
+  const int64_t m = gid();
+  if (m >= b.out.counts[0]) return;
+  const int64_t t = b.chain_head[m];
+  int64_t so = b.out.seg_off[m], ho = b.out.hit_off[m];
+  int64_t u = t;
+  do {
+    b.out.seg[so++] = (int32_t)u;
+    for (int64_t h = b.seg.hit_off[u]; h < b.seg.hit_off[u + 1]; h++)
+      b.out.hit_clu[ho++] = b.seg.hit_clu[h];
+    u = b.out.next[u];
+  } while (u >= 0 && u != t);
+}
+
+// --------------------------------------------------------------- refit
+__global__ __launch_bounds__(kBlock) void k_merge_refit(Consts k, MergeBufs b)
+{
+  __shared__ int64_t s_off[kInst + 1];
+  load_off(b, s_off);
+  const int64_t m = gid();
+  if (m >= b.out.counts[0]) return;
+  const int64_t a = b.out.hit_off[m], e = b.out.hit_off[m + 1];
+  const int64_t t0 = b.out.seg[b.out.seg_off[m]];
+  const int32_t* hits = b.out.hit_clu;
+  float p5[5];
+#pragma unroll
+  for (int j = 0; j < 5; j++) p5[j] = b.seg.param[t0 * 5 + j];
+  KSt s;
+  mseed(k, s, b, hits[a], p5);
+  float x = k.row_x[b.row[hits[a]]], chi2 = 0.0f;
+  int kf = b.seg_inst[t0] % kPhi;
+  bool good = mpass(k, b, s_off, s, x, kf, hits, a + 1, e - a - 1, 1, chi2);
+  if (good) {
+#pragma unroll
+    for (int j = 0; j < 15; j++) s.c[j] = s.c[j] * kInwardScale;
+    chi2 = 0.0f;
+    good = mpass(k, b, s_off, s, x, kf, hits, e - 1, e - a, -1, chi2);
+  }
+  b.out.status[m] = good ? 0 : 1;
+#pragma unroll
+  for (int j = 0; j < 5; j++) b.out.param[m * 5 + j] = good ? s.p[j] : 0.0f;
+#pragma unroll
+  for (int j = 0; j < 15; j++) b.out.cov[m * 15 + j] = good ? s.c[j] : 0.0f;
+  b.out.chi2[m] = good ? chi2 : 0.0f;
+  b.out.ndf[m] = (int32_t)(2 * (e - a) - 5);
+  b.out.sector[m] = kf;
+  b.out.x_ref[m] = x;
+}
+
+__global__ void k_merge_init(MergeBufs b)
+{
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    *b.n_seg = b.res->n_tracks < b.cap_seg ? b.res->n_tracks : b.cap_seg;
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge_clear(MergeBufs b)
+{
+  for (int64_t i = gid(); i < b.cap_seg; i += (int64_t)gridDim.x * blockDim.x) b.has_pred[i] = 0;
+}
+
+}  // namespace
+
+hipError_t merge_tracks(const Consts& k, const MergeBufs& b, hipStream_t s)
+{
+  const unsigned nb = (unsigned)((b.cap_seg + kBlock - 1) / kBlock);
+  if (b.cap_seg <= 0) return hipGetLastError();
+  int slot = prof_begin(s, "merge_init");
+  k_merge_init<<<1, 1, 0, s>>>(b);
+  prof_end(s, slot);
+  slot = prof_begin(s, "merge_clear");
+  k_merge_clear<<<nb < 1024u ? nb : 1024u, kBlock, 0, s>>>(b);
+  prof_end(s, slot);
+  slot = prof_begin(s, "merge_seg_info");
+  k_seg_info<<<nb, kBlock, 0, s>>>(k, b);
+  prof_end(s, slot);
+  slot = prof_begin(s, "merge_sort");
+  k_sort_count<<<nb, kBlock, 0, s>>>(b);
+  k_sort_scan<<<1, 1024, 0, s>>>(b);
+  k_sort_scatter<<<nb, kBlock, 0, s>>>(b);
+  prof_end(s, slot);
+  slot = prof_begin(s, "merge_succ");
+  k_best<false><<<nb, kBlock, 0, s>>>(k, b);
+  prof_end(s, slot);
+  slot = prof_begin(s, "merge_pred");
+  k_best<true><<<nb, kBlock, 0, s>>>(k, b);
+  prof_end(s, slot);
+  slot = prof_begin(s, "merge_link");
+  k_link<<<nb, kBlock, 0, s>>>(b);
+  k_chains<<<1, 1024, 0, s>>>(b);
+  prof_end(s, slot);
+  slot = prof_begin(s, "merge_chain_hits");
+  k_chain_hits<<<nb, kBlock, 0, s>>>(b);
+  prof_end(s, slot);
+  slot = prof_begin(s, "merge_refit");
+  k_merge_refit<<<nb, kBlock, 0, s>>>(k, b);
+  prof_end(s, slot);
+  return hipGetLastError();
+}
+
+}  // namespace TPC_NS
+}  // namespace tpcca

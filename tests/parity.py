@@ -191,21 +191,34 @@ def check_structure(g: dict, row: np.ndarray, min_track_hits: int = 10) -> list:
     return e
 
 
-K_PROD = 10.0   # production error allowed per component, relative to binary32's
+# Production error allowed per component, in units of the track's binary32
+# rounding-noise scale: the production build rounds each operation to within
+# about 2 ulp (fast reciprocal and square root) against 0.5 ulp, a factor 4
+# in the noise scale, and 5 standard deviations of that keep a sample of
+# 10^4 tracks clear of the tail.
+K_PROD = 20.0
+N_NOISE = 8     # perturbed binary32 replays per track for its noise scale
 
 
 def prod_param_errors(g: dict, kept=None):
-    """Per kept tracklet and parameter: the production error and the
-    deterministic binary32 filter's error on the same hit list, both against
-    the binary64 replay of that list, relative to max(|p64|, floor)."""
+    """Per kept tracklet and parameter, against the binary64 replay of its
+    hit list and relative to max(|p64|, floor): the production error, and
+    the binary32 filter's rounding-noise scale on that list -- the largest
+    of the deterministic binary32 error, the error of a binary32 replay with
+    fused multiply-adds (another rounding of the same formulas) and the RMS
+    error of N_NOISE binary32 replays with every hit moved by a random +-1
+    ulp (a single binary32 error can be small by chance, so one draw alone is
+    no scale)."""
     e_prod = replay_params(g, kept=kept)
     e_32 = replay_params(g, kept=kept, against=32)
-    return e_prod, e_32
+    e_c = replay_params(g, kept=kept, against="32c")
+    e_n = replay_params(g, kept=kept, against="noise")
+    return e_prod, np.maximum(np.maximum(e_32, e_c), e_n)
 
 
 def prod_bound_violations(e_prod, e_32, k=K_PROD, base=1e-4):
-    """Tracklets whose production error exceeds max(base, k * binary32 error)
-    in some parameter."""
+    """Tracklets whose production error exceeds max(base, k * binary32
+    rounding-noise scale) in some parameter."""
     bound = np.maximum(base, k * e_32)
     return np.nonzero(np.any(e_prod > bound, axis=1))[0]
 
@@ -234,9 +247,23 @@ def replay_params(g: dict, prec=64, kept=None, against=None):
         if not ok:
             rel.append(np.full(5, np.nan))
             continue
-        if against == 32:
-            ok32, p32, _, _ = oracle.replay(G, P, r0, rmin, rmax, hy, hz, has, prec=32)
+        if against in (32, "32c"):
+            ok32, p32, _, _ = oracle.replay(G, P, r0, rmin, rmax, hy, hz, has, prec=against)
             cand = p32.astype(np.float64) if ok32 else np.full(5, np.inf)
+        elif against == "noise":
+            rng = np.random.default_rng(int(t))
+            sq = np.zeros(5)
+            for _ in range(N_NOISE):
+                up = rng.integers(0, 2, (2, NR)).astype(bool)
+                hy2 = np.where(up[0], np.nextafter(hy, np.float32(np.inf)),
+                               np.nextafter(hy, np.float32(-np.inf))).astype(np.float32)
+                hz2 = np.where(up[1], np.nextafter(hz, np.float32(np.inf)),
+                               np.nextafter(hz, np.float32(-np.inf))).astype(np.float32)
+                okn, pn, _, _ = oracle.replay(G, P, r0, rmin, rmax, hy2, hz2, has, prec=32)
+                d = (pn.astype(np.float64) - par) if okn else np.full(5, np.inf)
+                sq += d * d
+            rel.append(np.sqrt(sq / N_NOISE) / np.maximum(np.abs(par), floor))
+            continue
         else:
             cand = g["tl_par"][t]
         rel.append(np.abs(cand - par) / np.maximum(np.abs(par), floor))

@@ -176,6 +176,35 @@ static void invalid_calls()
   tg.nw = 1;
   EXPECT(tpc_cluster_transform(&tg, 1u, 1000, raw, dmap, cm, f, f, f, ro, nullptr) ==
          TPC_ERR_INVALID);
+  // merging
+  tpc_merge_params mp;
+  tpc_default_merge_params(&mp);
+  EXPECT(mp.cos_d > 0.93f && mp.cos_d < 0.94f && mp.sin_a[0] > 0.17f && mp.sin_a[0] < 0.18f);
+  tpc_tracks seg = {(float*)fake(0xC000), (float*)fake(0xC000), (float*)fake(0xC000),
+                    (int32_t*)fake(0xC000), (float*)fake(0xC000), (int32_t*)fake(0xC000),
+                    (int32_t*)fake(0xC000), (int32_t*)fake(0xC000), 500, 20000};
+  tpc_merged mo;
+  memset(&mo, 0, sizeof(mo));
+  mo.param = mo.cov = mo.chi2 = mo.x_ref = (float*)fake(0xD000);
+  mo.ndf = mo.status = mo.sector = mo.hit_off = mo.hit_clu = mo.seg_off = mo.seg = mo.next =
+      (int32_t*)fake(0xD000);
+  mo.counts = (int64_t*)fake(0xD000);
+  mo.cap_tracks = 500;
+  mo.cap_hits = 20000;
+  std::vector<char> mws(tpc_merge_workspace_bytes(500));
+  stub::g_ws = mws.data();
+  stub::g_ws_bytes = mws.size();
+  const int64_t* io = (const int64_t*)fake(0xE000);
+  const tpc_result* rs = (const tpc_result*)fake(0xE000);
+  EXPECT(tpc_merge_tracks(&g, &p, &mp, 36, io, in, &seg, rs, &mo, mws.data(), mws.size(),
+                          nullptr) == TPC_OK);
+  EXPECT(tpc_merge_tracks(&g, &p, &mp, 35, io, in, &seg, rs, &mo, mws.data(), mws.size(),
+                          nullptr) == TPC_ERR_INVALID);
+  EXPECT(tpc_merge_tracks(&g, &p, &mp, 36, io, in, &seg, rs, &mo, mws.data(), mws.size() - 1,
+                          nullptr) == TPC_ERR_WORKSPACE);
+  mo.cap_hits = 19999;
+  EXPECT(tpc_merge_tracks(&g, &p, &mp, 36, io, in, &seg, rs, &mo, mws.data(), mws.size(),
+                          nullptr) == TPC_ERR_INVALID);
   for (int s = 1; s >= -5; s--) EXPECT(tpc_status_string((tpc_status)s) != nullptr);
   EXPECT(tpc_standard_configuration(&g, &p) == 1);
   EXPECT(tpc_standard_configuration(nullptr, &p) == TPC_ERR_INVALID);

@@ -104,6 +104,18 @@ static hipError_t refit_stub(const RefitBufs& b)
   {                                                                                  \
     return refit_stub(b);                                                            \
   }                                                                                  \
+  hipError_t merge_tracks(const Consts&, const MergeBufs& b, hipStream_t)           \
+  {                                                                                  \
+    using stub::in_ws;                                                               \
+    const int64_t c = b.cap_seg;                                                     \
+    in_ws(b.n_seg, 8, "n_seg");                                                      \
+    in_ws(b.seg_pos, 24 * c, "seg_pos");                                             \
+    in_ws(b.out_c, 60 * c, "out_c");                                                 \
+    in_ws(b.sort_cnt, 4 * 36 * b.sort_blocks, "sort_cnt");                           \
+    in_ws(b.chain_head, 4 * c, "chain_head");                                        \
+    stub::g_calls++;                                                                 \
+    return hipSuccess;                                                               \
+  }                                                                                  \
   hipError_t cluster_transform(const TransformConsts& k, const TransformBufs& b,    \
                                hipStream_t)                                          \
   {                                                                                  \
