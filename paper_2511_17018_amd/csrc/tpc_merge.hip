@@ -437,12 +437,14 @@ __global__ __launch_bounds__(1024) void k_chains(MergeBufs b)
           start = u == t && lowest == t;
         }
         if (start) {
+          // at most n segments: the walk ends whatever next holds
           int64_t u = t;
-          do {
+          for (int64_t step = 0; step < n; step++) {
             nseg++;
             nhit += b.seg.hit_off[u + 1] - b.seg.hit_off[u];
             u = b.out.next[u];
-          } while (u >= 0 && u != t);
+            if (u < 0 || u == t) break;
+          }
         }
       }
       // three exclusive scans in one: starts, segments, hits
@@ -497,14 +499,18 @@ __global__ __launch_bounds__(kBlock) void k_chain_hits(MergeBufs b)
   const int64_t m = gid();
   if (m >= b.out.counts[0]) return;
   const int64_t t = b.chain_head[m];
+  const int64_t n = *b.n_seg;
   int64_t so = b.out.seg_off[m], ho = b.out.hit_off[m];
+  const int64_t se = b.out.seg_off[m + 1];
   int64_t u = t;
-  do {
+  // the segment count of the chain was fixed by k_chains
+  while (so < se) {
     b.out.seg[so++] = (int32_t)u;
     for (int64_t h = b.seg.hit_off[u]; h < b.seg.hit_off[u + 1]; h++)
       b.out.hit_clu[ho++] = b.seg.hit_clu[h];
     u = b.out.next[u];
-  } while (u >= 0 && u != t);
+    if (u < 0 || u >= n) break;
+  }
 }
 
 // --------------------------------------------------------------- refit
