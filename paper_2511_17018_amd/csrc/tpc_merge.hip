@@ -202,6 +202,12 @@ __global__ __launch_bounds__(kBlock) void k_seg_info(Consts k, MergeBufs b)
   const int64_t t = gid();
   if (t >= n) return;
   const int64_t a = b.seg.hit_off[t], e = b.seg.hit_off[t + 1];
+  if (e <= a) {  // the tracker emits no empty track; kept safe all the same
+    b.seg_inst[t] = 0;
+    b.out_ok[t] = 0;
+    for (int j = 0; j < 6; j++) b.seg_pos[t * 6 + j] = NAN;
+    return;
+  }
   const int64_t c0 = b.seg.hit_clu[a], c1 = b.seg.hit_clu[e - 1];
   const int inst = inst_of(s_off, c0);
   const int kk = inst % kPhi;
@@ -522,6 +528,10 @@ __global__ __launch_bounds__(kBlock) void k_merge_refit(Consts k, MergeBufs b)
   if (m >= b.out.counts[0]) return;
   const int64_t a = b.out.hit_off[m], e = b.out.hit_off[m + 1];
   const int64_t t0 = b.out.seg[b.out.seg_off[m]];
+  if (e <= a) {
+    b.out.status[m] = 1;
+    return;
+  }
   const int32_t* hits = b.out.hit_clu;
   float p5[5];
 #pragma unroll
