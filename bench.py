@@ -55,9 +55,6 @@ def log(*a):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "chain_config4_traffic.md")
-VALU_PROFILE = os.path.join(ROOT, "profiles", "chain_config4_valu_counters.md")
-N_CU = 256
-CLOCK_HZ = 2.4e9
 KERNEL_SOURCES = ["paper_2511_17018_amd/csrc/tpc_kernels.hip", "paper_2511_17018_amd/csrc/tpc_kalman.h",
                   "paper_2511_17018_amd/csrc/tpc_internal.h", "include/tpcca.h",
                   "paper_2511_17018_amd/build.py"]
@@ -91,23 +88,6 @@ def _profiled(path: str, field: str, kernel: str, occ: float, chunk: int) -> int
 def measured_traffic(kernel: str, occ: float, chunk: int) -> int | None:
     """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated)."""
     return _profiled(TRAFFIC_PROFILE, "traffic_bytes", kernel, occ, chunk)
-
-
-def measured_valu(kernel: str, occ: float, chunk: int) -> int | None:
-    """VALU wave64 instructions per launch of `kernel` (SQ_INSTS_VALU)."""
-    return _profiled(VALU_PROFILE, "valu_insts", kernel, occ, chunk)
-
-
-def valu_issue(kernel: str, occ: float, chunk: int, avg_s: float) -> dict | None:
-    """The kernel's VALU issue rate in wave64 instructions per CU-cycle (256
-    CUs at the 2.4 GHz peak clock over the live launch duration), beside the
-    issue model's limit without packed FP32: one per CU-cycle (four 16-lane
-    SIMDs, four cycles per wave64 instruction)."""
-    n = measured_valu(kernel, occ, chunk)
-    if n is None:
-        return None
-    return {"insts_per_launch": n, "per_cu_cycle": n / (N_CU * CLOCK_HZ * avg_s),
-            "model_limit_per_cu_cycle": 1.0, "source": os.path.relpath(VALU_PROFILE, ROOT)}
 
 
 def kernel_bytes(name: str, c: dict) -> float | None:
@@ -244,8 +224,7 @@ def run(args) -> dict:
                 "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                 "traffic": traffic, "traffic_source": os.path.relpath(TRAFFIC_PROFILE, ROOT)
                 if traffic else None, "avg_launch_ms": avg_s * 1e3,
-                "alg_bytes_per_launch": kb, "counts": counts,
-                "valu_issue": valu_issue(name, tp["grid_occupancy"], tp["tl_chunk"], avg_s)}
+                "alg_bytes_per_launch": kb, "counts": counts}
     out["kernels_ms_per_step"] = {k: round(v[0] / args.steps, 4) for k, v in
                                   sorted(ktimes.items(), key=lambda kv: -kv[1][0])}
     out["kernels_sum_ms_per_step"] = round(sum(v[0] for v in ktimes.values()) / args.steps, 4)
@@ -373,17 +352,184 @@ def run_refit(args) -> dict:
                         "avg_launch_ms": avg_s * 1e3, "alg_bytes_per_launch": kb}
     out["roofline"] = rl
     if not args.no_cpu:
+        from concurrent.futures import ThreadPoolExecutor
+
         import oracle
-        sub = 4000
-        hs = ho[:sub + 1]
+        sub = 8000
+        workers = cpu_workers()
+        chunk = sub // workers
+
+        def part(i):
+            a, b = i * chunk, (i + 1) * chunk if i + 1 < workers else sub
+            hs = ho[a:b + 1] - ho[a]
+            oracle.refit_grad(synth.geometry(), oracle.DEFAULT_PARAMS, ev, hs,
+                              hc[ho[a]:ho[b]], seed[a:b], np.zeros((152, 18), np.float32))
+            return b - a
+
         t = time.perf_counter()
-        oracle.refit_grad(synth.geometry(), oracle.DEFAULT_PARAMS, ev, hs, hc[:hs[-1]], seed[:sub],
-                          np.zeros((152, 18), np.float32))
+        part_one = sub // 4
+        hs = ho[:part_one + 1]
+        oracle.refit_grad(synth.geometry(), oracle.DEFAULT_PARAMS, ev, hs, hc[:hs[-1]],
+                          seed[:part_one], np.zeros((152, 18), np.float32))
+        t1 = time.perf_counter() - t
+        t = time.perf_counter()
+        with ThreadPoolExecutor(workers) as ex:
+            done = sum(ex.map(part, range(workers)))
         tc = time.perf_counter() - t
-        out["cpu_baseline"] = {"value": sub / tc, "unit": "tracks/s", "cores": 1,
+        out["cpu_baseline"] = {"value": done / tc, "unit": "tracks/s", "cores": workers,
                                "kind": "oracle",
                                "sample": f"first {sub} tracks, binary64 forward + reverse pass, "
-                                         "one thread"}
+                                         f"in {workers} chunks on {workers} threads",
+                               "single_thread": {"value": part_one / t1, "cores": 1,
+                                                 "sample": f"first {part_one} tracks"},
+                               "host": host_info()}
+    return out
+
+
+def _prof_pass(L, torch, fn, steps):
+    """Per-kernel HIP-event times (ms per step) of `steps` calls of fn."""
+    assert L.tpc_profile_enable(1) == 0
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    rows = (tpc_kernel_time * 64)()
+    nk = L.tpc_profile_read(rows, 64)
+    L.tpc_profile_enable(0)
+    return {rows[i].name.decode(): (rows[i].total_ms / steps, rows[i].launches // steps)
+            for i in range(nk)}
+
+
+def run_transform(args, ev) -> dict:
+    """Cluster coordinate transformation with both correction maps over the
+    benchmark's clusters (raw readout coordinates of the same 15.65 M
+    clusters, displaced by a smooth distortion)."""
+    import torch
+
+    import paper_2511_17018_amd as tpc
+    import synth
+
+    tg = synth.transform_geometry()
+    dist = synth.Distortion(amp=1.0)
+    raw = synth.encode_raw(ev, tg, dist=dist)
+    rmap = synth.calibration_map(tg, dist)
+    D = np.random.default_rng(3).uniform(-0.8, 0.8, (152, 18)).astype(np.float32)
+    dev = "cuda:0"
+    L = tpc.lib()
+    s = torch.from_numpy(raw["sector"]).to(dev)
+    r = torch.from_numpy(raw["row"].view(np.int16)).to(dev)
+    pd = torch.from_numpy(raw["pad"]).to(dev)
+    tm = torch.from_numpy(raw["time"]).to(dev)
+    Dd = torch.from_numpy(D).to(dev)
+    rm = torch.from_numpy(rmap).to(dev)
+    n = len(raw["row"])
+    out = tuple(torch.empty(n, dtype=dt, device=dev) for dt in (torch.float32, torch.float32,
+                                                               torch.float32, torch.int16))
+
+    def step():
+        tpc.cluster_transform(tg, s, r, pd, tm, Dd, rm, det=True, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    kt = _prof_pass(L, torch, step, args.steps)
+    avg_s = kt["transform"][0] / 1e3
+    kb = 25 * n        # sector 1 + row 2 + pad 4 + time 4 in, x y z 12 + row 2 out
+    res = {"value": n / dt, "unit": "clusters/s", "ms_per_step": dt * 1e3,
+           "workload": f"{n} raw clusters (the benchmark's, displaced by a 1 cm distortion), "
+                       "radial map 152x18 and residual map 36x16x9x26, deterministic build",
+           "roofline": {"bound": "hbm", "kernel": "transform", "achieved": kb / avg_s / 1e9,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": kb / avg_s / 1e9 / HBM_PEAK_GBS, "avg_launch_ms": avg_s * 1e3,
+                        "alg_bytes_per_launch": kb}}
+    if not args.no_cpu:
+        import oracle
+        t = time.perf_counter()
+        oracle.transform(tg, raw["sector"], raw["row"], raw["pad"], raw["time"], D, rmap)
+        tc = time.perf_counter() - t
+        res["cpu_baseline"] = {"value": n / tc, "unit": "clusters/s", "cores": 1,
+                               "kind": "oracle", "sample": f"all {n} clusters, binary32 oracle, "
+                                                           "one thread"}
+    log(f"transform: {dt * 1e3:.3f} ms/step, kernel {avg_s * 1e3:.3f} ms, "
+        f"{kb / avg_s / 1e9:.0f} GB/s")
+    return res
+
+
+def run_sectors(args, which: int, tp: dict) -> dict:
+    """Configs 2 and 3 (36 TPC sectors: one central collision, or 128
+    collisions of a time frame in one pass): the batched deterministic chain
+    (graph-captured) and the merging of its tracks across sector edges, with
+    per-kernel times."""
+    import torch
+
+    import paper_2511_17018_amd as tpc
+    import synth
+    from paper_2511_17018_amd.runtime import Chain, GraphChain
+
+    t0 = time.time()
+    ev = synth.config2() if which == 2 else synth.config3()
+    N = ev.n
+    log(f"config {which}: {N} clusters ({time.time() - t0:.1f}s)")
+    geom = synth.geometry()
+    L = tpc.lib()
+    dev = "cuda:0"
+    stream = torch.cuda.Stream(dev)
+    batch = tpc.upload(ev.x, ev.y, ev.z, ev.row, ev.charge, ev.inst_off, dev)
+    ch = Chain(geom, batch, True, stream, **tp)
+    steps = max(1, args.steps if which == 2 else min(args.steps, 5))
+    with torch.cuda.stream(stream):
+        ch.enqueue()
+        merged = tpc.merge_tracks(geom, batch, ch.tracks, ch.ws.result)
+    stream.synchronize()
+    res = ch.result()
+    if int(res["overflow"]):
+        raise RuntimeError(f"config {which}: overflow {res}")
+    graph = GraphChain([ch], stream)
+
+    def timed(fn, label):
+        with torch.cuda.stream(stream):
+            for _ in range(max(1, args.warmup)):
+                fn()
+        stream.synchronize()
+        t = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for _ in range(steps):
+                fn()
+        stream.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        log(f"config {which} {label}: {dt * 1e3:.3f} ms/step")
+        return dt
+
+    dt = timed(graph.replay, "tracking (graph)")
+
+    def merge():
+        tpc.merge_tracks(geom, batch, ch.tracks, ch.ws.result, out=merged)
+
+    dtm = timed(merge, "merging")
+
+    def both():
+        with torch.cuda.stream(stream):
+            ch.enqueue()
+            merge()
+
+    kt = _prof_pass(L, torch, both, steps)
+    h = merged.host()
+    n_seg = int(res["n_tracks"])
+    out = {"value": N / dt, "unit": "clusters/s", "ms_per_step": dt * 1e3, "steps": steps,
+           "workload": ("config 2: one central collision, 8000 tracks, 36 sectors"
+                        if which == 2 else
+                        "config 3: 128 collisions over 3 ms of drift time, 36 sectors, one pass"),
+           "n_clusters": N, "n_tracks": n_seg, "n_hits": int(res["n_hits"]),
+           "merge": {"ms_per_step": dtm * 1e3, "segments": n_seg, "merged_tracks": h["n"],
+                     "links": int((h["next"][:n_seg] >= 0).sum()),
+                     "refit_failed": int((h["status"] != 0).sum())},
+           "kernels_ms_per_step": {k: round(v[0], 4) for k, v in
+                                   sorted(kt.items(), key=lambda kv: -kv[1][0])}}
+    del graph, ch, merged
     return out
 
 
@@ -425,6 +571,31 @@ def differently_assigned(a: dict, b: dict, n: int) -> dict:
     return {"clusters": diff, "fraction": diff / max(1, n)}
 
 
+def host_info() -> dict:
+    """The host the CPU baselines ran on: logical CPUs, the ones this process
+    may use, and the CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "affinity": aff, "cpu_model": model,
+            "share_note": "the GPU box grants one GPU's share of 16 host CPUs; the pools use "
+                          "min(16, affinity) threads"}
+
+
+def cpu_workers() -> int:
+    return max(1, min(16, host_info()["affinity"]))
+
+
 def cpu_baseline(ev, every: int) -> dict:
     """The binary32 oracle (whole chain a1-a6, as it stands) on every
     `every`-th instance: once on one thread, once with the instances dealt to
@@ -446,7 +617,7 @@ def cpu_baseline(ev, every: int) -> dict:
     t = time.perf_counter()
     n_tot = sum(one(i) for i in sel)
     t1 = time.perf_counter() - t
-    workers = max(1, min(16, os.cpu_count() or 1))
+    workers = cpu_workers()
     # largest instances first, so the pool ends together
     order = sorted(sel, key=lambda i: -(ev.inst_off[i + 1] - ev.inst_off[i]))
     t = time.perf_counter()
@@ -457,7 +628,8 @@ def cpu_baseline(ev, every: int) -> dict:
     return {"value": n_par / tp, "unit": "clusters/s", "cores": workers, "kind": "oracle",
             "sample": f"{len(sel)} of {ev.n_inst} instances (every {every}th), {n_tot} clusters, "
                       f"binary32 oracle, whole chain a1-a6, instances dealt to {workers} threads",
-            "single_thread": {"value": n_tot / t1, "cores": 1, "seconds": t1}}
+            "single_thread": {"value": n_tot / t1, "cores": 1, "seconds": t1},
+            "host": host_info()}
 
 
 class tpc_kernel_time(C.Structure):
@@ -475,6 +647,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-every", type=int, default=4)
     ap.add_argument("--no-refit", action="store_true")
+    ap.add_argument("--no-transform", action="store_true")
+    ap.add_argument("--no-sectors", action="store_true",
+                    help="skip the config 2 / config 3 lines (tracking + merging)")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--fixed", default="",
                     help="OCC,CHUNK: use these launch parameters instead of tuning "
@@ -523,8 +698,14 @@ def main():
             line[k] = r[k]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(ev, args.cpu_every)
+    if not args.no_transform:
+        line["transform"] = run_transform(args, ev)
+    del ev
+    if not args.no_sectors:
+        tp = {k: r["autotune"][k] for k in ("grid_occupancy", "tl_chunk")}
+        line["config2"] = run_sectors(args, 2, tp)
+        line["config3"] = run_sectors(args, 3, tp)
     if not args.no_refit:
-        del ev
         line["refit"] = run_refit(args)
     print(json.dumps(line))
 

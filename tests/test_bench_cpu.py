@@ -1,5 +1,5 @@
-"""Host-side pieces of bench.py: the traffic and VALU figures are taken from
-the committed counter summaries only while the kernel sources and launch
+"""Host-side pieces of bench.py: the traffic figures are taken from the
+committed counter summary only while the kernel sources and launch
 parameters match."""
 import hashlib
 
@@ -46,26 +46,10 @@ def test_traffic_block_of_the_matching_launch(tmp_path, monkeypatch):
     assert bench.measured_traffic("neighbours", 2.0, 64) is None
 
 
-def test_valu_issue_rate_from_the_counter_summary(tmp_path, monkeypatch):
-    p = tmp_path / "valu.md"
-    p.write_text(f"```\nsource_sha256: {_sources_sha()}\n"
-                 "launch: 1.0,64\nvalu_insts tracklets: 1228800000\n```\n")
-    monkeypatch.setattr(bench, "VALU_PROFILE", str(p))
-    # 256 CUs x 2.4 GHz x 2 ms = 1.2288e9 CU-cycles: one instruction per CU-cycle
-    v = bench.valu_issue("tracklets", 1.0, 64, 2e-3)
-    assert abs(v["per_cu_cycle"] - 1.0) < 1e-12 and v["insts_per_launch"] == 1228800000
-    assert abs(bench.valu_issue("tracklets", 1.0, 64, 4e-3)["per_cu_cycle"] - 0.5) < 1e-12
-    assert bench.valu_issue("tracklets", 0.5, 64, 2e-3) is None
-    assert bench.valu_issue("neighbours", 1.0, 64, 2e-3) is None
-    p.write_text("```\nsource_sha256: " + "0" * 64 + "\nlaunch: 1.0,64\n"
-                 "valu_insts tracklets: 1228800000\n```\n")
-    assert bench.valu_issue("tracklets", 1.0, 64, 2e-3) is None
-
-
 def test_committed_summaries_parse():
     # the committed counter summaries carry blocks for the usual launch
     # configuration (values present whenever the sources still match)
-    for f in (bench.TRAFFIC_PROFILE, bench.VALU_PROFILE):
+    for f in (bench.TRAFFIC_PROFILE,):
         text = open(f).read()
         assert "source_sha256: " in text and "launch: 1.0,64" in text
 
