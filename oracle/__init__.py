@@ -379,10 +379,12 @@ def _refit_args(geom, params, ev_like, hit_off, hit_clu, seed, dmap):
     return g, P, arrs
 
 
-def refit(geom, params, ev_like, hit_off, hit_clu, seed, dmap, prec=32):
+def refit(geom, params, ev_like, hit_off, hit_clu, seed, dmap, prec=32, mat=None):
     """Forward refit: (chi2[n], status[n], ckpt[n_hits, 20]).  status 1: the
-    propagation failed; 2: a hit names no cluster or a row beyond the map."""
+    propagation failed; 2: a hit names no cluster or a row beyond the map.
+    `mat`: field map and material (R42-R44), see _material."""
     g, P, a = _refit_args(geom, params, ev_like, hit_off, hit_clu, seed, dmap)
+    M = _material(mat)
     n = len(a["hit_off"]) - 1
     nh = int(a["hit_off"][-1])
     dt = _dt(prec)
@@ -391,36 +393,65 @@ def refit(geom, params, ev_like, hit_off, hit_clu, seed, dmap, prec=32):
     ckpt = np.zeros((max(nh, 1), 20), dt)
     f = _fn("orc_refit", prec)
     f.restype = None
-    f(C.byref(g), C.byref(P), C.c_int64(n), _p(a["hit_off"]), _p(a["hit_clu"]), _p(a["sector"]),
+    f(C.byref(g), C.byref(P), C.byref(M), C.c_int64(n), _p(a["hit_off"]), _p(a["hit_clu"]), _p(a["sector"]),
       _p(a["x"]), _p(a["y"]), _p(a["z"]), _p(a["row"]), C.c_int64(len(a["x"])), _p(a["seed"]),
       _p(a["dmap"]), _p(chi2), _p(status), _p(ckpt))
     return chi2[:n], status[:n], ckpt[:nh]
+
+
+class Material(C.Structure):
+    _fields_ = [("bz", C.c_void_p), ("nzb", C.c_int32), ("ix0", C.c_void_p),
+                ("eloss", C.c_void_p)]
+
+
+def _material(mat):
+    """orc_material from a dict with any of bz [152, nzb], ix0 [152],
+    eloss [152] (None: uniform field, no material); the arrays are kept
+    alive on the returned structure."""
+    m = Material()
+    if not mat:
+        return m
+    keep = []
+    if mat.get("bz") is not None:
+        b = np.ascontiguousarray(mat["bz"], np.float32)
+        keep.append(b)
+        m.bz, m.nzb = b.ctypes.data, b.shape[1]
+    for name in ("ix0", "eloss"):
+        if mat.get(name) is not None:
+            a = np.ascontiguousarray(mat[name], np.float32)
+            keep.append(a)
+            setattr(m, name, a.ctypes.data)
+    m._keep = keep
+    return m
 
 
 REFIT_WHICH = {"x": 0, "y": 1, "z": 2, "map": 3}
 
 
 def refit_loss(geom, params, ev_like, hit_off, hit_clu, seed, dmap, w, which=None, idx=-1,
-               h=0.0, mode="f64"):
+               h=0.0, mode="f64", mat=None):
     """sum_t w_t chi2_t with one input perturbed by h (mode f64 / f32), or
     the complex-step derivative w.r.t. that input (mode c128)."""
     g, P, a = _refit_args(geom, params, ev_like, hit_off, hit_clu, seed, dmap)
+    M = _material(mat)
     n = len(a["hit_off"]) - 1
     w = np.ascontiguousarray(w, np.float64)
     f = getattr(lib(), f"orc_refit_loss_{mode}")
     f.restype = C.c_double
-    return f(C.byref(g), C.byref(P), C.c_int64(n), _p(a["hit_off"]), _p(a["hit_clu"]),
+    return f(C.byref(g), C.byref(P), C.byref(M), C.c_int64(n), _p(a["hit_off"]), _p(a["hit_clu"]),
              _p(a["sector"]), _p(a["x"]), _p(a["y"]), _p(a["z"]), _p(a["row"]),
              C.c_int64(len(a["x"])), _p(a["seed"]), _p(a["dmap"]), _p(w), C.c_int(-1 if which is None else REFIT_WHICH[which]),
              C.c_int64(idx), C.c_double(h))
 
 
 def refit_grad(geom, params, ev_like, hit_off, hit_clu, seed, dmap, w=None, ckpt=None,
-               status=None):
+               status=None, mat=None):
     """binary64 forward + reverse pass: (chi2, status, gmap[152,18], gx, gy, gz).
     With ckpt/status given (e.g. a binary32 forward's checkpoints) the reverse
     pass runs on those instead of the binary64 forward's."""
-    chi2, st64, ck64 = refit(geom, params, ev_like, hit_off, hit_clu, seed, dmap, prec=64)
+    chi2, st64, ck64 = refit(geom, params, ev_like, hit_off, hit_clu, seed, dmap, prec=64,
+                             mat=mat)
+    M = _material(mat)
     ckpt = ck64 if ckpt is None else ckpt
     status = st64 if status is None else status
     g, P, a = _refit_args(geom, params, ev_like, hit_off, hit_clu, seed, dmap)
@@ -434,7 +465,7 @@ def refit_grad(geom, params, ev_like, hit_off, hit_clu, seed, dmap, w=None, ckpt
     f = lib().orc_refit_grad_f64
     f.restype = None
     ck = np.ascontiguousarray(ckpt, np.float64) if len(ckpt) else np.zeros((1, 20))
-    f(C.byref(g), C.byref(P), C.c_int64(n), _p(a["hit_off"]), _p(a["hit_clu"]), _p(a["sector"]),
+    f(C.byref(g), C.byref(P), C.byref(M), C.c_int64(n), _p(a["hit_off"]), _p(a["hit_clu"]), _p(a["sector"]),
       _p(a["x"]), _p(a["y"]), _p(a["z"]), _p(a["row"]), _p(a["seed"]), _p(a["dmap"]), _p(ck),
       _p(np.ascontiguousarray(status, np.int32)), _p(w), C.c_int64(nc), _p(gmap), _p(gx), _p(gy),
       _p(gz))

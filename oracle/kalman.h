@@ -70,7 +70,16 @@ static int ci(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) 
  * F the exact derivative of these formulas.  Returns 0 (state untouched)
  * if |snp| would reach snp_max.
  */
+static int k_propagate_ds(kst* s, real x1, real x2, real kB, real snp_max, real* ds_out);
+
 static int k_propagate(kst* s, real x1, real x2, real kB, real snp_max)
+{
+  real ds;
+  return k_propagate_ds(s, x1, x2, kB, snp_max, &ds);
+}
+
+/* the same, also returning the step's signed transverse arc length ds */
+static int k_propagate_ds(kst* s, real x1, real x2, real kB, real snp_max, real* ds_out)
 {
   const real one = 1;
   real dx = x2 - x1;
@@ -89,6 +98,7 @@ static int k_propagate(kst* s, real x1, real x2, real kB, real snp_max)
   real g = one + u2 * (K_SIXTH + u2 * K_3_40);
   real sg = RE(dx) < 0 ? -one : one;
   real ds = (sg * L) * g;
+  *ds_out = ds;
   /* Jacobian entries */
   real h = (one + f * f) * (real)0.5;
   real ic1 = one / c1, ic2 = one / c2;

@@ -46,4 +46,13 @@ typedef struct {
   int32_t min_chain, tc_max_miss, min_tracklet_hits, min_track_hits;
 } orc_params;
 
+/* field map and material of the refit (readings R42-R44; any pointer may
+ * be NULL: uniform field of the geometry, no material) */
+typedef struct {
+  const float* bz;     /* [152][nzb] solenoid field [T] per row and z bin */
+  int32_t nzb;         /* z bins over [-250, 250] cm */
+  const float* ix0;    /* [152] inverse radiation length [1/cm] per row */
+  const float* eloss;  /* [152] mean energy loss at minimum ionisation [GeV/cm] per row */
+} orc_material;
+
 #endif

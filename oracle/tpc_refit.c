@@ -31,6 +31,60 @@
 
 static real kB_val(const orc_geom* g) { return (real)(-0.299792458e-2 * (double)g->bz); }
 
+/* R42: the field of the step into cluster c -- the map's value at c's row
+ * and the z bin of c's measured z (bins of 500 cm / nzb from -250 cm,
+ * clamped), converted like the geometry's field; piecewise constant, so it
+ * carries no derivative */
+static int zbin(float z, int nzb)
+{
+  const double f = floor(((double)z + 250.0) * (double)nzb / 500.0);
+  if (!(f >= 0)) return 0;
+  if (f > nzb - 1) return nzb - 1;
+  return (int)f;
+}
+
+static double step_B(const orc_geom* g, const orc_material* M, int64_t c, const float* z,
+                     const uint16_t* row)
+{
+  if (!M || !M->bz) return (double)g->bz;
+  return (double)M->bz[(int64_t)row[c] * M->nzb + zbin(z[c], M->nzb)];
+}
+
+/* R43, R44: material of the step (after the propagation, on its result):
+ * multiple-scattering noise on snp, tgl, q/pt from the Highland width
+ * without its logarithm, theta^2 = 0.0136^2 t / (beta p)^2 with t the
+ * traversed thickness in radiation lengths; then the mean energy loss
+ * dE/dx = K / beta^2 changes q/pt by the factor f = 1 + E dE / p^2 (sign
+ * of the step: outward steps lose energy), and the covariance row of q/pt
+ * by the same factor.  Pion mass hypothesis. */
+#define K_MS 1.8496e-4      /* 0.0136^2 [GeV^2] */
+#define M_PION2 0.019479785 /* 0.13957^2 [GeV^2] */
+
+static void mat_apply(kst* s, real ads, real sgn, real ix0, real K)
+{
+  const real one = 1;
+  const real snp = s->p[2], tgl = s->p[3], qpt = s->p[4];
+  const real t2 = one + tgl * tgl;
+  const real w = (qpt * qpt) / t2;
+  const real bg = one + (real)M_PION2 * w;
+  const real path = ads * SQRT(t2);
+  if (RE(ix0) > 0) {
+    const real th2 = ((real)K_MS * (path * ix0)) * (w * bg);
+    const real qt = qpt * tgl;
+    s->c[5] = s->c[5] + th2 * (((one - snp) * (one + snp)) * t2);
+    s->c[9] = s->c[9] + th2 * (t2 * t2);
+    s->c[13] = s->c[13] + th2 * (t2 * qt);
+    s->c[14] = s->c[14] + th2 * (qt * qt);
+  }
+  if (RE(K) > 0) {
+    const real corr = (SQRT(w * bg) * (K * bg)) * (path * sgn);
+    const real f = one + corr;
+    s->p[4] = qpt * f;
+    for (int j = 0; j < 4; j++) s->c[ci(4, j)] = s->c[ci(4, j)] * f;
+    s->c[14] = (s->c[14] * f) * f;
+  }
+}
+
 /* R21: measurement plane of cluster c (optionally perturbed) */
 static real plane_x(const float* x, const uint16_t* row, const uint8_t* sector, const float* dmap,
                     int64_t c)
@@ -41,12 +95,13 @@ static real plane_x(const float* x, const uint16_t* row, const uint8_t* sector, 
 /* R22-R24: refit of one track; returns 0 on a propagation failure.
  * pert_* adds a perturbation to one input (finite / complex-step checks):
  * which = 0 x[idx], 1 y[idx], 2 z[idx], 3 map cell idx, -1 none. */
-static int refit_one(const orc_geom* g, const orc_params* P, int64_t a, int64_t b,
-                     const int32_t* hit_clu, const uint8_t* sector, const float* x, const float* y,
-                     const float* z, const uint16_t* row, const float* seed5, const float* dmap,
-                     real* chi2_out, real* ckpt, int which, int64_t idx, real pert)
+static int refit_one(const orc_geom* g, const orc_params* P, const orc_material* M, int64_t a,
+                     int64_t b, const int32_t* hit_clu, const uint8_t* sector, const float* x,
+                     const float* y, const float* z, const uint16_t* row, const float* seed5,
+                     const float* dmap, real* chi2_out, real* ckpt, int which, int64_t idx,
+                     real pert)
 {
-  const real kB = kB_val(g);
+  const real kB0 = kB_val(g);
   const real vy = (real)g->sigma_y2, vz = (real)g->sigma_z2;
   const real smax = (real)P->snp_max;
 #define XK(c) (plane_x(x, row, sector, dmap, (c)) + \
@@ -71,9 +126,16 @@ static int refit_one(const orc_geom* g, const orc_params* P, int64_t a, int64_t 
   for (int64_t k = a + 1; k < b; k++) {
     const int64_t c = hit_clu[k];
     const real xk = XK(c);
-    if (!k_propagate(&st, xprev, xk, kB, smax)) {
+    const real kB = (M && M->bz) ? (real)(-0.299792458e-2 * step_B(g, M, c, z, row)) : kB0;
+    real ds;
+    if (!k_propagate_ds(&st, xprev, xk, kB, smax, &ds)) {
       *chi2_out = 0;
       return 0;
+    }
+    if (M && (M->ix0 || M->eloss)) {
+      const real sgn = RE(xk) - RE(xprev) < 0 ? (real)-1 : (real)1;
+      mat_apply(&st, ds * sgn, sgn, M->ix0 ? (real)M->ix0[row[c]] : (real)0,
+                M->eloss ? (real)M->eloss[row[c]] : (real)0);
     }
     chi2 += k_update(&st, YK(c), ZK(c), vy, vz);
     if (ckpt) {
@@ -103,10 +165,11 @@ static int hits_valid(const orc_geom* g, int64_t a, int64_t b, const int32_t* hi
 }
 
 /* a8 -- forward refit of n_tracks tracks (CSR hit lists, cluster indices). */
-void SFX(orc_refit)(const orc_geom* g, const orc_params* P, int64_t n_tracks, const int32_t* hit_off,
-                    const int32_t* hit_clu, const uint8_t* sector, const float* x, const float* y,
-                    const float* z, const uint16_t* row, int64_t n_clusters, const float* seed,
-                    const float* dmap, real* chi2, int32_t* status, real* ckpt)
+void SFX(orc_refit)(const orc_geom* g, const orc_params* P, const orc_material* M,
+                    int64_t n_tracks, const int32_t* hit_off, const int32_t* hit_clu,
+                    const uint8_t* sector, const float* x, const float* y, const float* z,
+                    const uint16_t* row, int64_t n_clusters, const float* seed, const float* dmap,
+                    real* chi2, int32_t* status, real* ckpt)
 {
   for (int64_t t = 0; t < n_tracks; t++) {
     const int64_t a = hit_off[t], b = hit_off[t + 1];
@@ -120,7 +183,7 @@ void SFX(orc_refit)(const orc_geom* g, const orc_params* P, int64_t n_tracks, co
       status[t] = 2;
       continue;
     }
-    status[t] = refit_one(g, P, a, b, hit_clu, sector, x, y, z, row, seed + 5 * t, dmap, &chi2[t],
+    status[t] = refit_one(g, P, M, a, b, hit_clu, sector, x, y, z, row, seed + 5 * t, dmap, &chi2[t],
                           ckpt, -1, -1, (real)0)
                     ? 0
                     : 1;
@@ -129,7 +192,8 @@ void SFX(orc_refit)(const orc_geom* g, const orc_params* P, int64_t n_tracks, co
 
 /* Sum_t w_t chi2_t with one input perturbed by h (binary builds: f(x + h);
  * complex build: Im f(x + i h) / h, the complex-step derivative). */
-double SFX(orc_refit_loss)(const orc_geom* g, const orc_params* P, int64_t n_tracks,
+double SFX(orc_refit_loss)(const orc_geom* g, const orc_params* P, const orc_material* M,
+                           int64_t n_tracks,
                            const int32_t* hit_off, const int32_t* hit_clu, const uint8_t* sector,
                            const float* x, const float* y, const float* z, const uint16_t* row,
                            int64_t n_clusters, const float* seed, const float* dmap,
@@ -140,7 +204,7 @@ double SFX(orc_refit_loss)(const orc_geom* g, const orc_params* P, int64_t n_tra
     const int64_t a = hit_off[t], b = hit_off[t + 1];
     if (b <= a || !hits_valid(g, a, b, hit_clu, row, n_clusters)) continue;
     real c2 = 0;
-    if (refit_one(g, P, a, b, hit_clu, sector, x, y, z, row, seed + 5 * t, dmap, &c2, NULL, which,
+    if (refit_one(g, P, M, a, b, hit_clu, sector, x, y, z, row, seed + 5 * t, dmap, &c2, NULL, which,
                   idx, (real)PERT(h)))
       tot += (real)w[t] * c2;
   }
@@ -248,11 +312,12 @@ static void mtm(double A[5][5], double B[5][5], double R[5][5]) /* R = A^T B */
 /* adjoint of the propagation's scalar chain: pb (in: adjoint of the
  * propagated state, out: adjoint of the state before), Fb = adjoints of the
  * six Jacobian entries; returns the adjoint of dx */
-static double prop_backward(const double* p, const prec* q, double kB, double* pb, const double Fb[6])
+static double prop_backward(const double* p, const prec* q, double kB, double* pb, const double Fb[6],
+                            double dsb_extra)
 {
   const double tgl = p[3], snp = p[2];
   double yb = pb[0], zb = pb[1], s2b = pb[2], tglb = pb[3], qptb = pb[4];
-  double dyb = yb, dsb = zb * tgl;
+  double dyb = yb, dsb = zb * tgl + dsb_extra;
   tglb += zb * q->ds;
   double ab = Fb[0], bb = Fb[1], db = Fb[2], eb = Fb[3], gqb = Fb[4], hqb = Fb[5];
   double dxb = 0, ccb = 0, Lb = 0, gb = 0, Lgb = 0, hlcb = 0, lcb = 0, u2b = 0, dylb = 0, hb = 0;
@@ -403,17 +468,119 @@ static void update_backward(const double* p, double C[5][5], double my, double m
   pb[1] -= rb[1];
 }
 
+/* the material step of mat_apply in binary64 with its intermediates, and
+ * its adjoint: (pp, C) is the propagated state and covariance on input, the
+ * state and covariance after the material on output */
+typedef struct {
+  double t2, w, bg, sq, path, th2, qt, corr, f, ads, sgn, ix0, K;
+  double C2[5][5];  /* covariance after the scattering noise, before the loss */
+  double q4;        /* q/pt before the loss */
+} mrec;
+
+static void mat_forward(double* pp, double C[5][5], double ads, double sgn, double ix0, double K,
+                        mrec* m)
+{
+  const double snp = pp[2], tgl = pp[3], qpt = pp[4];
+  m->ads = ads;
+  m->sgn = sgn;
+  m->ix0 = ix0;
+  m->K = K;
+  m->t2 = 1 + tgl * tgl;
+  m->w = (qpt * qpt) / m->t2;
+  m->bg = 1 + M_PION2 * m->w;
+  m->path = ads * sqrt(m->t2);
+  m->qt = qpt * tgl;
+  m->th2 = ix0 > 0 ? (K_MS * (m->path * ix0)) * (m->w * m->bg) : 0;
+  if (ix0 > 0) {
+    C[2][2] += m->th2 * (((1 - snp) * (1 + snp)) * m->t2);
+    C[3][3] += m->th2 * (m->t2 * m->t2);
+    C[4][3] += m->th2 * (m->t2 * m->qt);
+    C[3][4] = C[4][3];
+    C[4][4] += m->th2 * (m->qt * m->qt);
+  }
+  memcpy(m->C2, C, sizeof(m->C2));
+  m->q4 = qpt;
+  m->sq = sqrt(m->w * m->bg);
+  m->corr = K > 0 ? (m->sq * (K * m->bg)) * (m->path * sgn) : 0;
+  m->f = 1 + m->corr;
+  if (K > 0) {
+    pp[4] = qpt * m->f;
+    for (int j = 0; j < 4; j++) {
+      C[4][j] *= m->f;
+      C[j][4] = C[4][j];
+    }
+    C[4][4] = (C[4][4] * m->f) * m->f;
+  }
+}
+
+/* adjoint of mat_forward: pb, Xb in (adjoints after the material), out
+ * (adjoints of the propagated state and covariance); pp1 the propagated
+ * state; returns the adjoint of the step's signed arc length ds */
+static double mat_backward(const double* pp1, const mrec* m, double* pb, double Xb[5][5])
+{
+  const double snp = pp1[2], tgl = pp1[3], qpt = pp1[4];
+  double t2b = 0, wb = 0, bgb = 0, pathb = 0, qtb = 0;
+  if (m->K > 0) {
+    /* C = S C2 S with S = diag(1, 1, 1, 1, f); q/pt' = q/pt f */
+    double cb = pb[4] * m->q4;
+    double s = 0;
+    for (int j = 0; j < 4; j++) s += Xb[4][j] * m->C2[4][j];
+    cb += 2 * (s + Xb[4][4] * m->C2[4][4] * m->f);
+    pb[4] = pb[4] * m->f;
+    for (int j = 0; j < 4; j++) {
+      Xb[4][j] *= m->f;
+      Xb[j][4] = Xb[4][j];
+    }
+    Xb[4][4] = Xb[4][4] * m->f * m->f;
+    /* corr = sq * (K bg) * (path sgn), sq = sqrt(w bg) */
+    const double sqb = cb * (m->K * m->bg) * (m->path * m->sgn);
+    bgb += cb * m->sq * m->K * (m->path * m->sgn);
+    pathb += cb * m->sq * (m->K * m->bg) * m->sgn;
+    if (m->sq > 0) {
+      const double wbgb = sqb / (2 * m->sq);
+      wb += wbgb * m->bg;
+      bgb += wbgb * m->w;
+    }
+  }
+  if (m->ix0 > 0) {
+    /* <X, Q>: Q22, Q33, Q43 (= Q34), Q44 */
+    const double u22 = ((1 - snp) * (1 + snp)) * m->t2, u33 = m->t2 * m->t2;
+    const double u43 = m->t2 * m->qt, u44 = m->qt * m->qt;
+    const double A = Xb[2][2] * u22 + Xb[3][3] * u33 + 2 * Xb[4][3] * u43 + Xb[4][4] * u44;
+    const double th2 = m->th2;
+    pb[2] += th2 * Xb[2][2] * (-2 * snp) * m->t2;
+    t2b += th2 * (Xb[2][2] * ((1 - snp) * (1 + snp)) + Xb[3][3] * 2 * m->t2 + 2 * Xb[4][3] * m->qt);
+    qtb += th2 * (2 * Xb[4][3] * m->t2 + Xb[4][4] * 2 * m->qt);
+    /* th2 = K_MS path ix0 w bg */
+    pathb += A * K_MS * m->ix0 * m->w * m->bg;
+    wb += A * K_MS * m->path * m->ix0 * m->bg;
+    bgb += A * K_MS * m->path * m->ix0 * m->w;
+  }
+  /* qt = qpt tgl; bg = 1 + m2 w; w = qpt^2 / t2; path = ads sqrt(t2); t2 = 1 + tgl^2 */
+  pb[4] += qtb * tgl;
+  pb[3] += qtb * qpt;
+  wb += bgb * M_PION2;
+  pb[4] += wb * 2 * qpt / m->t2;
+  t2b += wb * (-m->w / m->t2);
+  const double st2 = sqrt(m->t2);
+  const double adsb = pathb * st2;
+  t2b += pathb * m->ads / (2 * st2);
+  pb[3] += t2b * 2 * tgl;
+  return adsb * m->sgn;  /* ads = sgn ds */
+}
+
 /* gradient of sum_t w[t] chi2_t w.r.t. the map (gmap[152*18]) and the
  * cluster coordinates (gx, gy, gz[n_clusters]); all outputs overwritten */
-void orc_refit_grad_f64(const orc_geom* g, const orc_params* P, int64_t n_tracks,
+void orc_refit_grad_f64(const orc_geom* g, const orc_params* P, const orc_material* M,
+                        int64_t n_tracks,
                         const int32_t* hit_off, const int32_t* hit_clu, const uint8_t* sector,
                         const float* x, const float* y, const float* z, const uint16_t* row,
                         const float* seed, const float* dmap, const double* ckpt,
                         const int32_t* status, const double* w, int64_t n_clusters, double* gmap,
                         double* gx, double* gy, double* gz)
 {
-  const double kB = -0.299792458e-2 * (double)g->bz;
   const double vy = g->sigma_y2, vz = g->sigma_z2;
+  const int mat = M && (M->ix0 || M->eloss);
   for (int64_t i = 0; i < (int64_t)g->n_rows * NPHI; i++) gmap[i] = 0;
   for (int64_t c = 0; c < n_clusters; c++) gx[c] = gy[c] = gz[c] = 0;
   for (int64_t t = 0; t < n_tracks; t++) {
@@ -430,6 +597,8 @@ void orc_refit_grad_f64(const orc_geom* g, const orc_params* P, int64_t n_tracks
       double p0[5], C0[5][5];
       for (int j = 0; j < 5; j++) p0[j] = ck[j];
       unpack(ck + 5, C0);
+      /* the step's field (R42), in binary64 like the binary64 forward */
+      const double kB = -0.299792458e-2 * step_B(g, M, c, z, row);
       prec q;
       prop_record(p0, X2 - X1, kB, &q);
       double F[5][5], Cp[5][5], pp[5];
@@ -444,8 +613,16 @@ void orc_refit_grad_f64(const orc_geom* g, const orc_params* P, int64_t n_tracks
       pp[2] = q.s2;
       pp[3] = p0[3];
       pp[4] = p0[4];
+      double pp1[5];
+      memcpy(pp1, pp, sizeof(pp1));
+      mrec mr;
+      memset(&mr, 0, sizeof(mr));
+      if (mat)
+        mat_forward(pp, Cp, q.ds * q.sg, q.sg, M->ix0 ? (double)M->ix0[row[c]] : 0,
+                    M->eloss ? (double)M->eloss[row[c]] : 0, &mr);
       double mb[2];
       update_backward(pp, Cp, (double)y[c], (double)z[c], vy, vz, w[t], pb, Xb, mb);
+      const double dsb_mat = mat ? mat_backward(pp1, &mr, pb, Xb) : 0;
       /* propagation: covariance part */
       double XF[5][5], XFC[5][5], Xn[5][5];
       mm(Xb, F, XF);
@@ -454,7 +631,7 @@ void orc_refit_grad_f64(const orc_geom* g, const orc_params* P, int64_t n_tracks
       const double Fb[6] = {2 * XFC[0][2], 2 * XFC[0][4], 2 * XFC[1][2],
                             2 * XFC[1][3], 2 * XFC[1][4], 2 * XFC[2][4]};
       memcpy(Xb, Xn, sizeof(Xn));
-      const double dxb = prop_backward(p0, &q, kB, pb, Fb);
+      const double dxb = prop_backward(p0, &q, kB, pb, Fb, dsb_mat);
       const double gXk = dxb + gX_next;
       gx[c] = gXk;
       gy[c] = mb[0];

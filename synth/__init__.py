@@ -560,3 +560,123 @@ def encode_raw(ev: Event, tg: dict, dist: Distortion | None = None,
     time = (drift / np.float64(tg["vdrift"]) + np.float64(tg["t0"])) / np.float64(tg["tbin"])
     return dict(sector=s.astype(np.uint8), row=ev.row.copy(), pad=pad.astype(np.float32),
                 time=time.astype(np.float32))
+
+
+# ---------------------------------------------------------------------------
+# tracks through a non-uniform field and material (refit with f2)
+
+M_PION = 0.13957                  # GeV
+
+
+def field_map(nzb=25, amp=0.03) -> np.ndarray:
+    """A smooth solenoid field [T] per (row, z bin): 0.5 T, varying by up to
+    1.5 `amp` (relative) with radius and z, not symmetric in z --
+    piecewise constant per cell, as the refit reads it."""
+    g = geometry()
+    xr = g["row_x"].astype(np.float64)
+    zc = -Z_MAX + (np.arange(nzb) + 0.5) * (2 * Z_MAX / nzb)
+    u = (xr - X_INNER) / (X_OUTER - X_INNER)
+    return (B_TESLA * (1 + amp * np.cos(np.pi * u)[:, None] * np.cos(np.pi * zc / Z_MAX)[None, :]
+                       + 0.5 * amp * np.sin(np.pi * zc / (2 * Z_MAX))[None, :])).astype(np.float32)
+
+
+def material_map(scale=1.0):
+    """Inverse radiation length [1/cm] and mean energy loss at minimum
+    ionisation [GeV/cm] per row: a Ne-CO2-N2-like gas (X0 ~ 86 m, about
+    3.2 MeV per metre), times `scale`."""
+    ix0 = np.full(N_ROWS, scale / 8600.0, np.float32)
+    eloss = np.full(N_ROWS, scale * 3.2e-6, np.float32)
+    return ix0, eloss
+
+
+def _zbin(z, nzb):
+    f = np.floor((z + Z_MAX) * nzb / (2 * Z_MAX))
+    return np.clip(np.where(np.isfinite(f), f, 0), 0, nzb - 1).astype(np.int64)
+
+
+def material_tracks(n=400, rep=0, bz=None, ix0=None, eloss=None, smear=True, pt_range=(0.15, 2.0),
+                    with_material=True) -> Event:
+    """Tracks of one sector (the local frame of sector 0, side A), simulated
+    row by row in binary64: an exact helix step between the pad-row planes
+    in the field of the destination cell (`bz` [152, nzb], or 0.5 T), then,
+    with material, a random multiple-scattering kick (Highland width without
+    its logarithm, both directions perpendicular to the track) and the mean
+    energy loss (dE/dx = K / beta^2, exact in energy), for pions.  One hit
+    per row, smeared; a track stops at |sin phi| > 0.95, the sector edge or
+    |z| > 250 cm.  Returns an Event with the refit's hit lists, the true
+    (snp, tgl, q/pt) at the first hit as seeds and the true q/pt at the
+    last hit (extra "qpt_last")."""
+    seed = SEED_BASE + 0x52 + 0x100 * rep
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = geometry()
+    xr = g["row_x"].astype(np.float64)
+    tan_half = np.tan(np.radians(SECTOR_DEG / 2))
+    ys, zs, rows, counts, seeds, truth_qpt = [], [], [], [], [], []   # q/pt at the last hit
+    while len(counts) < n:
+        pt = np.exp(rng.uniform(np.log(pt_range[0]), np.log(pt_range[1])))
+        q = rng.choice([-1.0, 1.0])
+        lam = np.arctan(np.sinh(rng.uniform(-0.9, 0.9)))
+        phi = rng.uniform(-0.3, 0.3)
+        p = pt / np.cos(lam)
+        y = rng.uniform(-0.1, 0.1) * xr[0]
+        z = rng.uniform(-20, 20)
+        hy, hz, hr = [y], [z], [0]
+        sd = (np.sin(phi), np.tan(lam), q / (p * np.cos(lam)))
+        for r in range(1, N_ROWS):
+            B = float(bz[r, _zbin(np.array([z]), bz.shape[1])[0]]) if bz is not None else B_TESLA
+            C = -C_LIGHT * B * q / (p * np.cos(lam))
+            dx = xr[r] - xr[r - 1]
+            s1 = np.sin(phi) + C * dx
+            if abs(s1) > 0.95:
+                break
+            phi1 = np.arcsin(s1)
+            if abs(C) > 1e-12:
+                y = y + (np.cos(phi) - np.cos(phi1)) / C
+                arc = (phi1 - phi) / C
+            else:
+                y = y + dx * np.tan(phi)
+                arc = dx / np.cos(phi)
+            z = z + np.tan(lam) * arc
+            phi = phi1
+            if abs(y) > xr[r] * tan_half or abs(z) > Z_MAX:
+                break
+            if with_material and ix0 is not None:
+                path = abs(arc) / np.cos(lam)
+                e = np.sqrt(p * p + M_PION ** 2)
+                beta2 = p * p / (e * e)
+                th = np.sqrt(0.0136 ** 2 * path * float(ix0[r]) / (beta2 * p * p))
+                phi += rng.normal(0, th) / np.cos(lam)
+                lam += rng.normal(0, th)
+                e -= float(eloss[r]) / beta2 * path
+                if e <= M_PION * 1.01:
+                    break
+                p = np.sqrt(e * e - M_PION ** 2)
+            hy.append(y)
+            hz.append(z)
+            hr.append(r)
+        if len(hr) < 20:
+            continue
+        ys += hy
+        zs += hz
+        rows += hr
+        counts.append(len(hr))
+        seeds.append(sd)
+        truth_qpt.append(q / (p * np.cos(lam)))
+    m = len(rows)
+    hit_off = np.zeros(n + 1, np.int64)
+    hit_off[1:] = np.cumsum(counts)
+    y = np.array(ys) + (rng.normal(0, SIGMA_Y, m) if smear else 0.0)
+    z = np.array(zs) + (rng.normal(0, SIGMA_Z, m) if smear else 0.0)
+    row = np.array(rows, np.uint16)
+    sp = np.zeros((n, 5), np.float32)
+    first = hit_off[:-1]
+    sp[:, 0] = y[first]
+    sp[:, 1] = z[first]
+    sp[:, 2:] = np.array(seeds)
+    ev = Event(name="material", seed=seed, x=g["row_x"][row], y=y.astype(np.float32),
+               z=z.astype(np.float32), row=row, charge=np.zeros(m, np.uint16),
+               inst_off=np.array([0, m], np.int64), label=np.repeat(np.arange(n), counts),
+               sector=np.zeros(m, np.uint8), inst_sector=np.zeros(1, np.int32))
+    ev.extra.update(hit_off=hit_off.astype(np.int32), hit_clu=np.arange(m, dtype=np.int32),
+                    seed_par=sp, qpt_last=np.array(truth_qpt))
+    return ev

@@ -88,6 +88,14 @@ MUTATIONS = [
     ("tpc_transform.c", TRANSFORM, "map w from z", "cell(d, (real)T->w0,", "cell(za, (real)T->w0,"),
     ("tpc_transform.c", TRANSFORM, "dz correction sign", "zc = zc + corr[2];", "zc = zc - corr[2];"),
     ("tpc_transform.c", TRANSFORM, "map u and w lerp swapped", "corr[q] = lerp(f0, f1, au);", "corr[q] = lerp(f0, f1, aw);"),
+    ("tpc_refit.c", REFIT, "scattering without 1/beta^2", "const real th2 = ((real)K_MS * (path * ix0)) * (w * bg);", "const real th2 = ((real)K_MS * (path * ix0)) * w;"),
+    ("tpc_refit.c", REFIT, "scattering snp noise without 1+tgl^2", "th2 * (((one - snp) * (one + snp)) * t2)", "th2 * ((one - snp) * (one + snp))"),
+    ("tpc_refit.c", REFIT, "scattering tgl-qpt correlation sign", "s->c[13] = s->c[13] + th2 * (t2 * qt);", "s->c[13] = s->c[13] - th2 * (t2 * qt);"),
+    ("tpc_refit.c", REFIT, "energy loss sign", "(SQRT(w * bg) * (K * bg)) * (path * sgn)", "(SQRT(w * bg) * (K * bg)) * (path * -sgn)"),
+    ("tpc_refit.c", REFIT, "energy loss q/pt variance scaled once", "s->c[14] = (s->c[14] * f) * f;", "s->c[14] = s->c[14] * f;"),
+    ("tpc_refit.c", REFIT, "adjoint scattering path term dropped", "pathb += A * K_MS * m->ix0 * m->w * m->bg;", "(void)0;"),
+    ("tpc_refit.c", REFIT, "adjoint energy loss sqrt term dropped", "wb += wbgb * m->bg;", "(void)0;"),
+    ("tpc_refit.c", REFIT, "field bin from |z|", "floor(((double)z + 250.0) *", "floor((fabs((double)z) + 250.0) *"),
     ("tpc_merge.c", MERGE, "rotated y sign", "s->p[0] = y * ca - x * sa;", "s->p[0] = y * ca + x * sa;"),
     ("tpc_merge.c", MERGE, "rotation jacobian j00 sign", "const real j00 = ca - sa * (snn / csn);", "const real j00 = ca + sa * (snn / csn);"),
     ("tpc_merge.c", MERGE, "rotation jacobian curvature term dropped", "const real j20 = -(kB * s->p[4]) * sa;", "const real j20 = 0;"),
