@@ -263,6 +263,36 @@ typedef struct {
 
 #define TPC_N_PHI 18
 
+/* f2: solenoid field map and material budget of the refit (Sec. 4 lists the
+ * field map and the material budget map among the components of the track
+ * propagation that TPC tracking shares; the formulas are this library's).
+ * A host struct of caller-owned device arrays; the struct pointer, and each
+ * array pointer in it, may be NULL:
+ *   bz     [152][nzb]  field [T] of a step, taken at the destination hit: its
+ *                      row and the z bin of its measured z (bins of 500/nzb cm
+ *                      from z = -250 cm, clamped to the first and last bin);
+ *                      NULL: the geometry's uniform bz_tesla
+ *   nzb                z bins, 1..65536 when bz is given
+ *   ix0    [152]       inverse radiation length [1/cm] of the gas at each row:
+ *                      after each step's propagation, multiple-scattering noise
+ *                      on (snp, tgl, q/pt) from the Highland width without its
+ *                      logarithm, theta^2 = 0.0136^2 * t / (beta p)^2 with t the
+ *                      traversed thickness in radiation lengths (pion mass);
+ *                      NULL or entries <= 0: no scattering
+ *   eloss  [152]       mean energy loss at minimum ionisation [GeV/cm]: dE/dx =
+ *                      eloss / beta^2 changes q/pt by the factor
+ *                      1 + E dE / p^2 along the step (outward steps lose
+ *                      energy), and the covariance row of q/pt by the same
+ *                      factor; NULL or entries <= 0: no energy loss
+ * The field cell is piecewise constant and carries no gradient; the material
+ * terms are differentiated like the rest of the filter. */
+typedef struct {
+  const float* bz;
+  int32_t nzb;
+  const float* ix0;
+  const float* eloss;
+} tpc_material;
+
 /* a8: Kalman refit of found tracks under a per-row radial distortion map.
  * Each hit is measured on the plane X = x + dist_map[row][sector % 18]; the
  * filter of the tracker (propagation, Jacobian, update) runs from the first
@@ -272,16 +302,20 @@ typedef struct {
  * tgl, qpt, lower-triangular covariance).  With TPC_FLAG_DETERMINISTIC chi2
  * and ckpt equal the binary32 CPU reference bit for bit.  This refit is the
  * differentiable extension of the tracking step; the paper's shared track
- * propagation with field and material maps (Sec. 4) is its context.
+ * propagation with field and material maps (Sec. 4) is its context.  With
+ * mat (NULL: uniform field, no material), each step uses the field of its
+ * destination hit's cell and is followed by the material's scattering noise
+ * and energy loss, before that hit's update (see tpc_material).
  * A hit must name a cluster in [0, n_clusters) whose row is below 152 (the
  * map has no plane for other rows): a track with any other hit is not
  * refitted (status 2, chi2 0; 2 takes precedence over 1).  Checkpoints of
  * tracks with status != 0 are unspecified.
  * Errors: TPC_ERR_INVALID (null pointers, n_tracks < 0, n_clusters >= 2^31,
- * n_rows != 152, unknown flags). */
+ * n_rows != 152, unknown flags, mat->bz given with nzb outside 1..65536). */
 tpc_status tpc_refit(const tpc_geometry* geom, const tpc_params* params, int64_t n_clusters,
                      tpc_clusters in, tpc_refit_tracks trk, const float* dist_map_dev,
-                     float* chi2_dev, int32_t* status_dev, float* ckpt_dev, void* stream);
+                     const tpc_material* mat, float* chi2_dev, int32_t* status_dev,
+                     float* ckpt_dev, void* stream);
 
 /* a9: gradient of L = sum_t grad_chi2[t] * chi2[t] with respect to the map
  * (grad_map[152][18]) and the cluster coordinates (grad_x, grad_y, grad_z,
@@ -290,7 +324,8 @@ tpc_status tpc_refit(const tpc_geometry* geom, const tpc_params* params, int64_t
  * propagation (Sec. 4) but no gradient: this reverse-mode derivative of the
  * refit's chi2 is the differentiable extension, for fitting such a
  * correction map.  All outputs are overwritten.  Uses the forward call's
- * ckpt and status (same inputs); tracks with status != 0 contribute nothing.
+ * ckpt and status (same inputs, mat included); tracks with status != 0
+ * contribute nothing.
  * Precondition: each cluster is a hit of at most one refitted track (as in
  * the tracker's output, where clu2trk names one track per cluster).  The
  * cluster gradients are stored, not added, so a cluster on several tracks
@@ -304,7 +339,8 @@ tpc_status tpc_refit(const tpc_geometry* geom, const tpc_params* params, int64_t
 size_t tpc_refit_workspace_bytes(void);
 tpc_status tpc_refit_backward(const tpc_geometry* geom, const tpc_params* params,
                               int64_t n_clusters, tpc_clusters in, tpc_refit_tracks trk,
-                              const float* dist_map_dev, const float* ckpt_dev,
+                              const float* dist_map_dev, const tpc_material* mat,
+                              const float* ckpt_dev,
                               const int32_t* status_dev, const float* grad_chi2_dev,
                               float* grad_map_dev, float* grad_x_dev, float* grad_y_dev,
                               float* grad_z_dev, void* ws_dev, size_t ws_bytes, void* stream);
@@ -323,7 +359,8 @@ tpc_status tpc_refit_backward(const tpc_geometry* geom, const tpc_params* params
  * call on a device (which looks the array's address up once). */
 tpc_status tpc_refit_backward_noalloc(const tpc_geometry* geom, const tpc_params* params,
                                       int64_t n_clusters, tpc_clusters in, tpc_refit_tracks trk,
-                                      const float* dist_map_dev, const float* ckpt_dev,
+                                      const float* dist_map_dev, const tpc_material* mat,
+                                      const float* ckpt_dev,
                                       const int32_t* status_dev, const float* grad_chi2_dev,
                                       float* grad_map_dev, float* grad_x_dev, float* grad_y_dev,
                                       float* grad_z_dev, void* stream);

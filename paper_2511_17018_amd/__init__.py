@@ -358,9 +358,48 @@ def _xyz_struct(xyz: torch.Tensor, row: torch.Tensor) -> Clusters:
     return Clusters(_ptr(xyz[0]), _ptr(xyz[1]), _ptr(xyz[2]), _ptr(row), C.c_void_p(0))
 
 
+class MaterialStruct(C.Structure):
+    _fields_ = [("bz", C.c_void_p), ("nzb", C.c_int32), ("ix0", C.c_void_p),
+                ("eloss", C.c_void_p)]
+
+
+@dataclass
+class Material:
+    """Field map and material of the refit (tpc_material): device tensors,
+    any of them None -- bz float32 [152, nzb] field [T] per row and z bin,
+    ix0 float32 [152] inverse radiation length [1/cm], eloss float32 [152]
+    mean energy loss at minimum ionisation [GeV/cm]."""
+    bz: torch.Tensor | None = None
+    ix0: torch.Tensor | None = None
+    eloss: torch.Tensor | None = None
+
+    def struct(self) -> MaterialStruct:
+        for t in (self.bz, self.ix0, self.eloss):
+            assert t is None or (t.dtype == torch.float32 and t.is_contiguous())
+        nzb = self.bz.shape[1] if self.bz is not None else 0
+        return MaterialStruct(_ptr(self.bz) if self.bz is not None else None, nzb,
+                              _ptr(self.ix0) if self.ix0 is not None else None,
+                              _ptr(self.eloss) if self.eloss is not None else None)
+
+
+def upload_material(bz=None, ix0=None, eloss=None, device="cuda") -> Material:
+    t = (lambda a: None if a is None
+         else torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device))  # noqa: E731
+    return Material(t(bz), t(ix0), t(eloss))
+
+
+def _mat_ref(mat: Material | None):
+    """(pointer argument, the struct kept alive by the caller)"""
+    if mat is None:
+        return None, None
+    m = mat.struct()
+    return C.byref(m), m
+
+
 def refit(geom: dict, xyz: torch.Tensor, row: torch.Tensor, trk: RefitTracks,
-          dist_map: torch.Tensor, det: bool = True):
-    """tpc_refit on the current stream: (chi2[n], status[n], ckpt[n_hits, 20])."""
+          dist_map: torch.Tensor, det: bool = True, mat: Material | None = None):
+    """tpc_refit on the current stream: (chi2[n], status[n], ckpt[n_hits, 20]).
+    mat: field map and material (None: uniform field, no material)."""
     assert xyz.dtype == torch.float32 and xyz.is_contiguous() and xyz.shape[0] == 3
     dev = xyz.device
     n = trk.n_tracks
@@ -371,15 +410,16 @@ def refit(geom: dict, xyz: torch.Tensor, row: torch.Tensor, trk: RefitTracks,
     p = make_params(det)
     L = lib()
     L.tpc_refit.restype = C.c_int
+    mref, _keep = _mat_ref(mat)
     _check(L.tpc_refit(C.byref(g), C.byref(p), C.c_int64(xyz.shape[1]), _xyz_struct(xyz, row),
-                       trk.struct(), _ptr(dist_map.contiguous()), _ptr(chi2), _ptr(status),
-                       _ptr(ckpt), _stream()), "tpc_refit")
+                       trk.struct(), _ptr(dist_map.contiguous()), mref, _ptr(chi2),
+                       _ptr(status), _ptr(ckpt), _stream()), "tpc_refit")
     return chi2[:n], status[:n], ckpt[:trk.n_hits]
 
 
 def refit_backward(geom: dict, xyz: torch.Tensor, row: torch.Tensor, trk: RefitTracks,
                    dist_map: torch.Tensor, ckpt: torch.Tensor, status: torch.Tensor,
-                   grad_chi2: torch.Tensor):
+                   grad_chi2: torch.Tensor, mat: Material | None = None):
     """tpc_refit_backward: (grad_map[152, 18], grad_xyz[3, n_clusters])."""
     dev = xyz.device
     nc = xyz.shape[1]
@@ -392,9 +432,10 @@ def refit_backward(geom: dict, xyz: torch.Tensor, row: torch.Tensor, trk: RefitT
     g = make_geometry(geom)
     p = make_params(True)
     ckpt_p = _ptr(ckpt) if trk.n_hits else C.c_void_p(0)
+    mref, _keep = _mat_ref(mat)
     _check(L.tpc_refit_backward(
         C.byref(g), C.byref(p), C.c_int64(nc), _xyz_struct(xyz, row), trk.struct(),
-        _ptr(dist_map.contiguous()), ckpt_p, _ptr(status), _ptr(grad_chi2.contiguous()),
+        _ptr(dist_map.contiguous()), mref, ckpt_p, _ptr(status), _ptr(grad_chi2.contiguous()),
         _ptr(gmap), _ptr(gxyz[0]), _ptr(gxyz[1]), _ptr(gxyz[2]), _ptr(ws),
         C.c_size_t(ws.numel()), _stream()), "tpc_refit_backward")
     return gmap, gxyz[:, :nc]
@@ -402,7 +443,8 @@ def refit_backward(geom: dict, xyz: torch.Tensor, row: torch.Tensor, trk: RefitT
 
 def refit_backward_noalloc(geom: dict, xyz: torch.Tensor, row: torch.Tensor, trk: RefitTracks,
                            dist_map: torch.Tensor, ckpt: torch.Tensor, status: torch.Tensor,
-                           grad_chi2: torch.Tensor, gmap: torch.Tensor, gxyz: torch.Tensor):
+                           grad_chi2: torch.Tensor, gmap: torch.Tensor, gxyz: torch.Tensor,
+                           mat: Material | None = None):
     """tpc_refit_backward_noalloc into caller-given outputs grad_map[152, 18]
     and grad_xyz[3, >= n_clusters] (the library allocates nothing)."""
     nc = xyz.shape[1]
@@ -413,9 +455,10 @@ def refit_backward_noalloc(geom: dict, xyz: torch.Tensor, row: torch.Tensor, trk
     g = make_geometry(geom)
     p = make_params(True)
     ckpt_p = _ptr(ckpt) if trk.n_hits else C.c_void_p(0)
+    mref, _keep = _mat_ref(mat)
     _check(L.tpc_refit_backward_noalloc(
         C.byref(g), C.byref(p), C.c_int64(nc), _xyz_struct(xyz, row), trk.struct(),
-        _ptr(dist_map.contiguous()), ckpt_p, _ptr(status), _ptr(grad_chi2.contiguous()),
+        _ptr(dist_map.contiguous()), mref, ckpt_p, _ptr(status), _ptr(grad_chi2.contiguous()),
         _ptr(gmap), _ptr(gxyz[0]), _ptr(gxyz[1]), _ptr(gxyz[2]), _stream()),
         "tpc_refit_backward_noalloc")
     return gmap, gxyz[:, :nc]
@@ -430,20 +473,20 @@ class TpcRefit(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, xyz, dist_map, row, tracks, geom, det=True):
+    def forward(ctx, xyz, dist_map, row, tracks, geom, det=True, mat=None):
         xyz_c = xyz.detach().contiguous()
         map_c = dist_map.detach().contiguous()
-        chi2, status, ckpt = refit(geom, xyz_c, row, tracks, map_c, det)
+        chi2, status, ckpt = refit(geom, xyz_c, row, tracks, map_c, det, mat)
         ctx.save_for_backward(xyz_c, map_c, ckpt, status)
-        ctx.row, ctx.tracks, ctx.geom = row, tracks, geom
+        ctx.row, ctx.tracks, ctx.geom, ctx.mat = row, tracks, geom, mat
         return chi2
 
     @staticmethod
     def backward(ctx, grad_chi2):
         xyz_c, map_c, ckpt, status = ctx.saved_tensors
         gmap, gxyz = refit_backward(ctx.geom, xyz_c, ctx.row, ctx.tracks, map_c, ckpt, status,
-                                    grad_chi2.float().contiguous())
-        return gxyz, gmap, None, None, None, None
+                                    grad_chi2.float().contiguous(), ctx.mat)
+        return gxyz, gmap, None, None, None, None, None
 
 
 # ----------------------------------------------------------------------------

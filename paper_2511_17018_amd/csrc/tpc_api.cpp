@@ -393,6 +393,21 @@ static tpc_status refit_check(const tpc_geometry* g, const tpc_params* p, int64_
   return TPC_OK;
 }
 
+// the field map's z binning must give at least one bin
+static bool material_ok(const tpc_material* m)
+{
+  return !m || !m->bz || (m->nzb >= 1 && m->nzb <= 65536);
+}
+
+static void set_material(RefitBufs& b, const tpc_material* m)
+{
+  if (!m) return;
+  b.bz = m->bz;
+  b.nzb = m->bz ? m->nzb : 0;
+  b.ix0 = m->ix0;
+  b.eloss = m->eloss;
+}
+
 static RefitBufs refit_bufs(int64_t n_clusters, const tpc_clusters& in, const tpc_refit_tracks& trk,
                             const float* dmap)
 {
@@ -414,14 +429,17 @@ static RefitBufs refit_bufs(int64_t n_clusters, const tpc_clusters& in, const tp
 
 tpc_status tpc_refit(const tpc_geometry* geom, const tpc_params* params, int64_t n_clusters,
                      tpc_clusters in, tpc_refit_tracks trk, const float* dist_map_dev,
-                     float* chi2_dev, int32_t* status_dev, float* ckpt_dev, void* stream)
+                     const tpc_material* mat, float* chi2_dev, int32_t* status_dev,
+                     float* ckpt_dev, void* stream)
 {
   tpc_status st = refit_check(geom, params, n_clusters, in, trk, dist_map_dev);
   if (st != TPC_OK) return st;
+  if (!material_ok(mat)) return TPC_ERR_INVALID;
   if (trk.n_tracks > 0 && (!chi2_dev || !status_dev)) return TPC_ERR_INVALID;
   if (trk.n_hits > 0 && (!ckpt_dev || reinterpret_cast<uintptr_t>(ckpt_dev) % 16))
     return TPC_ERR_INVALID;
   RefitBufs b = refit_bufs(n_clusters, in, trk, dist_map_dev);
+  set_material(b, mat);
   b.chi2 = chi2_dev;
   b.status = status_dev;
   b.ckpt = ckpt_dev;
@@ -435,6 +453,7 @@ tpc_status tpc_refit(const tpc_geometry* geom, const tpc_params* params, int64_t
 static tpc_status refit_backward_check(const tpc_geometry* geom, const tpc_params* params,
                                        int64_t n_clusters, const tpc_clusters& in,
                                        const tpc_refit_tracks& trk, const float* dist_map_dev,
+                                       const tpc_material* mat,
                                        const float* ckpt_dev, const int32_t* status_dev,
                                        const float* grad_chi2_dev, const float* grad_map_dev,
                                        const float* grad_x_dev, const float* grad_y_dev,
@@ -442,6 +461,7 @@ static tpc_status refit_backward_check(const tpc_geometry* geom, const tpc_param
 {
   tpc_status st = refit_check(geom, params, n_clusters, in, trk, dist_map_dev);
   if (st != TPC_OK) return st;
+  if (!material_ok(mat)) return TPC_ERR_INVALID;
   if (!grad_map_dev) return TPC_ERR_INVALID;
   if (trk.n_tracks > 0 && (!status_dev || !grad_chi2_dev)) return TPC_ERR_INVALID;
   if (trk.n_hits > 0 && (!ckpt_dev || reinterpret_cast<uintptr_t>(ckpt_dev) % 16))
@@ -452,16 +472,19 @@ static tpc_status refit_backward_check(const tpc_geometry* geom, const tpc_param
 
 tpc_status tpc_refit_backward_noalloc(const tpc_geometry* geom, const tpc_params* params,
                                       int64_t n_clusters, tpc_clusters in, tpc_refit_tracks trk,
-                                      const float* dist_map_dev, const float* ckpt_dev,
+                                      const float* dist_map_dev, const tpc_material* mat,
+                                      const float* ckpt_dev,
                                       const int32_t* status_dev, const float* grad_chi2_dev,
                                       float* grad_map_dev, float* grad_x_dev, float* grad_y_dev,
                                       float* grad_z_dev, void* stream)
 {
-  tpc_status st = refit_backward_check(geom, params, n_clusters, in, trk, dist_map_dev, ckpt_dev,
+  tpc_status st = refit_backward_check(geom, params, n_clusters, in, trk, dist_map_dev, mat,
+                                       ckpt_dev,
                                        status_dev, grad_chi2_dev, grad_map_dev, grad_x_dev,
                                        grad_y_dev, grad_z_dev);
   if (st != TPC_OK) return st;
   RefitBufs b = refit_bufs(n_clusters, in, trk, dist_map_dev);
+  set_material(b, mat);
   b.ckpt = const_cast<float*>(ckpt_dev);
   b.status = const_cast<int32_t*>(status_dev);
   b.grad_chi2 = grad_chi2_dev;
@@ -476,12 +499,14 @@ tpc_status tpc_refit_backward_noalloc(const tpc_geometry* geom, const tpc_params
 
 tpc_status tpc_refit_backward(const tpc_geometry* geom, const tpc_params* params,
                               int64_t n_clusters, tpc_clusters in, tpc_refit_tracks trk,
-                              const float* dist_map_dev, const float* ckpt_dev,
+                              const float* dist_map_dev, const tpc_material* mat,
+                              const float* ckpt_dev,
                               const int32_t* status_dev, const float* grad_chi2_dev,
                               float* grad_map_dev, float* grad_x_dev, float* grad_y_dev,
                               float* grad_z_dev, void* ws_dev, size_t ws_bytes, void* stream)
 {
-  tpc_status st = refit_backward_check(geom, params, n_clusters, in, trk, dist_map_dev, ckpt_dev,
+  tpc_status st = refit_backward_check(geom, params, n_clusters, in, trk, dist_map_dev, mat,
+                                       ckpt_dev,
                                        status_dev, grad_chi2_dev, grad_map_dev, grad_x_dev,
                                        grad_y_dev, grad_z_dev);
   if (st != TPC_OK) return st;
@@ -489,6 +514,7 @@ tpc_status tpc_refit_backward(const tpc_geometry* geom, const tpc_params* params
   if (ws_bytes < tpc_refit_workspace_bytes()) return TPC_ERR_WORKSPACE;
   if (reinterpret_cast<uintptr_t>(ws_dev) % 8) return TPC_ERR_INVALID;
   RefitBufs b = refit_bufs(n_clusters, in, trk, dist_map_dev);
+  set_material(b, mat);
   b.ckpt = const_cast<float*>(ckpt_dev);
   b.status = const_cast<int32_t*>(status_dev);
   b.grad_chi2 = grad_chi2_dev;

@@ -116,6 +116,12 @@ struct RefitBufs {
   float *gx, *gy, *gz;    // [n_clusters]
   long long* acc;         // [152*18] fixed-point map-gradient accumulators
   int* flags;             // [1] accumulator overflow flag
+  // field map and material (any may be null: the uniform field of Consts,
+  // no scattering, no energy loss)
+  const float* bz;        // [152][nzb] field [T] per row and z bin
+  int32_t nzb;            // z bins over [-250, 250] cm
+  const float* ix0;       // [152] inverse radiation length [1/cm]
+  const float* eloss;     // [152] mean energy loss at minimum ionisation [GeV/cm]
 };
 
 constexpr int kPhi = 18;

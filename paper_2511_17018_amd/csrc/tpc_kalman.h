@@ -20,8 +20,10 @@ __device__ __forceinline__ constexpr int ci(int i, int j)
   return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
 }
 
-// R7 + R8 (see the design notes for the exact operation order).
-__device__ __forceinline__ bool kprop(KSt& s, float x1, float x2, float kB, float smax)
+// R7 + R8 (see the design notes for the exact operation order); ds_out
+// receives the step's signed transverse arc length.
+__device__ __forceinline__ bool kprop_ds(KSt& s, float x1, float x2, float kB, float smax,
+                                         float& ds_out)
 {
   const float one = 1.0f;
   const float dx = x2 - x1;
@@ -41,6 +43,7 @@ __device__ __forceinline__ bool kprop(KSt& s, float x1, float x2, float kB, floa
   const float g = one + u2 * (kSixth + u2 * k3_40);
   const float sg = dx < 0.0f ? -one : one;
   const float ds = (sg * L) * g;
+  ds_out = ds;
   const float h = (one + f * f) * 0.5f;
   const float ic1 = one / c1, ic2 = one / c2;
   const float dfs = h * (ic1 + ic2);
@@ -88,6 +91,12 @@ __device__ __forceinline__ bool kprop(KSt& s, float x1, float x2, float kB, floa
   s.c[11] = n41;
   s.c[12] = n42;
   return true;
+}
+
+__device__ __forceinline__ bool kprop(KSt& s, float x1, float x2, float kB, float smax)
+{
+  float ds;
+  return kprop_ds(s, x1, x2, kB, smax, ds);
 }
 
 struct Innov {

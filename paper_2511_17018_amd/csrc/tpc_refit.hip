@@ -36,7 +36,55 @@ __device__ __noinline__ bool hits_valid(const RefitBufs& b, int64_t h, int64_t e
   return true;
 }
 
+// Highland constant squared [GeV^2] and the pion mass squared [GeV^2] of
+// the material model, as binary32 constants (rounded from these decimals)
+constexpr float kHighland2 = (float)1.8496e-4;
+constexpr float kPion2 = (float)0.019479785;
+
+// R42: curvature constant of a step from the field at the destination
+// hit's row and the z bin of its measured z (binary64, rounded once)
+__device__ __forceinline__ float step_kB(const Consts& k, const RefitBufs& b, int row, float z)
+{
+  if (!b.bz) return k.kB;
+  const int nzb = b.nzb;
+  const double f = floor(((double)z + 250.0) * (double)nzb / 500.0);
+  int zb = 0;
+  if (f >= 0.0) zb = f > (double)(nzb - 1) ? nzb - 1 : (int)f;
+  return (float)(-0.299792458e-2 * (double)b.bz[(int64_t)row * nzb + zb]);
+}
+
+// R43, R44: the material of a step, applied to the propagated state: the
+// scattering noise on snp, tgl, q/pt, then the energy loss scaling q/pt and
+// the covariance row of q/pt.  ads = |ds|, sgn = sign of the step in x.
+__device__ __forceinline__ void mat_step(KSt& s, float ads, float sgn, float ix0, float K)
+{
+  const float one = 1.0f;
+  const float snp = s.p[2], tgl = s.p[3], qpt = s.p[4];
+  const float t2 = one + tgl * tgl;
+  const float w = (qpt * qpt) / t2;
+  const float bg = one + kPion2 * w;
+  const float path = ads * sqrtf(t2);
+  if (ix0 > 0.0f) {
+    const float th2 = (kHighland2 * (path * ix0)) * (w * bg);
+    const float qt = qpt * tgl;
+    s.c[ci(2, 2)] = s.c[ci(2, 2)] + th2 * (((one - snp) * (one + snp)) * t2);
+    s.c[ci(3, 3)] = s.c[ci(3, 3)] + th2 * (t2 * t2);
+    s.c[ci(4, 3)] = s.c[ci(4, 3)] + th2 * (t2 * qt);
+    s.c[ci(4, 4)] = s.c[ci(4, 4)] + th2 * (qt * qt);
+  }
+  if (K > 0.0f) {
+    const float corr = (sqrtf(w * bg) * (K * bg)) * (path * sgn);
+    const float f = one + corr;
+    s.p[4] = qpt * f;
+#pragma unroll
+    for (int j = 0; j < 4; j++) s.c[ci(4, j)] = s.c[ci(4, j)] * f;
+    s.c[ci(4, 4)] = (s.c[ci(4, 4)] * f) * f;
+  }
+}
+
 // R21-R24: one lane per track; planes X_k = x_k + D[row_k][sector_k mod 18].
+// MAT: field map and material (R42-R44), read per hit.
+template <bool MAT>
 __global__ __launch_bounds__(kBlock) void k_refit_fwd(Consts k, RefitBufs b)
 {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -97,6 +145,16 @@ __global__ __launch_bounds__(kBlock) void k_refit_fwd(Consts k, RefitBufs b)
       ys[u] = b.y[ci[u]];
       zs[u] = b.z[ci[u]];
     }
+    // MAT: each hit's field and material (zero where a table is absent)
+    float kbs[MAT ? kFwdBlk : 1], ixs[MAT ? kFwdBlk : 1], els[MAT ? kFwdBlk : 1];
+    if constexpr (MAT) {
+#pragma unroll
+      for (int u = 0; u < kFwdBlk; u++) {
+        kbs[u] = step_kB(k, b, rw[u], zs[u]);
+        ixs[u] = b.ix0 ? b.ix0[rw[u]] : 0.0f;
+        els[u] = b.eloss ? b.eloss[rw[u]] : 0.0f;
+      }
+    }
     if (bad) {
       b.chi2[t] = 0.0f;
       b.status[t] = 2;
@@ -106,11 +164,18 @@ __global__ __launch_bounds__(kBlock) void k_refit_fwd(Consts k, RefitBufs b)
     for (int u = 0; u < kFwdBlk; u++) {
       const int64_t h = h0 + u;
       if (h >= e) break;
-      if (!kprop(st, xprev, xs[u], kB, smax)) {
+      float ds;
+      if (!kprop_ds(st, xprev, xs[u], MAT ? kbs[MAT ? u : 0] : kB, smax, ds)) {
         // an invalid hit further on still makes the track status 2
         b.chi2[t] = 0.0f;
         b.status[t] = hits_valid(b, h0 + kFwdBlk, e, ncl) ? 1 : 2;
         return;
+      }
+      if constexpr (MAT) {
+        if (b.ix0 || b.eloss) {
+          const float sgn = xs[u] - xprev < 0.0f ? -1.0f : 1.0f;
+          mat_step(st, ds * sgn, sgn, ixs[u], els[u]);
+        }
       }
       chi2 += kupdate(st, ys[u], zs[u], vy, vz);
       store_ckpt(b.ckpt + h * 20, st);
@@ -127,8 +192,12 @@ hipError_t refit_forward(const Consts& k, const RefitBufs& b, hipStream_t s)
 {
   if (b.n_tracks > 0) {
     const unsigned nb = (unsigned)((b.n_tracks + kBlock - 1) / kBlock);
-    const int slot = prof_begin(s, "refit_fwd");
-    k_refit_fwd<<<nb, kBlock, 0, s>>>(k, b);
+    const bool mat = b.bz || b.ix0 || b.eloss;
+    const int slot = prof_begin(s, mat ? "refit_fwd_mat" : "refit_fwd");
+    if (mat)
+      k_refit_fwd<true><<<nb, kBlock, 0, s>>>(k, b);
+    else
+      k_refit_fwd<false><<<nb, kBlock, 0, s>>>(k, b);
     prof_end(s, slot);
   }
   return hipGetLastError();

@@ -80,12 +80,12 @@ __device__ __forceinline__ void prop_record(const R* p, R dx, R kB, PRec& q)
 // adjoint of the propagation's scalar chain; pb in/out, Fb = adjoints of
 // (a, b, d, e, gq, hq); returns the adjoint of dx
 __device__ __forceinline__ R prop_backward(const R* p, const PRec& q, R kB, R* pb,
-                                               const R* Fb)
+                                               const R* Fb, R dsb_extra = 0.0)
 {
   const R tgl = p[3], snp = p[2];
   const R yb = pb[0], zb = pb[1];
   R s2b = pb[2], tglb = pb[3], qptb = pb[4];
-  R dyb = yb, dsb = zb * tgl;
+  R dyb = yb, dsb = zb * tgl + dsb_extra;
   tglb += zb * q.ds;
   R ab = Fb[0], bb = Fb[1];
   const R db = Fb[2], eb = Fb[3], gqb = Fb[4], hqb = Fb[5];
@@ -249,6 +249,116 @@ __device__ __forceinline__ void update_backward(const R* pp, const R* C, R my, R
   pb[1] -= rb[1];
 }
 
+// ---- field map and material (R42-R44) in binary64
+
+constexpr R kHighland2 = 1.8496e-4;   // 0.0136^2 [GeV^2]
+constexpr R kPion2 = 0.019479785;     // 0.13957^2 [GeV^2]
+
+// the z bin of a step's field, exactly as the forward pass takes it (this
+// file is built with fast math; the bin must not move at a boundary)
+#pragma float_control(precise, on, push)
+__device__ __forceinline__ int field_zbin(float z, int nzb)
+{
+  const double f = floor(((double)z + 250.0) * (double)nzb / 500.0);
+  if (!(f >= 0.0)) return 0;
+  return f > (double)(nzb - 1) ? nzb - 1 : (int)f;
+}
+#pragma float_control(pop)
+
+// intermediates of the material step that its adjoint needs
+struct MRec {
+  R t2, w, bg, sq, path, th2, qt, f, q4, ads, sgn, ix0, K;
+  R c4[5];  // covariance row of q/pt after the scattering noise, before the loss
+};
+
+// the material step on the propagated state pp and covariance C (lower
+// triangle); the scattering noise on snp, tgl, q/pt, then the energy loss
+__device__ __forceinline__ void mat_forward(R* pp, R* C, R ads, R sgn, R ix0, R K, MRec& m)
+{
+  const R snp = pp[2], tgl = pp[3], qpt = pp[4];
+  m.ads = ads;
+  m.sgn = sgn;
+  m.ix0 = ix0;
+  m.K = K;
+  m.t2 = 1.0 + tgl * tgl;
+  m.w = (qpt * qpt) / m.t2;
+  m.bg = 1.0 + kPion2 * m.w;
+  m.path = ads * sqrt(m.t2);
+  m.qt = qpt * tgl;
+  m.th2 = ix0 > 0.0 ? (kHighland2 * (m.path * ix0)) * (m.w * m.bg) : 0.0;
+  if (ix0 > 0.0) {
+    C[si(2, 2)] += m.th2 * (((1.0 - snp) * (1.0 + snp)) * m.t2);
+    C[si(3, 3)] += m.th2 * (m.t2 * m.t2);
+    C[si(4, 3)] += m.th2 * (m.t2 * m.qt);
+    C[si(4, 4)] += m.th2 * (m.qt * m.qt);
+  }
+#pragma unroll
+  for (int j = 0; j < 5; j++) m.c4[j] = C[si(4, j)];
+  m.q4 = qpt;
+  m.sq = sqrt(m.w * m.bg);
+  m.f = 1.0 + (K > 0.0 ? (m.sq * (K * m.bg)) * (m.path * sgn) : 0.0);
+  if (K > 0.0) {
+    pp[4] = qpt * m.f;
+#pragma unroll
+    for (int j = 0; j < 4; j++) C[si(4, j)] *= m.f;
+    C[si(4, 4)] = (C[si(4, 4)] * m.f) * m.f;
+  }
+}
+
+// adjoint of mat_forward: pb and X (the symmetric covariance adjoint) go
+// from after the material to the propagated state pp1; returns the adjoint
+// of the step's signed arc length
+__device__ __forceinline__ R mat_backward(const R* pp1, const MRec& m, R* pb, R* X)
+{
+  const R snp = pp1[2], tgl = pp1[3], qpt = pp1[4];
+  R t2b = 0.0, wb = 0.0, bgb = 0.0, pathb = 0.0, qtb = 0.0;
+  if (m.K > 0.0) {
+    // q/pt' = q/pt f; row 4 of the covariance scaled by f, its diagonal by f^2
+    R s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) s += X[si(4, j)] * m.c4[j];
+    const R cb = pb[4] * m.q4 + 2.0 * (s + X[si(4, 4)] * m.c4[4] * m.f);
+    pb[4] *= m.f;
+#pragma unroll
+    for (int j = 0; j < 4; j++) X[si(4, j)] *= m.f;
+    X[si(4, 4)] *= m.f * m.f;
+    // f - 1 = sq (K bg) (path sgn), sq = sqrt(w bg)
+    const R sqb = cb * (m.K * m.bg) * (m.path * m.sgn);
+    bgb += cb * m.sq * m.K * (m.path * m.sgn);
+    pathb += cb * m.sq * (m.K * m.bg) * m.sgn;
+    if (m.sq > 0.0) {
+      const R wbgb = sqb / (2.0 * m.sq);
+      wb += wbgb * m.bg;
+      bgb += wbgb * m.w;
+    }
+  }
+  if (m.ix0 > 0.0) {
+    const R u22 = ((1.0 - snp) * (1.0 + snp)) * m.t2, u33 = m.t2 * m.t2;
+    const R u43 = m.t2 * m.qt, u44 = m.qt * m.qt;
+    const R x22 = X[si(2, 2)], x33 = X[si(3, 3)], x43 = X[si(4, 3)], x44 = X[si(4, 4)];
+    const R A = x22 * u22 + x33 * u33 + 2.0 * x43 * u43 + x44 * u44;
+    pb[2] += m.th2 * x22 * (-2.0 * snp) * m.t2;
+    t2b += m.th2 * (x22 * ((1.0 - snp) * (1.0 + snp)) + x33 * 2.0 * m.t2 + 2.0 * x43 * m.qt);
+    qtb += m.th2 * (2.0 * x43 * m.t2 + x44 * 2.0 * m.qt);
+    // th2 = kHighland2 path ix0 w bg
+    const R a = A * kHighland2 * m.ix0;
+    pathb += a * m.w * m.bg;
+    wb += a * m.path * m.bg;
+    bgb += a * m.path * m.w;
+  }
+  // qt = qpt tgl, bg = 1 + m^2 w, w = qpt^2 / t2, path = ads sqrt(t2), t2 = 1 + tgl^2
+  pb[4] += qtb * tgl;
+  pb[3] += qtb * qpt;
+  wb += bgb * kPion2;
+  pb[4] += wb * 2.0 * qpt / m.t2;
+  t2b += wb * (-m.w / m.t2);
+  const R st2 = sqrt(m.t2);
+  const R adsb = pathb * st2;
+  t2b += pathb * m.ads / (2.0 * st2);
+  pb[3] += t2b * 2.0 * tgl;
+  return adsb * m.sgn;
+}
+
 // adds to the workgroup's partial sums in LDS (flushed once per workgroup);
 // true if the term was clamped (the caller raises the overflow flag once)
 __device__ __forceinline__ bool acc_add(unsigned long long* acc, int cell, double g)
@@ -307,6 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_refit_bwd_zero(RefitBufs b)
   }
 }
 
+template <bool MAT>
 __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, int64_t t,
                                           unsigned long long* acc, const BwdOut& o)
 {
@@ -376,10 +487,17 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
                       v3.y, v3.z, v3.w, v4.x, v4.y, v4.z, v4.w};
     // the Jacobian F = I + E has six off-identity entries: (0,2) a, (0,4) b,
     // (1,2) d, (1,3) e, (1,4) gq, (2,4) hq
-    R Ea, Eb, Ed, Ee, Egq, Ehq, pp[5];
+    // the step's field (R42): the destination hit's row and z bin
+    R kBs = kB;
+    if constexpr (MAT) {
+      if (b.bz) kBs = -0.299792458e-2 * (R)b.bz[(int64_t)(cell / kPhi) * b.nzb + field_zbin(zc, b.nzb)];
+    }
+    R Ea, Eb, Ed, Ee, Egq, Ehq, pp[5], dss = 0.0, sgs = 1.0;
     {
       PRec q;
-      prop_record(p0, X2 - X1, kB, q);
+      prop_record(p0, X2 - X1, kBs, q);
+      dss = q.ds;
+      sgs = q.sg;
       Ea = q.a;
       Eb = q.b;
       Ed = q.d;
@@ -413,8 +531,25 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
       if (i >= 3) Cp[si(i, 3)] = Bi[3];
       if (i >= 4) Cp[si(i, 4)] = Bi[4];
     }
+    // the material of the step (R43, R44) on the propagated state
+    const bool mat = MAT && (b.ix0 || b.eloss);
+    R pp1[5];
+    MRec mr;
+    if constexpr (MAT) {
+      if (mat) {
+#pragma unroll
+        for (int j = 0; j < 5; j++) pp1[j] = pp[j];
+        const int rr = cell / kPhi;
+        mat_forward(pp, Cp, dss * sgs, sgs, b.ix0 ? (R)b.ix0[rr] : 0.0,
+                    b.eloss ? (R)b.eloss[rr] : 0.0, mr);
+      }
+    }
     R mb[2];
     update_backward(pp, Cp, (R)yc, (R)zc, vy, vz, w, pb, X, mb);
+    R dsb_mat = 0.0;
+    if constexpr (MAT) {
+      if (mat) dsb_mat = mat_backward(pp1, mr, pb, X);
+    }
     // covariance part of the propagation: XF = X F, Fb = 2 (X F C0) at the
     // entries of E, X <- F^T X F
     R XF[5][5];
@@ -457,8 +592,8 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
     R pr[5] = {p0[0], p0[1], p0[2], p0[3], p0[4]};
     asm volatile("" : "+v"(dxr), "+v"(pr[2]), "+v"(pr[3]), "+v"(pr[4]));
     PRec q;
-    prop_record(pr, dxr, kB, q);
-    const R dxb = prop_backward(pr, q, kB, pb, Fb);
+    prop_record(pr, dxr, kBs, q);
+    const R dxb = prop_backward(pr, q, kBs, pb, Fb, dsb_mat);
     const R gX = dxb + gXn;
     out_put(o, j, c, (float)gX, (float)mb[0], (float)mb[1]);
     if (++j == kBwdOut) {
@@ -480,7 +615,9 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
 }
 
 // One lane per track; the map sums of the workgroup's tracks are gathered
-// in LDS and added to the device accumulators once per cell.
+// in LDS and added to the device accumulators once per cell.  MAT: field
+// map and material.
+template <bool MAT>
 __global__ __launch_bounds__(kBlock) void k_refit_bwd(Consts k, RefitBufs b)
 {
   __shared__ unsigned long long s_acc[kRows * kPhi];
@@ -489,7 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_refit_bwd(Consts k, RefitBufs b)
   for (int i = threadIdx.x; i < kRows * kPhi; i += kBlock) s_acc[i] = 0ull;
   __syncthreads();
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < b.n_tracks) bwd_track(k, b, t, s_acc, BwdOut{s_og, s_oc});
+  if (t < b.n_tracks) bwd_track<MAT>(k, b, t, s_acc, BwdOut{s_og, s_oc});
   __syncthreads();
   for (int i = threadIdx.x; i < kRows * kPhi; i += kBlock) {
     const unsigned long long v = s_acc[i];
@@ -561,8 +698,13 @@ hipError_t refit_backward(const Consts& k, const RefitBufs& b, hipStream_t s)
   k_refit_bwd_zero<<<(unsigned)zb, kBlock, 0, s>>>(b);
   prof_end(s, slot);
   if (b.n_tracks > 0) {
-    slot = prof_begin(s, "refit_bwd");
-    k_refit_bwd<<<(unsigned)((b.n_tracks + kBlock - 1) / kBlock), kBlock, 0, s>>>(k, b);
+    const unsigned nb = (unsigned)((b.n_tracks + kBlock - 1) / kBlock);
+    const bool mat = b.bz || b.ix0 || b.eloss;
+    slot = prof_begin(s, mat ? "refit_bwd_mat" : "refit_bwd");
+    if (mat)
+      k_refit_bwd<true><<<nb, kBlock, 0, s>>>(k, b);
+    else
+      k_refit_bwd<false><<<nb, kBlock, 0, s>>>(k, b);
     prof_end(s, slot);
   }
   slot = prof_begin(s, "refit_bwd_map");

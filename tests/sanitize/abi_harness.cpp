@@ -133,24 +133,34 @@ static void invalid_calls()
   const float* dmap = (const float*)fake(0x7000);
   float* f = (float*)fake(0x8000);
   int32_t* st = (int32_t*)fake(0x8000);
-  EXPECT(tpc_refit(&g, &p, 1000, in, trk, dmap, f, st, f, nullptr) == TPC_OK);
-  EXPECT(tpc_refit(&g, &p, (int64_t)1 << 31, in, trk, dmap, f, st, f, nullptr) == TPC_ERR_INVALID);
-  EXPECT(tpc_refit(&g, &p, 1000, in, trk, nullptr, f, st, f, nullptr) == TPC_ERR_INVALID);
+  EXPECT(tpc_refit(&g, &p, 1000, in, trk, dmap, nullptr, f, st, f, nullptr) == TPC_OK);
+  EXPECT(tpc_refit(&g, &p, (int64_t)1 << 31, in, trk, dmap, nullptr, f, st, f, nullptr) == TPC_ERR_INVALID);
+  EXPECT(tpc_refit(&g, &p, 1000, in, trk, nullptr, nullptr, f, st, f, nullptr) == TPC_ERR_INVALID);
   q = p;
   q.flags = 4u;
-  EXPECT(tpc_refit(&g, &q, 1000, in, trk, dmap, f, st, f, nullptr) == TPC_ERR_INVALID);
+  EXPECT(tpc_refit(&g, &q, 1000, in, trk, dmap, nullptr, f, st, f, nullptr) == TPC_ERR_INVALID);
+  // field map and material: the z binning of a given field map is checked
+  tpc_material mat = {(const float*)fake(0x7100), 0, (const float*)fake(0x7200), nullptr};
+  EXPECT(tpc_refit(&g, &p, 1000, in, trk, dmap, &mat, f, st, f, nullptr) == TPC_ERR_INVALID);
+  mat.nzb = 65537;
+  EXPECT(tpc_refit(&g, &p, 1000, in, trk, dmap, &mat, f, st, f, nullptr) == TPC_ERR_INVALID);
+  mat.nzb = 25;
+  EXPECT(tpc_refit(&g, &p, 1000, in, trk, dmap, &mat, f, st, f, nullptr) == TPC_OK);
+  mat.bz = nullptr;
+  mat.nzb = 0;  // ignored without a field map
+  EXPECT(tpc_refit(&g, &p, 1000, in, trk, dmap, &mat, f, st, f, nullptr) == TPC_OK);
   std::vector<char> rws(tpc_refit_workspace_bytes());
   stub::g_ws = rws.data();
   stub::g_ws_bytes = rws.size();
-  EXPECT(tpc_refit_backward(&g, &p, 1000, in, trk, dmap, f, st, f, f, f, f, f, rws.data(),
+  EXPECT(tpc_refit_backward(&g, &p, 1000, in, trk, dmap, nullptr, f, st, f, f, f, f, f, rws.data(),
                             rws.size(), nullptr) == TPC_OK);
-  EXPECT(tpc_refit_backward(&g, &p, 1000, in, trk, dmap, f, st, f, f, f, f, f, rws.data(),
+  EXPECT(tpc_refit_backward(&g, &p, 1000, in, trk, dmap, nullptr, f, st, f, f, f, f, f, rws.data(),
                             rws.size() - 1, nullptr) == TPC_ERR_WORKSPACE);
-  EXPECT(tpc_refit_backward_noalloc(&g, &p, 1000, in, trk, dmap, f, st, f, f, f, f, f,
+  EXPECT(tpc_refit_backward_noalloc(&g, &p, 1000, in, trk, dmap, nullptr, f, st, f, f, f, f, f,
                                     nullptr) == TPC_OK);
-  EXPECT(tpc_refit_backward_noalloc(&g, &q, 1000, in, trk, dmap, f, st, f, f, f, f, f,
+  EXPECT(tpc_refit_backward_noalloc(&g, &q, 1000, in, trk, dmap, nullptr, f, st, f, f, f, f, f,
                                     nullptr) == TPC_ERR_INVALID);
-  EXPECT(tpc_refit_backward_noalloc(&g, &p, 1000, in, trk, dmap, f, st, f, nullptr, f, f, f,
+  EXPECT(tpc_refit_backward_noalloc(&g, &p, 1000, in, trk, dmap, nullptr, f, st, f, nullptr, f, f, f,
                                     nullptr) == TPC_ERR_INVALID);
   // cluster transformation
   tpc_transform_geometry tg;

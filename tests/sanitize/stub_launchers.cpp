@@ -85,7 +85,7 @@ static hipError_t track_stub(const TrackBufs& b)
 
 static hipError_t refit_stub(const RefitBufs& b)
 {
-  if (b.n_tracks < 0 || b.n_clusters < 0) abort();
+  if (b.n_tracks < 0 || b.n_clusters < 0 || (b.bz && b.nzb < 1)) abort();
   stub::g_calls++;
   return hipSuccess;
 }

@@ -147,7 +147,8 @@ def test_grid_and_track_reject_unknown_flags_and_oversized_bin_tables(case):
     assert st == -1
 
 
-@pytest.mark.parametrize("case", ["unknown_flag", "clusters_over_int32", "null_map", "rows"])
+@pytest.mark.parametrize("case", ["unknown_flag", "clusters_over_int32", "null_map", "rows",
+                                  "field_bins_zero", "field_bins_over"])
 def test_refit_rejects_bad_arguments_on_host(case):
     L = tpc.lib()
     g = tpc.make_geometry(synth.geometry())
@@ -165,12 +166,22 @@ def test_refit_rejects_bad_arguments_on_host(case):
         dmap = C.c_void_p(0)
     elif case == "rows":
         g.n_rows = 150
+    mat = None
+    if case.startswith("field_bins"):
+        # a field map with no z bin, or more than the 65536 the header allows
+        mat = C.byref(tpc.MaterialStruct(dummy, 0 if case == "field_bins_zero" else 65537,
+                                         None, None))
     L.tpc_refit.restype = C.c_int
     L.tpc_refit_backward.restype = C.c_int
-    st = L.tpc_refit(C.byref(g), C.byref(p), C.c_int64(nc), cl, trk, dmap, dummy, dummy,
+    L.tpc_refit_backward_noalloc.restype = C.c_int
+    st = L.tpc_refit(C.byref(g), C.byref(p), C.c_int64(nc), cl, trk, dmap, mat, dummy, dummy,
                      C.c_void_p(0x2000), C.c_void_p(0))
     assert st == -1
-    st = L.tpc_refit_backward(C.byref(g), C.byref(p), C.c_int64(nc), cl, trk, dmap,
+    st = L.tpc_refit_backward(C.byref(g), C.byref(p), C.c_int64(nc), cl, trk, dmap, mat,
                               C.c_void_p(0x2000), dummy, dummy, dummy, dummy, dummy, dummy,
                               C.c_void_p(0x3000), C.c_size_t(1 << 20), C.c_void_p(0))
+    assert st == -1
+    st = L.tpc_refit_backward_noalloc(C.byref(g), C.byref(p), C.c_int64(nc), cl, trk, dmap, mat,
+                                      C.c_void_p(0x2000), dummy, dummy, dummy, dummy, dummy,
+                                      dummy, C.c_void_p(0))
     assert st == -1

@@ -249,3 +249,133 @@ def test_refit_gradient_matches_finite_differences_and_complex_step():
             if not (nrm <= 1e-3 and el <= 1e-3):
                 fails.append((name, rname, nrm, el))
     assert not fails, fails
+
+
+# ---------------------------------------------------------------- field map and material (f2)
+
+def _material_case(n, rep, kind):
+    """Tracks simulated through a 10 % field variation and twenty times the
+    gas material; `kind` selects what the refit is given."""
+    bz = synth.field_map(amp=0.1)
+    ix0, el = synth.material_map(scale=20.0)
+    ev = synth.material_tracks(n, bz=bz, ix0=ix0, eloss=el, rep=rep)
+    mat = {"all": dict(bz=bz, ix0=ix0, eloss=el), "field": dict(bz=bz),
+           "material": dict(ix0=ix0, eloss=el), "loss": dict(eloss=el),
+           "scatter": dict(bz=bz, ix0=ix0)}[kind]
+    D = np.random.default_rng(rep).uniform(-0.3, 0.3, (152, 18)).astype(np.float32)
+    return ev, mat, D
+
+
+@pytest.mark.parametrize("kind", ["all", "field", "material", "loss", "scatter"])
+def test_material_refit_forward_bit_exact(kind):
+    """f2 forward (R42-R44): with the field map and any part of the material,
+    the deterministic GPU refit's chi2, status and checkpoints equal the
+    binary32 oracle bit for bit."""
+    ev, mat, D = _material_case(300, 5, kind)
+    _say(f"[refit mat fwd] kind={kind} tracks=300 hits={ev.n}")
+    ho, hc, seed = _args(ev)
+    xyz, row, trk, m = _gpu(ev, D)
+    gm = tpc.upload_material(**mat)
+    chi2, status, ckpt = tpc.refit(G, xyz, row, trk, m, det=True, mat=gm)
+    torch.cuda.synchronize()
+    c_o, s_o, k_o = oracle.refit(G, P, ev, ho, hc, seed, D, prec=32, mat=mat)
+    assert (s_o == 0).mean() > 0.95
+    assert np.array_equal(status.cpu().numpy(), s_o)
+    assert np.array_equal(chi2.cpu().numpy().view(np.int32), c_o.view(np.int32))
+    ok = np.repeat(s_o == 0, np.diff(ho))
+    assert np.array_equal(ckpt.cpu().numpy()[ok].view(np.int32), k_o[ok].view(np.int32))
+    # the production build stays close to the binary64 fit of the same model
+    c_p, s_p, _ = tpc.refit(G, xyz, row, trk, m, det=False, mat=gm)
+    c_64, s_64, _ = oracle.refit(G, P, ev, ho, hc, seed, D, prec=64, mat=mat)
+    both = (s_p.cpu().numpy() == 0) & (s_64 == 0)
+    rel = np.abs(c_p.cpu().numpy()[both] - c_64[both]) / np.maximum(c_64[both], 1.0)
+    assert both.mean() > 0.95 and np.quantile(rel, 0.99) < 1e-3, np.quantile(rel, 0.99)
+
+
+def test_material_refit_backward_matches_adjoint_and_derivatives():
+    """f2 reverse pass: the GPU gradient of sum_t w_t chi2_t with the field
+    map, scattering and energy loss equals the binary64 oracle adjoint on the
+    same binary32 checkpoints (element-wise 1e-6, map cells against their
+    terms' magnitude 1e-6), and matches complex-step derivatives and central
+    differences (h = 1e-3 cm) of the binary64 forward on sampled coordinates
+    and cells within 1e-3 (norm-wise; element-wise relative to max(|ref|,
+    rms) as in the uniform-field test)."""
+    ev, mat, D = _material_case(400, 6, "all")
+    ho, hc, seed = _args(ev)
+    _say(f"[refit mat bwd] tracks=400 hits={ev.n}")
+    rng = np.random.default_rng(12)
+    w = rng.uniform(0.5, 1.5, len(ho) - 1).astype(np.float32)
+    w64 = w.astype(np.float64)
+    xyz, row, trk, m = _gpu(ev, D)
+    gm = tpc.upload_material(**mat)
+    chi2, status, ckpt = tpc.refit(G, xyz, row, trk, m, mat=gm)
+    gmap, gxyz = tpc.refit_backward(G, xyz, row, trk, m, ckpt, status,
+                                    torch.from_numpy(w).cuda(), mat=gm)
+    gmap2, gxyz2 = tpc.refit_backward(G, xyz, row, trk, m, ckpt, status,
+                                      torch.from_numpy(w).cuda(), mat=gm)
+    torch.cuda.synchronize()
+    assert torch.equal(gmap, gmap2) and torch.equal(gxyz, gxyz2)
+    c_o, s_o, k_o = oracle.refit(G, P, ev, ho, hc, seed, D, prec=32, mat=mat)
+    assert np.array_equal(status.cpu().numpy(), s_o)
+    _, _, smap, sx, sy, sz = oracle.refit_grad(G, P, ev, ho, hc, seed, D, w64, ckpt=k_o,
+                                               status=s_o, mat=mat)
+    g = gxyz.cpu().numpy().astype(np.float64)
+    gmp = gmap.cpu().numpy().reshape(-1).astype(np.float64)
+    fails = []
+    for name, a, b in (("x", g[0], sx), ("y", g[1], sy), ("z", g[2], sz)):
+        _, el = _r27(a, b)
+        _say(f"[refit mat bwd] {name}: element-wise vs binary64 adjoint {el:.2e}")
+        if not el <= 1e-6:
+            fails.append(name)
+    cell = ev.row.astype(np.int64) * 18 + ev.sector % 18
+    scale = np.bincount(cell, weights=np.abs(sx), minlength=152 * 18)
+    el = float((np.abs(gmp - smap.reshape(-1)) / np.maximum(scale, 1e-30))[scale > 0].max())
+    _say(f"[refit mat bwd] map: element-wise (term scale) {el:.2e}")
+    if not el <= 1e-6:
+        fails.append("map")
+    assert not fails, fails
+
+    def loss(which, i, h, mode):
+        return oracle.refit_loss(G, P, ev, ho, hc, seed, D, w64, which=which, idx=int(i), h=h,
+                                 mode=mode, mat=mat)
+
+    clus = rng.choice(ev.n, 30, replace=False)
+    cells = rng.choice(np.nonzero(scale)[0], 20, replace=False)
+    for name, ax, idx in (("x", 0, clus), ("y", 1, clus), ("z", 2, clus), ("map", None, cells)):
+        gs = gmp[idx] if ax is None else g[ax, idx]
+        allg = gmp if ax is None else g[ax]
+        rms = np.sqrt(np.mean(allg[allg != 0] ** 2))
+        cs = np.array([loss(name, i, 1e-30, "c128") for i in idx])
+        fd = np.array([(loss(name, i, 1e-3, "f64") - loss(name, i, -1e-3, "f64")) / 2e-3
+                       for i in idx])
+        for rname, ref in (("fd", fd), ("cs", cs)):
+            nrm = np.linalg.norm(gs - ref) / np.linalg.norm(ref)
+            el = float((np.abs(gs - ref) / np.maximum(np.abs(ref), rms)).max())
+            _say(f"[refit mat grad vs {rname}] {name}: norm-wise {nrm:.2e} element-wise {el:.2e}")
+            if not (nrm <= 1e-3 and el <= 1e-3):
+                fails.append((name, rname, nrm, el))
+    assert not fails, fails
+
+
+def test_material_neutral_maps_equal_plain_refit_on_gpu():
+    """A field map holding the geometry's field everywhere with zero material
+    gives the plain refit's outputs bit for bit (forward) and the same
+    gradient (reverse pass)."""
+    ev = synth.material_tracks(200, rep=7)
+    ho, hc, seed = _args(ev)
+    D = np.zeros((152, 18), np.float32)
+    xyz, row, trk, m = _gpu(ev, D)
+    flat = tpc.upload_material(bz=np.full((152, 9), np.float32(G["bz"])),
+                               ix0=np.zeros(152, np.float32), eloss=np.zeros(152, np.float32))
+    a = tpc.refit(G, xyz, row, trk, m)
+    b = tpc.refit(G, xyz, row, trk, m, mat=flat)
+    ones = torch.ones_like(a[0])
+    ga = tpc.refit_backward(G, xyz, row, trk, m, a[2], a[1], ones)
+    gb = tpc.refit_backward(G, xyz, row, trk, m, b[2], b[1], ones, mat=flat)
+    torch.cuda.synchronize()
+    for u, v in zip(a, b):
+        assert torch.equal(u, v)
+    # the same arithmetic in a differently scheduled kernel (fast math):
+    # equal up to the last bits of the binary64 sums
+    for u, v in zip(ga, gb):
+        assert torch.allclose(u, v, rtol=1e-6, atol=1e-9 * float(u.abs().max()))
