@@ -547,16 +547,15 @@ void tpc_default_merge_params(tpc_merge_params* m)
 
 namespace {
 struct MergeWs {
-  int64_t n_seg, seg_inst, seg_pos, out_ok, out_p, out_c, out_x, sort_cnt, inst_seg_off,
-      seg_order, succ, pred, succ_chi2, pred_chi2, has_pred, chain_head, total, sort_blocks;
+  int64_t n_seg, seg_inst, seg_pos, out_ok, out_p, out_c, out_x, seg_key, bkt_cur, bkt_off,
+      bkt_order, succ, pred, succ_chi2, pred_chi2, has_pred, chain_head, it_ns, it_nh, ch_part,
+      total;
 };
 
 MergeWs merge_ws(int64_t cap)
 {
   MergeWs w;
   Carve c;
-  w.sort_blocks = (cap + kBlock - 1) / kBlock;
-  if (w.sort_blocks < 1) w.sort_blocks = 1;
   w.n_seg = c.take(8);
   w.seg_inst = c.take(4 * cap);
   w.seg_pos = c.take(24 * cap);
@@ -564,15 +563,19 @@ MergeWs merge_ws(int64_t cap)
   w.out_p = c.take(20 * cap);
   w.out_c = c.take(60 * cap);
   w.out_x = c.take(4 * cap);
-  w.sort_cnt = c.take(4 * 2 * kPhi * w.sort_blocks);
-  w.inst_seg_off = c.take(4 * (2 * kPhi + 1));
-  w.seg_order = c.take(4 * cap);
+  w.seg_key = c.take(4 * 2 * cap);
+  w.bkt_cur = c.take(4 * 2 * kMergeBuckets);
+  w.bkt_off = c.take(4 * 2 * (kMergeBuckets + 1));
+  w.bkt_order = c.take(4 * 2 * cap);
   w.succ = c.take(4 * cap);
   w.pred = c.take(4 * cap);
   w.succ_chi2 = c.take(4 * cap);
   w.pred_chi2 = c.take(4 * cap);
   w.has_pred = c.take(4 * cap);
   w.chain_head = c.take(4 * cap);
+  w.it_ns = c.take(4 * 2 * cap);
+  w.it_nh = c.take(4 * 2 * cap);
+  w.ch_part = c.take(8 * 3 * ((2 * cap + kBlock - 1) / kBlock + 1));
   w.total = c.off;
   return w;
 }
@@ -626,16 +629,19 @@ tpc_status tpc_merge_tracks(const tpc_geometry* geom, const tpc_params* params,
   b.out_p = at<float>(ws_dev, w.out_p);
   b.out_c = at<float>(ws_dev, w.out_c);
   b.out_x = at<float>(ws_dev, w.out_x);
-  b.sort_cnt = at<int32_t>(ws_dev, w.sort_cnt);
-  b.sort_blocks = w.sort_blocks;
-  b.inst_seg_off = at<int32_t>(ws_dev, w.inst_seg_off);
-  b.seg_order = at<int32_t>(ws_dev, w.seg_order);
+  b.seg_key = at<int32_t>(ws_dev, w.seg_key);
+  b.bkt_cur = at<int32_t>(ws_dev, w.bkt_cur);
+  b.bkt_off = at<int32_t>(ws_dev, w.bkt_off);
+  b.bkt_order = at<int32_t>(ws_dev, w.bkt_order);
   b.succ = at<int32_t>(ws_dev, w.succ);
   b.pred = at<int32_t>(ws_dev, w.pred);
   b.succ_chi2 = at<float>(ws_dev, w.succ_chi2);
   b.pred_chi2 = at<float>(ws_dev, w.pred_chi2);
   b.has_pred = at<int32_t>(ws_dev, w.has_pred);
   b.chain_head = at<int32_t>(ws_dev, w.chain_head);
+  b.it_ns = at<int32_t>(ws_dev, w.it_ns);
+  b.it_nh = at<int32_t>(ws_dev, w.it_nh);
+  b.ch_part = at<int64_t>(ws_dev, w.ch_part);
   const Consts k = make_consts(geom, params);
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = (params->flags & TPC_FLAG_DETERMINISTIC) ? det::merge_tracks(k, b, s)

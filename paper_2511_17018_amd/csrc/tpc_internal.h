@@ -148,6 +148,14 @@ struct TransformBufs {
 };
 
 // Buffers of sector-track merging and the global refit (f1).
+// Pair-search buckets of the merging step: 36 instances x 1024 z bins of
+// 16 cm from -8192 cm (clusters of collisions later in a time frame sit up
+// to the frame's drift length away from the detector's +-250 cm; beyond
+// +-8192 cm the end bins take them).
+constexpr int kMergeZBins = 1024;
+constexpr float kMergeZ0 = -8192.0f, kMergeZInv = 1.0f / 16.0f;
+constexpr int kMergeBuckets = 36 * kMergeZBins;
+
 struct MergeBufs {
   const float *y, *z;
   const uint16_t* row;
@@ -163,14 +171,18 @@ struct MergeBufs {
   float* seg_pos;            // [cap][6] global x, y, z of the first and the last hit
   int32_t* out_ok;           // [cap] outer state valid
   float *out_p, *out_c, *out_x;  // [cap][5], [cap][15], [cap]
-  int32_t* sort_cnt;         // [36][sort_blocks] per-block instance counts, then offsets
-  int64_t sort_blocks;
-  int32_t* inst_seg_off;     // [37] first sorted segment of each instance
-  int32_t* seg_order;        // [cap] segments in (instance, index) order
+  // pair-search buckets: two keys per segment, (instance, z bin) of its
+  // first hit (key 0) and of its last hit (key 1)
+  int32_t* seg_key;          // [2][cap] bucket of each segment
+  int32_t* bkt_cur;          // [2][kMergeBuckets] counts, then scatter cursors
+  int32_t* bkt_off;          // [2][kMergeBuckets + 1] first position of each bucket
+  int32_t* bkt_order;        // [2][cap] segments in bucket order
   int32_t *succ, *pred;      // [cap] best successor / predecessor
   float *succ_chi2, *pred_chi2;
   int32_t* has_pred;         // [cap] a kept link ends here
   int32_t* chain_head;       // [cap] first segment of each chain
+  int32_t *it_ns, *it_nh;    // [2 cap] chain-start items: segment and hit counts
+  int64_t* ch_part;          // [3][ceil(2 cap / kBlock)] workgroup sums, then offsets
 };
 
 // Kernel timing hooks (tpc_profile_*): no-ops unless profiling is enabled.

@@ -8,15 +8,20 @@
 //   seg_info     one lane per segment: its sector, the global positions of
 //                its first and last hit, its outer state (outward filter over
 //                its own hits)
-//   seg_sort     the segments ordered by (instance, index): per-block
-//                instance counts, one-block offsets, stable per-block ranks
-//   succ / pred  one lane per segment, segments taken in instance order so
-//                that a wave's lanes loop over the same candidate lists (one
-//                cache line serves the wave): best successor and best
-//                predecessor over the three neighbouring instances
+//   buckets      every segment filed twice, by (instance, z bin) of its
+//                first hit and of its last hit: counts, one-block offsets,
+//                scatter
+//   succ / pred  one lane per segment, lanes in bucket order (neighbouring
+//                lanes search neighbouring buckets): best successor and best
+//                predecessor among the segments of the three neighbouring
+//                instances whose other end lies in the z bins that R37's
+//                z cut can reach -- a superset of the pairs that pass it,
+//                with the pick a total order (chi2, index), so the result
+//                equals the search over all pairs
 //   link, chain  mutual links; chain heads compacted by scans in index order
 //                (link cycles after them, from their lowest segment); chain
-//                lengths and hit counts scanned into offsets
+//                lengths and hit counts scanned into offsets (workgroup
+//                sums, one-workgroup scan of the sums, ordered write)
 //   chain_hits   one lane per chain: segment list and merged hit list
 //   refit        one lane per chain: outward and inward filter with
 //                rotations between the sector frames
@@ -193,6 +198,18 @@ __device__ __forceinline__ void load_off(const MergeBufs& b, int64_t* s_off)
   __syncthreads();
 }
 
+// Pair-search buckets.  The bin function is monotone (NaN goes to bin 0),
+// so the bins between those of z - w and z + w hold every value within w
+// of z.
+__device__ __forceinline__ int merge_zbin(float z)
+{
+  const float f = floorf((z - kMergeZ0) * kMergeZInv);
+  if (!(f >= 0.0f)) return 0;
+  return f > (float)(kMergeZBins - 1) ? kMergeZBins - 1 : (int)f;
+}
+
+__device__ __forceinline__ int bucket_of(int inst, float z) { return inst * kMergeZBins + merge_zbin(z); }
+
 // --------------------------------------------------------------- seg_info
 __global__ __launch_bounds__(kBlock) void k_seg_info(Consts k, MergeBufs b)
 {
@@ -206,6 +223,8 @@ __global__ __launch_bounds__(kBlock) void k_seg_info(Consts k, MergeBufs b)
     b.seg_inst[t] = 0;
     b.out_ok[t] = 0;
     for (int j = 0; j < 6; j++) b.seg_pos[t * 6 + j] = NAN;
+    b.seg_key[t] = 0;
+    b.seg_key[b.cap_seg + t] = 0;
     return;
   }
   const int64_t c0 = b.seg.hit_clu[a], c1 = b.seg.hit_clu[e - 1];
@@ -236,68 +255,76 @@ __global__ __launch_bounds__(kBlock) void k_seg_info(Consts k, MergeBufs b)
 #pragma unroll
   for (int j = 0; j < 15; j++) b.out_c[t * 15 + j] = ok ? s.c[j] : 0.0f;
   b.out_x[t] = ok ? x : 0.0f;
+  b.seg_key[t] = bucket_of(inst, b.seg_pos[t * 6 + 2]);
+  b.seg_key[b.cap_seg + t] = bucket_of(inst, b.seg_pos[t * 6 + 5]);
 }
 
-// --------------------------------------------------------------- seg_sort
-// segments in (instance, index) order: per-block instance counts ...
-__global__ __launch_bounds__(kBlock) void k_sort_count(MergeBufs b)
+// --------------------------------------------------------------- buckets
+__global__ __launch_bounds__(kBlock) void k_bkt_clear(MergeBufs b)
 {
-  __shared__ int s_cnt[kInst];
-  if (threadIdx.x < kInst) s_cnt[threadIdx.x] = 0;
-  __syncthreads();
+  for (int64_t i = gid(); i < 2 * kMergeBuckets; i += (int64_t)gridDim.x * blockDim.x)
+    b.bkt_cur[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bkt_count(MergeBufs b)
+{
   const int64_t n = *b.n_seg;
   const int64_t t = gid();
-  if (t < n) atomicAdd(&s_cnt[b.seg_inst[t]], 1);
-  __syncthreads();
-  if (threadIdx.x < kInst) b.sort_cnt[(int64_t)threadIdx.x * b.sort_blocks + blockIdx.x] =
-      s_cnt[threadIdx.x];
+  if (t >= n) return;
+  atomicAdd(&b.bkt_cur[b.seg_key[t]], 1);
+  atomicAdd(&b.bkt_cur[kMergeBuckets + b.seg_key[b.cap_seg + t]], 1);
 }
 
-// ... an exclusive scan of the (instance-major) counts in one block ...
-__global__ __launch_bounds__(1024) void k_sort_scan(MergeBufs b)
+// exclusive scans of both keys' counts in one block; the offsets are copied
+// into the cursors of the scatter
+__global__ __launch_bounds__(1024) void k_bkt_scan(MergeBufs b)
 {
   __shared__ int s_w[16];
-  const int64_t total = (int64_t)kInst * b.sort_blocks;
-  int carry = 0;
-  for (int64_t i0 = 0; i0 < total; i0 += 1024) {
-    const int64_t i = i0 + threadIdx.x;
-    const int v = i < total ? b.sort_cnt[i] : 0;
-    int x = v;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int w = 0; w < 2; w++) {
+    int* const cnt = b.bkt_cur + w * kMergeBuckets;
+    int* const off = b.bkt_off + w * (kMergeBuckets + 1);
+    int carry = 0;
+    for (int i0 = 0; i0 < kMergeBuckets; i0 += 1024) {
+      const int i = i0 + threadIdx.x;
+      const int v = i < kMergeBuckets ? cnt[i] : 0;
+      int x = v;
+      const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      if (lane == 63) s_w[wid] = x;
+      __syncthreads();
+      int wofs = 0, tot = 0;
+      for (int q = 0; q < 16; q++) {
+        if (q < wid) wofs += s_w[q];
+        tot += s_w[q];
+      }
+      if (i < kMergeBuckets) {
+        off[i] = carry + wofs + x - v;
+        cnt[i] = carry + wofs + x - v;
+      }
+      carry += tot;
+      __syncthreads();
     }
-    if (lane == 63) s_w[wid] = x;
-    __syncthreads();
-    int wofs = 0, tot = 0;
-    for (int w = 0; w < 16; w++) {
-      if (w < wid) wofs += s_w[w];
-      tot += s_w[w];
-    }
-    if (i < total) b.sort_cnt[i] = carry + wofs + x - v;
-    // the first block's offset of instance i starts instance i
-    if (i < total && i % b.sort_blocks == 0) b.inst_seg_off[i / b.sort_blocks] = carry + wofs + x - v;
-    carry += tot;
-    __syncthreads();
+    if (threadIdx.x == 0) off[kMergeBuckets] = carry;
   }
-  if (threadIdx.x == 0) b.inst_seg_off[kInst] = carry;
 }
 
-// ... and stable ranks within the block
-__global__ __launch_bounds__(kBlock) void k_sort_scatter(MergeBufs b)
+// a segment's place within its bucket comes from an atomic cursor: the
+// order within a bucket is arbitrary, and the pair search does not depend
+// on it
+__global__ __launch_bounds__(kBlock) void k_bkt_scatter(MergeBufs b)
 {
-  __shared__ int s_inst[kBlock];
   const int64_t n = *b.n_seg;
   const int64_t t = gid();
-  s_inst[threadIdx.x] = t < n ? b.seg_inst[t] : -1;
-  __syncthreads();
   if (t >= n) return;
-  const int me = s_inst[threadIdx.x];
-  int rank = 0;
-  for (int j = 0; j < (int)threadIdx.x; j++) rank += s_inst[j] == me ? 1 : 0;
-  b.seg_order[b.sort_cnt[(int64_t)me * b.sort_blocks + blockIdx.x] + rank] = (int32_t)t;
+#pragma unroll
+  for (int w = 0; w < 2; w++) {
+    const int p = atomicAdd(&b.bkt_cur[w * kMergeBuckets + b.seg_key[w * b.cap_seg + t]], 1);
+    b.bkt_order[w * b.cap_seg + p] = (int32_t)t;
+  }
 }
 
 // --------------------------------------------------------------- pairs
@@ -315,6 +342,24 @@ __device__ __forceinline__ float mpair(const Consts& k, const MergeBufs& b, int6
   const float d1 = b.seg_pos[A * 6 + 4] - b.seg_pos[B * 6 + 1];
   if (!(fabsf(b.seg_pos[A * 6 + 5] - b.seg_pos[B * 6 + 2]) <= b.mp.max_dz)) return -1.0f;
   if (!(d0 * d0 + d1 * d1 <= b.mp.max_dist * b.mp.max_dist)) return -1.0f;
+  // A's tgl and q/pt, and their variances, leave the rotation and the
+  // propagation unchanged (copies, no arithmetic), so two terms of the pair's
+  // chi2 are known before the transport: for the SPD sum S of the
+  // covariances, d^T S^-1 d >= d_i^2 / S_ii for every component i.  A pair
+  // whose larger such bound exceeds four times the cut cannot pass it: the
+  // binary32 LDL^T solve errs by far less than that factor (a Cholesky-type
+  // solve is accurate relative to the diagonal scaling, with an error set
+  // by the correlations, about 1e-4 at worst here), so skipping the
+  // transport leaves every decision as it is.
+  {
+    const float d3 = b.out_p[A * 5 + 3] - b.seg.param[B * 5 + 3];
+    const float d4 = b.out_p[A * 5 + 4] - b.seg.param[B * 5 + 4];
+    const float s33 = b.out_c[A * 15 + 9] + b.seg.cov[B * 15 + 9];
+    const float s44 = b.out_c[A * 15 + 14] + b.seg.cov[B * 15 + 14];
+    const float cut = 4.0f * b.mp.chi2_max;
+    if ((s33 > 0.0f && (d3 * d3) / s33 > cut) || (s44 > 0.0f && (d4 * d4) / s44 > cut))
+      return -1.0f;
+  }
   KSt s;
 #pragma unroll
   for (int j = 0; j < 5; j++) s.p[j] = b.out_p[A * 5 + j];
@@ -348,48 +393,41 @@ __device__ __forceinline__ int nbr_inst(int i, int which)
   return kk + kPhi * (1 - side);
 }
 
-// best successor (PRED = false: the lane's segment is A) or best
-// predecessor (PRED = true: the lane's segment is B); candidates of the three
-// neighbouring instances in increasing index (the order of the sort), so
-// the first minimum is the one of lowest index
+// best successor (PRED = false: the lane's segment is A, its last hit
+// against the candidates' first hits) or best predecessor (PRED = true: the
+// lane's segment is B, its first hit against the candidates' last hits),
+// over the candidates of the three neighbouring instances in the z bins
+// within R37's z cut (plus a margin for rounding) of the lane's end; the
+// pick is the smallest (chi2, index)
 template <bool PRED>
 __global__ __launch_bounds__(kBlock) void k_best(Consts k, MergeBufs b)
 {
   const int64_t n = *b.n_seg;
   const int64_t q = gid();
   if (q >= n) return;
-  const int64_t me = b.seg_order[q];
+  // lanes in the bucket order of their own end
+  const int own = PRED ? 0 : 1, oth = PRED ? 1 : 0;
+  const int64_t me = b.bkt_order[own * b.cap_seg + q];
   const int im = b.seg_inst[me];
+  const float zq = b.seg_pos[me * 6 + (PRED ? 2 : 5)];
+  const float wz = b.mp.max_dz + 0.1f;
+  const int zlo = merge_zbin(zq - wz), zhi = merge_zbin(zq + wz);
+  const int32_t* const off = b.bkt_off + oth * (kMergeBuckets + 1);
+  const int32_t* const ord = b.bkt_order + oth * b.cap_seg;
   int32_t best = -1;
   float bchi = 0.0f;
-  // candidates of the three instances merged in index order
-  int64_t pos[3], end[3];
-#pragma unroll
   for (int w = 0; w < 3; w++) {
-    const int j = nbr_inst(im, w);
-    pos[w] = b.inst_seg_off[j];
-    end[w] = b.inst_seg_off[j + 1];
-  }
-  for (;;) {
-    int64_t cand = INT64_MAX;
-    int wsel = -1;
-#pragma unroll
-    for (int w = 0; w < 3; w++) {
-      if (pos[w] < end[w]) {
-        const int64_t c = b.seg_order[pos[w]];
-        if (c < cand) {
-          cand = c;
-          wsel = w;
-        }
+    // the instance's bins zlo..zhi are one contiguous range of positions
+    const int bb = nbr_inst(im, w) * kMergeZBins;
+    const int pe = off[bb + zhi + 1];
+    for (int p = off[bb + zlo]; p < pe; p++) {
+      const int32_t cand = ord[p];
+      const float c2 = PRED ? mpair(k, b, cand, me) : mpair(k, b, me, cand);
+      if (c2 < 0.0f) continue;
+      if (best < 0 || c2 < bchi || (c2 == bchi && cand < best)) {
+        best = cand;
+        bchi = c2;
       }
-    }
-    if (wsel < 0) break;
-    pos[wsel]++;
-    const float c2 = PRED ? mpair(k, b, cand, me) : mpair(k, b, me, cand);
-    if (c2 < 0.0f) continue;
-    if (best < 0 || c2 < bchi) {
-      best = (int32_t)cand;
-      bchi = c2;
     }
   }
   if (PRED) {
@@ -413,82 +451,114 @@ __global__ __launch_bounds__(kBlock) void k_link(MergeBufs b)
   if (keep) b.has_pred[s] = 1;
 }
 
-// one block: chain starts (heads in index order, then the lowest segment of
-// every link cycle), their lengths and hit counts, and the offsets
-__global__ __launch_bounds__(1024) void k_chains(MergeBufs b)
+// Chain starts: item i < n is segment i as a head (no kept predecessor),
+// item n + i is segment i as the lowest segment of a link cycle.  An item
+// that starts a chain gets its segment and hit counts (both > 0), any
+// other item zeros; chains are numbered in item order, so heads come in
+// index order and then the cycles.
+__device__ __forceinline__ void chain_item(const MergeBufs& b, int64_t n, int64_t i, int32_t& ns,
+                                           int32_t& nh)
 {
-  __shared__ int64_t s_w[16];
-  __shared__ int64_t s_carry[3];
+  ns = 0;
+  nh = 0;
+  if (i >= 2 * n) return;
+  const int64_t t = i < n ? i : i - n;
+  bool start;
+  if (i < n) {
+    start = b.has_pred[t] == 0;
+  } else if (b.has_pred[t]) {
+    // every segment has at most one predecessor, so a segment with one is
+    // either on a head's chain (its successors end at -1) or on a link
+    // cycle (they come back to it); the cycle's lowest segment starts it
+    int64_t lowest = t, u = b.out.next[t];
+    for (int64_t step = 0; step < n && u >= 0 && u != t; step++) {
+      if (u < lowest) lowest = u;
+      u = b.out.next[u];
+    }
+    start = u == t && lowest == t;
+  } else {
+    start = false;
+  }
+  if (!start) return;
+  // at most n segments: the walk ends whatever next holds
+  int64_t u = t;
+  for (int64_t step = 0; step < n; step++) {
+    ns++;
+    nh += b.seg.hit_off[u + 1] - b.seg.hit_off[u];
+    u = b.out.next[u];
+    if (u < 0 || u == t) break;
+  }
+}
+
+// exclusive scans of three values over the workgroup (kBlock threads)
+__device__ __forceinline__ void block_scan3(const int64_t v[3], int64_t ex[3], int64_t tot[3])
+{
+  __shared__ int64_t s_w[3][kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int64_t x[3];
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    x[q] = v[q];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t y = __shfl_up(x[q], o, 64);
+      if (lane >= o) x[q] += y;
+    }
+    if (lane == 63) s_w[q][wid] = x[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    int64_t wofs = 0, tt = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; w++) {
+      if (w < wid) wofs += s_w[q][w];
+      tt += s_w[q][w];
+    }
+    ex[q] = x[q] - v[q] + wofs;
+    tot[q] = tt;
+  }
+  __syncthreads();
+}
+
+// pass 1: every item's counts, and each workgroup's sums (starts, segments, hits)
+__global__ __launch_bounds__(kBlock) void k_chain_count(MergeBufs b)
+{
   const int64_t n = *b.n_seg;
+  const int64_t i = gid();
+  int32_t ns, nh;
+  chain_item(b, n, i, ns, nh);
+  if (i < 2 * n) {
+    b.it_ns[i] = ns;
+    b.it_nh[i] = nh;
+  }
+  const int64_t v[3] = {ns > 0 ? 1 : 0, ns, nh};
+  int64_t ex[3], tot[3];
+  block_scan3(v, ex, tot);
+  if (threadIdx.x < 3) b.ch_part[blockIdx.x * 3 + threadIdx.x] = tot[threadIdx.x];
+}
+
+// pass 2, one workgroup: exclusive scan of the workgroup sums; the totals
+// close the offset arrays
+__global__ __launch_bounds__(kBlock) void k_chain_partials(MergeBufs b, int64_t nblk)
+{
+  __shared__ int64_t s_carry[3];
   if (threadIdx.x < 3) s_carry[threadIdx.x] = 0;
   __syncthreads();
-  for (int pass = 0; pass < 2; pass++) {
-    for (int64_t i0 = 0; i0 < n; i0 += 1024) {
-      const int64_t t = i0 + threadIdx.x;
-      bool start = false;
-      int64_t nseg = 0, nhit = 0;
-      if (t < n) {
-        if (pass == 0) {
-          start = b.has_pred[t] == 0;
-        } else if (b.has_pred[t]) {
-          // every segment has at most one predecessor, so a segment with one
-          // is either on a head's chain (its successors end at -1) or on a
-          // link cycle (they come back to it); the cycle's lowest segment
-          // starts its chain
-          int64_t lowest = t, u = b.out.next[t];
-          for (int64_t step = 0; step < n && u >= 0 && u != t; step++) {
-            if (u < lowest) lowest = u;
-            u = b.out.next[u];
-          }
-          start = u == t && lowest == t;
-        }
-        if (start) {
-          // at most n segments: the walk ends whatever next holds
-          int64_t u = t;
-          for (int64_t step = 0; step < n; step++) {
-            nseg++;
-            nhit += b.seg.hit_off[u + 1] - b.seg.hit_off[u];
-            u = b.out.next[u];
-            if (u < 0 || u == t) break;
-          }
-        }
-      }
-      // three exclusive scans in one: starts, segments, hits
-      int64_t v[3] = {start ? 1 : 0, nseg, nhit}, ex[3], tot[3];
-      const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int64_t i0 = 0; i0 < nblk; i0 += kBlock) {
+    const int64_t i = i0 + threadIdx.x;
+    int64_t v[3];
 #pragma unroll
-      for (int q = 0; q < 3; q++) {
-        int64_t x = v[q];
+    for (int q = 0; q < 3; q++) v[q] = i < nblk ? b.ch_part[i * 3 + q] : 0;
+    int64_t ex[3], tot[3];
+    block_scan3(v, ex, tot);
+    if (i < nblk) {
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const int64_t y = __shfl_up(x, o, 64);
-          if (lane >= o) x += y;
-        }
-        if (lane == 63) s_w[wid] = x;
-        __syncthreads();
-        int64_t wofs = 0, tt = 0;
-        for (int w = 0; w < 16; w++) {
-          if (w < wid) wofs += s_w[w];
-          tt += s_w[w];
-        }
-        ex[q] = x - v[q] + wofs;
-        tot[q] = tt;
-        __syncthreads();
-      }
-      if (start) {
-        const int64_t m = s_carry[0] + ex[0];
-        b.chain_head[m] = (int32_t)t;
-        b.out.seg_off[m] = (int32_t)(s_carry[1] + ex[1]);
-        b.out.hit_off[m] = (int32_t)(s_carry[2] + ex[2]);
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        s_carry[0] += tot[0];
-        s_carry[1] += tot[1];
-        s_carry[2] += tot[2];
-      }
-      __syncthreads();
+      for (int q = 0; q < 3; q++) b.ch_part[i * 3 + q] = s_carry[q] + ex[q];
     }
+    __syncthreads();
+    if (threadIdx.x < 3) s_carry[threadIdx.x] += tot[threadIdx.x];
+    __syncthreads();
   }
   if (threadIdx.x == 0) {
     const int64_t m = s_carry[0];
@@ -496,6 +566,25 @@ __global__ __launch_bounds__(1024) void k_chains(MergeBufs b)
     b.out.hit_off[m] = (int32_t)s_carry[2];
     b.out.counts[0] = m;
     b.out.counts[1] = s_carry[2];
+  }
+}
+
+// pass 3: chain heads and offsets in item order
+__global__ __launch_bounds__(kBlock) void k_chain_write(MergeBufs b)
+{
+  const int64_t n = *b.n_seg;
+  const int64_t i = gid();
+  const int32_t ns = i < 2 * n ? b.it_ns[i] : 0;
+  const int32_t nh = i < 2 * n ? b.it_nh[i] : 0;
+  const int64_t v[3] = {ns > 0 ? 1 : 0, ns, nh};
+  int64_t ex[3], tot[3];
+  block_scan3(v, ex, tot);
+  if (ns > 0) {
+    const int64_t* const base = b.ch_part + blockIdx.x * 3;
+    const int64_t m = base[0] + ex[0];
+    b.chain_head[m] = (int32_t)(i < n ? i : i - n);
+    b.out.seg_off[m] = (int32_t)(base[1] + ex[1]);
+    b.out.hit_off[m] = (int32_t)(base[2] + ex[2]);
   }
 }
 
@@ -509,7 +598,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_hits(MergeBufs b)
   int64_t so = b.out.seg_off[m], ho = b.out.hit_off[m];
   const int64_t se = b.out.seg_off[m + 1];
   int64_t u = t;
-  // the segment count of the chain was fixed by k_chains
+  // the segment count of the chain was fixed by k_chain_count
   while (so < se) {
     b.out.seg[so++] = (int32_t)u;
     for (int64_t h = b.seg.hit_off[u]; h < b.seg.hit_off[u + 1]; h++)
@@ -584,10 +673,11 @@ hipError_t merge_tracks(const Consts& k, const MergeBufs& b, hipStream_t s)
   slot = prof_begin(s, "merge_seg_info");
   k_seg_info<<<nb, kBlock, 0, s>>>(k, b);
   prof_end(s, slot);
-  slot = prof_begin(s, "merge_sort");
-  k_sort_count<<<nb, kBlock, 0, s>>>(b);
-  k_sort_scan<<<1, 1024, 0, s>>>(b);
-  k_sort_scatter<<<nb, kBlock, 0, s>>>(b);
+  slot = prof_begin(s, "merge_buckets");
+  k_bkt_clear<<<(2 * kMergeBuckets + kBlock - 1) / kBlock, kBlock, 0, s>>>(b);
+  k_bkt_count<<<nb, kBlock, 0, s>>>(b);
+  k_bkt_scan<<<1, 1024, 0, s>>>(b);
+  k_bkt_scatter<<<nb, kBlock, 0, s>>>(b);
   prof_end(s, slot);
   slot = prof_begin(s, "merge_succ");
   k_best<false><<<nb, kBlock, 0, s>>>(k, b);
@@ -597,7 +687,10 @@ hipError_t merge_tracks(const Consts& k, const MergeBufs& b, hipStream_t s)
   prof_end(s, slot);
   slot = prof_begin(s, "merge_link");
   k_link<<<nb, kBlock, 0, s>>>(b);
-  k_chains<<<1, 1024, 0, s>>>(b);
+  const int64_t nblk = (2 * b.cap_seg + kBlock - 1) / kBlock;
+  k_chain_count<<<(unsigned)nblk, kBlock, 0, s>>>(b);
+  k_chain_partials<<<1, kBlock, 0, s>>>(b, nblk);
+  k_chain_write<<<(unsigned)nblk, kBlock, 0, s>>>(b);
   prof_end(s, slot);
   slot = prof_begin(s, "merge_chain_hits");
   k_chain_hits<<<nb, kBlock, 0, s>>>(b);

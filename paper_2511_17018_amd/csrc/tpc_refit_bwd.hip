@@ -265,27 +265,35 @@ __device__ __forceinline__ int field_zbin(float z, int nzb)
 }
 #pragma float_control(pop)
 
-// intermediates of the material step that its adjoint needs
-struct MRec {
-  R t2, w, bg, sq, path, th2, qt, f, q4, ads, sgn, ix0, K;
-  R c4[5];  // covariance row of q/pt after the scattering noise, before the loss
+// The material step's scalars, a function of the propagated state's snp,
+// tgl, q/pt, the step length and the row's material: computed in the
+// forward rebuild and again in the adjoint, so that only the inputs (and
+// the covariance row of q/pt) stay live across the update's adjoint.
+struct MScal {
+  R t2, w, bg, sq, path, qt, th2, f;
 };
 
-// the material step on the propagated state pp and covariance C (lower
-// triangle); the scattering noise on snp, tgl, q/pt, then the energy loss
-__device__ __forceinline__ void mat_forward(R* pp, R* C, R ads, R sgn, R ix0, R K, MRec& m)
+__device__ __forceinline__ MScal mat_scalars(R tgl, R qpt, R ads, R sgn, R ix0, R K)
 {
-  const R snp = pp[2], tgl = pp[3], qpt = pp[4];
-  m.ads = ads;
-  m.sgn = sgn;
-  m.ix0 = ix0;
-  m.K = K;
+  MScal m;
   m.t2 = 1.0 + tgl * tgl;
   m.w = (qpt * qpt) / m.t2;
   m.bg = 1.0 + kPion2 * m.w;
   m.path = ads * sqrt(m.t2);
   m.qt = qpt * tgl;
   m.th2 = ix0 > 0.0 ? (kHighland2 * (m.path * ix0)) * (m.w * m.bg) : 0.0;
+  m.sq = sqrt(m.w * m.bg);
+  m.f = 1.0 + (K > 0.0 ? (m.sq * (K * m.bg)) * (m.path * sgn) : 0.0);
+  return m;
+}
+
+// the material step on the propagated state pp and covariance C (lower
+// triangle): the scattering noise on snp, tgl, q/pt, then the energy loss;
+// c4 receives the covariance row of q/pt between the two
+__device__ __forceinline__ void mat_forward(R* pp, R* C, R ads, R sgn, R ix0, R K, R* c4)
+{
+  const R snp = pp[2], qpt = pp[4];
+  const MScal m = mat_scalars(pp[3], qpt, ads, sgn, ix0, K);
   if (ix0 > 0.0) {
     C[si(2, 2)] += m.th2 * (((1.0 - snp) * (1.0 + snp)) * m.t2);
     C[si(3, 3)] += m.th2 * (m.t2 * m.t2);
@@ -293,10 +301,7 @@ __device__ __forceinline__ void mat_forward(R* pp, R* C, R ads, R sgn, R ix0, R 
     C[si(4, 4)] += m.th2 * (m.qt * m.qt);
   }
 #pragma unroll
-  for (int j = 0; j < 5; j++) m.c4[j] = C[si(4, j)];
-  m.q4 = qpt;
-  m.sq = sqrt(m.w * m.bg);
-  m.f = 1.0 + (K > 0.0 ? (m.sq * (K * m.bg)) * (m.path * sgn) : 0.0);
+  for (int j = 0; j < 5; j++) c4[j] = C[si(4, j)];
   if (K > 0.0) {
     pp[4] = qpt * m.f;
 #pragma unroll
@@ -306,33 +311,34 @@ __device__ __forceinline__ void mat_forward(R* pp, R* C, R ads, R sgn, R ix0, R 
 }
 
 // adjoint of mat_forward: pb and X (the symmetric covariance adjoint) go
-// from after the material to the propagated state pp1; returns the adjoint
-// of the step's signed arc length
-__device__ __forceinline__ R mat_backward(const R* pp1, const MRec& m, R* pb, R* X)
+// from after the material to the propagated state (snp, tgl, q/pt);
+// returns the adjoint of the step's signed arc length
+__device__ __forceinline__ R mat_backward(R snp, R tgl, R qpt, const R* c4, R ads, R sgn, R ix0,
+                                          R K, R* pb, R* X)
 {
-  const R snp = pp1[2], tgl = pp1[3], qpt = pp1[4];
+  const MScal m = mat_scalars(tgl, qpt, ads, sgn, ix0, K);
   R t2b = 0.0, wb = 0.0, bgb = 0.0, pathb = 0.0, qtb = 0.0;
-  if (m.K > 0.0) {
+  if (K > 0.0) {
     // q/pt' = q/pt f; row 4 of the covariance scaled by f, its diagonal by f^2
     R s = 0.0;
 #pragma unroll
-    for (int j = 0; j < 4; j++) s += X[si(4, j)] * m.c4[j];
-    const R cb = pb[4] * m.q4 + 2.0 * (s + X[si(4, 4)] * m.c4[4] * m.f);
+    for (int j = 0; j < 4; j++) s += X[si(4, j)] * c4[j];
+    const R cb = pb[4] * qpt + 2.0 * (s + X[si(4, 4)] * c4[4] * m.f);
     pb[4] *= m.f;
 #pragma unroll
     for (int j = 0; j < 4; j++) X[si(4, j)] *= m.f;
     X[si(4, 4)] *= m.f * m.f;
     // f - 1 = sq (K bg) (path sgn), sq = sqrt(w bg)
-    const R sqb = cb * (m.K * m.bg) * (m.path * m.sgn);
-    bgb += cb * m.sq * m.K * (m.path * m.sgn);
-    pathb += cb * m.sq * (m.K * m.bg) * m.sgn;
+    const R sqb = cb * (K * m.bg) * (m.path * sgn);
+    bgb += cb * m.sq * K * (m.path * sgn);
+    pathb += cb * m.sq * (K * m.bg) * sgn;
     if (m.sq > 0.0) {
       const R wbgb = sqb / (2.0 * m.sq);
       wb += wbgb * m.bg;
       bgb += wbgb * m.w;
     }
   }
-  if (m.ix0 > 0.0) {
+  if (ix0 > 0.0) {
     const R u22 = ((1.0 - snp) * (1.0 + snp)) * m.t2, u33 = m.t2 * m.t2;
     const R u43 = m.t2 * m.qt, u44 = m.qt * m.qt;
     const R x22 = X[si(2, 2)], x33 = X[si(3, 3)], x43 = X[si(4, 3)], x44 = X[si(4, 4)];
@@ -341,7 +347,7 @@ __device__ __forceinline__ R mat_backward(const R* pp1, const MRec& m, R* pb, R*
     t2b += m.th2 * (x22 * ((1.0 - snp) * (1.0 + snp)) + x33 * 2.0 * m.t2 + 2.0 * x43 * m.qt);
     qtb += m.th2 * (2.0 * x43 * m.t2 + x44 * 2.0 * m.qt);
     // th2 = kHighland2 path ix0 w bg
-    const R a = A * kHighland2 * m.ix0;
+    const R a = A * kHighland2 * ix0;
     pathb += a * m.w * m.bg;
     wb += a * m.path * m.bg;
     bgb += a * m.path * m.w;
@@ -354,9 +360,9 @@ __device__ __forceinline__ R mat_backward(const R* pp1, const MRec& m, R* pb, R*
   t2b += wb * (-m.w / m.t2);
   const R st2 = sqrt(m.t2);
   const R adsb = pathb * st2;
-  t2b += pathb * m.ads / (2.0 * st2);
+  t2b += pathb * ads / (2.0 * st2);
   pb[3] += t2b * 2.0 * tgl;
-  return adsb * m.sgn;
+  return adsb * sgn;
 }
 
 // adds to the workgroup's partial sums in LDS (flushed once per workgroup);
@@ -531,24 +537,27 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
       if (i >= 3) Cp[si(i, 3)] = Bi[3];
       if (i >= 4) Cp[si(i, 4)] = Bi[4];
     }
-    // the material of the step (R43, R44) on the propagated state
+    // the material of the step (R43, R44) on the propagated state; what its
+    // adjoint needs besides these inputs is recomputed there
     const bool mat = MAT && (b.ix0 || b.eloss);
-    R pp1[5];
-    MRec mr;
+    R m_snp = 0.0, m_tgl = 0.0, m_qpt = 0.0, m_ix0 = 0.0, m_K = 0.0, c4[5];
     if constexpr (MAT) {
       if (mat) {
-#pragma unroll
-        for (int j = 0; j < 5; j++) pp1[j] = pp[j];
+        m_snp = pp[2];
+        m_tgl = pp[3];
+        m_qpt = pp[4];
         const int rr = cell / kPhi;
-        mat_forward(pp, Cp, dss * sgs, sgs, b.ix0 ? (R)b.ix0[rr] : 0.0,
-                    b.eloss ? (R)b.eloss[rr] : 0.0, mr);
+        m_ix0 = b.ix0 ? (R)b.ix0[rr] : 0.0;
+        m_K = b.eloss ? (R)b.eloss[rr] : 0.0;
+        mat_forward(pp, Cp, dss * sgs, sgs, m_ix0, m_K, c4);
       }
     }
     R mb[2];
     update_backward(pp, Cp, (R)yc, (R)zc, vy, vz, w, pb, X, mb);
     R dsb_mat = 0.0;
     if constexpr (MAT) {
-      if (mat) dsb_mat = mat_backward(pp1, mr, pb, X);
+      if (mat)
+        dsb_mat = mat_backward(m_snp, m_tgl, m_qpt, c4, dss * sgs, sgs, m_ix0, m_K, pb, X);
     }
     // covariance part of the propagation: XF = X F, Fb = 2 (X F C0) at the
     // entries of E, X <- F^T X F

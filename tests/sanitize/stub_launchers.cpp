@@ -111,8 +111,10 @@ static hipError_t refit_stub(const RefitBufs& b)
     in_ws(b.n_seg, 8, "n_seg");                                                      \
     in_ws(b.seg_pos, 24 * c, "seg_pos");                                             \
     in_ws(b.out_c, 60 * c, "out_c");                                                 \
-    in_ws(b.sort_cnt, 4 * 36 * b.sort_blocks, "sort_cnt");                           \
+    in_ws(b.bkt_off, 4 * 2 * (kMergeBuckets + 1), "bkt_off");                       \
+    in_ws(b.bkt_order, 4 * 2 * c, "bkt_order");                                      \
     in_ws(b.chain_head, 4 * c, "chain_head");                                        \
+    in_ws(b.ch_part, 8 * 3 * ((2 * c + 255) / 256), "ch_part");                      \
     stub::g_calls++;                                                                 \
     return hipSuccess;                                                               \
   }                                                                                  \

@@ -143,10 +143,11 @@ def test_refit_config5_full_sampled_tracks():
 
 
 def test_prod_config4_full_within_r30_bounds():
-    # production mode on the full batch: clusters assigned differently from
-    # the deterministic (oracle-exact) output below 1e-5, and the parameters
-    # of sampled kept tracklets within 1e-4 of a binary64 replay of their own
-    # hits at the 99th percentile (R30)
+    # production mode on the full batch (R30): clusters assigned differently
+    # from the deterministic (oracle-exact) output below 1e-5, a valid
+    # partition, and every parameter of 3000 sampled kept tracklets within
+    # max(1e-4, K x the binary32 filter's rounding-noise scale on the same
+    # hits) of a binary64 replay of those hits
     ev = synth.config4()
     batch = tpc.upload(ev.x, ev.y, ev.z, ev.row, ev.charge, ev.inst_off, "cuda")
     od, _ = _batched(ev, True, batch)

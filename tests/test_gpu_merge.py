@@ -66,6 +66,43 @@ def test_merge_bit_exact(n_tracks):
     _compare(h, m)
 
 
+def test_merge_bit_exact_pileup():
+    """Collisions overlapping in drift time (the time-frame workload at a
+    tenth of its collisions): many segments share each sector edge's z and
+    distance window, so the bucketed pair search and its pre-transport
+    bound reject most candidates -- the result still equals the oracle's
+    search over all pairs."""
+    ev = synth.config3(n_coll=12)
+    _say(f"[merge] pile-up collisions=12 clusters={ev.n}")
+    run, h = _run(ev)
+    S = _oracle_segments(run, ev)
+    m = oracle.merge(G, ev.inst_off, ev.y, ev.z, ev.row, S)
+    _say(f"[merge] segments={len(S.hit_off) - 1} merged={len(m.chi2)} "
+         f"links={(m.next >= 0).sum()}")
+    _compare(h, m)
+
+
+def test_merge_run_to_run_identical():
+    """The pair-search buckets are filled in atomic order, which varies from
+    run to run; the deterministic output does not (ten runs)."""
+    ev = synth.config3(n_coll=4)
+    batch = tpc.upload(ev.x, ev.y, ev.z, ev.row, ev.charge, ev.inst_off, "cuda")
+    run = tpc.track(G, batch, det=True)
+    n_seg = int(run.result["n_tracks"])
+    first = None
+    for _ in range(10):
+        h = tpc.merge_tracks(G, batch, run.tracks, run.ws.result, det=True).host()
+        torch.cuda.synchronize()
+        h["next"] = h["next"][:n_seg]
+        if first is None:
+            first = h
+            continue
+        for k in ("next", "seg_off", "seg", "hit_off", "hit_clu", "status", "sector"):
+            assert np.array_equal(h[k], first[k]), k
+        for k in ("param", "cov", "chi2", "x_ref"):
+            assert np.array_equal(parity.bits(h[k]), parity.bits(first[k])), k
+
+
 def test_merge_crossing_the_membrane_and_empty_input():
     # noise-free tracks of shallow dip cross z = 0 (segments on both sides)
     ev = synth.config2(n_tracks=1500, noise=0.0)

@@ -213,9 +213,10 @@ def test_det_empty_and_tiny_batches():
 
 
 def test_det_run_to_run_identical():
+    # ten runs in all
     ev = synth.config2(n_tracks=1500)
     a = parity.gpu_arrays(parity.run_gpu(ev, det=True), ev.n)
-    for _ in range(3):
+    for _ in range(9):
         b = parity.gpu_arrays(parity.run_gpu(ev, det=True), ev.n)
         for k in ("perm", "up2", "start", "tl_par", "tl_cov", "hit_clu", "param", "clu2trk"):
             assert np.array_equal(parity.bits(a[k]), parity.bits(b[k])), k
