@@ -60,6 +60,22 @@ KERNEL_SOURCES = ["paper_2511_17018_amd/csrc/tpc_kernels.hip", "paper_2511_17018
                   "paper_2511_17018_amd/build.py"]
 
 
+def kernel_code_digest() -> str:
+    """SHA-256 of the kernel sources with comments and white space removed,
+    so that a committed profile stays valid across changes of comments only."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f)) as fh:
+            text = fh.read()
+        if f.endswith(".py"):
+            text = re.sub(r"#[^\n]*", "", text)
+        else:
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+        h.update(re.sub(r"\s+", "", text).encode())
+    return h.hexdigest()
+
+
 def _profiled(path: str, field: str, kernel: str, occ: float, chunk: int) -> int | None:
     """Per-launch figure `field` of `kernel` from a committed rocprofv3
     summary, or None when the kernel sources or the launch parameters differ
@@ -68,12 +84,8 @@ def _profiled(path: str, field: str, kernel: str, occ: float, chunk: int) -> int
         text = open(path).read()
     except OSError:
         return None
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
     m = re.search(r"source_sha256: ([0-9a-f]{64})", text)
-    if not m or m.group(1) != h.hexdigest():
+    if not m or m.group(1) != kernel_code_digest():
         return None
     # one block of figures per profiled launch configuration
     for block in re.split(r"^launch: ", text, flags=re.M)[1:]:

@@ -298,9 +298,20 @@ typedef struct {
  * filter of the tracker (propagation, Jacobian, update) runs from the first
  * hit outwards; chi2[t] is the sum of the update chi2 values, status[t] = 1
  * (and chi2 = 0) if the propagation failed (|snp| reaching snp_max).  The
- * state after every update is checkpointed: ckpt[n_hits][20] = (y, z, snp,
- * tgl, qpt, lower-triangular covariance).  With TPC_FLAG_DETERMINISTIC chi2
- * and ckpt equal the binary32 CPU reference bit for bit.  This refit is the
+ * state after every update (and the start state at the first hit) is
+ * checkpointed, 20 floats per hit: (y, z, snp, tgl, qpt, lower-triangular
+ * covariance), in five 16-byte parts of four floats.  ckpt holds n_hits * 20
+ * floats (16-byte aligned), grouped by 64 consecutive tracks: the group of
+ * tracks 64g .. 64g+63 fills floats [20 hit_off[64g], 20 hit_off[64g+64])
+ * (the last group ends at n_hits), by hit number j (0 = a track's first
+ * hit).  With L_k the group's track lengths, the a_j = #{k : L_k > j}
+ * tracks that have a hit j store it from float4 5 E_j on, E_j =
+ * hit_off[64g] + sum_k min(L_k, j): part q of track t at float4
+ *   5 E_j + q a_j + #{k < t : L_k > j}
+ * (so that the 64 lanes running a group store and load one contiguous run
+ * per part and step).
+ * With TPC_FLAG_DETERMINISTIC chi2 and every checkpoint equal the binary32
+ * CPU reference bit for bit.  This refit is the
  * differentiable extension of the tracking step; the paper's shared track
  * propagation with field and material maps (Sec. 4) is its context.  With
  * mat (NULL: uniform field, no material), each step uses the field of its

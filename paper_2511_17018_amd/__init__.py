@@ -396,9 +396,43 @@ def _mat_ref(mat: Material | None):
     return C.byref(m), m
 
 
+def checkpoint_index(hit_off) -> np.ndarray:
+    """Float indices into the refit's flat checkpoint array of each hit's 20
+    values, for the hits in hit order: ckpt.reshape(-1)[checkpoint_index(
+    hit_off)] is [n_hits, 20] in hit order.  tpc_refit's layout: groups of 64
+    consecutive tracks; in a group, by hit number j, the a_j tracks with more
+    than j hits share 80 * a_j bytes starting at entry E_j (the group's first
+    hit plus sum_k min(L_k, j)), as five runs of 16-byte parts, part q of the
+    track of rank r at float4 5 E_j + q a_j + r."""
+    ho = np.asarray(hit_off, np.int64)
+    n = len(ho) - 1
+    L = np.diff(ho)
+    trk = np.repeat(np.arange(n, dtype=np.int64), L)
+    j = np.arange(int(ho[-1]), dtype=np.int64) - np.repeat(ho[:-1], L)
+    g = trk // 64
+    # rank among the group's tracks with more than j hits, and their count:
+    # the hits sorted by (group, j, track) enumerate each (group, j) run
+    order = np.lexsort((trk, j, g))
+    key = g[order] * (int(L.max(initial=0)) + 1) + j[order]
+    first = np.r_[True, key[1:] != key[:-1]]
+    run_start = np.maximum.accumulate(np.where(first, np.arange(len(key)), 0))
+    rank = np.empty(len(trk), np.int64)
+    rank[order] = np.arange(len(key)) - run_start
+    run_len = np.diff(np.r_[np.nonzero(first)[0], len(key)])
+    act = np.empty(len(trk), np.int64)
+    act[order] = np.repeat(run_len, run_len)
+    # E_j: the run's first entry (the hits before it in the same order)
+    e0 = np.empty(len(trk), np.int64)
+    e0[order] = run_start
+    q = np.arange(5, dtype=np.int64)
+    f4 = 5 * e0[:, None] + q[None, :] * act[:, None] + rank[:, None]
+    return (4 * f4[:, :, None] + np.arange(4)[None, None, :]).reshape(len(trk), 20)
+
+
 def refit(geom: dict, xyz: torch.Tensor, row: torch.Tensor, trk: RefitTracks,
           dist_map: torch.Tensor, det: bool = True, mat: Material | None = None):
-    """tpc_refit on the current stream: (chi2[n], status[n], ckpt[n_hits, 20]).
+    """tpc_refit on the current stream: (chi2[n], status[n], ckpt[n_hits, 20]);
+    ckpt in the library's layout (checkpoint_index gives the hit order).
     mat: field map and material (None: uniform field, no material)."""
     assert xyz.dtype == torch.float32 and xyz.is_contiguous() and xyz.shape[0] == 3
     dev = xyz.device

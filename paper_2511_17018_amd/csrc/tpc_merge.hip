@@ -157,26 +157,72 @@ __device__ __forceinline__ float mchi2(const float* S, const float* d)
 }
 
 // R40: filter pass over hits[first + dir q], q < count, from state s at
-// plane x in frame k; chi2 accumulates
+// plane x in frame k; chi2 accumulates.  The hits go in blocks of kMBlk:
+// the block's cluster indices, then their rows, positions and sectors, then
+// the row planes are loaded at once (three memory latencies per block
+// instead of three per hit).  The block's hits in the current frame are
+// filtered in an unrolled loop; the first hit of another sector ends it,
+// is transported (one copy of that code) and filtered, and the next block
+// starts after it.
+constexpr int kMBlk = 8;
+
 __device__ __forceinline__ bool mpass(const Consts& k, const MergeBufs& b, const int64_t* s_off,
                                    KSt& s, float& x, int& kf, const int32_t* hits, int64_t first,
                                    int64_t count, int dir, float& chi2)
 {
   const float kB = k.kB, vy = k.vy, vz = k.vz;
-  for (int64_t q = 0; q < count; q++) {
-    const int64_t c = hits[first + dir * q];
-    const int kk = inst_of(s_off, c) % kPhi;
-    const float xh = k.row_x[b.row[c]];
-    if (kk != kf) {
-      const bool up = (kk - kf + kPhi) % kPhi == 1;
-      const float sa = up ? b.mp.sin_d : -b.mp.sin_d;
-      if (!mtransport(s, x, b.mp.cos_d, sa, xh, b.y[c], kB)) return false;
-      kf = kk;
-    } else {
-      if (!mmove(s, x, xh, kB)) return false;
-      x = xh;
+  int64_t q = 0;
+  while (q < count) {
+    int64_t c[kMBlk];
+#pragma unroll
+    for (int u = 0; u < kMBlk; u++) c[u] = hits[first + dir * (q + u < count ? q + u : count - 1)];
+    int rw[kMBlk], kk[kMBlk];
+    float yc[kMBlk], zc[kMBlk];
+#pragma unroll
+    for (int u = 0; u < kMBlk; u++) {
+      rw[u] = b.row[c[u]];
+      yc[u] = b.y[c[u]];
+      zc[u] = b.z[c[u]];
+      kk[u] = inst_of(s_off, c[u]) % kPhi;
     }
-    chi2 = chi2 + kupdate(s, b.y[c], b.z[c], vy, vz);
+    float xh[kMBlk];
+#pragma unroll
+    for (int u = 0; u < kMBlk; u++) xh[u] = k.row_x[rw[u]];
+    int done = 0;
+    bool rot = false;
+#pragma unroll
+    for (int u = 0; u < kMBlk; u++) {
+      if (!rot && q + u < count) {
+        if (kk[u] != kf) {
+          rot = true;
+        } else {
+          if (!mmove(s, x, xh[u], kB)) return false;
+          x = xh[u];
+          chi2 = chi2 + kupdate(s, yc[u], zc[u], vy, vz);
+          done = u + 1;
+        }
+      }
+    }
+    if (rot) {
+      // the hit at q + done enters another sector
+      float xt = xh[0], yt = yc[0], zt = zc[0];
+      int kt = kk[0];
+#pragma unroll
+      for (int u = 1; u < kMBlk; u++) {
+        const bool m = u == done;
+        xt = m ? xh[u] : xt;
+        yt = m ? yc[u] : yt;
+        zt = m ? zc[u] : zt;
+        kt = m ? kk[u] : kt;
+      }
+      const bool up = (kt - kf + kPhi) % kPhi == 1;
+      const float sa = up ? b.mp.sin_d : -b.mp.sin_d;
+      if (!mtransport(s, x, b.mp.cos_d, sa, xt, yt, kB)) return false;
+      kf = kt;
+      chi2 = chi2 + kupdate(s, yt, zt, vy, vz);
+      done++;
+    }
+    q += done;
   }
   return true;
 }

@@ -3,6 +3,7 @@
 // kernels: in the deterministic build the chi2 and the checkpoints equal the
 // binary32 CPU reference bit for bit.
 #include "tpc_internal.h"
+#include "tpc_ckpt.h"
 
 #ifndef TPC_NS
 #error "TPC_NS must name the build (det or prod)"
@@ -14,14 +15,14 @@ namespace {
 
 #include "tpc_kalman.h"
 
-__device__ __forceinline__ void store_ckpt(float* ck, const KSt& st)
+// the five 16-byte parts of a checkpoint at q[0], q[d], .. q[4 d]
+__device__ __forceinline__ void store_ckpt(float4* q, int64_t d, const KSt& st)
 {
-  float4* q = reinterpret_cast<float4*>(ck);  // 80 bytes, 16-byte aligned
   q[0] = make_float4(st.p[0], st.p[1], st.p[2], st.p[3]);
-  q[1] = make_float4(st.p[4], st.c[0], st.c[1], st.c[2]);
-  q[2] = make_float4(st.c[3], st.c[4], st.c[5], st.c[6]);
-  q[3] = make_float4(st.c[7], st.c[8], st.c[9], st.c[10]);
-  q[4] = make_float4(st.c[11], st.c[12], st.c[13], st.c[14]);
+  q[d] = make_float4(st.p[4], st.c[0], st.c[1], st.c[2]);
+  q[2 * d] = make_float4(st.c[3], st.c[4], st.c[5], st.c[6]);
+  q[3 * d] = make_float4(st.c[7], st.c[8], st.c[9], st.c[10]);
+  q[4 * d] = make_float4(st.c[11], st.c[12], st.c[13], st.c[14]);
 }
 
 constexpr int kFwdBlk = 8;  // hits per load block of the forward pass
@@ -87,8 +88,13 @@ __device__ __forceinline__ void mat_step(KSt& s, float ads, float sgn, float ix0
 template <bool MAT>
 __global__ __launch_bounds__(kBlock) void k_refit_fwd(Consts k, RefitBufs b)
 {
+  __shared__ CkTables s_ck;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int lmax;
+  ck_build(s_ck, b.hit_off, b.n_tracks, t, lmax);
   if (t >= b.n_tracks) return;
+  // the checkpoints of this wave's group of tracks start at its first hit
+  float4* const ck = reinterpret_cast<float4*>(b.ckpt) + ck_group_base(b.hit_off) * 5;
   const int64_t a = b.hit_off[t], e = b.hit_off[t + 1];
   if (e <= a) {
     b.chi2[t] = 0.0f;
@@ -113,7 +119,10 @@ __global__ __launch_bounds__(kBlock) void k_refit_fwd(Consts k, RefitBufs b)
   st.p[3] = b.seed[t * 5 + 3];
   st.p[4] = b.seed[t * 5 + 4];
   kinit_cov(st, vy, vz);
-  store_ckpt(b.ckpt + a * 20, st);
+  {
+    const CkSlot sl = ck_slot(s_ck, 0);
+    store_ckpt(ck + sl.idx, sl.stride, st);
+  }
   float xprev = b.x[c] + b.dmap[(int)b.row[c] * kPhi + b.sector[c] % kPhi];
   float chi2 = 0.0f;
   // the hits go in blocks of kFwdBlk: the block's cluster indices, then
@@ -178,7 +187,8 @@ __global__ __launch_bounds__(kBlock) void k_refit_fwd(Consts k, RefitBufs b)
         }
       }
       chi2 += kupdate(st, ys[u], zs[u], vy, vz);
-      store_ckpt(b.ckpt + h * 20, st);
+      const CkSlot sl = ck_slot(s_ck, h - a);
+      store_ckpt(ck + sl.idx, sl.stride, st);
       xprev = xs[u];
     }
   }

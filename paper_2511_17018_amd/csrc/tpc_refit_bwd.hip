@@ -23,6 +23,7 @@
 #include <mutex>
 
 #include "tpc_internal.h"
+#include "tpc_ckpt.h"
 
 namespace tpcca {
 namespace bwd {
@@ -425,10 +426,13 @@ __global__ __launch_bounds__(kBlock) void k_refit_bwd_zero(RefitBufs b)
 
 template <bool MAT>
 __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, int64_t t,
-                                          unsigned long long* acc, const BwdOut& o)
+                                          unsigned long long* acc, const BwdOut& o,
+                                          const CkTables& tab, int lmax)
 {
   const int64_t a = b.hit_off[t], e = b.hit_off[t + 1];
   if (e - a < 1 || b.status[t] != 0) return;
+  // the checkpoints of this wave's group of tracks start at its first hit
+  const float4* const ck = reinterpret_cast<const float4*>(b.ckpt) + ck_group_base(b.hit_off) * 5;
   // binary64 throughout: the checkpoints (binary32) are widened on load
   const R kB = -0.299792458e-2 * (R)k.bz, vy = k.vy, vz = k.vz, w = b.grad_chi2[t];
   R pb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -466,7 +470,13 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
   int32_t i3 = clu(e - 4);
   bool ovf = false;
   int j = 0;  // gradients buffered in o
-  for (int64_t h = e - 1; h >= a + 1; h--) {
+  // the wave's lanes step through the hit numbers together, from its
+  // longest track's last hit down, each lane from its own last hit on: at
+  // every step they read the checkpoints of one hit number, which sit
+  // together
+  for (int64_t jn = lmax - 1; jn >= 1; jn--) {
+    if (jn > e - 1 - a) continue;
+    const int64_t h = a + jn;
     const int32_t cp = cp1;
     const int cellp = cell1;
     const R X1 = (R)x1 + (R)dm1;
@@ -486,8 +496,10 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
     sec2 = b.sector[i3];
     i3 = clu(h - 4);
     // checkpoint h-1: state and covariance (lower triangle, row-major)
-    const float4* q4 = reinterpret_cast<const float4*>(b.ckpt + (h - 1) * 20);
-    const float4 v0 = q4[0], v1 = q4[1], v2 = q4[2], v3 = q4[3], v4 = q4[4];
+    const CkSlot sl = ck_slot(tab, h - 1 - a);
+    const float4* q4 = ck + sl.idx;
+    const int64_t d4 = sl.stride;
+    const float4 v0 = q4[0], v1 = q4[d4], v2 = q4[2 * d4], v3 = q4[3 * d4], v4 = q4[4 * d4];
     const R p0[5] = {v0.x, v0.y, v0.z, v0.w, v1.x};
     const R C0[15] = {v1.y, v1.z, v1.w, v2.x, v2.y, v2.z, v2.w, v3.x,
                       v3.y, v3.z, v3.w, v4.x, v4.y, v4.z, v4.w};
@@ -627,15 +639,17 @@ __device__ __forceinline__ void bwd_track(const Consts& k, const RefitBufs& b, i
 // in LDS and added to the device accumulators once per cell.  MAT: field
 // map and material.
 template <bool MAT>
-__global__ __launch_bounds__(kBlock) void k_refit_bwd(Consts k, RefitBufs b)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_refit_bwd(Consts k, RefitBufs b)
 {
   __shared__ unsigned long long s_acc[kRows * kPhi];
   __shared__ float s_og[kBwdOut][3][kBlock];
   __shared__ int32_t s_oc[kBwdOut][kBlock];
+  __shared__ CkTables s_ck;
   for (int i = threadIdx.x; i < kRows * kPhi; i += kBlock) s_acc[i] = 0ull;
-  __syncthreads();
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < b.n_tracks) bwd_track<MAT>(k, b, t, s_acc, BwdOut{s_og, s_oc});
+  int lmax;
+  ck_build(s_ck, b.hit_off, b.n_tracks, t, lmax);  // ends with a barrier
+  if (t < b.n_tracks) bwd_track<MAT>(k, b, t, s_acc, BwdOut{s_og, s_oc}, s_ck, lmax);
   __syncthreads();
   for (int i = threadIdx.x; i < kRows * kPhi; i += kBlock) {
     const unsigned long long v = s_acc[i];

@@ -1,8 +1,6 @@
 """Host-side pieces of bench.py: the traffic figures are taken from the
 committed counter summary only while the kernel sources and launch
 parameters match."""
-import hashlib
-
 import bench
 
 
@@ -13,11 +11,24 @@ def _write(tmp_path, sha, launch="0.5,64", line="traffic_bytes neighbours: 1234"
 
 
 def _sources_sha():
-    h = hashlib.sha256()
-    for f in bench.KERNEL_SOURCES:
-        with open(f"{bench.ROOT}/{f}", "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    return bench.kernel_code_digest()
+
+
+def test_code_digest_ignores_comments_and_white_space(tmp_path, monkeypatch):
+    src = tmp_path / "k.hip"
+    py = tmp_path / "b.py"
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", ["k.hip", "b.py"])
+
+    def digest(hip, pyt):
+        src.write_text(hip)
+        py.write_text(pyt)
+        return bench.kernel_code_digest()
+    d0 = digest("int f(int a) { return a + 1; }\n", "X = 1\n")
+    assert digest("// a note\nint f(int a)\n{\n  return a + 1;  /* the next */\n}\n",
+                  "X = 1  # one\n") == d0
+    assert digest("int f(int a) { return a + 2; }\n", "X = 1\n") != d0
+    assert digest("int f(int a) { return a + 1; }\n", "X = 2\n") != d0
 
 
 def test_traffic_only_for_matching_sources_and_launch(tmp_path, monkeypatch):

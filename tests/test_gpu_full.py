@@ -110,7 +110,8 @@ def test_refit_config5_full_sampled_tracks():
     chi2, status, ckpt = tpc.refit(G, xyz, row, trk, m, det=True)
     gmap, gxyz = tpc.refit_backward(G, xyz, row, trk, m, ckpt, status, torch.from_numpy(w).cuda())
     torch.cuda.synchronize()
-    chi2, status, ckpt = chi2.cpu().numpy(), status.cpu().numpy(), ckpt.cpu().numpy()
+    chi2, status = chi2.cpu().numpy(), status.cpu().numpy()
+    ckpt = ckpt.cpu().numpy().reshape(-1)[tpc.checkpoint_index(ho)]  # hit order
     gx, gy, gz = gxyz.cpu().numpy()
     # sampled tracks, refitted by the oracle on their own
     sel = np.sort(rng.choice(nt, 2000, replace=False))

@@ -40,6 +40,12 @@ def _args(ev):
     return ev.extra["hit_off"], ev.extra["hit_clu"], ev.extra["seed_par"]
 
 
+def _hit_order(ckpt, hit_off):
+    """The GPU checkpoints in hit order (the library stores them by group
+    of 64 tracks and hit number, in parts of 16 bytes)."""
+    return ckpt.cpu().numpy().reshape(-1)[tpc.checkpoint_index(hit_off)]
+
+
 def _r27_elements(g, ref):
     g = np.asarray(g, np.float64).reshape(-1)
     ref = np.asarray(ref, np.float64).reshape(-1)
@@ -69,7 +75,7 @@ def test_refit_forward_bit_exact(n_found, smear):
         assert np.array_equal(status.cpu().numpy(), s_o)
         assert np.array_equal(chi2.cpu().numpy().view(np.int32), c_o.view(np.int32))
         ok = np.repeat(s_o == 0, np.diff(ho))
-        assert np.array_equal(ckpt.cpu().numpy()[ok].view(np.int32), k_o[ok].view(np.int32))
+        assert np.array_equal(_hit_order(ckpt, ho)[ok].view(np.int32), k_o[ok].view(np.int32))
 
 
 def test_refit_backward_matches_binary64_adjoint():
@@ -90,7 +96,7 @@ def test_refit_backward_matches_binary64_adjoint():
         c_o, s_o, k_o = oracle.refit(G, P, ev, ho, hc, seed, dmap, prec=32)
         ok = np.repeat(s_o == 0, np.diff(ho))
         assert np.array_equal(status.cpu().numpy(), s_o)
-        assert np.array_equal(ckpt.cpu().numpy()[ok].view(np.int32), k_o[ok].view(np.int32))
+        assert np.array_equal(_hit_order(ckpt, ho)[ok].view(np.int32), k_o[ok].view(np.int32))
         _, _, _, sx, sy, sz = oracle.refit_grad(G, P, ev, ho, hc, seed, dmap, w32,
                                                 ckpt=k_o, status=s_o)
         gx, gy, gz = gxyz.cpu().numpy()
@@ -189,7 +195,7 @@ def test_refit_rejects_tracks_with_invalid_hits_like_the_oracle():
     assert np.array_equal(status.cpu().numpy(), s_o)
     assert np.array_equal(chi2.cpu().numpy().view(np.int32), c_o.view(np.int32))
     ok = np.repeat(s_o == 0, np.diff(ho))
-    assert np.array_equal(ckpt.cpu().numpy()[ok].view(np.int32), k_o[ok].view(np.int32))
+    assert np.array_equal(_hit_order(ckpt, ho)[ok].view(np.int32), k_o[ok].view(np.int32))
     g = gxyz.cpu().numpy()
     for t in (3, 5, 7, 11):
         cl = hc[ho[t]:ho[t + 1]]
@@ -283,7 +289,7 @@ def test_material_refit_forward_bit_exact(kind):
     assert np.array_equal(status.cpu().numpy(), s_o)
     assert np.array_equal(chi2.cpu().numpy().view(np.int32), c_o.view(np.int32))
     ok = np.repeat(s_o == 0, np.diff(ho))
-    assert np.array_equal(ckpt.cpu().numpy()[ok].view(np.int32), k_o[ok].view(np.int32))
+    assert np.array_equal(_hit_order(ckpt, ho)[ok].view(np.int32), k_o[ok].view(np.int32))
     # the production build stays close to the binary64 fit of the same model
     c_p, s_p, _ = tpc.refit(G, xyz, row, trk, m, det=False, mat=gm)
     c_64, s_64, _ = oracle.refit(G, P, ev, ho, hc, seed, D, prec=64, mat=mat)
@@ -379,3 +385,43 @@ def test_material_neutral_maps_equal_plain_refit_on_gpu():
     # equal up to the last bits of the binary64 sums
     for u, v in zip(ga, gb):
         assert torch.allclose(u, v, rtol=1e-6, atol=1e-9 * float(u.abs().max()))
+
+
+def test_refit_checkpoints_of_tracks_longer_than_the_layout_table():
+    """Checkpoint layout beyond the per-wave table of 160 hit numbers: hit
+    lists that run along a track, back and out again (up to 454 hits, the
+    same clusters visited three times), in two groups of 64 tracks mixed with
+    ordinary ones -- forward bit-exact with the binary32 oracle after
+    decoding the layout, map gradient within R27 of the binary64 adjoint of
+    those checkpoints (the map sums every hit; cluster gradients are not
+    defined for a cluster hit more than once)."""
+    ev = synth.config5(n_found=150, rep=3)
+    ho0, hc0, seed = _args(ev)
+    lists = []
+    for t in range(len(ho0) - 1):
+        h = hc0[ho0[t]:ho0[t + 1]]
+        lists.append(np.concatenate([h, h[::-1][1:], h[1:]]) if t % 3 == 0 else h)
+    ho = np.concatenate([[0], np.cumsum([len(x) for x in lists])]).astype(np.int32)
+    hc = np.concatenate(lists).astype(np.int32)
+    assert np.diff(ho).max() > 160
+    ev2 = synth.Event(**{**ev.__dict__})
+    ev2.extra = dict(ev.extra, hit_off=ho, hit_clu=hc)
+    dmap = ev.extra["D_true"]
+    _say(f"[refit long tracks] tracks={len(ho) - 1} longest={np.diff(ho).max()}")
+    xyz, row, trk, m = _gpu(ev2, dmap)
+    chi2, status, ckpt = tpc.refit(G, xyz, row, trk, m, det=True)
+    w = torch.ones_like(chi2)
+    gmap, _ = tpc.refit_backward(G, xyz, row, trk, m, ckpt, status, w)
+    torch.cuda.synchronize()
+    c_o, s_o, k_o = oracle.refit(G, P, ev2, ho, hc, seed, dmap, prec=32)
+    long_ok = (np.diff(ho) > 160) & (s_o == 0)
+    assert long_ok.sum() >= 10
+    assert np.array_equal(status.cpu().numpy(), s_o)
+    assert np.array_equal(chi2.cpu().numpy().view(np.int32), c_o.view(np.int32))
+    ok = np.repeat(s_o == 0, np.diff(ho))
+    assert np.array_equal(_hit_order(ckpt, ho)[ok].view(np.int32), k_o[ok].view(np.int32))
+    _, _, smap, _, _, _ = oracle.refit_grad(G, P, ev2, ho, hc, seed, dmap, np.ones(len(ho) - 1),
+                                            ckpt=k_o, status=s_o)
+    nrm, _ = _r27(gmap.cpu().numpy(), smap)
+    _say(f"[refit long tracks] map gradient norm-wise {nrm:.2e}")
+    assert nrm <= 1e-6
