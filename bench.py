@@ -499,6 +499,43 @@ def run_transform(args, ev) -> dict:
     return res
 
 
+def run_config1(args, tp: dict) -> dict:
+    """Config 1 (one sector wedge, 50 tracks, about 7 k clusters): the
+    chain is bound by its launches' latency, not by work; graph-captured and
+    eager times per step."""
+    import torch
+
+    import paper_2511_17018_amd as tpc
+    import synth
+    from paper_2511_17018_amd.runtime import Chain, GraphChain
+
+    ev = synth.config1()
+    dev = "cuda:0"
+    stream = torch.cuda.Stream(dev)
+    batch = tpc.upload(ev.x, ev.y, ev.z, ev.row, ev.charge, ev.inst_off, dev)
+    ch = Chain(synth.geometry(), batch, True, stream, **tp)
+    graph = GraphChain([ch], stream)
+    steps = max(10, args.steps * 10)
+    out = {"unit": "clusters/s", "workload": "config 1: one sector wedge, 50 tracks",
+           "n_clusters": ev.n, "steps": steps}
+    for label, fn in (("graph", graph.replay), ("eager", ch.enqueue)):
+        with torch.cuda.stream(stream):
+            for _ in range(max(1, args.warmup)):
+                fn()
+        stream.synchronize()
+        t = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for _ in range(steps):
+                fn()
+        stream.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        log(f"config 1 tracking ({label}): {dt * 1e6:.1f} us/step")
+        out[label] = {"value": ev.n / dt, "ms_per_step": dt * 1e3}
+    res = ch.result()
+    out["n_tracks"] = int(res["n_tracks"])
+    return out
+
+
 def run_sectors(args, which: int, tp: dict) -> dict:
     """Configs 2 and 3 (36 TPC sectors: one central collision, or 128
     collisions of a time frame in one pass): the batched deterministic chain
@@ -689,7 +726,7 @@ def main():
     ap.add_argument("--no-refit", action="store_true")
     ap.add_argument("--no-transform", action="store_true")
     ap.add_argument("--no-sectors", action="store_true",
-                    help="skip the config 2 / config 3 lines (tracking + merging)")
+                    help="skip the config 1 / 2 / 3 lines (tracking; merging for 2 and 3)")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--fixed", default="",
                     help="OCC,CHUNK: use these launch parameters instead of tuning "
@@ -743,6 +780,7 @@ def main():
     del ev
     if not args.no_sectors:
         tp = {k: r["autotune"][k] for k in ("grid_occupancy", "tl_chunk")}
+        line["config1"] = run_config1(args, tp)
         line["config2"] = run_sectors(args, 2, tp)
         line["config3"] = run_sectors(args, 3, tp)
     if not args.no_refit:
