@@ -1188,45 +1188,54 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
   // phase 2 searches the rows (R15)
   bool up = mine;
   int phase = 1, miss = 0;
-  for (int r = rlo + 1; r < kRows; r++) {
+  // every lane writes its slot of each row the sweeps visit (the hit, -1 for
+  // a miss, -1 above or below where it stopped), so that each row's slots
+  // of the chunk are written together; the rows neither sweep reaches get
+  // -1 at the end
+  int r_up = rlo + 1;
+  for (; r_up < kRows; r_up++) {
+    const int r = r_up;
     if constexpr (CH == 64) {
       if (!__ballot(up)) break;  // one wave: a vote, no barrier
     } else {
       if (!__syncthreads_or(up)) break;
     }
     const tpc_row_meta m = b.meta[segb + r];
-    if (!(up && r > r0)) continue;
-    if (phase == 1 && hn < 0) {
-      // links exhausted at row r - 1: the phase-2 restart state is kept
-      phase = 2;
-      put_keep(st);
-    }
-    if (!kprop(st, k.row_x[r - 1], k.row_x[r], kB, smax)) {
-      up = false;
-    } else if (phase == 2 && !(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) {
-      up = false;
-    } else {
-      // one filter update for both phases: the link's hit (phase 1, no cut)
-      // or the row's best cluster (phase 2)
-      const Innov q = innov(st, vy, vz);
-      const int32_t bh = phase == 1 ? hn : ksearch<COUNT>(k, b, m, st, q, ncand);
-      if (bh >= 0) {
-        const float2 qb = b.yz[bh];
-        chi2 += kupdate_q(st, q, qb.x, qb.y);
-        H[(int64_t)r * cap] = bh;
-        n++;
-        rmax = r;
-        if (phase == 1) {
-          hn = b.up2[hn];
-        } else {
-          put_keep(st);
-          miss = 0;
-        }
+    // this row's slot: the hit, or -1 (a miss, or a lane that has stopped)
+    int32_t slot = -1;
+    if (up && r > r0) {
+      if (phase == 1 && hn < 0) {
+        // links exhausted at row r - 1: the phase-2 restart state is kept
+        phase = 2;
+        put_keep(st);
+      }
+      if (!kprop(st, k.row_x[r - 1], k.row_x[r], kB, smax)) {
+        up = false;
+      } else if (phase == 2 && !(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) {
+        up = false;
       } else {
-        H[(int64_t)r * cap] = -1;
-        if (++miss >= k.tc_max_miss) up = false;
+        // one filter update for both phases: the link's hit (phase 1, no cut)
+        // or the row's best cluster (phase 2)
+        const Innov q = innov(st, vy, vz);
+        const int32_t bh = phase == 1 ? hn : ksearch<COUNT>(k, b, m, st, q, ncand);
+        if (bh >= 0) {
+          const float2 qb = b.yz[bh];
+          chi2 += kupdate_q(st, q, qb.x, qb.y);
+          slot = bh;
+          n++;
+          rmax = r;
+          if (phase == 1) {
+            hn = b.up2[hn];
+          } else {
+            put_keep(st);
+            miss = 0;
+          }
+        } else if (++miss >= k.tc_max_miss) {
+          up = false;
+        }
       }
     }
+    if (mine && r > r0) H[(int64_t)r * cap] = slot;
   }
   // a lane that never left phase 1 restarts from its last linked row
   if (phase == 1) put_keep(st);
@@ -1245,34 +1254,38 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
   }
   bool dn = mine && stat == 0;
   miss = 0;
-  for (int r = rhi - 1; r >= 0; r--) {
+  int r_dn = rhi - 1;
+  for (; r_dn >= 0; r_dn--) {
+    const int r = r_dn;
     if constexpr (CH == 64) {
       if (!__ballot(dn)) break;  // one wave: a vote, no barrier
     } else {
       if (!__syncthreads_or(dn)) break;
     }
     const tpc_row_meta m = b.meta[segb + r];
-    if (!(dn && r < r0)) continue;
-    if (!kprop(st, k.row_x[r + 1], k.row_x[r], kB, smax)) {
-      dn = false;
-    } else if (!(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) {
-      dn = false;
-    } else {
-      const Innov q = innov(st, vy, vz);
-      const int32_t bh = ksearch<COUNT>(k, b, m, st, q, ncand);
-      if (bh >= 0) {
-        const float2 qb = b.yz[bh];
-        chi2 += kupdate_q(st, q, qb.x, qb.y);
-        H[(int64_t)r * cap] = bh;
-        n++;
-        rmin = r;
-        put_keep(st);
-        miss = 0;
+    int32_t slot = -1;
+    if (dn && r < r0) {
+      if (!kprop(st, k.row_x[r + 1], k.row_x[r], kB, smax)) {
+        dn = false;
+      } else if (!(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) {
+        dn = false;
       } else {
-        H[(int64_t)r * cap] = -1;
-        if (++miss >= k.tc_max_miss) dn = false;
+        const Innov q = innov(st, vy, vz);
+        const int32_t bh = ksearch<COUNT>(k, b, m, st, q, ncand);
+        if (bh >= 0) {
+          const float2 qb = b.yz[bh];
+          chi2 += kupdate_q(st, q, qb.x, qb.y);
+          slot = bh;
+          n++;
+          rmin = r;
+          put_keep(st);
+          miss = 0;
+        } else if (++miss >= k.tc_max_miss) {
+          dn = false;
+        }
       }
     }
+    if (mine && r < r0) H[(int64_t)r * cap] = slot;
   }
   if (mine) {
     if (stat == 0) {
@@ -1290,12 +1303,17 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
     b.tl_status[t] = stat;
     if constexpr (COUNT) b.tl_ncand[t] = ncand;
   }
-  // the sweeps wrote every row of [rmin, rmax] (a hit or -1); the other rows
-  // read -1 too, since the selection scans whole rows.  The rows go in the
-  // same order in every lane, so a wave's stores of one row are contiguous
-  // (lane-own row ranges scattered them over 64 cache lines).
-  for (int r = 0; r < kRows; r++)
-    if (mine && (r < rmin || r > rmax)) H[(int64_t)r * cap] = -1;
+  // the rows neither sweep visited (above where the upward sweep ended,
+  // below where the downward sweep ended) read -1 too, since the selection
+  // scans whole rows; the lanes write each of them together, so a wave's
+  // stores of one row are contiguous.  Every lane that took part in the
+  // downward sweep went below its start row before the sweep ended, but a
+  // lane that failed the way back (status 2) never did: its start row and
+  // the rows above stay as the upward sweep left them.
+  for (int r = r_up; r < kRows; r++)
+    if (mine) H[(int64_t)r * cap] = -1;
+  for (int r = 0; r <= r_dn; r++)
+    if (mine && r < r0) H[(int64_t)r * cap] = -1;
   if (mine) {
     // selection key, 0 for a rejected tracklet (it never owns a hit)
     const int64_t lid = (int64_t)b.perm[b.start[t]] - b.inst_off[inst];

@@ -114,6 +114,9 @@ def compare_det(g: dict, o: oracle.ChainResult) -> list:
     rows = np.arange(NR)[None, :]
     m = (rows >= tl.rmin[:, None]) & (rows <= tl.rmax[:, None])
     _eq("tl_hit", np.where(m, g["tl_hit"], -7), np.where(m, tl.hit, -7), e)
+    # outside [rmin, rmax] every slot reads -1 (the selection scans whole rows)
+    _eq("tl_hit outside the row range", np.where(m, -1, g["tl_hit"]),
+        np.full(g["tl_hit"].shape, -1, g["tl_hit"].dtype), e)
     T = o.tracks
     if int(res["need_tracks"]) != T.need_tracks or int(res["need_hits"]) != T.need_hits:
         e.append(f"need {res['need_tracks']},{res['need_hits']} vs {T.need_tracks},{T.need_hits}")
