@@ -998,11 +998,11 @@ constexpr int kSrchZ = 4, kSrchC = 4;
 // R15: best grid position of row segment m for the predicted state, or -1.
 // The pick is a total order -- smallest chi2, then smallest input index --
 // so the scan order does not matter; the input index is read only on an
-// exact tie.
+// exact tie.  bq receives the picked position (left alone if none).
 template <bool COUNT>
 __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b,
                                            const tpc_row_meta& m, const KSt& st,
-                                           const Innov& q, int& ncand)
+                                           const Innov& q, int& ncand, float2& bq)
 {
   const int32_t* const off = b.bin_off + m.bin_base;  // the segment's bin boundaries
   const float2* const yz = b.yz;
@@ -1050,8 +1050,10 @@ __device__ __forceinline__ int32_t ksearch(const Consts& k, const TrackBufs& b,
           if (best < 0 || ch < bchi) {
             best = p;
             bchi = ch;
+            bq = qv[c];
           } else if (ch == bchi && b.perm[p] < b.perm[best]) {
             best = p;
+            bq = qv[c];
           }
         }
       }
@@ -1078,9 +1080,8 @@ __device__ __forceinline__ unsigned long long sel_key(int nhit, float chi2, int6
 // 2), each lane walks its state back to its start row (phase 3, no data),
 // and the workgroup sweeps downward from the highest start row.  The lanes
 // of a sweep search the same row at the same time, so the row's bin
-// boundaries and cluster positions are read from the cache; the kernel is
-// bound by instruction issue, and staging each row in LDS first cost more
-// instructions than it saved.  Hit slots are [row][tracklet], so the lanes'
+// boundaries and cluster positions are read from the cache (staging each
+// row in LDS first cost more instructions than it saved).  Hit slots are [row][tracklet], so the lanes'
 // writes of one row are contiguous.
 //
 // Chunks of one instance are consecutive; workgroup w runs on XCD w % 8
@@ -1116,8 +1117,16 @@ __global__ __launch_bounds__(kBlock) void k_tl_chunks(TrackBufs b, int ch)
   }
 }
 
+// The 64-lane kernel asks for six waves per SIMD (at most 80 VGPRs): with
+// the compiler's own choice of 81 registers it ran at five and took 5 %
+// longer.  The wider chunks and the counting build keep the compiler's
+// choice (held to 80 registers they spill).
+template <int CH, bool COUNT>
+constexpr int tl_min_waves() { return CH == 64 && !COUNT ? 6 : 1; }
+
 template <int CH, bool SPEC, bool COUNT>
-__global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
+__global__ __launch_bounds__(CH) __attribute__((amdgpu_waves_per_eu(tl_min_waves<CH, COUNT>())))
+void k_tracklets(Consts karg, TrackBufs b)
 {
   const Consts& k = kconsts<SPEC>(karg);
   __shared__ int s_inst;
@@ -1209,6 +1218,14 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
         phase = 2;
         put_keep(st);
       }
+      // phase 1: the link's position and its next link are loaded before
+      // the propagation, phase 2 takes the position from the search
+      float2 qb = make_float2(0.0f, 0.0f);
+      int32_t hnext = -1;
+      if (phase == 1) {
+        qb = b.yz[hn];
+        hnext = b.up2[hn];
+      }
       if (!kprop(st, k.row_x[r - 1], k.row_x[r], kB, smax)) {
         up = false;
       } else if (phase == 2 && !(fabsf(st.p[0]) <= k.row_x[r] * tanh_ + edge)) {
@@ -1217,15 +1234,14 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
         // one filter update for both phases: the link's hit (phase 1, no cut)
         // or the row's best cluster (phase 2)
         const Innov q = innov(st, vy, vz);
-        const int32_t bh = phase == 1 ? hn : ksearch<COUNT>(k, b, m, st, q, ncand);
+        const int32_t bh = phase == 1 ? hn : ksearch<COUNT>(k, b, m, st, q, ncand, qb);
         if (bh >= 0) {
-          const float2 qb = b.yz[bh];
           chi2 += kupdate_q(st, q, qb.x, qb.y);
           slot = bh;
           n++;
           rmax = r;
           if (phase == 1) {
-            hn = b.up2[hn];
+            hn = hnext;
           } else {
             put_keep(st);
             miss = 0;
@@ -1271,9 +1287,9 @@ __global__ __launch_bounds__(CH) void k_tracklets(Consts karg, TrackBufs b)
         dn = false;
       } else {
         const Innov q = innov(st, vy, vz);
-        const int32_t bh = ksearch<COUNT>(k, b, m, st, q, ncand);
+        float2 qb = make_float2(0.0f, 0.0f);
+        const int32_t bh = ksearch<COUNT>(k, b, m, st, q, ncand, qb);
         if (bh >= 0) {
-          const float2 qb = b.yz[bh];
           chi2 += kupdate_q(st, q, qb.x, qb.y);
           slot = bh;
           n++;
