@@ -548,7 +548,7 @@ void tpc_default_merge_params(tpc_merge_params* m)
 namespace {
 struct MergeWs {
   int64_t n_seg, seg_inst, seg_pos, out_ok, out_p, out_c, out_x, seg_key, bkt_cur, bkt_off,
-      bkt_order, succ, pred, succ_chi2, pred_chi2, has_pred, chain_head, it_ns, it_nh, ch_part,
+      bkt_order, bkt_pos, bkt_tq, succ, pred, succ_chi2, pred_chi2, has_pred, chain_head, it_ns, it_nh, ch_part,
       total;
 };
 
@@ -567,6 +567,8 @@ MergeWs merge_ws(int64_t cap)
   w.bkt_cur = c.take(4 * 2 * kMergeBuckets);
   w.bkt_off = c.take(4 * 2 * (kMergeBuckets + 1));
   w.bkt_order = c.take(4 * 2 * cap);
+  w.bkt_pos = c.take(16 * 2 * cap);
+  w.bkt_tq = c.take(16 * 2 * cap);
   w.succ = c.take(4 * cap);
   w.pred = c.take(4 * cap);
   w.succ_chi2 = c.take(4 * cap);
@@ -633,6 +635,8 @@ tpc_status tpc_merge_tracks(const tpc_geometry* geom, const tpc_params* params,
   b.bkt_cur = at<int32_t>(ws_dev, w.bkt_cur);
   b.bkt_off = at<int32_t>(ws_dev, w.bkt_off);
   b.bkt_order = at<int32_t>(ws_dev, w.bkt_order);
+  b.bkt_pos = at<float4>(ws_dev, w.bkt_pos);
+  b.bkt_tq = at<float4>(ws_dev, w.bkt_tq);
   b.succ = at<int32_t>(ws_dev, w.succ);
   b.pred = at<int32_t>(ws_dev, w.pred);
   b.succ_chi2 = at<float>(ws_dev, w.succ_chi2);

@@ -177,6 +177,9 @@ struct MergeBufs {
   int32_t* bkt_cur;          // [2][kMergeBuckets] counts, then scatter cursors
   int32_t* bkt_off;          // [2][kMergeBuckets + 1] first position of each bucket
   int32_t* bkt_order;        // [2][cap] segments in bucket order
+  float4* bkt_pos;           // [2][cap] their end of key w: x, y, z, outer state valid (1/0)
+  float4* bkt_tq;            // [2][cap] tgl, q/pt and their variances: key 0 of the inner
+                             // (tracker's) state, key 1 of the outer state
   int32_t *succ, *pred;      // [cap] best successor / predecessor
   float *succ_chi2, *pred_chi2;
   int32_t* has_pred;         // [cap] a kept link ends here

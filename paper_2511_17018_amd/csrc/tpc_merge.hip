@@ -366,46 +366,63 @@ __global__ __launch_bounds__(kBlock) void k_bkt_scatter(MergeBufs b)
   const int64_t n = *b.n_seg;
   const int64_t t = gid();
   if (t >= n) return;
+  const float ok = b.out_ok[t] ? 1.0f : 0.0f;
 #pragma unroll
   for (int w = 0; w < 2; w++) {
     const int p = atomicAdd(&b.bkt_cur[w * kMergeBuckets + b.seg_key[w * b.cap_seg + t]], 1);
     b.bkt_order[w * b.cap_seg + p] = (int32_t)t;
+    // what the pair search's cuts read, in bucket order next to the index:
+    // the end (first hit for key 0, last hit for key 1) and the tgl and q/pt
+    // terms of the state the pair compares there (the tracker's inner state
+    // for key 0, the outer state for key 1)
+    b.bkt_pos[w * b.cap_seg + p] = make_float4(b.seg_pos[t * 6 + 3 * w], b.seg_pos[t * 6 + 3 * w + 1],
+                                               b.seg_pos[t * 6 + 3 * w + 2], ok);
+    b.bkt_tq[w * b.cap_seg + p] =
+        w == 0 ? make_float4(b.seg.param[t * 5 + 3], b.seg.param[t * 5 + 4], b.seg.cov[t * 15 + 9],
+                             b.seg.cov[t * 15 + 14])
+               : make_float4(b.out_p[t * 5 + 3], b.out_p[t * 5 + 4], b.out_c[t * 15 + 9],
+                             b.out_c[t * 15 + 14]);
   }
 }
 
 // --------------------------------------------------------------- pairs
-// R37: chi2 of A's outer state against B's inner state, -1 if no candidate
-__device__ __forceinline__ float mpair(const Consts& k, const MergeBufs& b, int64_t A, int64_t B)
+// R37's position cuts: A's last hit (pa) against B's first hit (pb)
+__device__ __forceinline__ bool mpair_near(const MergeBufs& b, float4 pa, float4 pb)
+{
+  const float d0 = pa.x - pb.x;
+  const float d1 = pa.y - pb.y;
+  if (!(fabsf(pa.z - pb.z) <= b.mp.max_dz)) return false;
+  return d0 * d0 + d1 * d1 <= b.mp.max_dist * b.mp.max_dist;
+}
+
+// A's tgl and q/pt, and their variances, leave the rotation and the
+// propagation unchanged (copies, no arithmetic), so two terms of the pair's
+// chi2 are known before the transport (ta: A's outer, tb: B's inner tgl,
+// q/pt, var tgl, var q/pt): for the SPD sum S of the covariances,
+// d^T S^-1 d >= d_i^2 / S_ii for every component i.  A pair whose larger
+// such bound exceeds one and a half times the cut cannot pass it: the
+// binary32 LDL^T solve errs by far less than a third (a Cholesky-type solve
+// is accurate relative to the diagonal scaling, with an error set by the
+// correlations, about 1e-4 at worst here), so skipping the transport leaves
+// every decision as it is.
+__device__ __forceinline__ bool mpair_bound(const MergeBufs& b, float4 ta, float4 tb)
+{
+  const float d3 = ta.x - tb.x;
+  const float d4 = ta.y - tb.y;
+  const float s33 = ta.z + tb.z;
+  const float s44 = ta.w + tb.w;
+  const float cut = 1.5f * b.mp.chi2_max;
+  return !((s33 > 0.0f && (d3 * d3) / s33 > cut) || (s44 > 0.0f && (d4 * d4) / s44 > cut));
+}
+
+// R37: chi2 of A's outer state against B's inner state, -1 if no candidate.
+// The caller has found A's outer state valid, B in one of the three
+// instances A pairs with (nb: sector of B minus sector of A, modulo 18),
+// the two ends within the position cuts and the pair within the bound.
+__device__ __forceinline__ float mpair_fit(const Consts& k, const MergeBufs& b, int64_t A,
+                                           int64_t B, int nb)
 {
   const float kB = k.kB;
-  if (!b.out_ok[A]) return -1.0f;
-  const int ia = b.seg_inst[A], ib = b.seg_inst[B];
-  const int ka = ia % kPhi, kb = ib % kPhi;
-  const int nb = (kb - ka + kPhi) % kPhi;
-  const bool same_side = ia / kPhi == ib / kPhi;
-  if (!((same_side && (nb == 1 || nb == kPhi - 1)) || (!same_side && nb == 0))) return -1.0f;
-  const float d0 = b.seg_pos[A * 6 + 3] - b.seg_pos[B * 6 + 0];
-  const float d1 = b.seg_pos[A * 6 + 4] - b.seg_pos[B * 6 + 1];
-  if (!(fabsf(b.seg_pos[A * 6 + 5] - b.seg_pos[B * 6 + 2]) <= b.mp.max_dz)) return -1.0f;
-  if (!(d0 * d0 + d1 * d1 <= b.mp.max_dist * b.mp.max_dist)) return -1.0f;
-  // A's tgl and q/pt, and their variances, leave the rotation and the
-  // propagation unchanged (copies, no arithmetic), so two terms of the pair's
-  // chi2 are known before the transport: for the SPD sum S of the
-  // covariances, d^T S^-1 d >= d_i^2 / S_ii for every component i.  A pair
-  // whose larger such bound exceeds four times the cut cannot pass it: the
-  // binary32 LDL^T solve errs by far less than that factor (a Cholesky-type
-  // solve is accurate relative to the diagonal scaling, with an error set
-  // by the correlations, about 1e-4 at worst here), so skipping the
-  // transport leaves every decision as it is.
-  {
-    const float d3 = b.out_p[A * 5 + 3] - b.seg.param[B * 5 + 3];
-    const float d4 = b.out_p[A * 5 + 4] - b.seg.param[B * 5 + 4];
-    const float s33 = b.out_c[A * 15 + 9] + b.seg.cov[B * 15 + 9];
-    const float s44 = b.out_c[A * 15 + 14] + b.seg.cov[B * 15 + 14];
-    const float cut = 4.0f * b.mp.chi2_max;
-    if ((s33 > 0.0f && (d3 * d3) / s33 > cut) || (s44 > 0.0f && (d4 * d4) / s44 > cut))
-      return -1.0f;
-  }
   KSt s;
 #pragma unroll
   for (int j = 0; j < 5; j++) s.p[j] = b.out_p[A * 5 + j];
@@ -445,37 +462,83 @@ __device__ __forceinline__ int nbr_inst(int i, int which)
 // over the candidates of the three neighbouring instances in the z bins
 // within R37's z cut (plus a margin for rounding) of the lane's end; the
 // pick is the smallest (chi2, index)
+constexpr int kPairBlk = 4;  // candidates loaded at once
+
+// Four lanes per segment: lane w < 3 scans the candidates of neighbouring
+// instance w, and the group's picks are combined by the same order.
 template <bool PRED>
 __global__ __launch_bounds__(kBlock) void k_best(Consts k, MergeBufs b)
 {
   const int64_t n = *b.n_seg;
-  const int64_t q = gid();
-  if (q >= n) return;
-  // lanes in the bucket order of their own end
+  const int64_t q = gid() >> 2;
+  const int w = (int)(gid() & 3);
+  if (q >= n) return;  // whole groups of four
+  // groups in the bucket order of their own end
   const int own = PRED ? 0 : 1, oth = PRED ? 1 : 0;
   const int64_t me = b.bkt_order[own * b.cap_seg + q];
+  const float4 mine = b.bkt_pos[own * b.cap_seg + q];
+  const float4 mtq = b.bkt_tq[own * b.cap_seg + q];
   const int im = b.seg_inst[me];
-  const float zq = b.seg_pos[me * 6 + (PRED ? 2 : 5)];
   const float wz = b.mp.max_dz + 0.1f;
-  const int zlo = merge_zbin(zq - wz), zhi = merge_zbin(zq + wz);
+  const int zlo = merge_zbin(mine.z - wz), zhi = merge_zbin(mine.z + wz);
   const int32_t* const off = b.bkt_off + oth * (kMergeBuckets + 1);
   const int32_t* const ord = b.bkt_order + oth * b.cap_seg;
+  const float4* const pos = b.bkt_pos + oth * b.cap_seg;
+  const float4* const tqs = b.bkt_tq + oth * b.cap_seg;
   int32_t best = -1;
   float bchi = 0.0f;
-  for (int w = 0; w < 3; w++) {
-    // the instance's bins zlo..zhi are one contiguous range of positions
-    const int bb = nbr_inst(im, w) * kMergeZBins;
-    const int pe = off[bb + zhi + 1];
-    for (int p = off[bb + zlo]; p < pe; p++) {
-      const int32_t cand = ord[p];
-      const float c2 = PRED ? mpair(k, b, cand, me) : mpair(k, b, me, cand);
-      if (c2 < 0.0f) continue;
-      if (best < 0 || c2 < bchi || (c2 == bchi && cand < best)) {
-        best = cand;
-        bchi = c2;
+  // a successor needs the lane's own outer state
+  if (w < 3 && (PRED || mine.w != 0.0f)) {
+    // the instance's bins zlo..zhi are one contiguous range of positions;
+    // each candidate's end and tgl, q/pt terms are stored in bucket order
+    // too, so the cuts take blocks of kPairBlk candidates with contiguous
+    // loads, and only the candidates within them are fitted
+    const int ic = nbr_inst(im, w);
+    const int nb = ((ic % kPhi) - (im % kPhi) + kPhi) % kPhi;
+    const int bb = ic * kMergeZBins;
+    const int pa = off[bb + zlo], pe = off[bb + zhi + 1];
+    for (int p0 = pa; p0 < pe; p0 += kPairBlk) {
+      float4 pv[kPairBlk], tv[kPairBlk];
+#pragma unroll
+      for (int u = 0; u < kPairBlk; u++) {
+        const int p = p0 + u < pe ? p0 + u : pe - 1;
+        pv[u] = pos[p];
+        tv[u] = tqs[p];
+      }
+      unsigned pass = 0;
+#pragma unroll
+      for (int u = 0; u < kPairBlk; u++) {
+        // PRED: the candidate is A (its outer state must be valid), the lane B
+        const bool c = PRED ? pv[u].w != 0.0f && mpair_near(b, pv[u], mine) && mpair_bound(b, tv[u], mtq)
+                            : mpair_near(b, mine, pv[u]) && mpair_bound(b, mtq, tv[u]);
+        if (p0 + u < pe && c) pass |= 1u << u;
+      }
+      // the fit, one copy of its code, for the candidates within the cuts
+      while (pass) {
+        const int u = __builtin_ctz(pass);
+        pass &= pass - 1;
+        const int32_t cand = ord[p0 + u];
+        const float c2 = PRED ? mpair_fit(k, b, cand, me, (kPhi - nb) % kPhi)
+                              : mpair_fit(k, b, me, cand, nb);
+        if (c2 < 0.0f) continue;
+        if (best < 0 || c2 < bchi || (c2 == bchi && cand < best)) {
+          best = cand;
+          bchi = c2;
+        }
       }
     }
   }
+  // the smallest (chi2, index) of the group
+#pragma unroll
+  for (int o = 1; o < 4; o <<= 1) {
+    const int32_t ob = __shfl_xor(best, o, 64);
+    const float oc = __shfl_xor(bchi, o, 64);
+    if (ob >= 0 && (best < 0 || oc < bchi || (oc == bchi && ob < best))) {
+      best = ob;
+      bchi = oc;
+    }
+  }
+  if (w != 0) return;
   if (PRED) {
     b.pred[me] = best;
     b.pred_chi2[me] = bchi;
@@ -725,11 +788,12 @@ hipError_t merge_tracks(const Consts& k, const MergeBufs& b, hipStream_t s)
   k_bkt_scan<<<1, 1024, 0, s>>>(b);
   k_bkt_scatter<<<nb, kBlock, 0, s>>>(b);
   prof_end(s, slot);
+  const unsigned nb4 = (unsigned)((4 * b.cap_seg + kBlock - 1) / kBlock);
   slot = prof_begin(s, "merge_succ");
-  k_best<false><<<nb, kBlock, 0, s>>>(k, b);
+  k_best<false><<<nb4, kBlock, 0, s>>>(k, b);
   prof_end(s, slot);
   slot = prof_begin(s, "merge_pred");
-  k_best<true><<<nb, kBlock, 0, s>>>(k, b);
+  k_best<true><<<nb4, kBlock, 0, s>>>(k, b);
   prof_end(s, slot);
   slot = prof_begin(s, "merge_link");
   k_link<<<nb, kBlock, 0, s>>>(b);

@@ -113,6 +113,8 @@ static hipError_t refit_stub(const RefitBufs& b)
     in_ws(b.out_c, 60 * c, "out_c");                                                 \
     in_ws(b.bkt_off, 4 * 2 * (kMergeBuckets + 1), "bkt_off");                       \
     in_ws(b.bkt_order, 4 * 2 * c, "bkt_order");                                      \
+    in_ws(b.bkt_pos, 16 * 2 * c, "bkt_pos");                                         \
+    in_ws(b.bkt_tq, 16 * 2 * c, "bkt_tq");                                           \
     in_ws(b.chain_head, 4 * c, "chain_head");                                        \
     in_ws(b.ch_part, 8 * 3 * ((2 * c + 255) / 256), "ch_part");                      \
     stub::g_calls++;                                                                 \

@@ -5,7 +5,10 @@ helix (closed form: the same point and direction seen from the rotated
 axes, computed with trigonometric functions); up then down is the identity.
 P22 the rotated covariance equals J C J^T with J the finite-difference
 Jacobian of (rotate, then propagate to the nominal new plane).
-P23 the LDL^T chi2 equals d^T S^-1 d from a library solve.
+P23 the LDL^T chi2 equals d^T S^-1 d from a library solve; in binary32 it
+does not fall below the single-component bound d_i^2 / S_ii that the pair
+search uses to skip transports (by more than 1e-3, on strongly correlated
+covariances).
 P24 noise-free helices crossing sector edges: every segment link joins
 segments of one particle, and the merged refit stays on the helix (chi2
 ~ 0, parameters at the first hit equal the truth).
@@ -113,6 +116,31 @@ def test_ldl_chi2_equals_library_solve():
     S[0, 0] = -1.0
     assert oracle.chi2_5(np.array([S[i, j] for i in range(5) for j in range(i + 1)]),
                          np.ones(5)) < 0
+
+
+@pytest.mark.parametrize("floor", [1e-2, 1e-4, 1e-6])
+def test_ldl_chi2_in_binary32_keeps_the_single_component_bound(floor):
+    # The pair search skips the transport of a pair whose bound
+    # max(d_3^2 / S_33, d_4^2 / S_44) exceeds 1.5 times the cut, which is
+    # exact only if the binary32 LDL^T chi2 never falls below a third of
+    # d^T S^-1 d >= d_i^2 / S_ii.  Covariances of track-like scales, strongly
+    # correlated (the diagonal floor sets how nearly singular they are):
+    # the binary32 chi2 stays within 1e-3 of the bound or above it.
+    rng = np.random.default_rng(11)
+    scale = np.array([0.1, 0.15, 0.01, 0.01, 0.05])
+    worst = np.inf
+    for _ in range(4000):
+        a = rng.normal(0, 1, (5, 3)) * scale[:, None]
+        C = a @ a.T + np.diag(floor * scale ** 2)
+        c15 = np.array([C[i, j] for i in range(5) for j in range(i + 1)], np.float32)
+        d = (rng.normal(0, 1, 5) * scale * rng.uniform(0.1, 30)).astype(np.float32)
+        S = _full(c15.astype(np.float64))
+        exact = d.astype(np.float64) @ np.linalg.solve(S, d.astype(np.float64))
+        bound = max(float(np.float32(d[3] * d[3]) / c15[9]), float(np.float32(d[4] * d[4]) / c15[14]))
+        assert exact >= bound * (1 - 1e-5)
+        got = oracle.chi2_5(c15, d, prec=32)
+        worst = min(worst, got / bound)
+    assert worst >= 1 - 1e-3, worst
 
 
 def _segments(ev, tracks):
