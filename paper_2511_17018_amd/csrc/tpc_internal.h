@@ -170,7 +170,7 @@ struct MergeBufs {
   int32_t* seg_inst;         // [cap] instance of each segment
   float* seg_pos;            // [cap][6] global x, y, z of the first and the last hit
   int32_t* out_ok;           // [cap] outer state valid
-  float *out_p, *out_c, *out_x;  // [cap][5], [cap][15], [cap]
+  float *out_p, *out_c, *out_x;  // [cap][5], [cap][15], [cap] (x: also where a failed pass stopped)
   // pair-search buckets: two keys per segment, (instance, z bin) of its
   // first hit (key 0) and of its last hit (key 1)
   int32_t* seg_key;          // [2][cap] bucket of each segment

@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_info(Consts k, MergeBufs b)
   for (int j = 0; j < 5; j++) b.out_p[t * 5 + j] = ok ? s.p[j] : 0.0f;
 #pragma unroll
   for (int j = 0; j < 15; j++) b.out_c[t * 15 + j] = ok ? s.c[j] : 0.0f;
-  b.out_x[t] = ok ? x : 0.0f;
+  b.out_x[t] = x;  // the outer plane, or where the pass stopped
   b.seg_key[t] = bucket_of(inst, b.seg_pos[t * 6 + 2]);
   b.seg_key[b.cap_seg + t] = bucket_of(inst, b.seg_pos[t * 6 + 5]);
 }
@@ -697,21 +697,24 @@ __global__ __launch_bounds__(kBlock) void k_chain_write(MergeBufs b)
   }
 }
 
-// one lane per chain: its segment list and merged hit list
+// one wave per chain: its segment list (lane 0) and merged hit list, each
+// segment's hits copied by the wave's lanes together (coalesced)
 __global__ __launch_bounds__(kBlock) void k_chain_hits(MergeBufs b)
 {
-  const int64_t m = gid();
-  if (m >= b.out.counts[0]) return;
-  const int64_t t = b.chain_head[m];
+  const int64_t m = gid() >> 6;
+  const int lane = threadIdx.x & 63;
+  if (m >= b.out.counts[0]) return;  // whole waves
   const int64_t n = *b.n_seg;
   int64_t so = b.out.seg_off[m], ho = b.out.hit_off[m];
   const int64_t se = b.out.seg_off[m + 1];
-  int64_t u = t;
+  int64_t u = b.chain_head[m];
   // the segment count of the chain was fixed by k_chain_count
   while (so < se) {
-    b.out.seg[so++] = (int32_t)u;
-    for (int64_t h = b.seg.hit_off[u]; h < b.seg.hit_off[u + 1]; h++)
-      b.out.hit_clu[ho++] = b.seg.hit_clu[h];
+    if (lane == 0) b.out.seg[so] = (int32_t)u;
+    so++;
+    const int64_t a = b.seg.hit_off[u], e = b.seg.hit_off[u + 1];
+    for (int64_t h = a + lane; h < e; h += 64) b.out.hit_clu[ho + (h - a)] = b.seg.hit_clu[h];
+    ho += e - a;
     u = b.out.next[u];
     if (u < 0 || u >= n) break;
   }
@@ -731,14 +734,33 @@ __global__ __launch_bounds__(kBlock) void k_merge_refit(Consts k, MergeBufs b)
     return;
   }
   const int32_t* hits = b.out.hit_clu;
-  float p5[5];
-#pragma unroll
-  for (int j = 0; j < 5; j++) p5[j] = b.seg.param[t0 * 5 + j];
   KSt s;
-  mseed(k, s, b, hits[a], p5);
-  float x = k.row_x[b.row[hits[a]]], chi2 = 0.0f;
+  float x, chi2 = 0.0f;
   int kf = b.seg_inst[t0] % kPhi;
-  bool good = mpass(k, b, s_off, s, x, kf, hits, a + 1, e - a - 1, 1, chi2);
+  bool good;
+  const int64_t l0 = b.seg.hit_off[t0 + 1] - b.seg.hit_off[t0];
+  if (l0 > 0) {
+    // the merged hits start with the first segment's, so the outward pass
+    // through them is the outer-state pass of the pair search (same seed,
+    // hits and operations, no sector change within a segment): its state
+    // is taken over and the pass goes on from the second segment
+    good = b.out_ok[t0] != 0;
+    x = b.out_x[t0];
+    if (good) {
+#pragma unroll
+      for (int j = 0; j < 5; j++) s.p[j] = b.out_p[t0 * 5 + j];
+#pragma unroll
+      for (int j = 0; j < 15; j++) s.c[j] = b.out_c[t0 * 15 + j];
+      good = mpass(k, b, s_off, s, x, kf, hits, a + l0, e - a - l0, 1, chi2);
+    }
+  } else {
+    float p5[5];
+#pragma unroll
+    for (int j = 0; j < 5; j++) p5[j] = b.seg.param[t0 * 5 + j];
+    mseed(k, s, b, hits[a], p5);
+    x = k.row_x[b.row[hits[a]]];
+    good = mpass(k, b, s_off, s, x, kf, hits, a + 1, e - a - 1, 1, chi2);
+  }
   if (good) {
 #pragma unroll
     for (int j = 0; j < 15; j++) s.c[j] = s.c[j] * kInwardScale;
@@ -803,7 +825,7 @@ hipError_t merge_tracks(const Consts& k, const MergeBufs& b, hipStream_t s)
   k_chain_write<<<(unsigned)nblk, kBlock, 0, s>>>(b);
   prof_end(s, slot);
   slot = prof_begin(s, "merge_chain_hits");
-  k_chain_hits<<<nb, kBlock, 0, s>>>(b);
+  k_chain_hits<<<(unsigned)((64 * b.cap_seg + kBlock - 1) / kBlock), kBlock, 0, s>>>(b);
   prof_end(s, slot);
   slot = prof_begin(s, "merge_refit");
   k_merge_refit<<<nb, kBlock, 0, s>>>(k, b);
