@@ -494,27 +494,36 @@ __global__ __launch_bounds__(kBlock) void k_grid_part(GridBufs b)
 
 // Counting sort of one segment by bin (R10), one workgroup per segment: the
 // workgroup owns the segment's positions and bins, so its bin counters live
-// in LDS (or, for more than kSegBins bins, in the segment's own range of the
-// workspace counters) with no other writer.  Histogram, exclusive scan
+// in LDS (or, for more than kSegBinsBig bins, in the segment's own range of
+// the workspace counters) with no other writer.  Histogram, exclusive scan
 // (written as the bins' first positions, sentinel included), placement with
 // the scanned counters as cursors, and in the deterministic build the
 // ordering of each bin by input index -- an ordering kernel after atomic
 // placement (Sec. 2, run-time part), here inside the workgroup.
+//
+// Two instantiations split the segments by bin count: up to kSegBins bins
+// with 16 KB of LDS (ten workgroups per CU), more with 48 KB (the rows of
+// a whole time frame in one sector hold several thousand clusters).
 constexpr int kSegBins = 4096;
+constexpr int kSegBinsBig = 12288;
 constexpr int kSegBatch = 4;
 constexpr int kSortReg = 8;
 
+template <int NB>
 __global__ __launch_bounds__(kBlock) void k_grid_seg(GridBufs b)
 {
-  __shared__ int32_t s_c[kSegBins];
+  __shared__ int32_t s_c[NB];
   if (b.res->overflow & 1) return;
   const int64_t s = blockIdx.x;
   const int tx = threadIdx.x;
   const tpc_row_meta m = b.meta[s];
   const int nb = m.ny * m.nz;
+  // the small instantiation takes the segments whose bins fit its LDS, the
+  // big one all others
+  if ((nb + 1 <= kSegBins) != (NB == kSegBins)) return;
   const int cnt = b.seg_cnt[s];
   const int32_t P = b.seg_pos[s];
-  const bool lds = nb + 1 <= kSegBins;
+  const bool lds = nb + 1 <= NB;
   int32_t* const gc = b.fill + m.bin_base;
   for (int j = tx; j <= nb; j += kBlock) {
     if (lds) s_c[j] = 0;
@@ -1358,21 +1367,26 @@ __global__ __launch_bounds__(kBlock) void k_sel_prep(TrackBufs b)
 // tracklets with a hit on the row in LDS (coalesced reads of the [row]
 // [tracklet] hit slots and the keys), and after a barrier -- every claim on
 // the row is in -- writes per (row, tracklet) whether the tracklet owns its
-// hit there, and the row's owner keys.  A row of more than kSelRowPos
+// hit there, and the row's owner keys.  A row of more than kSelRowPosBig
 // positions is reduced with device atomics on the owner array instead (still
-// claimed only by this workgroup).
+// claimed only by this workgroup).  Two instantiations split the rows by
+// position count, as in the segment sort: up to kSelRowPos with 32 KB of
+// LDS, more with 64 KB.
 constexpr int kSelRowPos = 4096;
+constexpr int kSelRowPosBig = 8192;
 constexpr int kSelBatch = 8;
 
+template <int NP>
 __global__ __launch_bounds__(kBlock) void k_sel_rows(TrackBufs b)
 {
-  __shared__ unsigned long long s_own[kSelRowPos];
+  __shared__ unsigned long long s_own[NP];
   const int inst = blockIdx.x / kRows, r = blockIdx.x % kRows;
   const int64_t tf = b.tl_first[inst], tl = b.tl_first[inst + 1];
   if (tf == tl) return;
   const int32_t p0 = b.row_off[inst * (kRows + 1) + r];
   const int cnt = b.row_off[inst * (kRows + 1) + r + 1] - p0;
-  const bool lds = cnt <= kSelRowPos;
+  if ((cnt <= kSelRowPos) != (NP == kSelRowPos)) return;
+  const bool lds = cnt <= NP;
   const int32_t* H = b.tl_hit + (int64_t)r * b.cap;
   if (lds)
     for (int j = threadIdx.x; j < cnt; j += kBlock) s_own[j] = 0ull;
@@ -1602,7 +1616,8 @@ hipError_t grid_build(const Consts& k, const GridBufs& b, hipStream_t s)
   scan_exclusive<int32_t>(b.seg_pos, n_seg, nullptr, nullptr, b.scan_tmp, s);
   if (b.n > 0)
     TPC_LAUNCH("grid_part", xcd_grid(blocks_for(b.n, kPartItems)), kBlock, s, k_grid_part, b);
-  TPC_LAUNCH("grid_seg", (unsigned)n_seg, kBlock, s, k_grid_seg, b);
+  TPC_LAUNCH("grid_seg", (unsigned)n_seg, kBlock, s, k_grid_seg<kSegBins>, b);
+  TPC_LAUNCH("grid_seg_big", (unsigned)n_seg, kBlock, s, k_grid_seg<kSegBinsBig>, b);
   TPC_LAUNCH("grid_rowoff", blocks_for(n_seg), kBlock, s, k_grid_rowoff, b);
   return hipGetLastError();
 }
@@ -1640,7 +1655,10 @@ hipError_t sector_track_t(const Consts& k, const TrackBufs& b, hipStream_t s)
     else
       TPC_LAUNCH("tracklets", tl_blocks, 256, s, kt256, k, b);
     const unsigned tblocks = blocks_for(b.cap);
-    TPC_LAUNCH("sel_rows", (unsigned)((int64_t)b.n_inst * kRows), kBlock, s, k_sel_rows, b);
+    TPC_LAUNCH("sel_rows", (unsigned)((int64_t)b.n_inst * kRows), kBlock, s,
+               k_sel_rows<kSelRowPos>, b);
+    TPC_LAUNCH("sel_rows_big", (unsigned)((int64_t)b.n_inst * kRows), kBlock, s,
+               k_sel_rows<kSelRowPosBig>, b);
     TPC_LAUNCH("sel_count", tblocks, kBlock, s, k_sel_count<SPEC>, k, b, b.tl_own);
 #if TPC_DET
     scan_exclusive<int64_t>(b.tsv, b.cap, &b.counters[CNT_START], &b.counters[CNT_TRACKS],

@@ -98,19 +98,23 @@ def test_det_dense_z_band_bit_exact():
     _det_case(_arrays(y, z, row, [0, len(y)]))
 
 
-def test_det_selection_rows_beyond_lds_bit_exact():
-    # one wedge of 4000 tracks: 10 rows hold more than the 4096 positions the
-    # selection reduces in LDS, so they take the device-atomic path in the
-    # same launch as the others
-    _det_case(synth.config1(n_tracks=4000))
+@pytest.mark.parametrize("n_tracks", [4000, 9000])
+def test_det_selection_rows_beyond_lds_bit_exact(n_tracks):
+    # one wedge of 4000 tracks: 10 rows hold more than the 4096 positions of
+    # the small selection kernel and go to the one with 8192 in LDS; of 9000
+    # tracks: every row is beyond 4096 and 69 rows beyond 8192, reduced with
+    # device atomics
+    _det_case(synth.config1(n_tracks=n_tracks))
 
 
-def test_det_grid_segments_beyond_lds_bit_exact():
-    # grid occupancy 0.25 (four bins per cluster) on an 1100-track wedge: 74
-    # of the 152 rows have more bins (4095) than the segment sort holds in
-    # LDS and count in the workspace instead, in the same launch as the
-    # smaller rows; the oracle builds its grid at the same occupancy
-    _det_case(synth.config1(n_tracks=1100), grid_occupancy=0.25)
+@pytest.mark.parametrize("n_tracks", [1100, 3000])
+def test_det_grid_segments_beyond_lds_bit_exact(n_tracks):
+    # grid occupancy 0.25 (four bins per cluster): on an 1100-track wedge 74
+    # of the 152 rows have more bins (4095) than the small segment sort holds
+    # in LDS and go to the one with 12287; on a 3000-track wedge all rows do,
+    # and 17 have more than 12287 and count in the workspace instead; the
+    # oracle builds its grid at the same occupancy
+    _det_case(synth.config1(n_tracks=n_tracks), grid_occupancy=0.25)
 
 
 def test_det_many_tiny_instances_bit_exact():
