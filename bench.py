@@ -556,7 +556,9 @@ def run_sectors(args, which: int, tp: dict) -> dict:
     dev = "cuda:0"
     stream = torch.cuda.Stream(dev)
     batch = tpc.upload(ev.x, ev.y, ev.z, ev.row, ev.charge, ev.inst_off, dev)
-    ch = Chain(geom, batch, True, stream, **tp)
+    # the tracker also writes each hit's plane, position and sector, which
+    # the merging reads instead of gathering the clusters
+    ch = Chain(geom, batch, True, stream, hit_data=True, **tp)
     steps = max(1, args.steps if which == 2 else min(args.steps, 5))
     with torch.cuda.stream(stream):
         ch.enqueue()

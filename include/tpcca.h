@@ -139,7 +139,13 @@ typedef struct {
  * hit_clu[cap_hits], input indices, ascending row); clu2trk[n_clusters]
  * = track index or -1.  Deterministic mode emits tracks in tracklet order;
  * production mode in any order.  If capacity is short the longest prefix
- * that fits is written and tpc_result says what was needed. */
+ * that fits is written and tpc_result says what was needed.
+ * hit_data (optional, NULL to skip): per hit slot of hit_clu, four floats
+ * -- the x of the hit's row plane, its y and z, and the phi sector k of its
+ * instance (i mod 18, as a float) -- written by tpc_sector_track beside the
+ * hit list, 16-byte aligned.  tpc_merge_tracks reads its segments' hits
+ * from there when it is not NULL (contiguously instead of through the
+ * cluster arrays); the values are the same, so is the result. */
 typedef struct {
   float* param;    /* [cap_tracks][5]  */
   float* cov;      /* [cap_tracks][15] */
@@ -150,6 +156,7 @@ typedef struct {
   int32_t* hit_clu;
   int32_t* clu2trk;
   int64_t cap_tracks, cap_hits;
+  float* hit_data; /* [cap_hits][4] or NULL */
 } tpc_tracks;
 
 /* Device-resident status word, written by the calls.  overflow bits:
@@ -239,7 +246,8 @@ tpc_status tpc_grid_build(const tpc_geometry* geom, const tpc_params* params, in
  * default capacity (tpc_track_workspace_bytes); more start hits than the
  * capacity set overflow bit 2 and the tracklets beyond it are dropped.
  * Errors: TPC_ERR_INVALID (as tpc_grid_build; also null output arrays,
- * capacities >= 2^31), TPC_ERR_WORKSPACE, TPC_ERR_HIP. */
+ * capacities >= 2^31, hit_data not 16-byte aligned), TPC_ERR_WORKSPACE,
+ * TPC_ERR_HIP. */
 tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, int32_t n_inst,
                             const int64_t* inst_off_host, const int64_t* inst_off_dev,
                             tpc_clusters in, const tpc_grid* grid, const tpc_tracks* out,
@@ -460,7 +468,8 @@ tpc_status tpc_cluster_transform(const tpc_transform_geometry* tg, uint32_t flag
  * seg->cap_tracks and cap_hits bound them.  With TPC_FLAG_DETERMINISTIC the
  * outputs equal the binary32 CPU reference bit for bit.
  * Errors: TPC_ERR_INVALID (null pointers, n_inst != 36, capacities below
- * the segment arrays', unknown flags), TPC_ERR_WORKSPACE, TPC_ERR_HIP. */
+ * the segment arrays', unknown flags, seg->hit_data not 16-byte aligned),
+ * TPC_ERR_WORKSPACE, TPC_ERR_HIP. */
 typedef struct {
   float max_dz, max_dist, chi2_max;
   float cos_a[TPC_N_PHI], sin_a[TPC_N_PHI];  /* sector axis k at (k + 1/2) 20 deg */
@@ -493,7 +502,9 @@ typedef struct {
 } tpc_merged;
 
 void tpc_default_merge_params(tpc_merge_params* m);
-size_t tpc_merge_workspace_bytes(int64_t cap_segments);
+/* Workspace of tpc_merge_tracks for cap_segments = seg->cap_tracks and
+ * cap_hits = seg->cap_hits (0 if either is negative). */
+size_t tpc_merge_workspace_bytes(int64_t cap_segments, int64_t cap_hits);
 tpc_status tpc_merge_tracks(const tpc_geometry* geom, const tpc_params* params,
                             const tpc_merge_params* mp, int32_t n_inst,
                             const int64_t* inst_off_dev, tpc_clusters in,

@@ -82,7 +82,7 @@ class TracksStruct(C.Structure):
     _fields_ = [("param", C.c_void_p), ("cov", C.c_void_p), ("chi2", C.c_void_p),
                 ("ndf", C.c_void_p), ("x_ref", C.c_void_p), ("hit_off", C.c_void_p),
                 ("hit_clu", C.c_void_p), ("clu2trk", C.c_void_p), ("cap_tracks", C.c_int64),
-                ("cap_hits", C.c_int64)]
+                ("cap_hits", C.c_int64), ("hit_data", C.c_void_p)]
 
 
 class TrackWsLayout(C.Structure):
@@ -214,11 +214,15 @@ class Tracks:
     hit_off: torch.Tensor
     hit_clu: torch.Tensor
     clu2trk: torch.Tensor
+    # optional float32 [cap_hits, 4]: each hit's row plane x, y, z and phi
+    # sector (the merging reads its segments' hits from here when present)
+    hit_data: torch.Tensor | None = None
 
     def struct(self) -> TracksStruct:
         return TracksStruct(_ptr(self.param), _ptr(self.cov), _ptr(self.chi2), _ptr(self.ndf),
                             _ptr(self.x_ref), _ptr(self.hit_off), _ptr(self.hit_clu),
-                            _ptr(self.clu2trk), self.param.shape[0], self.hit_clu.numel())
+                            _ptr(self.clu2trk), self.param.shape[0], self.hit_clu.numel(),
+                            _ptr(self.hit_data))
 
 
 def alloc_grid(n_inst: int, n: int, device="cuda", params: Params | None = None) -> Grid:
@@ -231,14 +235,15 @@ def alloc_grid(n_inst: int, n: int, device="cuda", params: Params | None = None)
 
 
 def alloc_tracks(n: int, cap_tracks: int | None = None, cap_hits: int | None = None,
-                 device="cuda") -> Tracks:
+                 device="cuda", hit_data: bool = False) -> Tracks:
     ct = max(1, n // 10 + 16) if cap_tracks is None else cap_tracks
     ch = n if cap_hits is None else cap_hits
     f32 = dict(dtype=torch.float32, device=device)
     i32 = dict(dtype=torch.int32, device=device)
     return Tracks(torch.empty((ct, 5), **f32), torch.empty((ct, 15), **f32), torch.empty(ct, **f32),
                   torch.empty(ct, **i32), torch.empty(ct, **f32), torch.empty(ct + 1, **i32),
-                  torch.empty(ch, **i32), torch.empty(n, **i32))
+                  torch.empty(ch, **i32), torch.empty(n, **i32),
+                  torch.empty((ch, 4), **f32) if hit_data and ch > 0 else None)
 
 
 class Workspace:
@@ -301,13 +306,14 @@ class TrackRun:
 
 
 def track(geom: dict, batch: Batch, det: bool = True, cap_tracks=None, cap_hits=None,
-          cap_tracklets: int = 0, **param_over) -> TrackRun:
-    """Grid + sector tracking of a batch; synchronises and returns the result."""
+          cap_tracklets: int = 0, hit_data: bool = False, **param_over) -> TrackRun:
+    """Grid + sector tracking of a batch; synchronises and returns the result.
+    hit_data: also write each hit's plane, position and sector (for merging)."""
     g = make_geometry(geom)
     p = make_params(det, **param_over)
     dev = batch.x.device
     grid = alloc_grid(batch.n_inst, batch.n, dev, p)
-    tracks = alloc_tracks(batch.n, cap_tracks, cap_hits, dev)
+    tracks = alloc_tracks(batch.n, cap_tracks, cap_hits, dev, hit_data)
     ws = Workspace(batch.n_inst, batch.n, cap_tracklets, dev, p)
     grid_build(g, p, batch, grid, ws)
     sector_track(g, p, batch, grid, tracks, ws)
@@ -639,7 +645,9 @@ def alloc_merged(cap_tracks: int, cap_hits: int, device="cuda") -> Merged:
     f32 = dict(dtype=torch.float32, device=device)
     i32 = dict(dtype=torch.int32, device=device)
     ct = max(cap_tracks, 1)
-    wsb = int(lib().tpc_merge_workspace_bytes(C.c_int64(cap_tracks)))
+    L = lib()
+    L.tpc_merge_workspace_bytes.restype = C.c_size_t
+    wsb = int(L.tpc_merge_workspace_bytes(C.c_int64(cap_tracks), C.c_int64(cap_hits)))
     return Merged(torch.empty((ct, 5), **f32), torch.empty((ct, 15), **f32), torch.empty(ct, **f32),
                   torch.empty(ct, **i32), torch.empty(ct, **i32), torch.empty(ct, **i32),
                   torch.empty(ct, **f32), torch.empty(ct + 1, **i32),

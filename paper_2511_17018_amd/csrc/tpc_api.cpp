@@ -322,6 +322,7 @@ tpc_status tpc_sector_track(const tpc_geometry* geom, const tpc_params* params, 
   if (out->cap_tracks > 0 && (!out->param || !out->cov || !out->chi2 || !out->ndf || !out->x_ref))
     return TPC_ERR_INVALID;
   if (out->cap_hits > 0 && !out->hit_clu) return TPC_ERR_INVALID;
+  if (out->hit_data && reinterpret_cast<uintptr_t>(out->hit_data) % 16) return TPC_ERR_INVALID;
   if (out->cap_tracks >= ((int64_t)1 << 31) || out->cap_hits >= ((int64_t)1 << 31))
     return TPC_ERR_INVALID;
   const TrackWs w = track_ws(n_inst, n, cap_tracklets);
@@ -548,11 +549,11 @@ void tpc_default_merge_params(tpc_merge_params* m)
 namespace {
 struct MergeWs {
   int64_t n_seg, seg_inst, seg_pos, out_ok, out_p, out_c, out_x, seg_key, bkt_cur, bkt_off,
-      bkt_order, bkt_pos, bkt_tq, succ, pred, succ_chi2, pred_chi2, has_pred, chain_head, it_ns, it_nh, ch_part,
+      bkt_order, bkt_pos, bkt_tq, hit_md, succ, pred, succ_chi2, pred_chi2, has_pred, chain_head, it_ns, it_nh, ch_part,
       total;
 };
 
-MergeWs merge_ws(int64_t cap)
+MergeWs merge_ws(int64_t cap, int64_t cap_hits)
 {
   MergeWs w;
   Carve c;
@@ -569,6 +570,7 @@ MergeWs merge_ws(int64_t cap)
   w.bkt_order = c.take(4 * 2 * cap);
   w.bkt_pos = c.take(16 * 2 * cap);
   w.bkt_tq = c.take(16 * 2 * cap);
+  w.hit_md = c.take(16 * cap_hits);
   w.succ = c.take(4 * cap);
   w.pred = c.take(4 * cap);
   w.succ_chi2 = c.take(4 * cap);
@@ -583,10 +585,10 @@ MergeWs merge_ws(int64_t cap)
 }
 }  // namespace
 
-size_t tpc_merge_workspace_bytes(int64_t cap_segments)
+size_t tpc_merge_workspace_bytes(int64_t cap_segments, int64_t cap_hits)
 {
-  if (cap_segments < 0) return 0;
-  return (size_t)merge_ws(cap_segments).total;
+  if (cap_segments < 0 || cap_hits < 0) return 0;
+  return (size_t)merge_ws(cap_segments, cap_hits).total;
 }
 
 tpc_status tpc_merge_tracks(const tpc_geometry* geom, const tpc_params* params,
@@ -608,11 +610,12 @@ tpc_status tpc_merge_tracks(const tpc_geometry* geom, const tpc_params* params,
                   !in.y || !in.z || !in.row))
     return TPC_ERR_INVALID;
   if (out->cap_tracks < cap || out->cap_hits < seg->cap_hits) return TPC_ERR_INVALID;
+  if (seg->hit_data && reinterpret_cast<uintptr_t>(seg->hit_data) % 16) return TPC_ERR_INVALID;
   if (cap > 0 && (!out->param || !out->cov || !out->chi2 || !out->ndf || !out->status ||
                   !out->sector || !out->x_ref || !out->hit_off || !out->hit_clu ||
                   !out->seg_off || !out->seg || !out->next || !out->counts))
     return TPC_ERR_INVALID;
-  const MergeWs w = merge_ws(cap);
+  const MergeWs w = merge_ws(cap, seg->cap_hits);
   if ((int64_t)ws_bytes < w.total) return TPC_ERR_WORKSPACE;
   MergeBufs b;
   b.y = in.y;
@@ -637,6 +640,7 @@ tpc_status tpc_merge_tracks(const tpc_geometry* geom, const tpc_params* params,
   b.bkt_order = at<int32_t>(ws_dev, w.bkt_order);
   b.bkt_pos = at<float4>(ws_dev, w.bkt_pos);
   b.bkt_tq = at<float4>(ws_dev, w.bkt_tq);
+  b.hit_md = at<float4>(ws_dev, w.hit_md);
   b.succ = at<int32_t>(ws_dev, w.succ);
   b.pred = at<int32_t>(ws_dev, w.pred);
   b.succ_chi2 = at<float>(ws_dev, w.succ_chi2);

@@ -180,6 +180,7 @@ struct MergeBufs {
   float4* bkt_pos;           // [2][cap] their end of key w: x, y, z, outer state valid (1/0)
   float4* bkt_tq;            // [2][cap] tgl, q/pt and their variances: key 0 of the inner
                              // (tracker's) state, key 1 of the outer state
+  float4* hit_md;            // [seg.cap_hits] the tracker's hit data in merged order
   int32_t *succ, *pred;      // [cap] best successor / predecessor
   float *succ_chi2, *pred_chi2;
   int32_t* has_pred;         // [cap] a kept link ends here

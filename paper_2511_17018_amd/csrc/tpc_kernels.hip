@@ -1559,8 +1559,10 @@ __global__ __launch_bounds__(kBlock) void k_sel_write(Consts karg, TrackBufs b, 
 // position's owner (k_sel_rows) decides, and the hit's place in its track's
 // list is the number of the track's owned rows below the position's row, so
 // every list is in ascending row order whatever the thread order.
-__global__ __launch_bounds__(kBlock) void k_sel_hits(TrackBufs b)
+template <bool SPEC>
+__global__ __launch_bounds__(kBlock) void k_sel_hits(Consts karg, TrackBufs b)
 {
+  const Consts& k = kconsts<SPEC>(karg);
   // contiguous eighths per XCD: the scattered writes of one instance's
   // clusters and tracks meet in one L2
   const int64_t blk = xcd_block((b.n + kBlock - 1) / kBlock);
@@ -1584,6 +1586,12 @@ __global__ __launch_bounds__(kBlock) void k_sel_hits(TrackBufs b)
     if (j <= w) rank += __popc(m[j] & (j == w ? (1u << (r & 31)) - 1 : ~0u));
   b.out.hit_clu[(int64_t)r0.y + rank] = c;
   b.out.clu2trk[c] = r0.x;
+  if (b.out.hit_data) {
+    // the hit's plane, position and sector beside its slot (optional)
+    const float2 q = b.yz[p];
+    reinterpret_cast<float4*>(b.out.hit_data)[(int64_t)r0.y + rank] =
+        make_float4(k.row_x[r], q.x, q.y, (float)((seg / kRows) % kPhi));
+  }
 }
 
 __global__ void k_sel_finish(TrackBufs b)
@@ -1665,7 +1673,8 @@ hipError_t sector_track_t(const Consts& k, const TrackBufs& b, hipStream_t s)
                             b.scan_tmp, s);
 #endif
     TPC_LAUNCH("sel_write", tblocks, kBlock, s, k_sel_write<SPEC>, k, b, b.tl_own);
-    if (b.n > 0) TPC_LAUNCH("sel_hits", xcd_grid(blocks_for(b.n)), kBlock, s, k_sel_hits, b);
+    if (b.n > 0)
+      TPC_LAUNCH("sel_hits", xcd_grid(blocks_for(b.n)), kBlock, s, k_sel_hits<SPEC>, k, b);
   }
   TPC_LAUNCH("sel_finish", 1, 1, s, k_sel_finish, b);
   return hipGetLastError();

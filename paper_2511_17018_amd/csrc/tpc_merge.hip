@@ -156,38 +156,54 @@ __device__ __forceinline__ float mchi2(const float* S, const float* d)
   return chi2;
 }
 
-// R40: filter pass over hits[first + dir q], q < count, from state s at
-// plane x in frame k; chi2 accumulates.  The hits go in blocks of kMBlk:
-// the block's cluster indices, then their rows, positions and sectors, then
-// the row planes are loaded at once (three memory latencies per block
-// instead of three per hit).  The block's hits in the current frame are
+// R40: filter pass over the hits at first + dir q, q < count, from state s
+// at plane x in frame k; chi2 accumulates.  The hits go in blocks of kMBlk.
+// HD = false: hits[] holds cluster indices, and the block's indices, then
+// their rows, positions and sectors, then the row planes are loaded at once
+// (three memory latencies per block instead of three per hit); HD = true:
+// hd[] holds each hit's plane, position and sector (the tracker's hit data),
+// one contiguous load per hit.  The block's hits in the current frame are
 // filtered in an unrolled loop; the first hit of another sector ends it,
 // is transported (one copy of that code) and filtered, and the next block
 // starts after it.
 constexpr int kMBlk = 8;
 
+template <bool HD>
 __device__ __forceinline__ bool mpass(const Consts& k, const MergeBufs& b, const int64_t* s_off,
-                                   KSt& s, float& x, int& kf, const int32_t* hits, int64_t first,
-                                   int64_t count, int dir, float& chi2)
+                                   KSt& s, float& x, int& kf, const int32_t* hits,
+                                   const float4* hd, int64_t first, int64_t count, int dir,
+                                   float& chi2)
 {
   const float kB = k.kB, vy = k.vy, vz = k.vz;
   int64_t q = 0;
   while (q < count) {
-    int64_t c[kMBlk];
+    int kk[kMBlk];
+    float xh[kMBlk], yc[kMBlk], zc[kMBlk];
+    if constexpr (HD) {
 #pragma unroll
-    for (int u = 0; u < kMBlk; u++) c[u] = hits[first + dir * (q + u < count ? q + u : count - 1)];
-    int rw[kMBlk], kk[kMBlk];
-    float yc[kMBlk], zc[kMBlk];
+      for (int u = 0; u < kMBlk; u++) {
+        const float4 d = hd[first + dir * (q + u < count ? q + u : count - 1)];
+        xh[u] = d.x;
+        yc[u] = d.y;
+        zc[u] = d.z;
+        kk[u] = (int)d.w;
+      }
+    } else {
+      int64_t c[kMBlk];
 #pragma unroll
-    for (int u = 0; u < kMBlk; u++) {
-      rw[u] = b.row[c[u]];
-      yc[u] = b.y[c[u]];
-      zc[u] = b.z[c[u]];
-      kk[u] = inst_of(s_off, c[u]) % kPhi;
+      for (int u = 0; u < kMBlk; u++)
+        c[u] = hits[first + dir * (q + u < count ? q + u : count - 1)];
+      int rw[kMBlk];
+#pragma unroll
+      for (int u = 0; u < kMBlk; u++) {
+        rw[u] = b.row[c[u]];
+        yc[u] = b.y[c[u]];
+        zc[u] = b.z[c[u]];
+        kk[u] = inst_of(s_off, c[u]) % kPhi;
+      }
+#pragma unroll
+      for (int u = 0; u < kMBlk; u++) xh[u] = k.row_x[rw[u]];
     }
-    float xh[kMBlk];
-#pragma unroll
-    for (int u = 0; u < kMBlk; u++) xh[u] = k.row_x[rw[u]];
     int done = 0;
     bool rot = false;
 #pragma unroll
@@ -294,7 +310,10 @@ __global__ __launch_bounds__(kBlock) void k_seg_info(Consts k, MergeBufs b)
   mseed(k, s, b, c0, p5);
   float x = x0, chi2 = 0.0f;
   int kf = kk;
-  const bool ok = mpass(k, b, s_off, s, x, kf, b.seg.hit_clu, a + 1, e - a - 1, 1, chi2);
+  const float4* const hd = reinterpret_cast<const float4*>(b.seg.hit_data);
+  const bool ok = hd ? mpass<true>(k, b, s_off, s, x, kf, nullptr, hd, a + 1, e - a - 1, 1, chi2)
+                     : mpass<false>(k, b, s_off, s, x, kf, b.seg.hit_clu, nullptr, a + 1,
+                                    e - a - 1, 1, chi2);
   b.out_ok[t] = ok ? 1 : 0;
 #pragma unroll
   for (int j = 0; j < 5; j++) b.out_p[t * 5 + j] = ok ? s.p[j] : 0.0f;
@@ -697,8 +716,9 @@ __global__ __launch_bounds__(kBlock) void k_chain_write(MergeBufs b)
   }
 }
 
-// one wave per chain: its segment list (lane 0) and merged hit list, each
-// segment's hits copied by the wave's lanes together (coalesced)
+// one wave per chain: its segment list (lane 0) and merged hit list (and
+// hit data), each segment's hits copied by the wave's lanes together
+// (coalesced)
 __global__ __launch_bounds__(kBlock) void k_chain_hits(MergeBufs b)
 {
   const int64_t m = gid() >> 6;
@@ -708,12 +728,15 @@ __global__ __launch_bounds__(kBlock) void k_chain_hits(MergeBufs b)
   int64_t so = b.out.seg_off[m], ho = b.out.hit_off[m];
   const int64_t se = b.out.seg_off[m + 1];
   int64_t u = b.chain_head[m];
+  const float4* const hd = reinterpret_cast<const float4*>(b.seg.hit_data);
   // the segment count of the chain was fixed by k_chain_count
   while (so < se) {
     if (lane == 0) b.out.seg[so] = (int32_t)u;
     so++;
     const int64_t a = b.seg.hit_off[u], e = b.seg.hit_off[u + 1];
     for (int64_t h = a + lane; h < e; h += 64) b.out.hit_clu[ho + (h - a)] = b.seg.hit_clu[h];
+    if (hd)  // the tracker's hit data, in merged order for the global refit
+      for (int64_t h = a + lane; h < e; h += 64) b.hit_md[ho + (h - a)] = hd[h];
     ho += e - a;
     u = b.out.next[u];
     if (u < 0 || u >= n) break;
@@ -734,6 +757,9 @@ __global__ __launch_bounds__(kBlock) void k_merge_refit(Consts k, MergeBufs b)
     return;
   }
   const int32_t* hits = b.out.hit_clu;
+  // with the tracker's hit data the passes read the merged hits' data as
+  // the chain copy laid it out (contiguous, merged order)
+  const float4* const hd = reinterpret_cast<const float4*>(b.seg.hit_data);
   KSt s;
   float x, chi2 = 0.0f;
   int kf = b.seg_inst[t0] % kPhi;
@@ -751,7 +777,11 @@ __global__ __launch_bounds__(kBlock) void k_merge_refit(Consts k, MergeBufs b)
       for (int j = 0; j < 5; j++) s.p[j] = b.out_p[t0 * 5 + j];
 #pragma unroll
       for (int j = 0; j < 15; j++) s.c[j] = b.out_c[t0 * 15 + j];
-      good = mpass(k, b, s_off, s, x, kf, hits, a + l0, e - a - l0, 1, chi2);
+      if (hd) {
+        good = mpass<true>(k, b, s_off, s, x, kf, nullptr, b.hit_md, a + l0, e - a - l0, 1, chi2);
+      } else {
+        good = mpass<false>(k, b, s_off, s, x, kf, hits, nullptr, a + l0, e - a - l0, 1, chi2);
+      }
     }
   } else {
     float p5[5];
@@ -759,13 +789,17 @@ __global__ __launch_bounds__(kBlock) void k_merge_refit(Consts k, MergeBufs b)
     for (int j = 0; j < 5; j++) p5[j] = b.seg.param[t0 * 5 + j];
     mseed(k, s, b, hits[a], p5);
     x = k.row_x[b.row[hits[a]]];
-    good = mpass(k, b, s_off, s, x, kf, hits, a + 1, e - a - 1, 1, chi2);
+    good = mpass<false>(k, b, s_off, s, x, kf, hits, nullptr, a + 1, e - a - 1, 1, chi2);
   }
   if (good) {
 #pragma unroll
     for (int j = 0; j < 15; j++) s.c[j] = s.c[j] * kInwardScale;
     chi2 = 0.0f;
-    good = mpass(k, b, s_off, s, x, kf, hits, e - 1, e - a, -1, chi2);
+    if (hd) {
+      good = mpass<true>(k, b, s_off, s, x, kf, nullptr, b.hit_md, e - 1, e - a, -1, chi2);
+    } else {
+      good = mpass<false>(k, b, s_off, s, x, kf, hits, nullptr, e - 1, e - a, -1, chi2);
+    }
   }
   b.out.status[m] = good ? 0 : 1;
 #pragma unroll

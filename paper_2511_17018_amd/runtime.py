@@ -23,13 +23,13 @@ class Chain:
     """One grid build + sector tracking call with its own outputs."""
 
     def __init__(self, geom: dict, batch: Batch, det: bool = True, stream=None,
-                 cap_tracklets: int = 0, **param_over):
+                 cap_tracklets: int = 0, hit_data: bool = False, **param_over):
         dev = batch.x.device
         self.batch = batch
         self.geom = make_geometry(geom)
         self.params = make_params(det, **param_over)
         self.grid = alloc_grid(batch.n_inst, batch.n, dev, self.params)
-        self.tracks = alloc_tracks(batch.n, device=dev)
+        self.tracks = alloc_tracks(batch.n, device=dev, hit_data=hit_data)
         self.ws = Workspace(batch.n_inst, batch.n, cap_tracklets, dev, self.params)
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         sp = C.c_void_p(self.stream.cuda_stream)

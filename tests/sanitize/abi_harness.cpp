@@ -78,10 +78,20 @@ static void grid_and_track(int32_t n_inst, const std::vector<int64_t>& off, floa
                             &out, (tpc_result*)fake(0x4000), ws.data(), tws, cap_tl,
                             nullptr) == TPC_OK);
   }
+  // optional per-hit data: 16-byte aligned or rejected
+  out.hit_data = (float*)fake(0x6000);
+  EXPECT(tpc_sector_track(&g, &p, n_inst, off.data(), (const int64_t*)fake(0x3000), in, &grid,
+                          &out, (tpc_result*)fake(0x4000), ws.data(), tws, cap_tl,
+                          nullptr) == TPC_OK);
+  out.hit_data = (float*)fake(0x6008);
+  EXPECT(tpc_sector_track(&g, &p, n_inst, off.data(), (const int64_t*)fake(0x3000), in, &grid,
+                          &out, (tpc_result*)fake(0x4000), ws.data(), tws, cap_tl,
+                          nullptr) == TPC_ERR_INVALID);
+  out.hit_data = nullptr;
   EXPECT(tpc_sector_track(&g, &p, n_inst, off.data(), (const int64_t*)fake(0x3000), in, &grid,
                           &out, (tpc_result*)fake(0x4000), ws.data(), tws - 1, cap_tl,
                           nullptr) == TPC_ERR_WORKSPACE);
-  EXPECT(stub::g_calls == before + 3);
+  EXPECT(stub::g_calls == before + 4);
   tpc_track_ws_layout lay;
   EXPECT(tpc_track_workspace_layout(n_inst, n, cap_tl, &lay) == TPC_OK);
   EXPECT(lay.total == (int64_t)tws);
@@ -201,7 +211,8 @@ static void invalid_calls()
   mo.counts = (int64_t*)fake(0xD000);
   mo.cap_tracks = 500;
   mo.cap_hits = 20000;
-  std::vector<char> mws(tpc_merge_workspace_bytes(500));
+  std::vector<char> mws(tpc_merge_workspace_bytes(500, 20000));
+  EXPECT(tpc_merge_workspace_bytes(500, -1) == 0 && tpc_merge_workspace_bytes(-1, 20000) == 0);
   stub::g_ws = mws.data();
   stub::g_ws_bytes = mws.size();
   const int64_t* io = (const int64_t*)fake(0xE000);
@@ -212,6 +223,14 @@ static void invalid_calls()
                           nullptr) == TPC_ERR_INVALID);
   EXPECT(tpc_merge_tracks(&g, &p, &mp, 36, io, in, &seg, rs, &mo, mws.data(), mws.size() - 1,
                           nullptr) == TPC_ERR_WORKSPACE);
+  // optional per-hit data of the segments: 16-byte aligned or rejected
+  seg.hit_data = (float*)fake(0xF000);
+  EXPECT(tpc_merge_tracks(&g, &p, &mp, 36, io, in, &seg, rs, &mo, mws.data(), mws.size(),
+                          nullptr) == TPC_OK);
+  seg.hit_data = (float*)fake(0xF004);
+  EXPECT(tpc_merge_tracks(&g, &p, &mp, 36, io, in, &seg, rs, &mo, mws.data(), mws.size(),
+                          nullptr) == TPC_ERR_INVALID);
+  seg.hit_data = nullptr;
   mo.cap_hits = 19999;
   EXPECT(tpc_merge_tracks(&g, &p, &mp, 36, io, in, &seg, rs, &mo, mws.data(), mws.size(),
                           nullptr) == TPC_ERR_INVALID);

@@ -115,6 +115,7 @@ static hipError_t refit_stub(const RefitBufs& b)
     in_ws(b.bkt_order, 4 * 2 * c, "bkt_order");                                      \
     in_ws(b.bkt_pos, 16 * 2 * c, "bkt_pos");                                         \
     in_ws(b.bkt_tq, 16 * 2 * c, "bkt_tq");                                           \
+    in_ws(b.hit_md, 16 * b.seg.cap_hits, "hit_md");                                 \
     in_ws(b.chain_head, 4 * c, "chain_head");                                        \
     in_ws(b.ch_part, 8 * 3 * ((2 * c + 255) / 256), "ch_part");                      \
     stub::g_calls++;                                                                 \

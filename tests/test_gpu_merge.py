@@ -24,9 +24,22 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _run(ev, det=True):
+def _check_hit_data(run, ev):
+    # the tracker's optional per-hit output: the row plane, the cluster's y
+    # and z, and the instance's phi sector of every hit, bit for bit
+    nh = int(run.result["n_hits"])
+    hc = run.tracks.hit_clu[:nh].cpu().numpy()
+    hd = run.tracks.hit_data[:nh].cpu().numpy()
+    inst = np.searchsorted(ev.inst_off, hc, side="right") - 1
+    want = np.stack([G["row_x"][ev.row[hc]], ev.y[hc], ev.z[hc], (inst % 18).astype(np.float32)], 1)
+    assert np.array_equal(parity.bits(hd), parity.bits(want.astype(np.float32)))
+
+
+def _run(ev, det=True, hit_data=True):
     batch = tpc.upload(ev.x, ev.y, ev.z, ev.row, ev.charge, ev.inst_off, "cuda")
-    run = tpc.track(G, batch, det=det)
+    run = tpc.track(G, batch, det=det, hit_data=hit_data)
+    if hit_data:
+        _check_hit_data(run, ev)
     m = tpc.merge_tracks(G, batch, run.tracks, run.ws.result, det=det)
     torch.cuda.synchronize()
     return run, m.host()
@@ -54,11 +67,14 @@ def _compare(h, m):
         assert np.array_equal(parity.bits(a), parity.bits(b)), name
 
 
-@pytest.mark.parametrize("n_tracks", [300, 2500, 8000])
-def test_merge_bit_exact(n_tracks):
+@pytest.mark.parametrize("n_tracks,hit_data", [(300, True), (2500, True), (8000, True),
+                                               (8000, False)])
+def test_merge_bit_exact(n_tracks, hit_data):
+    # hit_data: the segments' hits read from the tracker's per-hit output
+    # (contiguous) or through the cluster arrays; the result is the same
     ev = synth.config2(n_tracks=n_tracks)
-    _say(f"[merge] config2 tracks={n_tracks} clusters={ev.n}")
-    run, h = _run(ev)
+    _say(f"[merge] config2 tracks={n_tracks} clusters={ev.n} hit_data={hit_data}")
+    run, h = _run(ev, hit_data=hit_data)
     S = _oracle_segments(run, ev)
     m = oracle.merge(G, ev.inst_off, ev.y, ev.z, ev.row, S)
     _say(f"[merge] segments={len(S.hit_off) - 1} merged={len(m.chi2)} "
