@@ -673,14 +673,18 @@ __global__ __launch_bounds__(kBlock) void k_chain_partials(MergeBufs b, int64_t 
   __shared__ int64_t s_carry[3];
   if (threadIdx.x < 3) s_carry[threadIdx.x] = 0;
   __syncthreads();
-  for (int64_t i0 = 0; i0 < nblk; i0 += kBlock) {
+  // the workgroups past the call's 2 n items hold zero sums and write
+  // nothing, so the scan stops at the last one that has items
+  const int64_t nact = (2 * *b.n_seg + kBlock - 1) / kBlock;
+  const int64_t nscan = nact < nblk ? nact : nblk;
+  for (int64_t i0 = 0; i0 < nscan; i0 += kBlock) {
     const int64_t i = i0 + threadIdx.x;
     int64_t v[3];
 #pragma unroll
-    for (int q = 0; q < 3; q++) v[q] = i < nblk ? b.ch_part[i * 3 + q] : 0;
+    for (int q = 0; q < 3; q++) v[q] = i < nscan ? b.ch_part[i * 3 + q] : 0;
     int64_t ex[3], tot[3];
     block_scan3(v, ex, tot);
-    if (i < nblk) {
+    if (i < nscan) {
 #pragma unroll
       for (int q = 0; q < 3; q++) b.ch_part[i * 3 + q] = s_carry[q] + ex[q];
     }
