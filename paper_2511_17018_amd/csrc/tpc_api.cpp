@@ -549,7 +549,7 @@ void tpc_default_merge_params(tpc_merge_params* m)
 namespace {
 struct MergeWs {
   int64_t n_seg, seg_inst, seg_pos, out_ok, out_p, out_c, out_x, seg_key, bkt_cur, bkt_off,
-      bkt_order, bkt_pos, bkt_tq, hit_md, succ, pred, succ_chi2, pred_chi2, has_pred, chain_head, it_ns, it_nh, ch_part,
+      bkt_order, bkt_pos, bkt_tq, hit_md, succ, pred_key, has_pred, chain_head, it_ns, it_nh, ch_part,
       total;
 };
 
@@ -572,9 +572,7 @@ MergeWs merge_ws(int64_t cap, int64_t cap_hits)
   w.bkt_tq = c.take(16 * 2 * cap);
   w.hit_md = c.take(16 * cap_hits);
   w.succ = c.take(4 * cap);
-  w.pred = c.take(4 * cap);
-  w.succ_chi2 = c.take(4 * cap);
-  w.pred_chi2 = c.take(4 * cap);
+  w.pred_key = c.take(8 * cap);
   w.has_pred = c.take(4 * cap);
   w.chain_head = c.take(4 * cap);
   w.it_ns = c.take(4 * 2 * cap);
@@ -642,9 +640,7 @@ tpc_status tpc_merge_tracks(const tpc_geometry* geom, const tpc_params* params,
   b.bkt_tq = at<float4>(ws_dev, w.bkt_tq);
   b.hit_md = at<float4>(ws_dev, w.hit_md);
   b.succ = at<int32_t>(ws_dev, w.succ);
-  b.pred = at<int32_t>(ws_dev, w.pred);
-  b.succ_chi2 = at<float>(ws_dev, w.succ_chi2);
-  b.pred_chi2 = at<float>(ws_dev, w.pred_chi2);
+  b.pred_key = at<unsigned long long>(ws_dev, w.pred_key);
   b.has_pred = at<int32_t>(ws_dev, w.has_pred);
   b.chain_head = at<int32_t>(ws_dev, w.chain_head);
   b.it_ns = at<int32_t>(ws_dev, w.it_ns);

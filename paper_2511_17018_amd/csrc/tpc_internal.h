@@ -181,8 +181,8 @@ struct MergeBufs {
   float4* bkt_tq;            // [2][cap] tgl, q/pt and their variances: key 0 of the inner
                              // (tracker's) state, key 1 of the outer state
   float4* hit_md;            // [seg.cap_hits] the tracker's hit data in merged order
-  int32_t *succ, *pred;      // [cap] best successor / predecessor
-  float *succ_chi2, *pred_chi2;
+  int32_t* succ;             // [cap] best successor
+  unsigned long long* pred_key;  // [cap] best predecessor: min of (chi2 bits << 32 | segment)
   int32_t* has_pred;         // [cap] a kept link ends here
   int32_t* chain_head;       // [cap] first segment of each chain
   int32_t *it_ns, *it_nh;    // [2 cap] chain-start items: segment and hit counts

@@ -11,18 +11,21 @@
 //   buckets      every segment filed twice, by (instance, z bin) of its
 //                first hit and of its last hit: counts, one-block offsets,
 //                scatter
-//   succ / pred  one lane per segment, lanes in bucket order (neighbouring
-//                lanes search neighbouring buckets): best successor and best
-//                predecessor among the segments of the three neighbouring
-//                instances whose other end lies in the z bins that R37's
-//                z cut can reach -- a superset of the pairs that pass it,
-//                with the pick a total order (chi2, index), so the result
-//                equals the search over all pairs
+//   pairs        three lanes per segment (one per neighbouring instance),
+//                groups in bucket order (neighbouring lanes search
+//                neighbouring buckets): best successor among the segments
+//                whose first hit lies in the z bins that R37's z cut can
+//                reach from the lane's last hit -- a superset of the pairs
+//                that pass it, with the pick a total order (chi2, index), so
+//                the result equals the search over all pairs; each passing
+//                pair also bids for its candidate's best predecessor by an
+//                atomic minimum of the same order
 //   link, chain  mutual links; chain heads compacted by scans in index order
 //                (link cycles after them, from their lowest segment); chain
 //                lengths and hit counts scanned into offsets (workgroup
 //                sums, one-workgroup scan of the sums, ordered write)
-//   chain_hits   one lane per chain: segment list and merged hit list
+//   chain_hits   one wave per chain: segment list, merged hit list (and the
+//                tracker's hit data in merged order)
 //   refit        one lane per chain: outward and inward filter with
 //                rotations between the sector frames
 #include "tpc_internal.h"
@@ -475,39 +478,39 @@ __device__ __forceinline__ int nbr_inst(int i, int which)
   return kk + kPhi * (1 - side);
 }
 
-// best successor (PRED = false: the lane's segment is A, its last hit
-// against the candidates' first hits) or best predecessor (PRED = true: the
-// lane's segment is B, its first hit against the candidates' last hits),
-// over the candidates of the three neighbouring instances in the z bins
-// within R37's z cut (plus a margin for rounding) of the lane's end; the
-// pick is the smallest (chi2, index)
+// The pair search (R37, R38), one pass over the pairs: each segment A's
+// best successor over the candidates B of the three neighbouring instances
+// in the z bins within R37's z cut (plus a margin for rounding) of A's last
+// hit, the pick being the smallest (chi2, index); every pair that passes
+// also offers A as B's predecessor through a 64-bit atomic minimum of
+// (chi2 bits, A), which is B's smallest (chi2, index) over the same pairs
+// (the neighbour relation and the cuts are symmetric) in any order.
 constexpr int kPairBlk = 4;  // candidates loaded at once
 
 // Four lanes per segment: lane w < 3 scans the candidates of neighbouring
 // instance w, and the group's picks are combined by the same order.
-template <bool PRED>
 __global__ __launch_bounds__(kBlock) void k_best(Consts k, MergeBufs b)
 {
   const int64_t n = *b.n_seg;
   const int64_t q = gid() >> 2;
   const int w = (int)(gid() & 3);
   if (q >= n) return;  // whole groups of four
-  // groups in the bucket order of their own end
-  const int own = PRED ? 0 : 1, oth = PRED ? 1 : 0;
-  const int64_t me = b.bkt_order[own * b.cap_seg + q];
-  const float4 mine = b.bkt_pos[own * b.cap_seg + q];
-  const float4 mtq = b.bkt_tq[own * b.cap_seg + q];
+  // groups in the bucket order of their own last hit (key 1), candidates
+  // by their first hit (key 0)
+  const int64_t me = b.bkt_order[b.cap_seg + q];
+  const float4 mine = b.bkt_pos[b.cap_seg + q];
+  const float4 mtq = b.bkt_tq[b.cap_seg + q];
   const int im = b.seg_inst[me];
   const float wz = b.mp.max_dz + 0.1f;
   const int zlo = merge_zbin(mine.z - wz), zhi = merge_zbin(mine.z + wz);
-  const int32_t* const off = b.bkt_off + oth * (kMergeBuckets + 1);
-  const int32_t* const ord = b.bkt_order + oth * b.cap_seg;
-  const float4* const pos = b.bkt_pos + oth * b.cap_seg;
-  const float4* const tqs = b.bkt_tq + oth * b.cap_seg;
+  const int32_t* const off = b.bkt_off;
+  const int32_t* const ord = b.bkt_order;
+  const float4* const pos = b.bkt_pos;
+  const float4* const tqs = b.bkt_tq;
   int32_t best = -1;
   float bchi = 0.0f;
-  // a successor needs the lane's own outer state
-  if (w < 3 && (PRED || mine.w != 0.0f)) {
+  // a segment without a valid outer state has no successor
+  if (w < 3 && mine.w != 0.0f) {
     // the instance's bins zlo..zhi are one contiguous range of positions;
     // each candidate's end and tgl, q/pt terms are stored in bucket order
     // too, so the cuts take blocks of kPairBlk candidates with contiguous
@@ -527,9 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_best(Consts k, MergeBufs b)
       unsigned pass = 0;
 #pragma unroll
       for (int u = 0; u < kPairBlk; u++) {
-        // PRED: the candidate is A (its outer state must be valid), the lane B
-        const bool c = PRED ? pv[u].w != 0.0f && mpair_near(b, pv[u], mine) && mpair_bound(b, tv[u], mtq)
-                            : mpair_near(b, mine, pv[u]) && mpair_bound(b, mtq, tv[u]);
+        const bool c = mpair_near(b, mine, pv[u]) && mpair_bound(b, mtq, tv[u]);
         if (p0 + u < pe && c) pass |= 1u << u;
       }
       // the fit, one copy of its code, for the candidates within the cuts
@@ -537,13 +538,16 @@ __global__ __launch_bounds__(kBlock) void k_best(Consts k, MergeBufs b)
         const int u = __builtin_ctz(pass);
         pass &= pass - 1;
         const int32_t cand = ord[p0 + u];
-        const float c2 = PRED ? mpair_fit(k, b, cand, me, (kPhi - nb) % kPhi)
-                              : mpair_fit(k, b, me, cand, nb);
+        const float c2 = mpair_fit(k, b, me, cand, nb);
         if (c2 < 0.0f) continue;
         if (best < 0 || c2 < bchi || (c2 == bchi && cand < best)) {
           best = cand;
           bchi = c2;
         }
+        // chi2 >= 0 here (-0 made +0), so its bits order like its value
+        const float cz = c2 + 0.0f;
+        atomicMin(&b.pred_key[cand],
+                  ((unsigned long long)__float_as_uint(cz) << 32) | (unsigned long long)(uint32_t)me);
       }
     }
   }
@@ -557,14 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_best(Consts k, MergeBufs b)
       bchi = oc;
     }
   }
-  if (w != 0) return;
-  if (PRED) {
-    b.pred[me] = best;
-    b.pred_chi2[me] = bchi;
-  } else {
-    b.succ[me] = best;
-    b.succ_chi2[me] = bchi;
-  }
+  if (w == 0) b.succ[me] = best;
 }
 
 // --------------------------------------------------------------- links, chains
@@ -574,7 +571,8 @@ __global__ __launch_bounds__(kBlock) void k_link(MergeBufs b)
   const int64_t a = gid();
   if (a >= n) return;
   const int32_t s = b.succ[a];
-  const bool keep = s >= 0 && b.pred[s] == a;
+  // the predecessor of s is the segment in the low half of its key
+  const bool keep = s >= 0 && b.pred_key[s] != ~0ull && (uint32_t)b.pred_key[s] == (uint32_t)a;
   b.out.next[a] = keep ? s : -1;
   if (keep) b.has_pred[s] = 1;
 }
@@ -824,7 +822,10 @@ __global__ void k_merge_init(MergeBufs b)
 
 __global__ __launch_bounds__(kBlock) void k_merge_clear(MergeBufs b)
 {
-  for (int64_t i = gid(); i < b.cap_seg; i += (int64_t)gridDim.x * blockDim.x) b.has_pred[i] = 0;
+  for (int64_t i = gid(); i < b.cap_seg; i += (int64_t)gridDim.x * blockDim.x) {
+    b.has_pred[i] = 0;
+    b.pred_key[i] = ~0ull;  // no predecessor
+  }
 }
 
 }  // namespace
@@ -849,11 +850,8 @@ hipError_t merge_tracks(const Consts& k, const MergeBufs& b, hipStream_t s)
   k_bkt_scatter<<<nb, kBlock, 0, s>>>(b);
   prof_end(s, slot);
   const unsigned nb4 = (unsigned)((4 * b.cap_seg + kBlock - 1) / kBlock);
-  slot = prof_begin(s, "merge_succ");
-  k_best<false><<<nb4, kBlock, 0, s>>>(k, b);
-  prof_end(s, slot);
-  slot = prof_begin(s, "merge_pred");
-  k_best<true><<<nb4, kBlock, 0, s>>>(k, b);
+  slot = prof_begin(s, "merge_pairs");
+  k_best<<<nb4, kBlock, 0, s>>>(k, b);
   prof_end(s, slot);
   slot = prof_begin(s, "merge_link");
   k_link<<<nb, kBlock, 0, s>>>(b);
