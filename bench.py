@@ -667,7 +667,7 @@ def host_info() -> dict:
     except (AttributeError, OSError):
         aff = os.cpu_count() or 1
     return {"nproc": os.cpu_count(), "affinity": aff, "cpu_model": model,
-            "share_note": "the GPU box grants one GPU's share of 16 host CPUs; the pools use "
+            "share_note": "a one-GPU share of the host is 16 CPUs; the pools use "
                           "min(16, affinity) threads"}
 
 
