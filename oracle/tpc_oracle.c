@@ -25,6 +25,9 @@
 #include "kalman.h"
 
 #define NROWS_MAX ORC_MAX_ROWS
+/* R16: rows per propagation step of the walk back to the start row (no
+ * updates on the way, so the steps may span several rows) */
+#define WALK_ROWS 8
 
 /* ------------------------------------------------------------------------ */
 /* derived constants (R3, R9, R11): computed once in binary64 from the inputs */
@@ -428,13 +431,15 @@ void SFX(orc_tracklets)(const orc_geom* g, const orc_params* P, int64_t S, const
         }
       }
     }
-    /* phase 3: back down to the start row without updates, then extend
-     * downward (R16); the output state is the one at the innermost hit */
+    /* phase 3: back down to the start row without updates, in steps of at
+     * most WALK_ROWS rows, then extend downward (R16); the output state is
+     * the one at the innermost hit */
     st = save;
     r = rmax;
     while (r > r0) {
-      if (!k_propagate(&st, X[r], X[r - 1], kB, smax)) { stat = 2; break; }
-      r--;
+      int rn = r - WALK_ROWS > r0 ? r - WALK_ROWS : r0;
+      if (!k_propagate(&st, X[r], X[rn], kB, smax)) { stat = 2; break; }
+      r = rn;
     }
     kst out = st;
     if (stat == 0) {
@@ -582,8 +587,11 @@ int SFX(orc_replay)(const orc_geom* g, const orc_params* P, int r0, int rmin, in
     if (!k_propagate(&st, X[r - 1], X[r], kB, smax)) return 0;
     if (has[r]) chi2 += k_update(&st, (real)hy[r], (real)hz[r], vy, vz);
   }
-  for (int r = rmax; r > r0; r--)
-    if (!k_propagate(&st, X[r], X[r - 1], kB, smax)) return 0;
+  for (int r = rmax; r > r0;) {
+    int rn = r - WALK_ROWS > r0 ? r - WALK_ROWS : r0;
+    if (!k_propagate(&st, X[r], X[rn], kB, smax)) return 0;
+    r = rn;
+  }
   kst out = st;
   for (int r = r0 - 1; r >= rmin; r--) {
     if (!k_propagate(&st, X[r + 1], X[r], kB, smax)) return 0;

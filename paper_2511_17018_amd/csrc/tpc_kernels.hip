@@ -1003,6 +1003,8 @@ __global__ void k_start_finish(TrackBufs b)
 #include "tpc_kalman.h"
 
 constexpr int kSrchZ = 4, kSrchC = 4;
+// R16: rows per propagation step of the walk back to the start row
+constexpr int kWalkRows = 8;
 
 // R15: best grid position of row segment m for the predicted state, or -1.
 // The pick is a total order -- smallest chi2, then smallest input index --
@@ -1265,15 +1267,18 @@ void k_tracklets(Consts karg, TrackBufs b)
   // a lane that never left phase 1 restarts from its last linked row
   if (phase == 1) put_keep(st);
 
-  // phase 3 (R16): back to the start row, then downward
+  // phase 3 (R16): back to the start row in steps of at most kWalkRows
+  // rows (no updates on the way), then downward
   int stat = 0;
   if (mine) {
     get_keep(st);
-    for (int r = rmax; r > r0; r--) {
-      if (!kprop(st, k.row_x[r], k.row_x[r - 1], kB, smax)) {
+    for (int r = rmax; r > r0;) {
+      const int rn = r - kWalkRows > r0 ? r - kWalkRows : r0;
+      if (!kprop(st, k.row_x[r], k.row_x[rn], kB, smax)) {
         stat = 2;
         break;
       }
+      r = rn;
     }
     put_keep(st);  // output state (innermost hit)
   }

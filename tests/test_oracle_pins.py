@@ -80,6 +80,36 @@ def test_propagation_matches_exact_helix(prec, tol):
         assert np.allclose(p, st, atol=tol)
 
 
+def test_walk_back_step_over_eight_rows_matches_helix_and_single_rows():
+    # R16 walks the state back to the start row in steps of up to 8 rows:
+    # one step over 8 rows lands on the exact helix (the arc-length series'
+    # truncation aside) and carries the covariance as the 8 single-row steps
+    # do, for curvatures down to pT = 0.1 GeV and |snp| up to the limit
+    rng = np.random.default_rng(31)
+    worst_pos = worst_cov = 0.0
+    n = 0
+    for st in _random_states(rng, 400, qmax=10.0, smax=0.97):
+        for r in (151, 100, 40, 9):
+            with np.errstate(invalid="ignore"):
+                y1, z1, s1 = helix.at(st, RX[r], RX[r - 8])
+            if not abs(s1) < 0.99:
+                continue
+            ok, p, c = oracle.propagate(G, P, st, _cov0(), RX[r], RX[r - 8], prec=64)
+            if not ok:
+                continue
+            n += 1
+            worst_pos = max(worst_pos, abs(p[0] - y1), abs(p[1] - z1))
+            assert abs(p[2] - s1) < 1e-9
+            q, cq = st.copy(), _cov0()
+            for k in range(8):
+                ok1, q, cq = oracle.propagate(G, P, q, cq, RX[r - k], RX[r - k - 1], prec=64)
+                assert ok1
+            assert np.allclose(p, q, rtol=0, atol=1e-3)
+            worst_cov = max(worst_cov, np.max(np.abs(c - cq)) / np.max(np.abs(cq)))
+    assert n > 1000
+    assert worst_pos < 1e-3 and worst_cov < 1e-3, (worst_pos, worst_cov)
+
+
 def test_propagation_straight_line_exact():
     st = np.array([1.0, 2.0, 0.3, 0.5, 0.0])
     ok, p, _ = oracle.propagate(G, P, st, _cov0(), 100.0, 110.0, prec=64)
