@@ -58,6 +58,16 @@ def test_workspace_sizes_grow_and_layout_is_ordered():
                                       "tl_hit", "tl_ncand", "owner", "scratch", "total")]
     assert offs == sorted(offs) and all(o % 256 == 0 for o in offs)
     assert lay.tl_hit + 4 * 152 * lay.cap_tracklets <= lay.tl_ncand
+    # the merging's workspace grows with the segment capacity and, for the
+    # merged-order hit data, by 16 bytes per hit slot (size_t beyond 2^31)
+    L.tpc_merge_workspace_bytes.restype = C.c_size_t
+    m0 = L.tpc_merge_workspace_bytes(C.c_int64(1000), C.c_int64(0))
+    m1 = L.tpc_merge_workspace_bytes(C.c_int64(1000), C.c_int64(50000))
+    assert 0 < m0 and m1 - m0 >= 16 * 50000
+    assert L.tpc_merge_workspace_bytes(C.c_int64(2000), C.c_int64(0)) > m0
+    assert L.tpc_merge_workspace_bytes(C.c_int64(-1), C.c_int64(0)) == 0
+    assert L.tpc_merge_workspace_bytes(C.c_int64(1000), C.c_int64(-1)) == 0
+    assert L.tpc_merge_workspace_bytes(C.c_int64(1 << 26), C.c_int64(1 << 28)) > 1 << 32
     p = tpc.make_params()
     assert L.tpc_grid_bin_capacity(C.byref(p), C.c_int32(2), C.c_int64(100)) >= 5 * 50 + 2 * 152 * 9
     p.grid_occupancy = 0.5
